@@ -1,0 +1,280 @@
+"""Plain CPU oracle for the FuseFSS hot path (ctypes wrapper of fss_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  It shares no code
+with the GPU library; the only thing both sides consume is the seeded input
+description in ``paper_2606_09551_amd.workloads`` (specs as real numbers and
+plaintext inputs), which holds none of the method's arithmetic.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fss_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+
+MAXN, MAXP, MAXM, MAXPRED, MAXT, MAXL = 32, 4, 64, 8, 12, 8
+LT_SIGNED, LT_UNSIGNED, LOWBITS_LT, MSB_SHIFT = 0, 1, 2, 3
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/_build/liboracle.so."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+                               "-pthread", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Blk(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_uint64)]
+
+
+class DcfKey(C.Structure):
+    _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("root", Blk), ("scw", Blk * MAXN),
+                ("tl", C.c_uint8 * MAXN), ("tr", C.c_uint8 * MAXN),
+                ("vcw", (C.c_uint64 * MAXP) * MAXN), ("fin", C.c_uint64 * MAXP)]
+
+
+class ElemKey(C.Structure):
+    _fields_ = [("atom", DcfKey * MAXT), ("wshare", C.c_uint64), ("coeff", DcfKey),
+                ("rho", C.c_uint64 * MAXP), ("rout", C.c_uint64)]
+
+
+class Interval(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double)]
+
+
+class Piece(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("coef", C.c_double * 4)]
+
+
+class Pred(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("negate", C.c_int32), ("out", C.c_int32),
+                ("f_bits", C.c_int32), ("thr", C.c_double), ("gamma", C.c_int64),
+                ("c", C.c_int64)]
+
+
+class Spec(C.Structure):
+    _fields_ = [("n", C.c_int32), ("f", C.c_int32), ("m", C.c_int32), ("d", C.c_int32),
+                ("p", C.c_int32), ("F_out", C.c_int32), ("ell", C.c_int32),
+                ("alpha", C.c_int64 * (MAXM + 1)), ("aprime", C.c_uint64 * (MAXM + 1)),
+                ("coef", (C.c_uint64 * MAXP) * MAXM),
+                ("n_user", C.c_int32),
+                ("u_kind", C.c_int32 * MAXPRED), ("u_out", C.c_int32 * MAXPRED),
+                ("u_neg", C.c_int32 * MAXPRED), ("u_f", C.c_int32 * MAXPRED),
+                ("u_beta", C.c_int64 * MAXPRED), ("u_c", C.c_uint64 * MAXPRED),
+                ("n_prim", C.c_int32),
+                ("prim_k", C.c_int32 * MAXPRED), ("prim_view", C.c_int32 * MAXPRED),
+                ("prim_out", C.c_int32 * MAXPRED), ("prim_bprime", C.c_uint64 * MAXPRED),
+                ("n_views", C.c_int32), ("view_k", C.c_int32 * MAXPRED),
+                ("view_c", C.c_uint64 * MAXPRED), ("T", C.c_int32),
+                ("negate", C.c_uint8 * MAXL)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        u8p, u64p, i64p = C.POINTER(C.c_uint8), C.POINTER(C.c_uint64), C.POINTER(C.c_int64)
+        L.orc_aes128_encrypt_key.argtypes = [u8p, u8p, u8p]
+        L.orc_sbox.argtypes = [u8p]
+        L.orc_prg.argtypes = [Blk, C.c_int]
+        L.orc_prg.restype = Blk
+        L.orc_seed_sched.argtypes = [C.c_uint64, C.c_void_p]
+        L.orc_rand.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int]
+        L.orc_rand.restype = Blk
+        L.orc_dcf_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk,
+                                  C.POINTER(DcfKey), C.POINTER(DcfKey)]
+        L.orc_dcf_eval.argtypes = [C.c_int, C.POINTER(DcfKey), C.c_uint64, u64p]
+        L.orc_spec_compile.argtypes = [C.POINTER(Interval), C.c_int32, C.POINTER(Piece),
+                                       C.POINTER(Pred), C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_int32, C.POINTER(Spec)]
+        L.orc_keygen_batch.argtypes = [C.POINTER(Spec), C.c_uint64, i64p, C.c_int64,
+                                       C.POINTER(ElemKey), C.POINTER(ElemKey), u64p, u64p, C.c_int]
+        L.orc_eval_batch.argtypes = [C.c_int, C.POINTER(Spec), C.POINTER(ElemKey), u64p,
+                                     C.c_int64, u64p, u64p, C.c_int]
+        L.orc_full_batch.argtypes = [C.POINTER(Spec), C.c_uint64, i64p, C.c_int64, i64p,
+                                     u64p, u64p, u64p, u64p, C.c_int]
+        L.orc_plain_eval.argtypes = [C.POINTER(Spec), C.c_int64, u64p, u64p]
+        L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
+                                    C.POINTER(C.c_int32)]
+        for name, cls in (("orc_sizeof_elem_key", ElemKey), ("orc_sizeof_dcf_key", DcfKey),
+                          ("orc_sizeof_spec", Spec)):
+            got = getattr(L, name)()
+            if got != C.sizeof(cls):
+                raise RuntimeError(f"oracle struct layout mismatch: {name} {got} != {C.sizeof(cls)}")
+        _lib = L
+    return _lib
+
+
+def _u64p(a: np.ndarray):
+    assert a.dtype == np.uint64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def _i64p(a: np.ndarray):
+    assert a.dtype == np.int64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+# ---- AES / PRG / randomness ------------------------------------------------
+
+def aes128(key: bytes, block: bytes) -> bytes:
+    k = (C.c_uint8 * 16).from_buffer_copy(key)
+    i = (C.c_uint8 * 16).from_buffer_copy(block)
+    o = (C.c_uint8 * 16)()
+    lib().orc_aes128_encrypt_key(k, i, o)
+    return bytes(o)
+
+
+def sbox() -> bytes:
+    o = (C.c_uint8 * 256)()
+    lib().orc_sbox(o)
+    return bytes(o)
+
+
+def prg(lo: int, hi: int, j: int) -> tuple[int, int]:
+    r = lib().orc_prg(Blk(lo, hi), j)
+    return r.lo, r.hi
+
+
+def rand(seed: int, e: int, purpose: int, ctr: int = 0) -> tuple[int, int]:
+    ks = (C.c_uint8 * 176)()
+    lib().orc_seed_sched(seed, ks)
+    r = lib().orc_rand(ks, e, purpose, ctr)
+    return r.lo, r.hi
+
+
+# ---- DCF ---------------------------------------------------------------------
+
+def dcf_gen(n: int, p: int, alpha: int, beta, root0, root1):
+    """p == 0: payload in Z_2 (beta one bit); else beta is a length-p list in Z_{2^64}."""
+    b = (C.c_uint64 * MAXP)(*([int(v) & (2**64 - 1) for v in (beta if p else [beta])]))
+    k0, k1 = DcfKey(), DcfKey()
+    lib().orc_dcf_gen(n, p, alpha, b, Blk(*root0), Blk(*root1), C.byref(k0), C.byref(k1))
+    return k0, k1
+
+
+def dcf_eval(b: int, key: DcfKey, x: int):
+    out = (C.c_uint64 * MAXP)()
+    lib().orc_dcf_eval(b, C.byref(key), x, out)
+    return out[0] if key.p == 0 else list(out[: key.p])
+
+
+# ---- specs -------------------------------------------------------------------
+
+class SpecError(ValueError):
+    pass
+
+
+def compile_spec(desc, n_bits: int, frac_bits: int) -> Spec:
+    """desc: paper_2606_09551_amd.workloads.SpecDesc (real-valued spec)."""
+    m = len(desc.intervals)
+    iv = (Interval * m)(*[Interval(lo, hi) for lo, hi in desc.intervals])
+    pcs = (Piece * m)()
+    for i, coefs in enumerate(desc.pieces):
+        pcs[i].degree = len(coefs) - 1          # degree > 3 is rejected by the C side
+        for l, c in enumerate(coefs[:4]):
+            pcs[i].coef[l] = c
+    np_ = len(desc.preds)
+    prs = (Pred * max(np_, 1))()
+    for j, q in enumerate(desc.preds):
+        prs[j] = Pred(q.kind, int(q.negate), q.out, q.f_bits, q.thr, q.gamma, q.c)
+    S = Spec()
+    rc = lib().orc_spec_compile(iv, m, pcs, prs, np_, n_bits, frac_bits, desc.out_frac_bits,
+                                C.byref(S))
+    if rc != 0:
+        raise SpecError(f"oracle rejected spec {getattr(desc, 'name', '?')}: rc={rc}")
+    return S
+
+
+def spec_tables(S: Spec) -> dict:
+    """Integer tables of a compiled spec, for comparison with the library."""
+    m, p = S.m, S.p
+    return {
+        "n": S.n, "f": S.f, "m": m, "d": S.d, "p": p, "F_out": S.F_out, "ell": S.ell, "T": S.T,
+        "alpha": [S.alpha[i] for i in range(m + 1)],
+        "aprime": [S.aprime[i] for i in range(m + 1)],
+        "coef": [[S.coef[i][l] for l in range(p)] for i in range(m)],
+        "atoms": ([(S.prim_k[t], S.view_c[S.prim_view[t]], 0) for t in range(S.n_prim)]
+                  + [(S.view_k[v], S.view_c[v], 1) for v in range(S.n_views)]),
+        "negate": [S.negate[j] for j in range(S.ell)],
+    }
+
+
+# ---- keygen / eval -----------------------------------------------------------
+
+def keygen(S: Spec, seed: int, elems, threads: int = 0):
+    elems = np.ascontiguousarray(elems, dtype=np.int64)
+    cnt = len(elems)
+    K0 = (ElemKey * max(cnt, 1))()
+    K1 = (ElemKey * max(cnt, 1))()
+    r_in = np.zeros(cnt, np.uint64)
+    r_out = np.zeros(cnt, np.uint64)
+    lib().orc_keygen_batch(C.byref(S), seed, _i64p(elems), cnt, K0, K1, _u64p(r_in),
+                           _u64p(r_out), threads)
+    return K0, K1, r_in, r_out
+
+
+def evaluate(b: int, S: Spec, K, xhat, threads: int = 0):
+    xhat = np.ascontiguousarray(xhat, dtype=np.uint64)
+    cnt = len(xhat)
+    y = np.zeros(cnt, np.uint64)
+    z = np.zeros(cnt, np.uint64)
+    lib().orc_eval_batch(b, C.byref(S), K, _u64p(xhat), cnt, _u64p(y), _u64p(z), threads)
+    return y, z
+
+
+def full(S: Spec, seed: int, elems, x, threads: int = 0):
+    """Dealer keygen + both parties' evaluation for the given element indices.
+
+    Returns (y0, y1, z0, z1, threads_used)."""
+    elems = np.ascontiguousarray(elems, dtype=np.int64)
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    cnt = len(elems)
+    y0, y1, z0, z1 = (np.zeros(cnt, np.uint64) for _ in range(4))
+    used = lib().orc_full_batch(C.byref(S), seed, _i64p(elems), cnt, _i64p(x), _u64p(y0),
+                                _u64p(y1), _u64p(z0), _u64p(z1), threads)
+    return y0, y1, z0, z1, used
+
+
+def plain(S: Spec, x: int) -> tuple[int, int]:
+    y, z = C.c_uint64(), C.c_uint64()
+    lib().orc_plain_eval(C.byref(S), int(x), C.byref(y), C.byref(z))
+    return y.value, z.value
+
+
+def plain_many(S: Spec, xs):
+    ys = np.zeros(len(xs), np.uint64)
+    zs = np.zeros(len(xs), np.uint64)
+    for i, x in enumerate(np.asarray(xs, dtype=np.int64)):
+        ys[i], zs[i] = plain(S, int(x))
+    return ys, zs
+
+
+def protocol3(n: int, alpha, r: int):
+    m = len(alpha) - 1
+    a = np.ascontiguousarray(alpha, dtype=np.uint64)
+    B = np.zeros(m + 3, np.uint64)
+    ordv = (C.c_int32 * (m + 2))()
+    M = lib().orc_protocol3(n, _u64p(a), m, r, _u64p(B), ordv)
+    if M < 0:
+        raise RuntimeError("protocol3 shape error")
+    return [int(v) for v in B[: M + 1]], list(ordv[:M])
+
+
+def hw_threads() -> int:
+    return lib().orc_hw_threads()

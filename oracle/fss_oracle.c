@@ -1,0 +1,764 @@
+/*
+ * fss_oracle.c -- plain CPU oracle for the FuseFSS hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the library.  Written for
+ * readability, not speed: every step follows the paper (or the cited
+ * construction) in its own order.
+ *
+ * Conventions fixed here (the paper leaves them open):
+ *   * 16-byte blocks are (lo, hi) = little-endian u64 of bytes 0..7, 8..15.
+ *   * PRG: H(s, j) = AES_K(s ^ J_j) ^ s ^ J_j, K = 00 01 .. 0f, J_j is the
+ *     block whose byte 15 is j (j < 8) and every other byte 0.
+ *   * Randomness: R(e, pi, c) = AES_{K_seed}(e u64 | pi u16 | c u16 | 0 u32),
+ *     K_seed = seed u64 little-endian followed by eight zero bytes.
+ *   * DCF: Boyle et al. EUROCRYPT'21 comparison function f(x) = beta*[x < alpha],
+ *     MSB-first over n bits, seeds with bits 0..1 of byte 0 cleared.
+ */
+#include "fss_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <string.h>
+#include <unistd.h>
+
+/* ========================================================================= */
+/* AES-128 (FIPS-197)                                                        */
+/* ========================================================================= */
+
+static uint8_t SBOX[256];
+static orc_aes_sched PRG_SCHED;
+
+static uint8_t xtime(uint8_t a) { return (uint8_t)((a << 1) ^ ((a & 0x80) ? 0x1b : 0x00)); }
+
+static uint8_t gf_mul(uint8_t a, uint8_t b) {
+  uint8_t r = 0;
+  while (b) {
+    if (b & 1) r ^= a;
+    a = xtime(a);
+    b >>= 1;
+  }
+  return r;
+}
+
+static uint8_t rotl8(uint8_t x, int k) { return (uint8_t)((x << k) | (x >> (8 - k))); }
+
+/* FIPS-197 Sec. 5.1.1: multiplicative inverse in GF(2^8) (0 maps to 0),
+ * then the affine transformation with constant 0x63. */
+static void build_sbox(void) {
+  for (int a = 0; a < 256; a++) {
+    uint8_t inv = 0;
+    if (a) {
+      /* a^254 = a^-1 in GF(2^8) */
+      uint8_t r = 1, base = (uint8_t)a;
+      int e = 254;
+      while (e) {
+        if (e & 1) r = gf_mul(r, base);
+        base = gf_mul(base, base);
+        e >>= 1;
+      }
+      inv = r;
+    }
+    SBOX[a] = (uint8_t)(inv ^ rotl8(inv, 1) ^ rotl8(inv, 2) ^ rotl8(inv, 3) ^ rotl8(inv, 4) ^ 0x63);
+  }
+}
+
+void orc_sbox(uint8_t out[256]) { memcpy(out, SBOX, 256); }
+
+/* FIPS-197 Sec. 5.2 key expansion, Nk = 4, Nr = 10. rk[4*i + j] = byte j of w[i]. */
+void orc_aes128_expand(const uint8_t key[16], orc_aes_sched* ks) {
+  uint8_t* w = ks->rk;
+  memcpy(w, key, 16);
+  uint8_t rcon = 0x01;
+  for (int i = 4; i < 44; i++) {
+    uint8_t t[4];
+    memcpy(t, &w[4 * (i - 1)], 4);
+    if (i % 4 == 0) {
+      uint8_t t0 = t[0]; /* RotWord */
+      t[0] = t[1]; t[1] = t[2]; t[2] = t[3]; t[3] = t0;
+      for (int j = 0; j < 4; j++) t[j] = SBOX[t[j]]; /* SubWord */
+      t[0] ^= rcon;
+      rcon = xtime(rcon);
+    }
+    for (int j = 0; j < 4; j++) w[4 * i + j] = (uint8_t)(w[4 * (i - 4) + j] ^ t[j]);
+  }
+}
+
+/* FIPS-197 Sec. 5.1: state[r][c] = in[r + 4c]. */
+void orc_aes128_encrypt(const orc_aes_sched* ks, const uint8_t in[16], uint8_t out[16]) {
+  uint8_t st[4][4];
+  for (int c = 0; c < 4; c++)
+    for (int r = 0; r < 4; r++) st[r][c] = in[r + 4 * c];
+
+  for (int round = 0; round <= 10; round++) {
+    if (round > 0) {
+      /* SubBytes */
+      for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) st[r][c] = SBOX[st[r][c]];
+      /* ShiftRows: row r rotates left by r */
+      for (int r = 1; r < 4; r++) {
+        uint8_t row[4];
+        for (int c = 0; c < 4; c++) row[c] = st[r][(c + r) % 4];
+        for (int c = 0; c < 4; c++) st[r][c] = row[c];
+      }
+      /* MixColumns (not in the final round) */
+      if (round < 10) {
+        for (int c = 0; c < 4; c++) {
+          uint8_t a0 = st[0][c], a1 = st[1][c], a2 = st[2][c], a3 = st[3][c];
+          st[0][c] = (uint8_t)(gf_mul(a0, 2) ^ gf_mul(a1, 3) ^ a2 ^ a3);
+          st[1][c] = (uint8_t)(a0 ^ gf_mul(a1, 2) ^ gf_mul(a2, 3) ^ a3);
+          st[2][c] = (uint8_t)(a0 ^ a1 ^ gf_mul(a2, 2) ^ gf_mul(a3, 3));
+          st[3][c] = (uint8_t)(gf_mul(a0, 3) ^ a1 ^ a2 ^ gf_mul(a3, 2));
+        }
+      }
+    }
+    /* AddRoundKey */
+    for (int c = 0; c < 4; c++)
+      for (int r = 0; r < 4; r++) st[r][c] ^= ks->rk[16 * round + 4 * c + r];
+  }
+  for (int c = 0; c < 4; c++)
+    for (int r = 0; r < 4; r++) out[r + 4 * c] = st[r][c];
+}
+
+void orc_aes128_encrypt_key(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]) {
+  orc_aes_sched ks;
+  orc_aes128_expand(key, &ks);
+  orc_aes128_encrypt(&ks, in, out);
+}
+
+__attribute__((constructor)) static void oracle_init(void) {
+  build_sbox();
+  uint8_t k[16];
+  for (int i = 0; i < 16; i++) k[i] = (uint8_t)i;
+  orc_aes128_expand(k, &PRG_SCHED);
+}
+
+/* ========================================================================= */
+/* Blocks, PRG, randomness                                                   */
+/* ========================================================================= */
+
+static void blk_to_bytes(orc_blk b, uint8_t out[16]) {
+  for (int i = 0; i < 8; i++) {
+    out[i] = (uint8_t)(b.lo >> (8 * i));
+    out[8 + i] = (uint8_t)(b.hi >> (8 * i));
+  }
+}
+
+static orc_blk bytes_to_blk(const uint8_t in[16]) {
+  orc_blk b = {0, 0};
+  for (int i = 0; i < 8; i++) {
+    b.lo |= (uint64_t)in[i] << (8 * i);
+    b.hi |= (uint64_t)in[8 + i] << (8 * i);
+  }
+  return b;
+}
+
+orc_blk orc_prg(orc_blk s, int j) {
+  orc_blk x = s;
+  x.hi ^= (uint64_t)(uint8_t)j << 56; /* byte 15 */
+  uint8_t in[16], out[16];
+  blk_to_bytes(x, in);
+  orc_aes128_encrypt(&PRG_SCHED, in, out);
+  orc_blk y = bytes_to_blk(out);
+  y.lo ^= x.lo;
+  y.hi ^= x.hi;
+  return y;
+}
+
+void orc_seed_sched(uint64_t seed, orc_aes_sched* ks) {
+  uint8_t k[16] = {0};
+  for (int i = 0; i < 8; i++) k[i] = (uint8_t)(seed >> (8 * i));
+  orc_aes128_expand(k, ks);
+}
+
+orc_blk orc_rand(const orc_aes_sched* kseed, uint64_t e, int purpose, int ctr) {
+  orc_blk x;
+  x.lo = e;
+  x.hi = (uint64_t)(uint16_t)purpose | ((uint64_t)(uint16_t)ctr << 16);
+  uint8_t in[16], out[16];
+  blk_to_bytes(x, in);
+  orc_aes128_encrypt(kseed, in, out);
+  return bytes_to_blk(out);
+}
+
+/* ========================================================================= */
+/* DCF (Boyle, Chandran, Gilboa, Gupta, Ishai, Kumar, Rathee, EUROCRYPT'21)  */
+/* ========================================================================= */
+/* Group elements are uint64_t[ORC_MAXP].  p == 0 encodes Z_2 (value in g[0],
+ * addition is XOR, negation is the identity); p >= 1 encodes Z_{2^64}^p.   */
+
+static int glen(int p) { return p == 0 ? 1 : p; }
+
+static void g_zero(int p, uint64_t* a) { for (int k = 0; k < glen(p); k++) a[k] = 0; }
+static void g_add(int p, uint64_t* a, const uint64_t* b) {
+  for (int k = 0; k < glen(p); k++) a[k] = (p == 0) ? (a[k] ^ b[k]) : (a[k] + b[k]);
+}
+static void g_sub(int p, uint64_t* a, const uint64_t* b) {
+  for (int k = 0; k < glen(p); k++) a[k] = (p == 0) ? (a[k] ^ b[k]) : (a[k] - b[k]);
+}
+/* a = (-1)^t * a */
+static void g_sign(int p, int t, uint64_t* a) {
+  if (p == 0 || !t) return;
+  for (int k = 0; k < p; k++) a[k] = (uint64_t)0 - a[k];
+}
+
+static orc_blk clear2(orc_blk s) { s.lo &= ~(uint64_t)3; return s; }
+
+/* Child c of seed s: next seed, control bit t, and group value v. */
+static void expand(int p, orc_blk s, int c, orc_blk* s_out, int* t_out, uint64_t* v_out) {
+  orc_blk n = orc_prg(s, c);
+  *t_out = (int)(n.lo & 1);
+  *s_out = clear2(n);
+  if (p == 0) {
+    v_out[0] = (n.lo >> 1) & 1;
+  } else {
+    uint64_t w[4];
+    orc_blk a = orc_prg(s, 2 + 2 * c);
+    w[0] = a.lo; w[1] = a.hi;
+    if (p > 2) { orc_blk b = orc_prg(s, 3 + 2 * c); w[2] = b.lo; w[3] = b.hi; }
+    for (int k = 0; k < p; k++) v_out[k] = w[k];
+  }
+}
+
+/* Convert(s) at the leaves. */
+static void convert(int p, orc_blk s, uint64_t* out) {
+  if (p == 0) {
+    out[0] = (s.lo >> 2) & 1;
+  } else {
+    uint64_t w[4];
+    orc_blk a = orc_prg(s, 6);
+    w[0] = a.lo; w[1] = a.hi;
+    if (p > 2) { orc_blk b = orc_prg(s, 7); w[2] = b.lo; w[3] = b.hi; }
+    for (int k = 0; k < p; k++) out[k] = w[k];
+  }
+}
+
+void orc_dcf_gen(int n, int p, uint64_t alpha, const uint64_t* beta,
+                 orc_blk root0, orc_blk root1, orc_dcf_key* k0, orc_dcf_key* k1) {
+  memset(k0, 0, sizeof *k0);
+  memset(k1, 0, sizeof *k1);
+  k0->n = k1->n = n;
+  k0->p = k1->p = p;
+  orc_blk s[2] = {clear2(root0), clear2(root1)};
+  int t[2] = {0, 1};
+  k0->root = s[0];
+  k1->root = s[1];
+  uint64_t Va[ORC_MAXP];
+  g_zero(p, Va);
+
+  for (int i = 0; i < n; i++) {
+    int ai = (int)((alpha >> (n - 1 - i)) & 1);
+    orc_blk sc[2][2];          /* [party][child] */
+    int tc[2][2];
+    uint64_t vc[2][2][ORC_MAXP];
+    for (int b = 0; b < 2; b++)
+      for (int c = 0; c < 2; c++) expand(p, s[b], c, &sc[b][c], &tc[b][c], vc[b][c]);
+    int keep = ai, lose = 1 - ai;   /* child 0 = L, child 1 = R */
+
+    orc_blk scw;
+    scw.lo = sc[0][lose].lo ^ sc[1][lose].lo;
+    scw.hi = sc[0][lose].hi ^ sc[1][lose].hi;
+
+    /* V_CW = (-1)^{t1} (v1^Lose - v0^Lose - V_alpha) [+ (-1)^{t1} beta if Lose = L] */
+    uint64_t vcw[ORC_MAXP], tmp[ORC_MAXP];
+    memcpy(vcw, vc[1][lose], sizeof vcw);
+    g_sub(p, vcw, vc[0][lose]);
+    g_sub(p, vcw, Va);
+    g_sign(p, t[1], vcw);
+    if (lose == 0) {
+      memcpy(tmp, beta, sizeof(uint64_t) * glen(p));
+      g_sign(p, t[1], tmp);
+      g_add(p, vcw, tmp);
+    }
+    /* V_alpha = V_alpha - v1^Keep + v0^Keep + (-1)^{t1} V_CW */
+    g_sub(p, Va, vc[1][keep]);
+    g_add(p, Va, vc[0][keep]);
+    memcpy(tmp, vcw, sizeof tmp);
+    g_sign(p, t[1], tmp);
+    g_add(p, Va, tmp);
+
+    int tlcw = tc[0][0] ^ tc[1][0] ^ ai ^ 1;
+    int trcw = tc[0][1] ^ tc[1][1] ^ ai;
+    int tkeep = keep ? trcw : tlcw;
+
+    k0->scw[i] = k1->scw[i] = scw;
+    k0->tl[i] = k1->tl[i] = (uint8_t)tlcw;
+    k0->tr[i] = k1->tr[i] = (uint8_t)trcw;
+    for (int k = 0; k < glen(p); k++) k0->vcw[i][k] = k1->vcw[i][k] = vcw[k];
+
+    for (int b = 0; b < 2; b++) {
+      orc_blk ns = sc[b][keep];
+      if (t[b]) { ns.lo ^= scw.lo; ns.hi ^= scw.hi; }
+      int nt = tc[b][keep] ^ (t[b] & tkeep);
+      s[b] = ns;
+      t[b] = nt;
+    }
+  }
+  /* CW^(n+1) = (-1)^{t1} (Convert(s1) - Convert(s0) - V_alpha) */
+  uint64_t c0[ORC_MAXP], c1[ORC_MAXP];
+  convert(p, s[0], c0);
+  convert(p, s[1], c1);
+  g_sub(p, c1, c0);
+  g_sub(p, c1, Va);
+  g_sign(p, t[1], c1);
+  for (int k = 0; k < glen(p); k++) k0->fin[k] = k1->fin[k] = c1[k];
+}
+
+void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out) {
+  int n = k->n, p = k->p;
+  orc_blk s = k->root;
+  int t = b;
+  uint64_t V[ORC_MAXP], tmp[ORC_MAXP];
+  g_zero(p, V);
+  for (int i = 0; i < n; i++) {
+    int xi = (int)((x >> (n - 1 - i)) & 1);
+    orc_blk ns;
+    int nt;
+    uint64_t v[ORC_MAXP];
+    expand(p, s, xi, &ns, &nt, v);
+    if (t) {
+      ns.lo ^= k->scw[i].lo;
+      ns.hi ^= k->scw[i].hi;
+      nt ^= xi ? k->tr[i] : k->tl[i];
+      g_add(p, v, k->vcw[i]);   /* v + t * V_CW, with the parent's t */
+    }
+    memcpy(tmp, v, sizeof tmp);
+    g_sign(p, b, tmp);
+    g_add(p, V, tmp);
+    s = ns;
+    t = nt;
+  }
+  convert(p, s, tmp);
+  if (t) g_add(p, tmp, k->fin);
+  g_sign(p, b, tmp);
+  g_add(p, V, tmp);
+  for (int q = 0; q < glen(p); q++) out[q] = V[q];
+}
+
+/* ========================================================================= */
+/* Operator specification                                                    */
+/* ========================================================================= */
+
+static int64_t clamp_ceil(double v, int64_t lo, int64_t hi) {
+  double c = ceil(v);
+  if (c <= (double)lo) return lo;
+  if (c >= (double)hi) return hi;
+  return (int64_t)c;
+}
+
+static int find_or_add_view(orc_spec* S, int k, uint64_t c) {
+  for (int v = 0; v < S->n_views; v++)
+    if (S->view_k[v] == k && S->view_c[v] == c) return v;
+  if (S->n_views >= ORC_MAXPRED) return -1;
+  S->view_k[S->n_views] = k;
+  S->view_c[S->n_views] = c;
+  return S->n_views++;
+}
+
+int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
+                     const orc_pred* pr, int32_t n_pred, int32_t n_bits,
+                     int32_t frac_bits, int32_t out_frac_bits, orc_spec* S) {
+  memset(S, 0, sizeof *S);
+  if (n_bits < 2 || n_bits > ORC_MAXN) return -2;
+  if (frac_bits < 0 || frac_bits >= n_bits) return -2;
+  if (m < 1 || m > ORC_MAXM) return -1;
+  if (n_pred < 0 || n_pred > ORC_MAXPRED) return -2;
+  const int n = n_bits, f = frac_bits;
+  const int64_t N = (int64_t)1 << n, s = N / 2;
+  S->n = n; S->f = f; S->m = m;
+
+  /* Partition: contiguous half-open real intervals, tails at -inf / +inf. */
+  if (!(isinf(iv[0].lo) && iv[0].lo < 0)) return -1;
+  if (!(isinf(iv[m - 1].hi) && iv[m - 1].hi > 0)) return -1;
+  for (int i = 0; i < m; i++)
+    if (!(iv[i].lo < iv[i].hi)) return -1;
+  for (int i = 0; i + 1 < m; i++)
+    if (iv[i].hi != iv[i + 1].lo) return -1;
+  S->alpha[0] = -s;
+  S->alpha[m] = s;
+  /* Real boundary a maps to ceil(a 2^f): the integers whose real value is >= a. */
+  for (int i = 1; i < m; i++) S->alpha[i] = clamp_ceil(ldexp(iv[i].lo, f), -s, s);
+  for (int i = 1; i <= m; i++)
+    if (!(S->alpha[i - 1] < S->alpha[i])) return -1;
+  for (int i = 0; i <= m; i++) S->aprime[i] = (uint64_t)(S->alpha[i] + s);
+
+  /* Pieces: coefficient a_l scaled by 2^(F_out - l f), ties to even. */
+  int d = 0;
+  for (int i = 0; i < m; i++) {
+    if (pc[i].degree < 0 || pc[i].degree > 3) return -1;
+    if (pc[i].degree > d) d = pc[i].degree;
+  }
+  S->d = d;
+  S->p = d + 1;
+  S->F_out = out_frac_bits >= 0 ? out_frac_bits : (d <= 1 ? 2 * f : 4 * f);
+  for (int i = 0; i < m; i++) {
+    double X = fmax(fabs((double)S->alpha[i]), fabs((double)(S->alpha[i + 1] - 1)));
+    double bound = 0;
+    for (int l = 0; l <= d; l++) {
+      double a = (l <= pc[i].degree) ? pc[i].coef[l] : 0.0;
+      double q = nearbyint(ldexp(a, S->F_out - l * f));
+      if (!(fabs(q) < 9223372036854775808.0)) return -1; /* also rejects NaN */
+      S->coef[i][l] = (uint64_t)(int64_t)q;
+      bound += fabs(q) * pow(X, l);
+    }
+    if (!(bound < 4611686018427387904.0)) return -1; /* |P_i(x)| < 2^62 on I_i */
+  }
+
+  /* Predicates: quantise, map to a view and a threshold in view space. */
+  S->n_user = n_pred;
+  S->ell = 0;
+  for (int j = 0; j < n_pred; j++) {
+    const orc_pred* q = &pr[j];
+    if (q->out < 0 || q->out >= ORC_MAXL) return -2;
+    if (q->out + 1 > S->ell) S->ell = q->out + 1;
+    int k = n;
+    uint64_t c = 0, bprime = 0;
+    int flip = q->negate ? 1 : 0;
+    S->u_kind[j] = q->kind;
+    S->u_out[j] = q->out;
+    S->u_neg[j] = flip;
+    switch (q->kind) {
+      case ORC_LT_SIGNED: {        /* x <_s beta  ==  view_{n,s}(x) < beta + s */
+        if (isnan(q->thr)) return -1;
+        int64_t beta = clamp_ceil(ldexp(q->thr, f), -s, s);
+        S->u_beta[j] = beta;
+        c = (uint64_t)s;
+        bprime = (uint64_t)(beta + s);
+        break;
+      }
+      case ORC_LT_UNSIGNED: {      /* rep(x) < beta */
+        if (isnan(q->thr)) return -1;
+        int64_t beta = clamp_ceil(ldexp(q->thr, f), 0, N);
+        S->u_beta[j] = beta;
+        bprime = (uint64_t)beta;
+        break;
+      }
+      case ORC_LOWBITS_LT: {       /* (x mod 2^fb) < gamma */
+        if (q->f_bits < 1 || q->f_bits > n) return -2;
+        if (q->gamma < 0 || q->gamma > ((int64_t)1 << q->f_bits)) return -1;
+        k = q->f_bits;
+        S->u_f[j] = k;
+        S->u_beta[j] = q->gamma;
+        bprime = (uint64_t)q->gamma;
+        break;
+      }
+      case ORC_MSB_SHIFT: {        /* MSB(x + c) == NOT [view_{n,c}(x) < 2^(n-1)] */
+        c = (uint64_t)q->c & (uint64_t)(N - 1);
+        S->u_c[j] = c;
+        bprime = (uint64_t)s;
+        flip ^= 1;
+        break;
+      }
+      default:
+        return -2;
+    }
+    S->negate[q->out] ^= (uint8_t)flip;
+    if (bprime == 0) continue;                     /* sentinel: constant 0 */
+    if (bprime == ((uint64_t)1 << k)) {            /* sentinel: constant 1 */
+      S->negate[q->out] ^= 1;
+      continue;
+    }
+    int v = find_or_add_view(S, k, c);
+    if (v < 0) return -2;
+    int t = S->n_prim++;
+    S->prim_k[t] = k;
+    S->prim_view[t] = v;
+    S->prim_out[t] = q->out;
+    S->prim_bprime[t] = bprime;
+  }
+  S->T = S->n_prim + S->n_views;
+  if (S->T > ORC_MAXT) return -2;
+  return 0;
+}
+
+/* ========================================================================= */
+/* Dealer key generation for one element                                     */
+/* ========================================================================= */
+
+static uint64_t lowmask(int k) { return k >= 64 ? ~(uint64_t)0 : (((uint64_t)1 << k) - 1); }
+
+void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
+                     orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in_out, uint64_t* r_out_out) {
+  /* Masks and the output-mask sharing. */
+  orc_blk r0 = orc_rand(kseed, e, 0, 0);
+  uint64_t r_in = r0.lo, r_out = r0.hi;
+  orc_blk r1 = orc_rand(kseed, e, 1, 0);
+  k0->rout = r1.lo;
+  k1->rout = r_out - r1.lo;
+
+  /* Packed comparison: one Z_2 DCF per atom.  Threshold atoms follow the
+   * masked rewrite 1[x' < b'] = 1[v < theta] ^ 1[v < r_k] ^ w with
+   * theta = (r_k + b') mod 2^k and w = 1[r_k + b' >= 2^k]. */
+  uint64_t wout = 0;
+  for (int t = 0; t < S->T; t++) {
+    int k;
+    uint64_t alpha;
+    if (t < S->n_prim) {
+      k = S->prim_k[t];
+      uint64_t rk = r_in & lowmask(k);
+      uint64_t sum = rk + S->prim_bprime[t];
+      alpha = sum & lowmask(k);
+      if (sum >> k) wout ^= (uint64_t)1 << S->prim_out[t];
+    } else {
+      k = S->view_k[t - S->n_prim];
+      alpha = r_in & lowmask(k);
+    }
+    uint64_t beta = 1;
+    orc_blk a = orc_rand(kseed, e, 2 + 2 * t, 0);
+    orc_blk b = orc_rand(kseed, e, 3 + 2 * t, 0);
+    orc_dcf_gen(k, 0, alpha, &beta, a, b, &k0->atom[t], &k1->atom[t]);
+  }
+  uint64_t W = orc_rand(kseed, e, 66, 0).lo & lowmask(S->ell);
+  k0->wshare = W;
+  k1->wshare = W ^ wout;
+
+  /* Interval lookup: one vector DCF at alpha = r_in mod 2^n with payload
+   * rho = ((-r_in)^k)_{k<p}, plus additive shares of rho. */
+  uint64_t rho[ORC_MAXP];
+  rho[0] = 1;
+  for (int k = 1; k < S->p; k++) rho[k] = rho[k - 1] * ((uint64_t)0 - r_in);
+  orc_blk c0 = orc_rand(kseed, e, 64, 0);
+  orc_blk c1 = orc_rand(kseed, e, 65, 0);
+  orc_dcf_gen(S->n, S->p, r_in & lowmask(S->n), rho, c0, c1, &k0->coeff, &k1->coeff);
+  orc_blk ra = orc_rand(kseed, e, 67, 0), rb = orc_rand(kseed, e, 68, 0);
+  uint64_t sh[4] = {ra.lo, ra.hi, rb.lo, rb.hi};
+  for (int k = 0; k < S->p; k++) {
+    k0->rho[k] = sh[k];
+    k1->rho[k] = rho[k] - sh[k];
+  }
+  *r_in_out = r_in;
+  *r_out_out = r_out;
+}
+
+/* ========================================================================= */
+/* Evaluation by party b of one element at public xhat                       */
+/* ========================================================================= */
+
+static uint64_t binom(int l, int j) {
+  uint64_t r = 1;
+  for (int i = 0; i < j; i++) r = r * (uint64_t)(l - i) / (uint64_t)(i + 1);
+  return r;
+}
+
+void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xhat,
+                   uint64_t* y_out, uint64_t* z_out) {
+  /* Call 1: packed comparison.  Atom t is evaluated at view_{k,c}(xhat). */
+  int A[ORC_MAXT];
+  for (int t = 0; t < S->T; t++) {
+    int vi = (t < S->n_prim) ? S->prim_view[t] : t - S->n_prim;
+    int k = S->view_k[vi];
+    uint64_t u = ((xhat & lowmask(k)) + S->view_c[vi]) & lowmask(k);
+    uint64_t bit;
+    orc_dcf_eval(b, &K->atom[t], u, &bit);
+    A[t] = (int)bit;
+  }
+  uint64_t z = K->wshare;
+  if (b == 0)
+    for (int j = 0; j < S->ell; j++) z ^= (uint64_t)S->negate[j] << j;
+  for (int t = 0; t < S->n_prim; t++) {
+    int bit = A[t] ^ A[S->n_prim + S->prim_view[t]];
+    z ^= (uint64_t)bit << S->prim_out[t];
+  }
+
+  /* Call 2: interval lookup.  With v = view_{n,s}(xhat) and the offset-binary
+   * x' = (v - r_n) mod N, for each interior boundary a'_i:
+   *   1[x' < a'_i] = 1[(v - a'_i) mod N < r_n] - 1[v < r_n] + 1[v < a'_i],
+   * so g_i = D(u_i) - D(v) + 1[v < a'_i] rho_b shares 1[x' < a'_i] rho. */
+  const int n = S->n, m = S->m, p = S->p, d = S->d;
+  const uint64_t N = (uint64_t)1 << n, s = N / 2;
+  uint64_t v = ((xhat & (N - 1)) + s) & (N - 1);
+  uint64_t Dv[ORC_MAXP];
+  orc_dcf_eval(b, &K->coeff, v, Dv);
+  uint64_t g[ORC_MAXM + 1][ORC_MAXP];
+  for (int k = 0; k < p; k++) { g[0][k] = 0; g[m][k] = K->rho[k]; }
+  for (int i = 1; i < m; i++) {
+    uint64_t u = (v - S->aprime[i]) & (N - 1);
+    uint64_t D[ORC_MAXP];
+    orc_dcf_eval(b, &K->coeff, u, D);
+    for (int k = 0; k < p; k++)
+      g[i][k] = D[k] - Dv[k] + (v < S->aprime[i] ? K->rho[k] : 0);
+  }
+  /* e_i shares 1[x in I_i] rho; the active piece's coefficients at xhat are
+   * q_j = sum_l a_{i*,l} C(l,j) (-r_in)^(l-j). */
+  uint64_t q[ORC_MAXP] = {0};
+  for (int i = 0; i < m; i++) {
+    for (int j = 0; j <= d; j++) {
+      for (int l = j; l <= d; l++) {
+        uint64_t e = g[i + 1][l - j] - g[i][l - j];
+        q[j] += S->coef[i][l] * binom(l, j) * e;
+      }
+    }
+  }
+  q[0] += K->rout;
+  /* Local combination at the public xhat. */
+  uint64_t y = 0, xp = 1;
+  for (int j = 0; j <= d; j++) {
+    y += q[j] * xp;
+    xp *= xhat;
+  }
+  *y_out = y;
+  *z_out = z;
+}
+
+/* ========================================================================= */
+/* Plaintext evaluation                                                      */
+/* ========================================================================= */
+
+void orc_plain_eval(const orc_spec* S, int64_t x, uint64_t* y_out, uint64_t* z_out) {
+  const int n = S->n;
+  const uint64_t N = (uint64_t)1 << n, s = N / 2;
+  int is = 0;
+  while (is + 1 < S->m && x >= S->alpha[is + 1]) is++;
+  uint64_t y = 0, xp = 1;
+  for (int l = 0; l <= S->d; l++) {
+    y += S->coef[is][l] * xp;
+    xp *= (uint64_t)x;
+  }
+  uint64_t z = 0;
+  for (int j = 0; j < S->n_user; j++) {
+    int bit = 0;
+    switch (S->u_kind[j]) {
+      case ORC_LT_SIGNED: bit = x < S->u_beta[j]; break;
+      case ORC_LT_UNSIGNED: bit = (int64_t)((uint64_t)x & (N - 1)) < S->u_beta[j]; break;
+      case ORC_LOWBITS_LT: bit = (int64_t)((uint64_t)x & lowmask(S->u_f[j])) < S->u_beta[j]; break;
+      case ORC_MSB_SHIFT: bit = (((uint64_t)x + S->u_c[j]) & (N - 1)) >= s; break;
+    }
+    z ^= (uint64_t)(bit ^ S->u_neg[j]) << S->u_out[j];
+  }
+  *y_out = y;
+  *z_out = z;
+}
+
+/* ========================================================================= */
+/* Protocol "Compile a scalar gate instance", lookup part                    */
+/* ========================================================================= */
+
+int orc_protocol3(int n, const uint64_t* alpha, int m, uint64_t r, uint64_t* B, int32_t* ord) {
+  const uint64_t N = (uint64_t)1 << n;
+  int M = (uint64_t)(m + 1) < N ? m + 1 : (int)N;
+  uint64_t st[ORC_MAXM + 2];
+  int32_t pi[ORC_MAXM + 2];
+  for (int i = 0; i < m; i++) { st[i] = (alpha[i] + r) % N; pi[i] = i; }
+  /* sort translated starts (insertion sort, plain) */
+  for (int i = 1; i < m; i++)
+    for (int j = i; j > 0 && st[pi[j - 1]] > st[pi[j]]; j--) {
+      int32_t t = pi[j]; pi[j] = pi[j - 1]; pi[j - 1] = t;
+    }
+  int nb = 0, no = 0;
+  if (st[pi[0]] == 0) {
+    for (int j = 0; j < m; j++) B[nb++] = st[pi[j]];
+    B[nb++] = N;
+    for (int j = 0; j < m; j++) ord[no++] = pi[j];
+    if ((uint64_t)m < N) {
+      int js = 0;
+      while (B[js + 1] - B[js] < 2) js++;
+      uint64_t delta = B[js] + 1;
+      for (int q = nb; q > js + 1; q--) B[q] = B[q - 1];
+      B[js + 1] = delta;
+      nb++;
+      for (int q = no; q > js + 1; q--) ord[q] = ord[q - 1];
+      ord[js + 1] = ord[js];
+      no++;
+    }
+  } else {
+    B[nb++] = 0;
+    for (int j = 0; j < m; j++) B[nb++] = st[pi[j]];
+    B[nb++] = N;
+    ord[no++] = pi[m - 1];
+    for (int j = 0; j < m; j++) ord[no++] = pi[j];
+  }
+  (void)nb;
+  return no == M ? M : -1;
+}
+
+/* ========================================================================= */
+/* Batched drivers                                                           */
+/* ========================================================================= */
+
+int orc_hw_threads(void) {
+  long c = sysconf(_SC_NPROCESSORS_ONLN);
+  return c > 0 ? (int)c : 1;
+}
+int orc_sizeof_elem_key(void) { return (int)sizeof(orc_elem_key); }
+int orc_sizeof_dcf_key(void) { return (int)sizeof(orc_dcf_key); }
+int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
+
+typedef struct {
+  int kind;  /* 0 keygen, 1 eval, 2 full */
+  const orc_spec* S;
+  uint64_t seed;
+  const int64_t* elems;
+  int64_t lo, hi;
+  orc_elem_key *k0, *k1;
+  const orc_elem_key* K;
+  uint64_t *r_in, *r_out;
+  int b;
+  const uint64_t* xhat;
+  const int64_t* x;
+  uint64_t *y0, *y1, *z0, *z1;
+} job_t;
+
+static void* run_job(void* arg) {
+  job_t* J = (job_t*)arg;
+  orc_aes_sched ks;
+  orc_seed_sched(J->seed, &ks);
+  for (int64_t i = J->lo; i < J->hi; i++) {
+    if (J->kind == 0) {
+      orc_keygen_elem(J->S, &ks, (uint64_t)J->elems[i], &J->k0[i], &J->k1[i], &J->r_in[i], &J->r_out[i]);
+    } else if (J->kind == 1) {
+      orc_eval_elem(J->b, J->S, &J->K[i], J->xhat[i], &J->y0[i], &J->z0[i]);
+    } else {
+      orc_elem_key a, b;
+      uint64_t rin, rout;
+      orc_keygen_elem(J->S, &ks, (uint64_t)J->elems[i], &a, &b, &rin, &rout);
+      uint64_t xh = (uint64_t)J->x[i] + rin;
+      orc_eval_elem(0, J->S, &a, xh, &J->y0[i], &J->z0[i]);
+      orc_eval_elem(1, J->S, &b, xh, &J->y1[i], &J->z1[i]);
+    }
+  }
+  return 0;
+}
+
+static int run_jobs(job_t proto, int64_t count, int threads) {
+  if (threads <= 0) threads = orc_hw_threads();
+  if (threads > 256) threads = 256;
+  if ((int64_t)threads > count) threads = count > 0 ? (int)count : 1;
+  pthread_t th[256];
+  job_t jobs[256];
+  for (int t = 0; t < threads; t++) {
+    jobs[t] = proto;
+    jobs[t].lo = count * t / threads;
+    jobs[t].hi = count * (t + 1) / threads;
+    if (pthread_create(&th[t], 0, run_job, &jobs[t]) != 0) return -1;
+  }
+  for (int t = 0; t < threads; t++) pthread_join(th[t], 0);
+  return threads;
+}
+
+int orc_keygen_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+                     orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in, uint64_t* r_out,
+                     int threads) {
+  job_t J;
+  memset(&J, 0, sizeof J);
+  J.kind = 0; J.S = S; J.seed = seed; J.elems = elems;
+  J.k0 = k0; J.k1 = k1; J.r_in = r_in; J.r_out = r_out;
+  return run_jobs(J, count, threads);
+}
+
+int orc_eval_batch(int b, const orc_spec* S, const orc_elem_key* K, const uint64_t* xhat,
+                   int64_t count, uint64_t* y, uint64_t* zbits, int threads) {
+  job_t J;
+  memset(&J, 0, sizeof J);
+  J.kind = 1; J.S = S; J.b = b; J.K = K; J.xhat = xhat; J.y0 = y; J.z0 = zbits;
+  return run_jobs(J, count, threads);
+}
+
+int orc_full_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+                   const int64_t* x, uint64_t* y0, uint64_t* y1, uint64_t* z0, uint64_t* z1,
+                   int threads) {
+  job_t J;
+  memset(&J, 0, sizeof J);
+  J.kind = 2; J.S = S; J.seed = seed; J.elems = elems; J.x = x;
+  J.y0 = y0; J.y1 = y1; J.z0 = z0; J.z1 = z1;
+  return run_jobs(J, count, threads);
+}

@@ -1,0 +1,141 @@
+/*
+ * fss_oracle.h -- plain CPU oracle for the FuseFSS hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library; only
+ * tests, the smoke check and the benchmark's CPU-baseline leg may load it.
+ * It shares no code, header, table or constant generator with the GPU path.
+ *
+ * What it computes (paper sections in brackets):
+ *   - AES-128 from FIPS-197, byte oriented, S-box derived from GF(2^8)
+ *     inversion + the affine map.
+ *   - A fixed-key AES PRG (tweaked Matyas-Meyer-Oseas) and a counter-based
+ *     randomness source keyed by the dealer seed.
+ *   - The distributed comparison function of Boyle et al. (EUROCRYPT 2021),
+ *     cited by the paper for its backend [Backend Interface appendix], with
+ *     payload group Z_2 (predicates) or Z_{2^64}^p (coefficient lookup).
+ *   - Operator-specification quantisation [Definition "Operator
+ *     specification", Sec. 3.2 fixed-point encoding].
+ *   - Dealer key generation and per-party evaluation of the packed
+ *     comparison [Lemma "Masked rewrite for unsigned comparison", signed /
+ *     MSB appendix, low-bit appendix] and of the vector interval lookup
+ *     [Definition "Interval lookup with vector payload"], followed by the
+ *     local combination at the public masked input.
+ *   - Protocol "Compile a scalar gate instance" (translated lookup table),
+ *     used only to cross-check the lookup.
+ *   - A plaintext evaluator of the quantised specification.
+ */
+#ifndef FSS_ORACLE_H
+#define FSS_ORACLE_H
+#include <stdint.h>
+
+#define ORC_MAXN 32   /* comparison bit width n */
+#define ORC_MAXP 4    /* payload length p = d + 1 */
+#define ORC_MAXM 64   /* intervals m */
+#define ORC_MAXPRED 8 /* primitive predicates */
+#define ORC_MAXT 12   /* comparison atoms */
+#define ORC_MAXL 8    /* predicate output bits */
+
+typedef struct { uint64_t lo, hi; } orc_blk;
+
+typedef struct { uint8_t rk[176]; } orc_aes_sched;
+
+/* ---- AES / PRG / randomness --------------------------------------------- */
+void orc_aes128_expand(const uint8_t key[16], orc_aes_sched* ks);
+void orc_aes128_encrypt(const orc_aes_sched* ks, const uint8_t in[16], uint8_t out[16]);
+void orc_aes128_encrypt_key(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]);
+void orc_sbox(uint8_t out[256]);
+/* H(s, j) = AES_K(s ^ J_j) ^ s ^ J_j with the fixed PRG key. */
+orc_blk orc_prg(orc_blk s, int j);
+void orc_seed_sched(uint64_t seed, orc_aes_sched* ks);
+/* R(e, purpose, ctr) = AES_{K_seed}(e || purpose || ctr || 0). */
+orc_blk orc_rand(const orc_aes_sched* kseed, uint64_t e, int purpose, int ctr);
+
+/* ---- DCF ------------------------------------------------------------------ */
+/* group: p == 0 means Z_2 (one bit, XOR); p in 1..4 means Z_{2^64}^p. */
+typedef struct {
+  int32_t n, p;
+  orc_blk root;                     /* this party's root seed (bits 0..1 zero) */
+  orc_blk scw[ORC_MAXN];            /* seed corrections (bits 0..1 zero) */
+  uint8_t tl[ORC_MAXN], tr[ORC_MAXN];
+  uint64_t vcw[ORC_MAXN][ORC_MAXP]; /* value corrections (Z_2: vcw[i][0] in {0,1}) */
+  uint64_t fin[ORC_MAXP];           /* final correction */
+} orc_dcf_key;
+
+void orc_dcf_gen(int n, int p, uint64_t alpha, const uint64_t* beta,
+                 orc_blk root0, orc_blk root1, orc_dcf_key* k0, orc_dcf_key* k1);
+void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out);
+
+/* ---- operator specification ------------------------------------------------ */
+typedef struct { double lo, hi; } orc_interval;
+typedef struct { int32_t degree; double coef[4]; } orc_piece;
+enum { ORC_LT_SIGNED = 0, ORC_LT_UNSIGNED = 1, ORC_LOWBITS_LT = 2, ORC_MSB_SHIFT = 3 };
+typedef struct {
+  int32_t kind, negate, out, f_bits;
+  double thr;      /* real threshold for LT_SIGNED / LT_UNSIGNED */
+  int64_t gamma;   /* integer threshold for LOWBITS_LT */
+  int64_t c;       /* public shift for MSB_SHIFT */
+} orc_pred;
+
+typedef struct {
+  int32_t n, f, m, d, p, F_out, ell;
+  int64_t alpha[ORC_MAXM + 1];          /* signed integer boundaries, alpha[0]=-s, alpha[m]=s */
+  uint64_t aprime[ORC_MAXM + 1];        /* offset-binary boundaries alpha + s */
+  uint64_t coef[ORC_MAXM][ORC_MAXP];    /* ring coefficients, lowest degree first */
+  /* user predicates, quantised, evaluated directly by the plaintext path */
+  int32_t n_user;
+  int32_t u_kind[ORC_MAXPRED], u_out[ORC_MAXPRED], u_neg[ORC_MAXPRED], u_f[ORC_MAXPRED];
+  int64_t u_beta[ORC_MAXPRED];          /* signed beta / unsigned beta / gamma */
+  uint64_t u_c[ORC_MAXPRED];
+  /* compiled (masked) predicate form */
+  int32_t n_prim;                       /* non-constant primitive predicates */
+  int32_t prim_k[ORC_MAXPRED], prim_view[ORC_MAXPRED], prim_out[ORC_MAXPRED];
+  uint64_t prim_bprime[ORC_MAXPRED];    /* threshold in view space */
+  int32_t n_views;
+  int32_t view_k[ORC_MAXPRED];
+  uint64_t view_c[ORC_MAXPRED];
+  int32_t T;                            /* atoms: n_prim thresholds, then n_views mask atoms */
+  uint8_t negate[ORC_MAXL];             /* public constant flip per output bit */
+} orc_spec;
+
+/* Returns 0 on success, negative on an invalid or unsupported spec. */
+int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
+                     const orc_pred* pr, int32_t n_pred, int32_t n_bits,
+                     int32_t frac_bits, int32_t out_frac_bits, orc_spec* S);
+
+/* ---- per-element keys ------------------------------------------------------- */
+typedef struct {
+  orc_dcf_key atom[ORC_MAXT];
+  uint64_t wshare;                      /* bit j: this party's share of the carry of output j */
+  orc_dcf_key coeff;
+  uint64_t rho[ORC_MAXP];               /* additive share of rho = ((-r_in)^k)_k */
+  uint64_t rout;                        /* additive share of r_out */
+} orc_elem_key;
+
+void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
+                     orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in, uint64_t* r_out);
+void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xhat,
+                   uint64_t* y, uint64_t* zbits);
+/* Plaintext fixed-point evaluation of the quantised spec at signed x. */
+void orc_plain_eval(const orc_spec* S, int64_t x, uint64_t* y, uint64_t* zbits);
+
+/* Batched drivers over a list of element indices (threads: 0 = all cores). */
+int orc_keygen_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+                     orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in, uint64_t* r_out,
+                     int threads);
+int orc_eval_batch(int b, const orc_spec* S, const orc_elem_key* K, const uint64_t* xhat,
+                   int64_t count, uint64_t* y, uint64_t* zbits, int threads);
+/* keygen + both parties' evaluation without storing keys (CPU baseline). */
+int orc_full_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+                   const int64_t* x, uint64_t* y0, uint64_t* y1, uint64_t* z0, uint64_t* z1,
+                   int threads);
+int orc_hw_threads(void);
+int orc_sizeof_elem_key(void);
+int orc_sizeof_dcf_key(void);
+int orc_sizeof_spec(void);
+
+/* ---- Protocol "Compile a scalar gate instance", lookup part ---------------- */
+/* alpha: boundaries 0=a_0<...<a_m=N of the partition being translated; r: mask.
+ * Writes B[0..M] and ord[0..M-1]; returns M. */
+int orc_protocol3(int n, const uint64_t* alpha, int m, uint64_t r, uint64_t* B, int32_t* ord);
+
+#endif

@@ -1,0 +1,71 @@
+"""Pins for the oracle's DCF (CPU only).
+
+A DCF key pair for (alpha, beta) must satisfy Eval_0(x) + Eval_1(x) =
+beta * 1[x < alpha] for every x (the comparison function of Boyle et al.,
+EUROCRYPT 2021, used by the paper's backend).  Checked by brute force over
+every alpha and x on small domains, for the Z_2 group and Z_{2^64}^p.
+"""
+import random
+
+import pytest
+
+import oracle as O
+
+M64 = 2**64 - 1
+
+
+def _roots(rnd):
+    return ((rnd.getrandbits(64), rnd.getrandbits(64)), (rnd.getrandbits(64), rnd.getrandbits(64)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6])
+def test_dcf_z2_bruteforce(n):
+    rnd = random.Random(100 + n)
+    for alpha in range(2**n):
+        for beta in (0, 1):
+            k0, k1 = O.dcf_gen(n, 0, alpha, beta, *_roots(rnd))
+            for x in range(2**n):
+                got = O.dcf_eval(0, k0, x) ^ O.dcf_eval(1, k1, x)
+                assert got == (beta if x < alpha else 0), (n, alpha, beta, x)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1, 4, 6])
+def test_dcf_vector_bruteforce(n, p):
+    rnd = random.Random(1000 * n + p)
+    for alpha in range(2**n):
+        beta = [rnd.getrandbits(64) for _ in range(p)]
+        k0, k1 = O.dcf_gen(n, p, alpha, beta, *_roots(rnd))
+        for x in range(2**n):
+            a, b = O.dcf_eval(0, k0, x), O.dcf_eval(1, k1, x)
+            got = [(u + v) & M64 for u, v in zip(a, b)]
+            assert got == (beta if x < alpha else [0] * p), (n, p, alpha, x)
+
+
+def test_dcf_wide_domain_sampled():
+    """n = 24 and 32: sampled points around alpha and across the domain."""
+    rnd = random.Random(5)
+    for n in (24, 32):
+        for _ in range(6):
+            alpha = rnd.getrandbits(n)
+            beta = [rnd.getrandbits(64) for _ in range(3)]
+            k0, k1 = O.dcf_gen(n, 3, alpha, beta, *_roots(rnd))
+            z0, z1 = O.dcf_gen(n, 0, alpha, 1, *_roots(rnd))
+            pts = {0, 2**n - 1, alpha, (alpha - 1) % 2**n, (alpha + 1) % 2**n}
+            pts |= {rnd.getrandbits(n) for _ in range(20)}
+            for x in pts:
+                got = [(u + v) & M64 for u, v in zip(O.dcf_eval(0, k0, x), O.dcf_eval(1, k1, x))]
+                assert got == (beta if x < alpha else [0, 0, 0])
+                assert O.dcf_eval(0, z0, x) ^ O.dcf_eval(1, z1, x) == int(x < alpha)
+
+
+def test_dcf_keys_share_corrections_and_differ_in_roots():
+    rnd = random.Random(9)
+    k0, k1 = O.dcf_gen(8, 3, 77, [1, 2, 3], *_roots(rnd))
+    assert (k0.root.lo, k0.root.hi) != (k1.root.lo, k1.root.hi)
+    assert k0.root.lo & 3 == 0 and k1.root.lo & 3 == 0
+    for i in range(8):
+        assert (k0.scw[i].lo, k0.scw[i].hi) == (k1.scw[i].lo, k1.scw[i].hi)
+        assert k0.scw[i].lo & 3 == 0
+        assert list(k0.vcw[i][:3]) == list(k1.vcw[i][:3])
+    assert list(k0.fin[:3]) == list(k1.fin[:3])
