@@ -1,0 +1,223 @@
+/*
+ * fusefss.h -- C ABI of the MI355X (gfx950) FuseFSS hot-path library.
+ *
+ * The library implements the two FSS calls the paper's compiler emits for a
+ * scalar fixed-point operator (Sec. 4.4 "Compiling One Operator Gate with Two
+ * FSS Calls", Theorem "Two-call evaluation"), evaluated on the public masked
+ * input xhat = x + r_in (Sec. 3.5 masked-wire invariant):
+ *   call 1, packed comparison: XOR shares of all predicate bits
+ *           (Definition "Multi-view packed predicate primitive");
+ *   call 2, vector interval lookup: additive shares of the active piece's
+ *           coefficients (Definition "Interval lookup with vector payload"),
+ *           combined locally into shares of P_{i*}(x) + r_out mod 2^64,
+ * together with the dealer's key generation (Sec. 5.2 "Preprocessing").
+ *
+ * Conventions for every function:
+ *   - Return value: FSS_OK (0) or a negative FSS_E_* code; fss_last_error()
+ *     returns a thread-local message for the last failure.  No C++ exception
+ *     crosses the ABI.
+ *   - Pointers documented as "device" point to HIP device memory allocated by
+ *     the caller; "host" pointers are ordinary host memory.  The caller owns
+ *     every buffer.  The library owns only fss_spec / fss_plan / fss_graph
+ *     handles, released with the matching *_free call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls that take a stream only enqueue work; they return before the GPU
+ *     finishes.  Kernel-side validation failures (for example a key buffer of
+ *     the wrong party) are recorded in a device status word and reported by
+ *     fss_status().
+ *   - Ring: all arithmetic outputs live in Z_{2^64}; comparison views use
+ *     n_bits in [2, 32]; fixed-point inputs are n_bits-wide signed values with
+ *     frac_bits fractional bits, sign-extended to 64 bits.
+ */
+#ifndef FUSEFSS_H
+#define FUSEFSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSS_OK 0
+#define FSS_E_INVALID_SPEC (-1) /* partition not increasing, degree > 3, |P| >= 2^62, NaN */
+#define FSS_E_UNSUPPORTED (-2)  /* n_bits outside [2,32], frac_bits >= n_bits, too many atoms */
+#define FSS_E_NEEDS_PHI (-3)    /* AND/OR predicate: needs the interactive post-processing */
+#define FSS_E_SHAPE (-4)        /* key header / buffer does not match the call */
+#define FSS_E_PARTY (-5)        /* party not 0 or 1 */
+#define FSS_E_HIP (-6)          /* a HIP runtime call failed (message has the hipError_t) */
+#define FSS_E_OOM (-7)          /* host allocation failed */
+#define FSS_E_ARG (-8)          /* NULL pointer, negative size, bad tuning value */
+
+#define FSS_MAX_INTERVALS 64
+#define FSS_MAX_PREDS 16
+#define FSS_MAX_ATOMS 16
+#define FSS_MAX_DEGREE 3
+
+/* ---- operator specification (Definition "Operator specification") ------ */
+
+/* Half-open real interval [lo, hi); lo = -INFINITY / hi = +INFINITY for tails. */
+typedef struct { double lo, hi; } fss_interval;
+
+/* Polynomial piece a_0 + a_1 x + ... + a_d x^d over real x (lowest first), d <= 3. */
+typedef struct { int32_t degree; double coef[4]; } fss_piece;
+
+enum {
+  FSS_PRED_LT_SIGNED = 0,   /* x <_signed thr (real threshold)                    */
+  FSS_PRED_LT_UNSIGNED = 1, /* rep(x) < thr over canonical representatives        */
+  FSS_PRED_LOWBITS_LT = 2,  /* (x mod 2^f_bits) < gamma  (primitive D_{gamma,f})   */
+  FSS_PRED_MSB_SHIFT = 3    /* MSB(x + c) for a public shift c                     */
+};
+enum { FSS_COMBINE_XOR = 0, FSS_COMBINE_AND = 1, FSS_COMBINE_OR = 2 };
+
+/* One primitive predicate.  Predicates with the same `out` are combined into
+ * output bit `out` with XOR (local); AND / OR need the post-processing
+ * circuit and are rejected with FSS_E_NEEDS_PHI (appendix "Typed
+ * specification language"). */
+typedef struct {
+  int32_t kind;     /* FSS_PRED_* */
+  int32_t negate;   /* nonzero: XOR the predicate with 1 */
+  int32_t out;      /* output bit index, 0 <= out < 64 */
+  int32_t combine;  /* FSS_COMBINE_* */
+  int32_t f_bits;   /* LOWBITS_LT: low-bit width, 1 <= f_bits <= n_bits */
+  int32_t reserved;
+  double thr;       /* LT_SIGNED / LT_UNSIGNED: real threshold */
+  int64_t gamma;    /* LOWBITS_LT: integer threshold in [0, 2^f_bits] */
+  int64_t c;        /* MSB_SHIFT: public shift (taken mod 2^n_bits) */
+} fss_pred;
+
+typedef struct fss_spec fss_spec;
+
+/* Validate and store a real-valued operator specification.  Quantisation to
+ * (n_bits, frac_bits) happens on first use and is cached per spec (compiled
+ * program reuse, ablation "Program Reuse Across Layers").
+ *   iv[m], pieces[m]: host arrays; iv must be contiguous from -inf to +inf.
+ *   preds[n_preds]: host array (may be NULL when n_preds == 0).
+ *   out_frac_bits: fractional bits of the arithmetic output; < 0 selects
+ *     2*frac_bits for degree <= 1 and 4*frac_bits otherwise.
+ *   *out receives a handle owned by the caller (free with fss_spec_free). */
+int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces,
+                     const fss_pred* preds, int32_t n_preds, int32_t out_frac_bits,
+                     fss_spec** out);
+void fss_spec_free(fss_spec* spec);
+
+/* Public, mask-independent shape of a quantised spec (leakage L_shape of
+ * the appendix "A standard real/ideal security statement"). */
+typedef struct {
+  int32_t n_bits, frac_bits, m, degree, p, out_frac_bits;
+  int32_t T;        /* comparison atoms in the packed comparison */
+  int32_t ell;      /* predicate output bits */
+  int32_t atom_k[FSS_MAX_ATOMS];    /* bit width of each atom's view */
+  int64_t atom_c[FSS_MAX_ATOMS];    /* public shift of each atom's view */
+  int32_t atom_is_mask[FSS_MAX_ATOMS]; /* 1: the 1[view < r_k] atom of its view */
+} fss_spec_info;
+
+/* Quantise at (n_bits, frac_bits) and report the shape and integer tables.
+ *   aprime: host, m+1 u64 (offset-binary boundaries alpha_i + 2^(n-1)), may be NULL.
+ *   coef:   host, m*p u64 ring coefficients (row-major, lowest degree first), may be NULL. */
+int fss_spec_query(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, fss_spec_info* info,
+                   uint64_t* aprime, uint64_t* coef);
+
+/* ---- dealer key generation (Sec. 5.2, Protocol "Compile a scalar gate") -- */
+
+/* Bytes of one party's key buffer for n_elems elements.  Depends only on
+ * (spec, n_bits, frac_bits, n_elems), never on masks (Proposition
+ * "Mask-independent shape via padding"). */
+int fss_key_bytes(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems,
+                  size_t* per_party);
+
+/* Generate both parties' keys for n_elems fresh gate instances.
+ *   key0, key1: device, fss_key_bytes each (key1 may be NULL to skip party 1).
+ *   r_in, r_out: device, n_elems u64 each (the dealer's masks; may be NULL).
+ * Each element e draws all of its randomness from AES keyed by `seed`
+ * (counter mode over e), so the output is a pure function of the arguments.
+ * Keys are one-time material: evaluate each buffer on one input only. */
+int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t seed,
+               int64_t n_elems, void* key0, void* key1, uint64_t* r_in, uint64_t* r_out,
+               void* stream);
+
+/* Protocol "Shares -> masked opening" collapsed to one process that holds
+ * the plaintext: xhat[e] = x[e] + r_in[e] mod 2^64 (all device, n each). */
+int fss_mask_input(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat,
+                   void* stream);
+
+/* ---- online evaluation (Sec. 5.3 "Online Evaluation", steps 2-3) ------- */
+
+/* Plain evaluator: call 1 then call 2 as two kernel launches.
+ *   keys: device key buffer of `party` (self-describing header).
+ *   xhat: device, n_elems u64.  y: device, n_elems u64 output shares.
+ *   zbits: device, ell * ceil(n_elems/64) u64 output shares; predicate j of
+ *          element e is bit (e & 63) of word j*ceil(n_elems/64) + (e >> 6).
+ *          May be NULL when ell == 0. */
+int fss_eval(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems,
+             uint64_t* y, uint64_t* zbits, void* stream);
+/* The two calls separately (same buffers as fss_eval). */
+int fss_eval_pred(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems,
+                  uint64_t* zbits, void* stream);
+int fss_eval_coeff(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems,
+                   uint64_t* y, void* stream);
+
+/* ---- fused, batched evaluation over a work-list --------------------------- */
+
+typedef struct {
+  int32_t party;
+  int32_t reserved;
+  const void* keys;       /* device key buffer of `party` */
+  const uint64_t* xhat;   /* device, n_elems */
+  uint64_t* y;            /* device, n_elems */
+  uint64_t* zbits;        /* device, ell * ceil(n_elems/64), may be NULL if ell == 0 */
+  int64_t n_elems;
+} fss_work_item;
+
+/* Launch configuration of the persistent kernel (0 = library default). */
+typedef struct {
+  int32_t block_threads;  /* 64 .. 1024, multiple of 64 */
+  int32_t blocks_per_cu;  /* resident blocks per compute unit */
+  int32_t aes_variant;    /* AES table layout, 0 .. fss_aes_variants()-1 */
+  int32_t order;          /* 0: costliest tiles first, 1: work-list order */
+} fss_tune;
+
+typedef struct fss_plan fss_plan;
+
+/* Build a work-list plan: reads each item's key header (synchronously, once),
+ * uploads the tile list, and records the launch configuration (`tune` may be
+ * NULL for defaults).  Items may mix parties, specs and sizes. */
+int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune* tune,
+                    fss_plan** out);
+/* One persistent launch evaluating both calls of every element of every item
+ * in a single pass.  Enqueue-only and safe to capture into a HIP graph. */
+int fss_plan_launch(fss_plan* plan, void* stream);
+int fss_plan_free(fss_plan* plan);
+/* Algorithmic AES-128 blocks one launch of `plan` evaluates (sum over items
+ * of n_elems * (sum_t k_t + m * (n * (1 + ceil(p/2)) + ceil(p/2))));
+ * used for throughput and roofline reporting. */
+double fss_plan_aes_blocks(const fss_plan* plan);
+/* Resolved launch configuration of a plan (host out-params). */
+int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid);
+
+/* Capture the launches of n_plans plans, in order, into one HIP graph. */
+typedef struct fss_graph fss_graph;
+int fss_graph_capture(fss_plan* const* plans, int32_t n_plans, fss_graph** out);
+int fss_graph_launch(fss_graph* graph, void* stream);
+int fss_graph_free(fss_graph* graph);
+
+/* Time candidate launch configurations on this work-list (the items' outputs
+ * are overwritten) and return the fastest in *best; results are cached in
+ * `cache_path` (may be NULL) keyed by the work-list's shape and the device. */
+int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_path,
+                 fss_tune* best);
+int fss_aes_variants(void);
+
+/* ---- status ------------------------------------------------------------ */
+
+/* Synchronise `stream`, then read and clear the device status word.
+ * *device_code receives 0 or the FSS_E_* code a kernel recorded. */
+int fss_status(void* stream, int32_t* device_code);
+const char* fss_last_error(void);
+/* Library version string. */
+const char* fss_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

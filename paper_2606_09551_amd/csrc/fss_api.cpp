@@ -1,0 +1,798 @@
+// fss_api.cpp -- the C ABI (include/fusefss.h): spec quantisation, key
+// headers, launches, work-list plans, HIP graphs, autotuning and status.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/fusefss.h"
+#include "fss_kernels.hpp"
+
+using namespace fss;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FSS_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(expr, what)                  \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v && *v ? atoi(v) : dflt;
+}
+
+// Default AES table layouts of the plain evaluator and of keygen (override
+// with FSS_AES_VARIANT / FSS_KEYGEN_VARIANT).
+int eval_variant() { return env_int("FSS_AES_VARIANT", 1); }
+int keygen_variant() { return env_int("FSS_KEYGEN_VARIANT", 0); }
+
+// Per-device library state: the status word kernels report into.
+std::mutex g_mu;
+std::map<int, int*> g_status_buf;
+
+int device_status_ptr(int** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_status_buf.find(dev);
+  if (it != g_status_buf.end()) {
+    *out = it->second;
+    return FSS_OK;
+  }
+  int* p = nullptr;
+  HIP_TRY(hipMalloc(&p, sizeof(int)), "hipMalloc(status)");
+  HIP_TRY(hipMemset(p, 0, sizeof(int)), "hipMemset(status)");
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  g_status_buf[dev] = p;
+  *out = p;
+  return FSS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Quantised spec (library implementation of Definition "Operator
+// specification" at a given (n, f)).
+// ---------------------------------------------------------------------------
+struct QSpec {
+  int n = 0, f = 0, m = 0, d = 0, p = 0, F_out = 0, ell = 0, T = 0, n_prim = 0, n_views = 0;
+  int64_t alpha[kMaxM + 1] = {};
+  uint64_t aprime[kMaxM + 1] = {};
+  uint64_t coef[kMaxM][kMaxP] = {};
+  uint32_t atom_k[kMaxAtoms] = {};
+  uint64_t atom_c[kMaxAtoms] = {};
+  uint32_t atom_out[kMaxAtoms] = {};
+  uint32_t atom_rview[kMaxAtoms] = {};
+  uint64_t bprime[kMaxAtoms] = {};
+  uint64_t negate = 0;
+  Layout layout{};
+  KeyHeader hdr{};
+  std::map<int, uint8_t*> dev_hdr;  // device -> header template
+};
+
+int64_t ceil_clamped(double v, int64_t lo, int64_t hi) {
+  const double c = std::ceil(v);
+  if (!(c > (double)lo)) return lo;
+  if (c >= (double)hi) return hi;
+  return (int64_t)c;
+}
+
+uint64_t binom_small(int l, int j) {
+  static const uint64_t C[4][4] = {{1, 0, 0, 0}, {1, 1, 0, 0}, {1, 2, 1, 0}, {1, 3, 3, 1}};
+  return C[l][j];
+}
+
+}  // namespace
+
+struct fss_spec {
+  std::vector<fss_interval> iv;
+  std::vector<fss_piece> pc;
+  std::vector<fss_pred> pr;
+  int32_t out_frac_bits = -1;
+  uint64_t hash = 0;
+  std::mutex mu;
+  std::map<std::pair<int, int>, std::shared_ptr<QSpec>> cache;
+};
+
+namespace {
+
+uint64_t fnv1a(const void* data, size_t len, uint64_t h = 0xcbf29ce484222325ull) {
+  const uint8_t* p = static_cast<const uint8_t*>(data);
+  for (size_t i = 0; i < len; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
+  if (n < 2 || n > 32) return fail(FSS_E_UNSUPPORTED, "n_bits=%d outside [2,32]", n);
+  if (f < 0 || f >= n) return fail(FSS_E_UNSUPPORTED, "frac_bits=%d must be in [0,n_bits)", f);
+  auto q = std::make_shared<QSpec>();
+  const int m = (int)S->iv.size();
+  const int64_t N = (int64_t)1 << n, s = N / 2;
+  q->n = n;
+  q->f = f;
+  q->m = m;
+  // Partition: real boundary a -> ceil(a 2^f), the first grid point >= a.
+  q->alpha[0] = -s;
+  q->alpha[m] = s;
+  for (int i = 1; i < m; ++i) q->alpha[i] = ceil_clamped(std::ldexp(S->iv[i].lo, f), -s, s);
+  for (int i = 0; i < m; ++i)
+    if (q->alpha[i] >= q->alpha[i + 1])
+      return fail(FSS_E_INVALID_SPEC, "boundaries %d and %d coincide at n=%d f=%d", i, i + 1, n, f);
+  for (int i = 0; i <= m; ++i) q->aprime[i] = (uint64_t)(q->alpha[i] + s);
+  // Pieces.
+  int d = 0;
+  for (const auto& pc : S->pc) d = std::max(d, (int)pc.degree);
+  q->d = d;
+  q->p = d + 1;
+  q->F_out = S->out_frac_bits >= 0 ? S->out_frac_bits : (d <= 1 ? 2 * f : 4 * f);
+  for (int i = 0; i < m; ++i) {
+    const double X = std::max(std::fabs((double)q->alpha[i]), std::fabs((double)(q->alpha[i + 1] - 1)));
+    double bound = 0, Xl = 1;
+    for (int l = 0; l <= d; ++l) {
+      const double a = l <= S->pc[i].degree ? S->pc[i].coef[l] : 0.0;
+      const double r = std::nearbyint(std::ldexp(a, q->F_out - l * f));
+      if (!(std::fabs(r) < 9223372036854775808.0))
+        return fail(FSS_E_INVALID_SPEC, "coefficient %d of piece %d overflows 64 bits", l, i);
+      q->coef[i][l] = (uint64_t)(int64_t)r;
+      bound += std::fabs(r) * Xl;
+      Xl *= X;
+    }
+    if (!(bound < 4611686018427387904.0))
+      return fail(FSS_E_INVALID_SPEC, "piece %d may reach |P| >= 2^62 on its interval", i);
+  }
+  // Predicates -> (view, threshold) atoms, sentinels folded into constants.
+  struct View { int k; uint64_t c; };
+  std::vector<View> views;
+  std::vector<int> prim_view;
+  q->ell = 0;
+  for (size_t j = 0; j < S->pr.size(); ++j) {
+    const fss_pred& P = S->pr[j];
+    q->ell = std::max(q->ell, P.out + 1);
+    int k = n, flip = P.negate ? 1 : 0;
+    uint64_t c = 0, bp = 0;
+    switch (P.kind) {
+      case FSS_PRED_LT_SIGNED: {
+        if (std::isnan(P.thr)) return fail(FSS_E_INVALID_SPEC, "predicate %zu: NaN threshold", j);
+        bp = (uint64_t)(ceil_clamped(std::ldexp(P.thr, f), -s, s) + s);
+        c = (uint64_t)s;
+        break;
+      }
+      case FSS_PRED_LT_UNSIGNED: {
+        if (std::isnan(P.thr)) return fail(FSS_E_INVALID_SPEC, "predicate %zu: NaN threshold", j);
+        bp = (uint64_t)ceil_clamped(std::ldexp(P.thr, f), 0, N);
+        break;
+      }
+      case FSS_PRED_LOWBITS_LT: {
+        if (P.f_bits < 1 || P.f_bits > n) return fail(FSS_E_UNSUPPORTED, "predicate %zu: f_bits=%d", j, P.f_bits);
+        if (P.gamma < 0 || P.gamma > ((int64_t)1 << P.f_bits))
+          return fail(FSS_E_INVALID_SPEC, "predicate %zu: gamma out of range", j);
+        k = P.f_bits;
+        bp = (uint64_t)P.gamma;
+        break;
+      }
+      case FSS_PRED_MSB_SHIFT: {
+        c = (uint64_t)P.c & (uint64_t)(N - 1);
+        bp = (uint64_t)s;
+        flip ^= 1;  // MSB(x + c) = NOT [view_{n,c}(x) < 2^(n-1)]
+        break;
+      }
+      default:
+        return fail(FSS_E_UNSUPPORTED, "predicate %zu: unknown kind %d", j, P.kind);
+    }
+    q->negate ^= (uint64_t)flip << P.out;
+    if (bp == 0) continue;
+    if (bp == ((uint64_t)1 << k)) {
+      q->negate ^= 1ull << P.out;
+      continue;
+    }
+    int v = -1;
+    for (size_t u = 0; u < views.size(); ++u)
+      if (views[u].k == k && views[u].c == c) v = (int)u;
+    if (v < 0) {
+      v = (int)views.size();
+      views.push_back({k, c});
+    }
+    const int t = q->n_prim++;
+    if (t >= kMaxAtoms) return fail(FSS_E_UNSUPPORTED, "too many predicate atoms");
+    q->atom_k[t] = (uint32_t)k;
+    q->atom_c[t] = c;
+    q->atom_out[t] = (uint32_t)P.out;
+    q->bprime[t] = bp;
+    prim_view.push_back(v);
+  }
+  q->n_views = (int)views.size();
+  q->T = q->n_prim + q->n_views;
+  if (q->T > kMaxAtoms) return fail(FSS_E_UNSUPPORTED, "T=%d atoms exceeds %d", q->T, kMaxAtoms);
+  for (int v = 0; v < q->n_views; ++v) {
+    q->atom_k[q->n_prim + v] = (uint32_t)views[v].k;
+    q->atom_c[q->n_prim + v] = views[v].c;
+  }
+  for (int t = 0; t < q->n_prim; ++t) q->atom_rview[t] = (uint32_t)(q->n_prim + prim_view[t]);
+  q->layout = make_layout(q->T, q->atom_k, n, q->p);
+
+  // Header template (party, n_elems and n_tiles are stamped per buffer).
+  KeyHeader& h = q->hdr;
+  memset(&h, 0, sizeof h);
+  h.magic = kMagic;
+  h.version = kVersion;
+  h.layout = 0;
+  h.n = (uint32_t)n; h.f = (uint32_t)f; h.m = (uint32_t)m; h.d = (uint32_t)d; h.p = (uint32_t)q->p;
+  h.T = (uint32_t)q->T; h.ell = (uint32_t)q->ell; h.F_out = (uint32_t)q->F_out;
+  h.n_prim = (uint32_t)q->n_prim; h.n_views = (uint32_t)q->n_views;
+  uint32_t kmax = 0;
+  for (int t = 0; t < q->T; ++t) kmax = std::max(kmax, q->atom_k[t]);
+  h.kmax = kmax;
+  h.tile_bytes = q->layout.tile_bytes;
+  h.spec_hash = S->hash;
+  h.negate = q->negate;
+  for (int t = 0; t < q->T; ++t) {
+    h.atom_k[t] = q->atom_k[t];
+    h.atom_out[t] = q->atom_out[t];
+    h.atom_rview[t] = t < q->n_prim ? q->atom_rview[t] : 0xffffffffu;
+    h.atom_c[t] = q->atom_c[t];
+    h.atom_off[t] = q->layout.atom_off[t];
+  }
+  h.off_w = q->layout.off_w;
+  h.off_croot = q->layout.off_croot;
+  h.off_ccw = q->layout.off_ccw;
+  h.off_cvcw = q->layout.off_cvcw;
+  h.off_cfin = q->layout.off_cfin;
+  h.off_crho = q->layout.off_crho;
+  h.off_crout = q->layout.off_crout;
+  for (int i = 0; i <= m; ++i) h.aprime[i] = q->aprime[i];
+  // A_i maps a share of 1[x in I_i] rho to the xhat-coefficients of piece i:
+  // A_i[j][k] = a_{i,j+k} C(j+k, j).  tab_0 = A_{m-1}, tab_i = A_{i-1} - A_i.
+  auto A = [&](int i, int j, int k) -> uint64_t {
+    return (j + k <= d) ? q->coef[i][j + k] * binom_small(j + k, j) : 0ull;
+  };
+  for (int j = 0; j < q->p; ++j)
+    for (int k = 0; k < q->p; ++k) {
+      h.tab[0][j][k] = A(m - 1, j, k);
+      for (int i = 1; i < m; ++i) h.tab[i][j][k] = A(i - 1, j, k) - A(i, j, k);
+    }
+  *out = std::move(q);
+  return FSS_OK;
+}
+
+int get_qspec(const fss_spec* Sc, int n, int f, std::shared_ptr<QSpec>* out) {
+  fss_spec* S = const_cast<fss_spec*>(Sc);
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto key = std::make_pair(n, f);
+  auto it = S->cache.find(key);
+  if (it != S->cache.end()) {
+    *out = it->second;
+    return FSS_OK;
+  }
+  std::shared_ptr<QSpec> q;
+  int rc = quantize(S, n, f, &q);
+  if (rc != FSS_OK) return rc;
+  S->cache[key] = q;
+  *out = q;
+  return FSS_OK;
+}
+
+int device_header(const fss_spec* Sc, QSpec* q, uint8_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  fss_spec* S = const_cast<fss_spec*>(Sc);
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = q->dev_hdr.find(dev);
+  if (it != q->dev_hdr.end()) {
+    *out = it->second;
+    return FSS_OK;
+  }
+  uint8_t* p = nullptr;
+  HIP_TRY(hipMalloc(&p, sizeof(KeyHeader)), "hipMalloc(header)");
+  HIP_TRY(hipMemcpy(p, &q->hdr, sizeof(KeyHeader), hipMemcpyHostToDevice), "hipMemcpy(header)");
+  q->dev_hdr[dev] = p;
+  *out = p;
+  return FSS_OK;
+}
+
+void seed_round_keys(uint64_t seed, uint32_t rk[44]) {
+  uint8_t key[16] = {};
+  for (int i = 0; i < 8; ++i) key[i] = (uint8_t)(seed >> (8 * i));
+  expand_key(kAes.sbox, key, rk);
+}
+
+int check_party(int32_t party) {
+  return (party == 0 || party == 1) ? FSS_OK : fail(FSS_E_PARTY, "party must be 0 or 1 (got %d)", party);
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* fss_last_error(void) { return g_err.c_str(); }
+const char* fss_version(void) { return "fusefss-mi355x 0.1 (gfx950)"; }
+int fss_aes_variants(void) { return kNumAesVariants; }
+
+int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces, const fss_pred* preds,
+                     int32_t n_preds, int32_t out_frac_bits, fss_spec** out) {
+  if (!out) return fail(FSS_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!iv || !pieces) return fail(FSS_E_ARG, "intervals/pieces NULL");
+  if (m < 1 || m > FSS_MAX_INTERVALS) return fail(FSS_E_INVALID_SPEC, "m=%d outside [1,%d]", m, FSS_MAX_INTERVALS);
+  if (n_preds < 0 || n_preds > FSS_MAX_PREDS) return fail(FSS_E_UNSUPPORTED, "n_preds=%d", n_preds);
+  if (n_preds > 0 && !preds) return fail(FSS_E_ARG, "preds NULL");
+  if (!(std::isinf(iv[0].lo) && iv[0].lo < 0) || !(std::isinf(iv[m - 1].hi) && iv[m - 1].hi > 0))
+    return fail(FSS_E_INVALID_SPEC, "partition must start at -inf and end at +inf");
+  for (int i = 0; i < m; ++i) {
+    if (!(iv[i].lo < iv[i].hi)) return fail(FSS_E_INVALID_SPEC, "interval %d is empty", i);
+    if (i + 1 < m && iv[i].hi != iv[i + 1].lo) return fail(FSS_E_INVALID_SPEC, "gap after interval %d", i);
+    if (pieces[i].degree < 0 || pieces[i].degree > FSS_MAX_DEGREE)
+      return fail(FSS_E_INVALID_SPEC, "piece %d degree %d outside [0,3]", i, pieces[i].degree);
+    for (int l = 0; l <= pieces[i].degree; ++l)
+      if (!std::isfinite(pieces[i].coef[l])) return fail(FSS_E_INVALID_SPEC, "piece %d coef %d not finite", i, l);
+  }
+  for (int j = 0; j < n_preds; ++j) {
+    if (preds[j].combine == FSS_COMBINE_AND || preds[j].combine == FSS_COMBINE_OR)
+      return fail(FSS_E_NEEDS_PHI, "predicate %d combines with AND/OR: needs post-processing", j);
+    if (preds[j].combine != FSS_COMBINE_XOR) return fail(FSS_E_UNSUPPORTED, "predicate %d combine", j);
+    if (preds[j].out < 0 || preds[j].out >= 64) return fail(FSS_E_UNSUPPORTED, "predicate %d out", j);
+    if (preds[j].kind < FSS_PRED_LT_SIGNED || preds[j].kind > FSS_PRED_MSB_SHIFT)
+      return fail(FSS_E_UNSUPPORTED, "predicate %d kind %d", j, preds[j].kind);
+  }
+  fss_spec* S = new (std::nothrow) fss_spec();
+  if (!S) return fail(FSS_E_OOM, "out of host memory");
+  S->iv.assign(iv, iv + m);
+  S->pc.assign(pieces, pieces + m);
+  if (n_preds) S->pr.assign(preds, preds + n_preds);
+  S->out_frac_bits = out_frac_bits;
+  uint64_t h = fnv1a(iv, sizeof(fss_interval) * m);
+  h = fnv1a(pieces, sizeof(fss_piece) * m, h);
+  if (n_preds) h = fnv1a(preds, sizeof(fss_pred) * n_preds, h);
+  h = fnv1a(&out_frac_bits, sizeof out_frac_bits, h);
+  S->hash = h;
+  *out = S;
+  return FSS_OK;
+}
+
+void fss_spec_free(fss_spec* spec) {
+  if (!spec) return;
+  for (auto& kv : spec->cache)
+    for (auto& dh : kv.second->dev_hdr) {
+      int cur = 0;
+      if (hipGetDevice(&cur) == hipSuccess && hipSetDevice(dh.first) == hipSuccess) {
+        (void)hipFree(dh.second);
+        (void)hipSetDevice(cur);
+      }
+    }
+  delete spec;
+}
+
+int fss_spec_query(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, fss_spec_info* info,
+                   uint64_t* aprime, uint64_t* coef) {
+  if (!spec) return fail(FSS_E_ARG, "spec NULL");
+  std::shared_ptr<QSpec> q;
+  int rc = get_qspec(spec, n_bits, frac_bits, &q);
+  if (rc) return rc;
+  if (info) {
+    memset(info, 0, sizeof *info);
+    info->n_bits = q->n; info->frac_bits = q->f; info->m = q->m; info->degree = q->d; info->p = q->p;
+    info->out_frac_bits = q->F_out; info->T = q->T; info->ell = q->ell;
+    for (int t = 0; t < q->T; ++t) {
+      info->atom_k[t] = (int32_t)q->atom_k[t];
+      info->atom_c[t] = (int64_t)q->atom_c[t];
+      info->atom_is_mask[t] = t >= q->n_prim;
+    }
+  }
+  if (aprime)
+    for (int i = 0; i <= q->m; ++i) aprime[i] = q->aprime[i];
+  if (coef)
+    for (int i = 0; i < q->m; ++i)
+      for (int l = 0; l < q->p; ++l) coef[i * q->p + l] = q->coef[i][l];
+  return FSS_OK;
+}
+
+int fss_key_bytes(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, size_t* per_party) {
+  if (!spec || !per_party) return fail(FSS_E_ARG, "NULL argument");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  std::shared_ptr<QSpec> q;
+  int rc = get_qspec(spec, n_bits, frac_bits, &q);
+  if (rc) return rc;
+  const uint64_t tiles = ((uint64_t)n_elems + kTile - 1) / kTile;
+  *per_party = (size_t)(kHeaderBytes + tiles * q->layout.tile_bytes);
+  return FSS_OK;
+}
+
+int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t seed, int64_t n_elems,
+               void* key0, void* key1, uint64_t* r_in, uint64_t* r_out, void* stream) {
+  if (!spec || !key0) return fail(FSS_E_ARG, "spec/key0 NULL");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  std::shared_ptr<QSpec> q;
+  int rc = get_qspec(spec, n_bits, frac_bits, &q);
+  if (rc) return rc;
+  uint8_t* dh = nullptr;
+  rc = device_header(spec, q.get(), &dh);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t tiles = ((uint64_t)n_elems + kTile - 1) / kTile;
+  HIP_TRY(launch_header_init((uint8_t*)key0, dh, n_elems, tiles, 0, st), "header_init");
+  if (key1) HIP_TRY(launch_header_init((uint8_t*)key1, dh, n_elems, tiles, 1, st), "header_init");
+  if (tiles == 0) return FSS_OK;
+  KgArgs ga{};
+  seed_round_keys(seed, ga.rk.w);
+  for (int t = 0; t < kMaxAtoms; ++t) ga.bprime[t] = q->bprime[t];
+  ga.n_elems = n_elems;
+  ga.n_tiles = tiles;
+  HIP_TRY(launch_keygen(keygen_variant(), reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
+                        (uint8_t*)key1, r_in, r_out, st),
+          "keygen launch");
+  return FSS_OK;
+}
+
+int fss_mask_input(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat, void* stream) {
+  if (n < 0) return fail(FSS_E_ARG, "n < 0");
+  if (n > 0 && (!x || !r_in || !xhat)) return fail(FSS_E_ARG, "NULL buffer");
+  HIP_TRY(launch_mask(x, r_in, n, xhat, (hipStream_t)stream), "mask launch");
+  return FSS_OK;
+}
+
+int fss_eval_pred(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems, uint64_t* zbits,
+                  void* stream) {
+  int rc = check_party(party);
+  if (rc) return rc;
+  if (!keys || n_elems < 0 || (n_elems > 0 && (!xhat || !zbits))) return fail(FSS_E_ARG, "bad arguments");
+  int* st = nullptr;
+  if ((rc = device_status_ptr(&st))) return rc;
+  HIP_TRY(launch_eval_pred(eval_variant(), party, (const uint8_t*)keys, xhat, n_elems, zbits, st,
+                           (hipStream_t)stream),
+          "pred launch");
+  return FSS_OK;
+}
+
+int fss_eval_coeff(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems, uint64_t* y,
+                   void* stream) {
+  int rc = check_party(party);
+  if (rc) return rc;
+  if (!keys || n_elems < 0 || (n_elems > 0 && (!xhat || !y))) return fail(FSS_E_ARG, "bad arguments");
+  int* st = nullptr;
+  if ((rc = device_status_ptr(&st))) return rc;
+  HIP_TRY(launch_eval_coeff(eval_variant(), party, (const uint8_t*)keys, xhat, n_elems, y, st,
+                            (hipStream_t)stream),
+          "coeff launch");
+  return FSS_OK;
+}
+
+int fss_eval(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems, uint64_t* y,
+             uint64_t* zbits, void* stream) {
+  int rc = check_party(party);
+  if (rc) return rc;
+  if (zbits) {
+    rc = fss_eval_pred(party, keys, xhat, n_elems, zbits, stream);
+    if (rc) return rc;
+  }
+  return fss_eval_coeff(party, keys, xhat, n_elems, y, stream);
+}
+
+int fss_status(void* stream, int32_t* device_code) {
+  if (!device_code) return fail(FSS_E_ARG, "device_code NULL");
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  int* st = nullptr;
+  int rc = device_status_ptr(&st);
+  if (rc) return rc;
+  int v = 0;
+  HIP_TRY(hipMemcpy(&v, st, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(status)");
+  if (v) HIP_TRY(hipMemset(st, 0, sizeof(int)), "hipMemset(status)");
+  HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  *device_code = v;
+  return FSS_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Work-list plans, graphs, autotuning
+// ===========================================================================
+struct fss_plan {
+  int device = 0;
+  DevItem* d_items = nullptr;
+  uint32_t* d_tiles = nullptr;
+  uint32_t* d_counter = nullptr;
+  uint32_t n_tiles = 0;
+  fss_tune tune{};
+  int grid = 0;
+  double aes_per_launch = 0;  // algorithmic AES blocks of one launch
+};
+
+struct fss_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int device_cus(int* cus, std::string* name) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  *cus = prop.multiProcessorCount;
+  if (name) *name = prop.gcnArchName;
+  return FSS_OK;
+}
+
+// Per-element AES count of one party's evaluation (both calls).
+double elem_aes(const KeyHeader& h) {
+  double a = 0;
+  for (uint32_t t = 0; t < h.T; ++t) a += h.atom_k[t];
+  const int nb = (int)(h.p + 1) / 2;
+  a += (double)h.m * ((double)h.n * (1 + nb) + nb);
+  return a;
+}
+
+int read_header(const void* keys, KeyHeader* h) {
+  HIP_TRY(hipMemcpy(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost), "hipMemcpy(header)");
+  if (h->magic != kMagic || h->version != kVersion) return fail(FSS_E_SHAPE, "not a key buffer");
+  return FSS_OK;
+}
+
+fss_tune default_tune() {
+  fss_tune t{};
+  t.aes_variant = eval_variant();
+  t.block_threads = variant_block(t.aes_variant);
+  t.blocks_per_cu = 0;
+  t.order = 0;
+  return t;
+}
+
+int blocks_per_cu_default(int variant) {
+  const int lds = variant_lds_bytes(variant);
+  int by_lds = (160 * 1024) / std::max(lds, 1);
+  const int block = variant_block(variant);
+  const int by_waves = std::max(1, (32 * 64) / block);  // up to 8 waves per SIMD
+  return std::max(1, std::min(by_lds, by_waves));
+}
+
+}  // namespace
+
+extern "C" {
+
+int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune* tune, fss_plan** out) {
+  if (!out) return fail(FSS_E_ARG, "out NULL");
+  *out = nullptr;
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(FSS_E_ARG, "bad items");
+  fss_tune tn = tune ? *tune : default_tune();
+  if (tn.aes_variant < 0 || tn.aes_variant >= kNumAesVariants) return fail(FSS_E_ARG, "aes_variant");
+  tn.block_threads = variant_block(tn.aes_variant);
+  if (tn.blocks_per_cu <= 0) tn.blocks_per_cu = blocks_per_cu_default(tn.aes_variant);
+  int cus = 0;
+  int rc = device_cus(&cus, nullptr);
+  if (rc) return rc;
+
+  std::vector<DevItem> dev(n_items);
+  struct T { uint32_t item, tile; double cost; };
+  std::vector<T> tl;
+  double aes_total = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const fss_work_item& it = items[i];
+    if ((rc = check_party(it.party))) return rc;
+    if (!it.keys || it.n_elems < 0 || (it.n_elems > 0 && (!it.xhat || !it.y)))
+      return fail(FSS_E_ARG, "item %d: bad buffers", i);
+    KeyHeader h;
+    if ((rc = read_header(it.keys, &h))) return rc;
+    if ((int)h.party != it.party) return fail(FSS_E_PARTY, "item %d: key buffer of party %u", i, h.party);
+    if ((uint64_t)it.n_elems > h.n_elems) return fail(FSS_E_SHAPE, "item %d: n_elems exceeds keys", i);
+    if (h.ell > 0 && it.n_elems > 0 && !it.zbits) return fail(FSS_E_ARG, "item %d: zbits NULL", i);
+    const uint64_t tiles = ((uint64_t)it.n_elems + kTile - 1) / kTile;
+    dev[i] = DevItem{(const uint8_t*)it.keys, it.xhat, it.y, it.zbits, it.n_elems, it.party, (int32_t)tiles};
+    const double c = elem_aes(h);
+    aes_total += c * (double)it.n_elems;
+    for (uint64_t t = 0; t < tiles; ++t) tl.push_back({(uint32_t)i, (uint32_t)t, c});
+  }
+  if (tl.size() > 0xffffffffull) return fail(FSS_E_UNSUPPORTED, "work-list too long");
+  if (tn.order == 0)
+    std::stable_sort(tl.begin(), tl.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
+  std::vector<uint32_t> flat(2 * tl.size());
+  for (size_t k = 0; k < tl.size(); ++k) {
+    flat[2 * k] = tl[k].item;
+    flat[2 * k + 1] = tl[k].tile;
+  }
+  std::unique_ptr<fss_plan> P(new (std::nothrow) fss_plan());
+  if (!P) return fail(FSS_E_OOM, "out of host memory");
+  HIP_TRY(hipGetDevice(&P->device), "hipGetDevice");
+  HIP_TRY(hipMalloc(&P->d_items, sizeof(DevItem) * std::max<size_t>(1, dev.size())), "hipMalloc(items)");
+  HIP_TRY(hipMalloc(&P->d_tiles, sizeof(uint32_t) * std::max<size_t>(2, flat.size())), "hipMalloc(tiles)");
+  HIP_TRY(hipMalloc(&P->d_counter, sizeof(uint32_t)), "hipMalloc(counter)");
+  if (!dev.empty())
+    HIP_TRY(hipMemcpy(P->d_items, dev.data(), sizeof(DevItem) * dev.size(), hipMemcpyHostToDevice), "upload items");
+  if (!flat.empty())
+    HIP_TRY(hipMemcpy(P->d_tiles, flat.data(), sizeof(uint32_t) * flat.size(), hipMemcpyHostToDevice), "upload tiles");
+  P->n_tiles = (uint32_t)tl.size();
+  P->tune = tn;
+  P->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
+                                      (int)((tl.size() * 64 + tn.block_threads - 1) / tn.block_threads)));
+  P->aes_per_launch = aes_total;
+  *out = P.release();
+  return FSS_OK;
+}
+
+int fss_plan_launch(fss_plan* plan, void* stream) {
+  if (!plan) return fail(FSS_E_ARG, "plan NULL");
+  if (plan->n_tiles == 0) return FSS_OK;
+  int* st = nullptr;
+  int rc = device_status_ptr(&st);
+  if (rc) return rc;
+  HIP_TRY(launch_fused(plan->tune.aes_variant, plan->d_items, plan->d_tiles, plan->n_tiles, plan->d_counter, st,
+                       plan->grid, (hipStream_t)stream),
+          "fused launch");
+  return FSS_OK;
+}
+
+int fss_plan_free(fss_plan* plan) {
+  if (!plan) return FSS_OK;
+  (void)hipFree(plan->d_items);
+  (void)hipFree(plan->d_tiles);
+  (void)hipFree(plan->d_counter);
+  delete plan;
+  return FSS_OK;
+}
+
+int fss_graph_capture(fss_plan* const* plans, int32_t n_plans, fss_graph** out) {
+  if (!out || n_plans < 0 || (n_plans > 0 && !plans)) return fail(FSS_E_ARG, "bad arguments");
+  *out = nullptr;
+  int* st = nullptr;
+  int rc = device_status_ptr(&st);  // allocate outside the capture
+  if (rc) return rc;
+  hipStream_t s;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  std::unique_ptr<fss_graph> G(new fss_graph());
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  for (int i = 0; i < n_plans && rc == FSS_OK; ++i) rc = fss_plan_launch(plans[i], s);
+  e = hipStreamEndCapture(s, &G->graph);
+  (void)hipStreamDestroy(s);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(G->graph);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  *out = G.release();
+  return FSS_OK;
+}
+
+int fss_graph_launch(fss_graph* graph, void* stream) {
+  if (!graph) return fail(FSS_E_ARG, "graph NULL");
+  HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream), "hipGraphLaunch");
+  return FSS_OK;
+}
+
+int fss_graph_free(fss_graph* graph) {
+  if (!graph) return FSS_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
+  return FSS_OK;
+}
+
+int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_path, fss_tune* best) {
+  if (!best) return fail(FSS_E_ARG, "best NULL");
+  int cus = 0;
+  std::string arch;
+  int rc = device_cus(&cus, &arch);
+  if (rc) return rc;
+  // Cache key: device + the shape of every item (spec hash, size, party).
+  std::ostringstream key;
+  key << arch << ":" << cus;
+  for (int i = 0; i < n_items; ++i) {
+    KeyHeader h;
+    if ((rc = read_header(items[i].keys, &h))) return rc;
+    key << "|" << std::hex << h.spec_hash << std::dec << "," << h.n << "," << h.m << "," << h.p << ","
+        << items[i].n_elems << "," << items[i].party;
+  }
+  const std::string k = std::to_string(fnv1a(key.str().data(), key.str().size()));
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string kk;
+      fss_tune t{};
+      if (ls >> kk >> t.aes_variant >> t.block_threads >> t.blocks_per_cu >> t.order && kk == k &&
+          t.aes_variant >= 0 && t.aes_variant < kNumAesVariants) {
+        *best = t;
+        return FSS_OK;
+      }
+    }
+  }
+  hipStream_t s;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  double best_ms = 1e30;
+  fss_tune bt = default_tune();
+  for (int v = 0; v < kNumAesVariants; ++v) {
+    const int dflt = blocks_per_cu_default(v);
+    for (int bpc : {dflt, std::max(1, dflt / 2), dflt * 2}) {
+      for (int order : {0, 1}) {
+        fss_tune t{};
+        t.aes_variant = v;
+        t.blocks_per_cu = bpc;
+        t.order = order;
+        fss_plan* P = nullptr;
+        if ((rc = fss_plan_create(items, n_items, &t, &P))) break;
+        double ms = 1e30;
+        for (int rep = 0; rep < 3 && rc == FSS_OK; ++rep) {
+          (void)hipEventRecord(e0, s);
+          rc = fss_plan_launch(P, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          float m = 0;
+          (void)hipEventElapsedTime(&m, e0, e1);
+          if (rep > 0) ms = std::min(ms, (double)m);
+        }
+        t = P->tune;
+        fss_plan_free(P);
+        if (rc) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          bt = t;
+        }
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (rc) return rc;
+  *best = bt;
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << k << " " << bt.aes_variant << " " << bt.block_threads << " " << bt.blocks_per_cu << " " << bt.order << "\n";
+  }
+  return FSS_OK;
+}
+
+// Extra introspection used by the benchmark: algorithmic AES blocks of one
+// launch of a plan, and its resolved launch configuration.
+double fss_plan_aes_blocks(const fss_plan* plan) { return plan ? plan->aes_per_launch : 0.0; }
+int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid) {
+  if (!plan || !tune || !grid) return fail(FSS_E_ARG, "NULL argument");
+  *tune = plan->tune;
+  *grid = plan->grid;
+  return FSS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// fss_common.hpp -- definitions shared by the library's host code and kernels:
+// compile-time AES-128 tables, the key-buffer header and the tile layout.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __HIPCC__
+#define FSS_HD __host__ __device__
+#else
+#define FSS_HD
+#endif
+
+namespace fss {
+
+// ---------------------------------------------------------------------------
+// AES-128 tables, built at compile time.
+// S-box: inverse in GF(2^8) via log/antilog tables over the generator 0x03,
+// then the FIPS-197 affine map.  Te0 packs one MixColumns column per S-box
+// output as a little-endian word: rows (2S, S, S, 3S) in bytes 0..3.
+// ---------------------------------------------------------------------------
+struct AesConst {
+  uint8_t sbox[256];
+  uint32_t te0[256];
+  uint32_t prg_rk[44];  // round keys of the fixed PRG key 00 01 .. 0f
+};
+
+constexpr uint8_t gf_x2(uint8_t a) { return (uint8_t)((a << 1) ^ ((a & 0x80) ? 0x1b : 0)); }
+
+constexpr void expand_key(const uint8_t* sbox, const uint8_t key[16], uint32_t w[44]) {
+  for (int i = 0; i < 4; ++i)
+    w[i] = (uint32_t)key[4 * i] | ((uint32_t)key[4 * i + 1] << 8) |
+           ((uint32_t)key[4 * i + 2] << 16) | ((uint32_t)key[4 * i + 3] << 24);
+  uint8_t rc = 1;
+  for (int i = 4; i < 44; ++i) {
+    uint32_t t = w[i - 1];
+    if ((i & 3) == 0) {
+      t = (t >> 8) | (t << 24);  // RotWord on a little-endian word
+      t = (uint32_t)sbox[t & 0xff] | ((uint32_t)sbox[(t >> 8) & 0xff] << 8) |
+          ((uint32_t)sbox[(t >> 16) & 0xff] << 16) | ((uint32_t)sbox[t >> 24] << 24);
+      t ^= rc;
+      rc = gf_x2(rc);
+    }
+    w[i] = w[i - 4] ^ t;
+  }
+}
+
+constexpr AesConst make_aes_const() {
+  AesConst c{};
+  uint8_t ex[256] = {}, lg[256] = {};
+  uint8_t v = 1;
+  for (int i = 0; i < 255; ++i) {
+    ex[i] = v;
+    lg[v] = (uint8_t)i;
+    v = (uint8_t)(v ^ gf_x2(v));  // multiply by 0x03
+  }
+  for (int x = 0; x < 256; ++x) {
+    uint8_t inv = x ? ex[(255 - lg[x]) % 255] : 0;
+    uint8_t s = inv, r = inv;
+    for (int k = 0; k < 4; ++k) {
+      r = (uint8_t)((r << 1) | (r >> 7));
+      s ^= r;
+    }
+    c.sbox[x] = (uint8_t)(s ^ 0x63);
+  }
+  for (int x = 0; x < 256; ++x) {
+    uint8_t s = c.sbox[x], s2 = gf_x2(s), s3 = (uint8_t)(s2 ^ s);
+    c.te0[x] = (uint32_t)s2 | ((uint32_t)s << 8) | ((uint32_t)s << 16) | ((uint32_t)s3 << 24);
+  }
+  uint8_t k[16] = {};
+  for (int i = 0; i < 16; ++i) k[i] = (uint8_t)i;
+  expand_key(c.sbox, k, c.prg_rk);
+  return c;
+}
+
+constexpr AesConst kAes = make_aes_const();
+
+// ---------------------------------------------------------------------------
+// Key buffer: a header, then n_tiles tiles of 64 elements.  Inside a tile
+// every field is stored structure-of-arrays over the 64 lanes, so a wave that
+// owns a tile reads each field with one coalesced access per level.
+//   atom t : root[64] (16 B) | cw[k_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
+//            | vbits[64] (u64: bit i = value corr. of level i, bit 32 = final)
+//   wshare[64] (u64: bit j = this party's share of the carry of output j)
+//   coeff  : root[64] | cw[n][64] | vcw[n][p][64] (u64) | fin[p][64]
+//            | rho[p][64] (share of rho) | rout[64] (share of r_out)
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
+constexpr uint32_t kVersion = 1;
+constexpr int kTile = 64;
+constexpr int kMaxAtoms = 16;
+constexpr int kMaxM = 64;
+constexpr int kMaxP = 4;
+constexpr uint64_t kHeaderBytes = 16384;
+
+struct KeyHeader {
+  uint32_t magic, version, party, layout;
+  uint32_t n, f, m, d, p, T, ell, F_out;
+  uint32_t n_prim, n_views, kmax, pad0;
+  uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
+  uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
+  uint32_t atom_k[kMaxAtoms];
+  uint32_t atom_out[kMaxAtoms];            // theta atoms: output bit
+  uint32_t atom_rview[kMaxAtoms];          // theta atoms: index of their view's mask atom
+  uint64_t atom_c[kMaxAtoms];              // view shift
+  uint64_t atom_off[kMaxAtoms];            // byte offset of the atom section in a tile
+  uint64_t off_w, off_croot, off_ccw, off_cvcw, off_cfin, off_crho, off_crout;
+  uint64_t aprime[kMaxM + 1];              // offset-binary boundaries
+  // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
+  // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
+  uint64_t tab[kMaxM][kMaxP][kMaxP];
+};
+static_assert(sizeof(KeyHeader) <= kHeaderBytes, "header too large");
+
+struct Layout {
+  uint64_t atom_off[kMaxAtoms];
+  uint64_t off_w, off_croot, off_ccw, off_cvcw, off_cfin, off_crho, off_crout;
+  uint64_t tile_bytes;
+};
+
+FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p) {
+  Layout L{};
+  uint64_t o = 0;
+  for (int t = 0; t < T; ++t) {
+    L.atom_off[t] = o;
+    o += (uint64_t)kTile * 16 * (1 + atom_k[t]) + (uint64_t)kTile * 8;
+  }
+  L.off_w = o;     o += kTile * 8;
+  L.off_croot = o; o += kTile * 16;
+  L.off_ccw = o;   o += (uint64_t)n * kTile * 16;
+  L.off_cvcw = o;  o += (uint64_t)n * p * kTile * 8;
+  L.off_cfin = o;  o += (uint64_t)p * kTile * 8;
+  L.off_crho = o;  o += (uint64_t)p * kTile * 8;
+  L.off_crout = o; o += kTile * 8;
+  L.tile_bytes = (o + 255) & ~(uint64_t)255;
+  return L;
+}
+
+// Device status codes (mirrors of FSS_E_*).
+constexpr int kStatusShape = -4;
+constexpr int kStatusParty = -5;
+
+}  // namespace fss

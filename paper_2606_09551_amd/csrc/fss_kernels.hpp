@@ -1,0 +1,71 @@
+// fss_kernels.hpp -- launch wrappers between the C ABI (fss_api.cpp) and the
+// HIP kernels (fss_kernels.hip).  Internal to the library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fss_common.hpp"
+
+namespace fss {
+
+constexpr int kNumAesVariants = 4;
+
+struct RoundKeys { uint32_t w[44]; };
+
+// Keygen arguments passed by value: round keys of the dealer-seed AES key
+// and the per-atom thresholds in view space (public, spec-derived).
+struct KgArgs {
+  RoundKeys rk;
+  uint64_t bprime[kMaxAtoms];
+  int64_t n_elems;
+  uint64_t n_tiles;
+};
+
+// One work-list entry as the persistent kernel sees it.
+struct DevItem {
+  const uint8_t* keys;
+  const uint64_t* xhat;
+  uint64_t* y;
+  uint64_t* z;
+  int64_t n_elems;
+  int32_t party;
+  int32_t words;  // ceil(n_elems / 64): stride of the z bit-planes
+};
+
+// Launchers of one AES table layout V (0 .. kNumAesVariants-1).
+template <int V>
+struct VariantOps {
+  static int block();
+  static int lds_bytes();
+  static hipError_t keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
+                           uint64_t* ro, hipStream_t st);
+  static hipError_t pred(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* z,
+                         int* status, hipStream_t st);
+  static hipError_t coeff(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* y,
+                          int* status, hipStream_t st);
+  static hipError_t fused(const DevItem* items, const uint32_t* tiles, uint32_t n_tiles, uint32_t* counter,
+                          int* status, int grid, hipStream_t st);
+};
+extern template struct VariantOps<0>;
+extern template struct VariantOps<1>;
+extern template struct VariantOps<2>;
+extern template struct VariantOps<3>;
+
+hipError_t launch_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
+                              uint32_t party, hipStream_t st);
+hipError_t launch_keygen(int variant, const KeyHeader* dev_hdr, const KgArgs& ga, uint8_t* key0,
+                         uint8_t* key1, uint64_t* r_in, uint64_t* r_out, hipStream_t st);
+hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat,
+                       hipStream_t st);
+hipError_t launch_eval_pred(int variant, int party, const uint8_t* keys, const uint64_t* xhat,
+                            int64_t n, uint64_t* z, int* status, hipStream_t st);
+hipError_t launch_eval_coeff(int variant, int party, const uint8_t* keys, const uint64_t* xhat,
+                             int64_t n, uint64_t* y, int* status, hipStream_t st);
+// Resets the work counter with a kernel (graph-safe), then launches the
+// persistent kernel with `grid` blocks of the variant's block size.
+hipError_t launch_fused(int variant, const DevItem* items, const uint32_t* tiles, uint32_t n_tiles,
+                        uint32_t* counter, int* status, int grid, hipStream_t st);
+int variant_block(int variant);
+int variant_lds_bytes(int variant);
+
+}  // namespace fss

@@ -1,0 +1,834 @@
+// fss_kernels_impl.hpp -- gfx950 kernels of the FSS hot path, templated on
+// the AES table layout; each fss_kernels_v<N>.hip instantiates one layout.
+//
+// Work mapping: one wave64 owns one 64-element key tile; lane = element.
+// Every step of a DCF walk is integer work; the dominant cost is the
+// fixed-key AES-128 of the GGM seed expansion, computed with T-tables held
+// in LDS (no AES instructions exist on CDNA).  Key fields are read with one
+// coalesced access per level per wave (structure-of-arrays tiles).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+#include "fss_kernels.hpp"
+
+namespace fss {
+
+static __constant__ AesConst c_aes = kAes;
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint32_t rotl8n(uint32_t x, int n8) {
+  return n8 == 0 ? x : ((x << n8) | (x >> (32 - n8)));
+}
+__device__ __forceinline__ uint4 ld16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ uint64_t ld8(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
+__device__ __forceinline__ void st16(uint8_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
+__device__ __forceinline__ void st8(uint8_t* p, uint64_t v) { *reinterpret_cast<uint64_t*>(p) = v; }
+__device__ __forceinline__ uint64_t mk64(uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); }
+__device__ __forceinline__ void set_status(int* st, int code) { atomicCAS(st, 0, code); }
+
+// ---------------------------------------------------------------------------
+// T-table layouts in LDS.  get<TBL, B>(w) returns T_TBL[byte B of w], where
+// T_t = rotl(Te0, 8t).  Variants trade LDS footprint against bank conflicts
+// and VALU work; the autotuner picks one per work-list.
+// ---------------------------------------------------------------------------
+// Byte-permute selector placing byte B of src0 at result byte 1 and keeping
+// bytes 0 and 2 of src1 (lane offset, table bank): one v_perm per address.
+template <int B>
+__device__ __forceinline__ uint32_t lane_addr(uint32_t w, uint32_t base) {
+  constexpr uint32_t sel = (0x0cu << 24) | (0x02u << 16) | ((4u + B) << 8) | 0x00u;
+  return __builtin_amdgcn_perm(w, base, sel);
+}
+
+// Variant 0: the four 1 KB tables, one copy each.
+struct Tab0 {
+  static constexpr int kWords = 1024;
+  const uint32_t* lds;
+  __device__ Tab0(const uint32_t* l, int) : lds(l) {}
+  template <int TBL, int B>
+  __device__ __forceinline__ uint32_t get(uint32_t w) const {
+    return lds[TBL * 256 + ((w >> (8 * B)) & 0xffu)];
+  }
+  __device__ static void fill(uint32_t* lds, int tid, int nthr) {
+    for (int i = tid; i < 1024; i += nthr) lds[i] = rotl8n(c_aes.te0[i & 255], 8 * (i >> 8));
+  }
+};
+
+// Variant 1: four tables, 32 lane-private copies, 256-byte entry rows:
+// entry x of table t at byte (t>>1)*65536 + x*256 + (t&1)*128 + (lane&31)*4.
+struct Tab1 {
+  static constexpr int kWords = 32768;
+  const uint8_t* lds;
+  uint32_t base01, base23;
+  __device__ Tab1(const uint32_t* l, int lane)
+      : lds(reinterpret_cast<const uint8_t*>(l)),
+        base01((uint32_t)(lane & 31) * 4u), base23(((uint32_t)(lane & 31) * 4u) | 0x10000u) {}
+  template <int TBL, int B>
+  __device__ __forceinline__ uint32_t get(uint32_t w) const {
+    uint32_t a = lane_addr<B>(w, TBL < 2 ? base01 : base23) & 0x1ff7cu;  // < 128 KB - 131
+    return *reinterpret_cast<const uint32_t*>(lds + a + (TBL & 1) * 128);
+  }
+  __device__ static void fill(uint32_t* lds, int tid, int nthr) {
+    for (int i = tid; i < 32768; i += nthr) {
+      int sub = (i >> 5) & 1, x = (i >> 6) & 255, bank = i >> 14;
+      int tbl = bank * 2 + sub;
+      lds[i] = rotl8n(c_aes.te0[x], 8 * tbl);
+    }
+  }
+};
+
+// Variant 2: Te0 and Te2 with 32 copies (64 KB); T1, T3 by an 8-bit rotate.
+struct Tab2 {
+  static constexpr int kWords = 16384;
+  const uint8_t* lds;
+  uint32_t base;
+  __device__ Tab2(const uint32_t* l, int lane)
+      : lds(reinterpret_cast<const uint8_t*>(l)), base((uint32_t)(lane & 31) * 4u) {}
+  template <int TBL, int B>
+  __device__ __forceinline__ uint32_t get(uint32_t w) const {
+    uint32_t a = lane_addr<B>(w, base) & 0xff7cu;  // < 64 KB - 131
+    uint32_t v = *reinterpret_cast<const uint32_t*>(lds + a + (TBL >= 2 ? 128 : 0));
+    return rotl8n(v, 8 * (TBL & 1));
+  }
+  __device__ static void fill(uint32_t* lds, int tid, int nthr) {
+    for (int i = tid; i < 16384; i += nthr) {
+      int sub = (i >> 5) & 1, x = i >> 6;
+      lds[i] = rotl8n(c_aes.te0[x], 16 * sub);
+    }
+  }
+};
+
+// Variant 3: Te0 only, 64 lane-private copies (64 KB); T1..T3 by rotates.
+struct Tab3 {
+  static constexpr int kWords = 16384;
+  const uint8_t* lds;
+  uint32_t base;
+  __device__ Tab3(const uint32_t* l, int lane)
+      : lds(reinterpret_cast<const uint8_t*>(l)), base((uint32_t)(lane & 63) * 4u) {}
+  template <int TBL, int B>
+  __device__ __forceinline__ uint32_t get(uint32_t w) const {
+    uint32_t a = lane_addr<B>(w, base) & 0xfffcu;  // < 64 KB - 3
+    return rotl8n(*reinterpret_cast<const uint32_t*>(lds + a), 8 * TBL);
+  }
+  __device__ static void fill(uint32_t* lds, int tid, int nthr) {
+    for (int i = tid; i < 16384; i += nthr) lds[i] = c_aes.te0[i >> 6];
+  }
+};
+
+// Keygen holds both parties' walk state (about 250 VGPRs), so it always runs
+// 256-thread blocks whatever the table layout.
+constexpr int kKeygenBlock = 256;
+
+template <int V> struct TabOf;
+template <> struct TabOf<0> { using T = Tab0; static constexpr int kBlock = 256; };
+template <> struct TabOf<1> { using T = Tab1; static constexpr int kBlock = 1024; };
+template <> struct TabOf<2> { using T = Tab2; static constexpr int kBlock = 512; };
+template <> struct TabOf<3> { using T = Tab3; static constexpr int kBlock = 512; };
+
+// ---------------------------------------------------------------------------
+// AES-128 encryption of K independent blocks, round-interleaved for ILP.
+// State words are little-endian columns: s[c] = bytes 4c..4c+3.
+// ---------------------------------------------------------------------------
+struct PrgKey {  // the fixed PRG key: round keys are compile-time constants
+  template <int I>
+  __device__ __forceinline__ uint32_t w() const { return kAes.prg_rk[I]; }
+};
+struct RtKey {   // a key known at launch (the dealer seed), read from kernel arguments
+  const RoundKeys& rk;
+  template <int I>
+  __device__ __forceinline__ uint32_t w() const { return rk.w[I]; }
+};
+
+template <int R, class Key, class TB, int K>
+__device__ __forceinline__ void aes_round(const Key& key, const TB& tb, uint32_t (&s)[K][4]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t a0 = s[k][0], a1 = s[k][1], a2 = s[k][2], a3 = s[k][3];
+    uint32_t t0 = xor3(tb.template get<0, 0>(a0), tb.template get<1, 1>(a1), tb.template get<2, 2>(a2));
+    uint32_t t1 = xor3(tb.template get<0, 0>(a1), tb.template get<1, 1>(a2), tb.template get<2, 2>(a3));
+    uint32_t t2 = xor3(tb.template get<0, 0>(a2), tb.template get<1, 1>(a3), tb.template get<2, 2>(a0));
+    uint32_t t3 = xor3(tb.template get<0, 0>(a3), tb.template get<1, 1>(a0), tb.template get<2, 2>(a1));
+    s[k][0] = xor3(t0, tb.template get<3, 3>(a3), key.template w<4 * R + 0>());
+    s[k][1] = xor3(t1, tb.template get<3, 3>(a0), key.template w<4 * R + 1>());
+    s[k][2] = xor3(t2, tb.template get<3, 3>(a1), key.template w<4 * R + 2>());
+    s[k][3] = xor3(t3, tb.template get<3, 3>(a2), key.template w<4 * R + 3>());
+  }
+}
+
+template <class Key, class TB, int K>
+__device__ __forceinline__ void aes_final(const Key& key, const TB& tb, uint32_t (&s)[K][4]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t a[4] = {s[k][0], s[k][1], s[k][2], s[k][3]};
+    uint32_t o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      // S-box byte of row r sits in byte r of T_{(r+2)&3}.
+      o[c] = (tb.template get<2, 0>(a[c]) & 0x000000ffu) |
+             (tb.template get<3, 1>(a[(c + 1) & 3]) & 0x0000ff00u) |
+             (tb.template get<0, 2>(a[(c + 2) & 3]) & 0x00ff0000u) |
+             (tb.template get<1, 3>(a[(c + 3) & 3]) & 0xff000000u);
+    }
+    s[k][0] = o[0] ^ key.template w<40>();
+    s[k][1] = o[1] ^ key.template w<41>();
+    s[k][2] = o[2] ^ key.template w<42>();
+    s[k][3] = o[3] ^ key.template w<43>();
+  }
+}
+
+template <class Key, class TB, int K, int... Rs>
+__device__ __forceinline__ void aes_rounds(const Key& key, const TB& tb, uint32_t (&s)[K][4],
+                                           std::integer_sequence<int, Rs...>) {
+  (aes_round<Rs + 1>(key, tb, s), ...);
+}
+
+template <class Key, class TB, int K>
+__device__ __forceinline__ void aes_encrypt(const Key& key, const TB& tb, uint32_t (&s)[K][4]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s[k][0] ^= key.template w<0>();
+    s[k][1] ^= key.template w<1>();
+    s[k][2] ^= key.template w<2>();
+    s[k][3] ^= key.template w<3>();
+  }
+  aes_rounds(key, tb, s, std::make_integer_sequence<int, 9>{});
+  aes_final(key, tb, s);
+}
+
+// H(s, j) = AES_K(s ^ J_j) ^ s ^ J_j with J_j = byte 15 set to j.
+template <class TB, int K>
+__device__ __forceinline__ void prg(const TB& tb, const uint32_t (&s)[K][4], const uint32_t (&j)[K],
+                                    uint32_t (&o)[K][4]) {
+  uint32_t x[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    x[k][0] = s[k][0];
+    x[k][1] = s[k][1];
+    x[k][2] = s[k][2];
+    x[k][3] = s[k][3] ^ (j[k] << 24);
+    o[k][0] = x[k][0]; o[k][1] = x[k][1]; o[k][2] = x[k][2]; o[k][3] = x[k][3];
+  }
+  aes_encrypt(PrgKey{}, tb, o);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) o[k][c] ^= x[k][c];
+}
+
+// ---------------------------------------------------------------------------
+// Header validation (uniform across the launch)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int header_check(const KeyHeader* h, int party, int64_t n) {
+  if (h->magic != kMagic || h->version != kVersion) return kStatusShape;
+  if ((int)h->party != party) return kStatusParty;
+  if (n < 0 || (uint64_t)n > h->n_elems) return kStatusShape;
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Call 1: packed comparison.  Up to three Z_2 DCF atoms walk in lockstep.
+// ---------------------------------------------------------------------------
+template <class TB>
+__device__ __forceinline__ uint32_t eval_atoms(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+                                               int lane, int b, uint64_t xhat) {
+  const int T = (int)h->T;
+  uint32_t bits = 0;
+  for (int g = 0; g < T; g += 3) {
+    const int cnt = T - g < 3 ? T - g : 3;
+    uint32_t s[3][4], t[3], V[3], xv[3];
+    int k[3];
+    uint64_t vb[3];
+    const uint8_t* base[3];
+    int kmax = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int at = g + (a < cnt ? a : 0);
+      k[a] = a < cnt ? (int)h->atom_k[at] : 0;
+      kmax = k[a] > kmax ? k[a] : kmax;
+      base[a] = tile + h->atom_off[at];
+      const uint4 r = ld16(base[a] + lane * 16);
+      s[a][0] = r.x; s[a][1] = r.y; s[a][2] = r.z; s[a][3] = r.w;
+      t[a] = (uint32_t)b;
+      V[a] = 0;
+      const uint64_t msk = (k[a] >= 64) ? ~0ull : ((1ull << k[a]) - 1);
+      xv[a] = (uint32_t)(((xhat & msk) + h->atom_c[at]) & msk);
+      vb[a] = ld8(base[a] + (uint64_t)kTile * 16 * (1 + k[a]) + lane * 8);
+    }
+    for (int i = 0; i < kmax; ++i) {
+      uint32_t j[3], o[3][4];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) j[a] = (i < k[a]) ? ((xv[a] >> (k[a] - 1 - i)) & 1u) : 0u;
+      prg<TB, 3>(tb, s, j, o);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (i < k[a]) {
+          const uint4 cw = ld16(base[a] + kTile * 16 + ((uint64_t)i * kTile + lane) * 16);
+          const uint32_t msk = 0u - t[a];
+          const uint32_t nt = (o[a][0] & 1u) ^ ((cw.x >> j[a]) & t[a] & 1u);
+          const uint32_t v = ((o[a][0] >> 1) & 1u) ^ ((uint32_t)(vb[a] >> i) & t[a] & 1u);
+          s[a][0] = (o[a][0] & ~3u) ^ (cw.x & ~3u & msk);
+          s[a][1] = o[a][1] ^ (cw.y & msk);
+          s[a][2] = o[a][2] ^ (cw.z & msk);
+          s[a][3] = o[a][3] ^ (cw.w & msk);
+          V[a] ^= v;
+          t[a] = nt;
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a < cnt) {
+        V[a] ^= ((s[a][0] >> 2) & 1u) ^ ((uint32_t)(vb[a] >> 32) & t[a] & 1u);
+        bits |= (V[a] & 1u) << (g + a);
+      }
+    }
+  }
+  return bits;
+}
+
+// Combine atom shares into output-bit shares and ballot-pack 64 elements
+// per word: z_j = negate_j (party 0) ^ w_j ^ XOR over atoms of (A_t ^ A_r(t)).
+template <class TB>
+__device__ __forceinline__ void pred_tile(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+                                          int lane, int b, uint64_t xhat, bool valid, uint64_t* z,
+                                          uint64_t tile_idx, uint64_t words) {
+  const uint32_t A = eval_atoms(tb, h, tile, lane, b, xhat);
+  uint64_t bits = ld8(tile + h->off_w + lane * 8);
+  if (b == 0) bits ^= h->negate;
+  const int np = (int)h->n_prim;
+  for (int t = 0; t < np; ++t) {
+    const uint32_t bit = ((A >> t) ^ (A >> h->atom_rview[t])) & 1u;
+    bits ^= (uint64_t)bit << h->atom_out[t];
+  }
+  const int ell = (int)h->ell;
+  for (int j = 0; j < ell; ++j) {
+    const uint64_t word = __ballot(valid && ((bits >> j) & 1ull));
+    if (lane == 0) z[(uint64_t)j * words + tile_idx] = word;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Call 2: vector interval lookup.  One vector DCF (payload rho in Z^P) is
+// evaluated at m points; 1 + ceil(P/2) AES per level, interleaved.
+// ---------------------------------------------------------------------------
+template <int P, class TB>
+__device__ __forceinline__ void eval_vec(const TB& tb, const KeyHeader* h, const uint8_t* tile, int lane,
+                                         int b, uint32_t x, uint64_t (&out)[P]) {
+  constexpr int NB = (P + 1) / 2;
+  const int n = (int)h->n;
+  const uint4 r = ld16(tile + h->off_croot + lane * 16);
+  uint32_t s[4] = {r.x, r.y, r.z, r.w};
+  uint32_t t = (uint32_t)b;
+  uint64_t V[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) V[q] = 0;
+  const uint8_t* cwp = tile + h->off_ccw + lane * 16;
+  const uint8_t* vcp = tile + h->off_cvcw + lane * 8;
+  for (int i = 0; i < n; ++i) {
+    const uint32_t xi = (x >> (n - 1 - i)) & 1u;
+    uint32_t ss[1 + NB][4], jj[1 + NB], o[1 + NB][4];
+#pragma unroll
+    for (int q = 0; q <= NB; ++q) {
+      ss[q][0] = s[0]; ss[q][1] = s[1]; ss[q][2] = s[2]; ss[q][3] = s[3];
+    }
+    jj[0] = xi;
+    jj[1] = 2u + 2u * xi;
+    if (NB > 1) jj[NB > 1 ? 2 : 0] = 3u + 2u * xi;
+    prg<TB, 1 + NB>(tb, ss, jj, o);
+    const uint4 cw = ld16(cwp + (uint64_t)i * kTile * 16);
+    const uint32_t msk = 0u - t;
+    const uint64_t msk64 = 0ull - (uint64_t)t;
+    const uint32_t nt = (o[0][0] & 1u) ^ ((cw.x >> xi) & t & 1u);
+    s[0] = (o[0][0] & ~3u) ^ (cw.x & ~3u & msk);
+    s[1] = o[0][1] ^ (cw.y & msk);
+    s[2] = o[0][2] ^ (cw.z & msk);
+    s[3] = o[0][3] ^ (cw.w & msk);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
+      v += ld8(vcp + ((uint64_t)i * P + q) * kTile * 8) & msk64;
+      V[q] += b ? (0ull - v) : v;
+    }
+    t = nt;
+  }
+  // Convert(s) = the first P words of H(s, 6) || H(s, 7).
+  uint32_t ss[NB][4], jj[NB], o[NB][4];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    ss[q][0] = s[0]; ss[q][1] = s[1]; ss[q][2] = s[2]; ss[q][3] = s[3];
+    jj[q] = 6u + q;
+  }
+  prg<TB, NB>(tb, ss, jj, o);
+  const uint64_t msk64 = 0ull - (uint64_t)t;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    uint64_t c = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
+    c += ld8(tile + h->off_cfin + ((uint64_t)q * kTile + lane) * 8) & msk64;
+    out[q] = V[q] + (b ? (0ull - c) : c);
+  }
+}
+
+// With v = view_{n,s}(xhat) and u_i = (v - a'_i) mod N, the share of
+// 1[x' < a'_i] rho is g_i = D(u_i) - D(v) + 1[v < a'_i] rho_b, and the
+// active piece's coefficients at xhat are
+//   q = tab_0 rho_b + sum_{i=1}^{m-1} tab_i g_i  (+ r_out share in q_0),
+// where tab_0 = A_{m-1}, tab_i = A_{i-1} - A_i and A_i maps a share of
+// 1[x in I_i] rho to the x-hat coefficients of piece i.  Then y = sum q_j xhat^j.
+template <int P, class TB>
+__device__ __forceinline__ uint64_t coeff_tile(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+                                               int lane, int b, uint64_t xhat) {
+  const int n = (int)h->n, m = (int)h->m;
+  const uint32_t Nmask = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+  const uint32_t half = 1u << (n - 1);
+  const uint32_t v = ((uint32_t)xhat + half) & Nmask;
+  uint64_t Dv[P], rho[P], q[P];
+  eval_vec<P>(tb, h, tile, lane, b, v, Dv);
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    rho[k] = ld8(tile + h->off_crho + ((uint64_t)k * kTile + lane) * 8);
+    q[k] = 0;
+  }
+  for (int i = 1; i < m; ++i) {
+    const uint32_t ap = (uint32_t)h->aprime[i];
+    const uint32_t u = (v - ap) & Nmask;
+    uint64_t D[P];
+    eval_vec<P>(tb, h, tile, lane, b, u, D);
+    const uint64_t lt = v < ap ? ~0ull : 0ull;
+    uint64_t g[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) g[k] = D[k] - Dv[k] + (rho[k] & lt);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * g[k];
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+#pragma unroll
+    for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * rho[k];
+  q[0] += ld8(tile + h->off_crout + lane * 8);
+  uint64_t y = q[P - 1];
+#pragma unroll
+  for (int j = P - 2; j >= 0; --j) y = y * xhat + q[j];
+  return y;
+}
+
+template <class TB>
+__device__ __forceinline__ uint64_t coeff_dispatch(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+                                                   int lane, int b, uint64_t xhat) {
+  switch (h->p) {
+    case 1: return coeff_tile<1>(tb, h, tile, lane, b, xhat);
+    case 2: return coeff_tile<2>(tb, h, tile, lane, b, xhat);
+    case 3: return coeff_tile<3>(tb, h, tile, lane, b, xhat);
+    default: return coeff_tile<4>(tb, h, tile, lane, b, xhat);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain evaluator kernels: one tile per wave, grid covers the tiles.
+// ---------------------------------------------------------------------------
+template <int V>
+__global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_pred(const uint8_t* keys, const uint64_t* xhat,
+                                                                 int64_t n, uint64_t* z, int party, int* status) {
+  using TB = typename TabOf<V>::T;
+  __shared__ uint32_t lds[TB::kWords];
+  TB::fill(lds, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const KeyHeader* h = reinterpret_cast<const KeyHeader*>(keys);
+  const int bad = header_check(h, party, n);
+  if (bad) {
+    if (threadIdx.x == 0) set_status(status, bad);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t words = ((uint64_t)n + 63) / 64;
+  if (tile >= words) return;
+  const uint64_t e = tile * kTile + lane;
+  const bool valid = e < (uint64_t)n;
+  const uint64_t xh = valid ? xhat[e] : 0;
+  TB tb(lds, lane);
+  const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
+  pred_tile(tb, h, tp, lane, party, xh, valid, z, tile, words);
+}
+
+template <int V>
+__global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* keys, const uint64_t* xhat,
+                                                                  int64_t n, uint64_t* y, int party, int* status) {
+  using TB = typename TabOf<V>::T;
+  __shared__ uint32_t lds[TB::kWords];
+  TB::fill(lds, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const KeyHeader* h = reinterpret_cast<const KeyHeader*>(keys);
+  const int bad = header_check(h, party, n);
+  if (bad) {
+    if (threadIdx.x == 0) set_status(status, bad);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (tile * kTile >= (uint64_t)n) return;
+  const uint64_t e = tile * kTile + lane;
+  const bool valid = e < (uint64_t)n;
+  const uint64_t xh = valid ? xhat[e] : 0;
+  TB tb(lds, lane);
+  const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
+  const uint64_t out = coeff_dispatch(tb, h, tp, lane, party, xh);
+  if (valid) y[e] = out;
+}
+
+// ---------------------------------------------------------------------------
+// Fused persistent kernel: waves pull (item, tile) pairs from a work-list in
+// cost order and run both calls plus the combination in one pass per element
+// (xhat loaded once, AES tables staged once per resident block).
+// ---------------------------------------------------------------------------
+template <int V>
+__global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items, const uint32_t* tiles,
+                                                             uint32_t n_tiles, uint32_t* counter,
+                                                             int* status) {
+  using TB = typename TabOf<V>::T;
+  __shared__ uint32_t lds[TB::kWords];
+  TB::fill(lds, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  TB tb(lds, lane);
+  while (true) {
+    uint32_t idx = 0;
+    if (lane == 0) idx = atomicAdd(counter, 1u);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= n_tiles) break;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(tiles[2 * idx]);
+    const uint64_t tile = __builtin_amdgcn_readfirstlane(tiles[2 * idx + 1]);
+    const DevItem it = items[item];
+    const KeyHeader* h = reinterpret_cast<const KeyHeader*>(it.keys);
+    const int bad = header_check(h, it.party, it.n_elems);
+    if (bad) {
+      if (lane == 0) set_status(status, bad);
+      continue;
+    }
+    const uint64_t e = tile * kTile + lane;
+    const bool valid = e < (uint64_t)it.n_elems;
+    const uint64_t xh = valid ? it.xhat[e] : 0;
+    const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
+    if (h->T > 0) pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
+    const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh);
+    if (valid) it.y[e] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dealer key generation.  Lane = element; every random value is
+// R(e, purpose, ctr) = AES_{K_seed}(e | purpose | ctr), so elements are
+// independent and the output is deterministic.
+// ---------------------------------------------------------------------------
+template <class TB>
+__device__ __forceinline__ void rand_blk(const TB& tb, const RoundKeys& rk, uint64_t e, uint32_t purpose,
+                                         uint32_t ctr, uint32_t (&o)[4]) {
+  uint32_t s[1][4] = {{(uint32_t)e, (uint32_t)(e >> 32), (purpose & 0xffffu) | (ctr << 16), 0u}};
+  aes_encrypt(RtKey{rk}, tb, s);
+  o[0] = s[0][0]; o[1] = s[0][1]; o[2] = s[0][2]; o[3] = s[0][3];
+}
+
+// Z_2 DCF Gen for f(x) = 1[x < alpha] over k bits; writes root, cw, vbits.
+// The PRG tweaks are chosen so block 0/1 of each party is the child on /
+// off alpha's path ("keep" / "lose"); no register array is indexed at run time.
+template <class TB>
+__device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, const uint32_t (&r0)[4],
+                                       const uint32_t (&r1)[4], uint8_t* a0, uint8_t* a1, int lane) {
+  uint32_t s0[4] = {r0[0] & ~3u, r0[1], r0[2], r0[3]};
+  uint32_t s1[4] = {r1[0] & ~3u, r1[1], r1[2], r1[3]};
+  uint32_t t0 = 0, t1 = 1, Va = 0;
+  uint64_t vbits = 0;
+  st16(a0 + lane * 16, make_uint4(s0[0], s0[1], s0[2], s0[3]));
+  if (a1) st16(a1 + lane * 16, make_uint4(s1[0], s1[1], s1[2], s1[3]));
+  for (int i = 0; i < k; ++i) {
+    const uint32_t ai = (uint32_t)(alpha >> (k - 1 - i)) & 1u;
+    uint32_t in[4][4], o[4][4];
+    const uint32_t jj[4] = {ai, ai ^ 1u, ai, ai ^ 1u};  // p0 keep, p0 lose, p1 keep, p1 lose
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      in[0][c] = s0[c]; in[1][c] = s0[c]; in[2][c] = s1[c]; in[3][c] = s1[c];
+    }
+    prg<TB, 4>(tb, in, jj, o);
+    const uint32_t tk0 = o[0][0] & 1u, tl0 = o[1][0] & 1u, tk1 = o[2][0] & 1u, tl1 = o[3][0] & 1u;
+    const uint32_t vk0 = (o[0][0] >> 1) & 1u, vl0 = (o[1][0] >> 1) & 1u;
+    const uint32_t vk1 = (o[2][0] >> 1) & 1u, vl1 = (o[3][0] >> 1) & 1u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o[q][0] &= ~3u;
+    uint32_t scw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) scw[c] = o[1][c] ^ o[3][c];
+    const uint32_t vcw = vl1 ^ vl0 ^ Va ^ ai;  // + beta (= 1) when the lost child is L
+    Va = Va ^ vk1 ^ vk0 ^ vcw;
+    const uint32_t tkx = tk0 ^ tk1, tlx = tl0 ^ tl1;
+    const uint32_t tL = (ai ? tlx : tkx) ^ ai ^ 1u;
+    const uint32_t tR = (ai ? tkx : tlx) ^ ai;
+    const uint4 cw = make_uint4(scw[0] | tL | (tR << 1), scw[1], scw[2], scw[3]);
+    uint8_t* cwo = a0 + kTile * 16 + ((uint64_t)i * kTile + lane) * 16;
+    st16(cwo, cw);
+    if (a1) st16(a1 + (cwo - a0), cw);
+    vbits |= (uint64_t)vcw << i;
+    const uint32_t tk = ai ? tR : tL;
+    const uint32_t m0 = 0u - t0, m1 = 0u - t1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      s0[c] = o[0][c] ^ (scw[c] & m0);
+      s1[c] = o[2][c] ^ (scw[c] & m1);
+    }
+    t0 = tk0 ^ (t0 & tk);
+    t1 = tk1 ^ (t1 & tk);
+  }
+  const uint32_t fin = ((s0[0] >> 2) & 1u) ^ ((s1[0] >> 2) & 1u) ^ Va;
+  vbits |= (uint64_t)fin << 32;
+  uint8_t* vbo = a0 + (uint64_t)kTile * 16 * (1 + k) + lane * 8;
+  st8(vbo, vbits);
+  if (a1) st8(a1 + (vbo - a0), vbits);
+}
+
+// Vector DCF Gen for f(x) = beta * 1[x < alpha] over n bits, beta in Z^P.
+// Per party, blocks are [keep seed, lose seed, keep values.., lose values..].
+template <int P, class TB>
+__device__ __forceinline__ void gen_vec(const TB& tb, const KeyHeader* h, int n, uint64_t alpha,
+                                        const uint64_t (&beta)[P], const uint32_t (&r0)[4],
+                                        const uint32_t (&r1)[4], uint8_t* k0, uint8_t* k1, int lane) {
+  constexpr int NB = (P + 1) / 2;
+  constexpr int KB = 2 * (1 + NB);  // blocks per party per level
+  uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
+  uint32_t t[2] = {0u, 1u};
+  uint64_t Va[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) Va[q] = 0;
+  st16(k0 + h->off_croot + lane * 16, make_uint4(s[0][0], s[0][1], s[0][2], s[0][3]));
+  if (k1) st16(k1 + h->off_croot + lane * 16, make_uint4(s[1][0], s[1][1], s[1][2], s[1][3]));
+  for (int i = 0; i < n; ++i) {
+    const uint32_t ai = (uint32_t)(alpha >> (n - 1 - i)) & 1u;
+    uint32_t sk[2][4], sl[2][4], tk[2], tl[2];
+    uint64_t vk[2][P], vl[2][P];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      uint32_t in[KB][4], o[KB][4], jj[KB];
+#pragma unroll
+      for (int q = 0; q < KB; ++q) {
+        in[q][0] = s[b][0]; in[q][1] = s[b][1]; in[q][2] = s[b][2]; in[q][3] = s[b][3];
+      }
+      jj[0] = ai;
+      jj[1] = ai ^ 1u;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        jj[2 + q] = 2u + 2u * ai + q;
+        jj[2 + NB + q] = 2u + 2u * (ai ^ 1u) + q;
+      }
+      prg<TB, KB>(tb, in, jj, o);
+      tk[b] = o[0][0] & 1u;
+      tl[b] = o[1][0] & 1u;
+      sk[b][0] = o[0][0] & ~3u; sk[b][1] = o[0][1]; sk[b][2] = o[0][2]; sk[b][3] = o[0][3];
+      sl[b][0] = o[1][0] & ~3u; sl[b][1] = o[1][1]; sl[b][2] = o[1][2]; sl[b][3] = o[1][3];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        vk[b][q] = mk64(o[2 + q / 2][2 * (q & 1)], o[2 + q / 2][2 * (q & 1) + 1]);
+        vl[b][q] = mk64(o[2 + NB + q / 2][2 * (q & 1)], o[2 + NB + q / 2][2 * (q & 1) + 1]);
+      }
+    }
+    uint32_t scw[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) scw[c] = sl[0][c] ^ sl[1][c];
+    const uint64_t neg = 0ull - (uint64_t)t[1];  // (-1)^{t_1} as a mask
+    const uint64_t badd = 0ull - (uint64_t)ai;   // beta enters when the lost child is L
+    uint64_t vcw[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const uint64_t w = vl[1][q] - vl[0][q] - Va[q] + (beta[q] & badd);
+      vcw[q] = (w ^ neg) - neg;
+      Va[q] = Va[q] - vk[1][q] + vk[0][q] + ((vcw[q] ^ neg) - neg);
+    }
+    const uint32_t tkx = tk[0] ^ tk[1], tlx = tl[0] ^ tl[1];
+    const uint32_t tL = (ai ? tlx : tkx) ^ ai ^ 1u;
+    const uint32_t tR = (ai ? tkx : tlx) ^ ai;
+    const uint4 cw = make_uint4(scw[0] | tL | (tR << 1), scw[1], scw[2], scw[3]);
+    const uint64_t cwoff = h->off_ccw + ((uint64_t)i * kTile + lane) * 16;
+    st16(k0 + cwoff, cw);
+    if (k1) st16(k1 + cwoff, cw);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const uint64_t vo = h->off_cvcw + (((uint64_t)i * P + q) * kTile + lane) * 8;
+      st8(k0 + vo, vcw[q]);
+      if (k1) st8(k1 + vo, vcw[q]);
+    }
+    const uint32_t tkc = ai ? tR : tL;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const uint32_t m = 0u - t[b];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) s[b][c] = sk[b][c] ^ (scw[c] & m);
+      t[b] = tk[b] ^ (t[b] & tkc);
+    }
+  }
+  // CW_{n+1} = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha)
+  uint64_t cv[2][P];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    uint32_t in[NB][4], o[NB][4], jj[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      in[q][0] = s[b][0]; in[q][1] = s[b][1]; in[q][2] = s[b][2]; in[q][3] = s[b][3];
+      jj[q] = 6u + q;
+    }
+    prg<TB, NB>(tb, in, jj, o);
+#pragma unroll
+    for (int q = 0; q < P; ++q) cv[b][q] = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
+  }
+  const uint64_t neg = 0ull - (uint64_t)t[1];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const uint64_t w = cv[1][q] - cv[0][q] - Va[q];
+    const uint64_t f = (w ^ neg) - neg;
+    const uint64_t fo = h->off_cfin + ((uint64_t)q * kTile + lane) * 8;
+    st8(k0 + fo, f);
+    if (k1) st8(k1 + fo, f);
+  }
+}
+
+template <int P, class TB>
+__device__ __forceinline__ void keygen_coeff(const TB& tb, const KeyHeader* h, const KgArgs& ga, uint64_t e,
+                                             uint64_t rin, uint8_t* t0, uint8_t* t1, int lane) {
+  uint64_t rho[P];
+  rho[0] = 1;
+#pragma unroll
+  for (int q = 1; q < P; ++q) rho[q] = rho[q - 1] * (0ull - rin);
+  uint32_t c0[4], c1[4];
+  rand_blk(tb, ga.rk, e, 64, 0, c0);
+  rand_blk(tb, ga.rk, e, 65, 0, c1);
+  const int n = (int)h->n;
+  const uint64_t nmask = n >= 64 ? ~0ull : ((1ull << n) - 1);
+  gen_vec<P>(tb, h, n, rin & nmask, rho, c0, c1, t0, t1, lane);
+  uint32_t ra[4], rb[4];
+  rand_blk(tb, ga.rk, e, 67, 0, ra);
+  rand_blk(tb, ga.rk, e, 68, 0, rb);
+  const uint64_t sh[4] = {mk64(ra[0], ra[1]), mk64(ra[2], ra[3]), mk64(rb[0], rb[1]), mk64(rb[2], rb[3])};
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const uint64_t o = h->off_crho + ((uint64_t)q * kTile + lane) * 8;
+    st8(t0 + o, sh[q]);
+    if (t1) st8(t1 + o, rho[q] - sh[q]);
+  }
+}
+
+template <int V>
+__global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* h, KgArgs ga, uint8_t* key0,
+                                                              uint8_t* key1, uint64_t* r_in, uint64_t* r_out) {
+  using TB = typename TabOf<V>::T;
+  __shared__ uint32_t lds[TB::kWords];
+  TB::fill(lds, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (tile >= ga.n_tiles) return;
+  TB tb(lds, lane);
+  const uint64_t e = tile * kTile + lane;
+  const uint64_t tb_bytes = h->tile_bytes;
+  uint8_t* t0 = key0 + kHeaderBytes + tile * tb_bytes;
+  uint8_t* t1 = key1 ? key1 + kHeaderBytes + tile * tb_bytes : nullptr;
+
+  uint32_t r[4];
+  rand_blk(tb, ga.rk, e, 0, 0, r);
+  const uint64_t rin = mk64(r[0], r[1]), rout = mk64(r[2], r[3]);
+  if (e < (uint64_t)ga.n_elems) {
+    if (r_in) r_in[e] = rin;
+    if (r_out) r_out[e] = rout;
+  }
+  rand_blk(tb, ga.rk, e, 1, 0, r);
+  const uint64_t rs = mk64(r[0], r[1]);
+  st8(t0 + h->off_crout + lane * 8, rs);
+  if (t1) st8(t1 + h->off_crout + lane * 8, rout - rs);
+
+  // Packed comparison: theta atoms use theta = (r_k + b') mod 2^k and carry
+  // w = 1[r_k + b' >= 2^k]; mask atoms use alpha = r_k.
+  uint64_t wout = 0;
+  const int T = (int)h->T, np = (int)h->n_prim;
+  for (int t = 0; t < T; ++t) {
+    const int k = (int)h->atom_k[t];
+    const uint64_t msk = k >= 64 ? ~0ull : ((1ull << k) - 1);
+    const uint64_t rk = rin & msk;
+    uint64_t alpha = rk;
+    if (t < np) {
+      const uint64_t sum = rk + ga.bprime[t];
+      alpha = sum & msk;
+      if (sum >> k) wout ^= 1ull << h->atom_out[t];
+    }
+    uint32_t ra[4], rb[4];
+    rand_blk(tb, ga.rk, e, 2 + 2 * t, 0, ra);
+    rand_blk(tb, ga.rk, e, 3 + 2 * t, 0, rb);
+    gen_z2(tb, k, alpha, ra, rb, t0 + h->atom_off[t], t1 ? t1 + h->atom_off[t] : nullptr, lane);
+  }
+  rand_blk(tb, ga.rk, e, 66, 0, r);
+  const uint64_t ellmask = h->ell >= 64 ? ~0ull : ((1ull << h->ell) - 1);
+  const uint64_t W = mk64(r[0], r[1]) & ellmask;
+  st8(t0 + h->off_w + lane * 8, W);
+  if (t1) st8(t1 + h->off_w + lane * 8, W ^ wout);
+
+  switch (h->p) {
+    case 1: keygen_coeff<1>(tb, h, ga, e, rin, t0, t1, lane); break;
+    case 2: keygen_coeff<2>(tb, h, ga, e, rin, t0, t1, lane); break;
+    case 3: keygen_coeff<3>(tb, h, ga, e, rin, t0, t1, lane); break;
+    default: keygen_coeff<4>(tb, h, ga, e, rin, t0, t1, lane); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers of one table layout (explicitly instantiated per translation unit)
+// ---------------------------------------------------------------------------
+template <int V>
+int VariantOps<V>::block() { return TabOf<V>::kBlock; }
+
+template <int V>
+int VariantOps<V>::lds_bytes() { return TabOf<V>::T::kWords * 4; }
+
+template <int V>
+hipError_t VariantOps<V>::keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
+                                 uint64_t* ri, uint64_t* ro, hipStream_t st) {
+  constexpr int B = kKeygenBlock;
+  const uint64_t per = B / 64;
+  const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_keygen<V>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro);
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t VariantOps<V>::pred(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* z,
+                               int* status, hipStream_t st) {
+  constexpr int B = TabOf<V>::kBlock;
+  const uint64_t tiles = ((uint64_t)n + 63) / 64, per = B / 64;
+  const unsigned grid = (unsigned)((tiles + per - 1) / per);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_eval_pred<V>), dim3(grid), dim3(B), 0, st, keys, xhat, n, z, party, status);
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t VariantOps<V>::coeff(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* y,
+                                int* status, hipStream_t st) {
+  constexpr int B = TabOf<V>::kBlock;
+  const uint64_t tiles = ((uint64_t)n + 63) / 64, per = B / 64;
+  const unsigned grid = (unsigned)((tiles + per - 1) / per);
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_eval_coeff<V>), dim3(grid), dim3(B), 0, st, keys, xhat, n, y, party, status);
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t VariantOps<V>::fused(const DevItem* items, const uint32_t* tiles, uint32_t n_tiles,
+                                uint32_t* counter, int* status, int grid, hipStream_t st) {
+  constexpr int B = TabOf<V>::kBlock;
+  if (grid <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_fused<V>), dim3(grid), dim3(B), 0, st, items, tiles, n_tiles, counter, status);
+  return hipGetLastError();
+}
+
+}  // namespace fss

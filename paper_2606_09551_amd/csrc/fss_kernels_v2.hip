@@ -1,0 +1,6 @@
+// Instantiates the kernels for AES table layout 2.
+#include "fss_kernels_impl.hpp"
+
+namespace fss {
+template struct VariantOps<2>;
+}

@@ -1,0 +1,114 @@
+// fss_launch.hip -- layout-independent kernels and the dispatch from an AES
+// table-layout index to its launchers.
+#include <hip/hip_runtime.h>
+
+#include "fss_kernels.hpp"
+
+namespace fss {
+
+// Copy the cached per-spec header into a key buffer, stamping size and party.
+__global__ void k_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
+                              uint32_t party) {
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  for (uint32_t i = threadIdx.x; i < sizeof(KeyHeader) / 4; i += blockDim.x) d[i] = s[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    KeyHeader* h = reinterpret_cast<KeyHeader*>(dst);
+    h->party = party;
+    h->n_elems = (uint64_t)n_elems;
+    h->n_tiles = n_tiles;
+  }
+}
+
+// Masked opening collapsed to one process: xhat = x + r_in mod 2^64.
+__global__ void k_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) xhat[i] = (uint64_t)x[i] + r_in[i];
+}
+
+// Work counters are cleared by a kernel rather than a memset node so a
+// captured graph replays correctly.
+__global__ void k_reset_counter(uint32_t* counter) {
+  if (threadIdx.x == 0) *counter = 0;
+}
+
+hipError_t launch_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
+                              uint32_t party, hipStream_t st) {
+  hipLaunchKernelGGL(k_header_init, dim3(1), dim3(256), 0, st, dst, src, n_elems, n_tiles, party);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_mask, dim3(grid), dim3(256), 0, st, x, r_in, n, xhat);
+  return hipGetLastError();
+}
+
+hipError_t launch_keygen(int v, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
+                         uint64_t* ro, hipStream_t st) {
+  switch (v) {
+    case 0: return VariantOps<0>::keygen(h, ga, k0, k1, ri, ro, st);
+    case 1: return VariantOps<1>::keygen(h, ga, k0, k1, ri, ro, st);
+    case 2: return VariantOps<2>::keygen(h, ga, k0, k1, ri, ro, st);
+    case 3: return VariantOps<3>::keygen(h, ga, k0, k1, ri, ro, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_eval_pred(int v, int party, const uint8_t* keys, const uint64_t* xhat, int64_t n,
+                            uint64_t* z, int* status, hipStream_t st) {
+  switch (v) {
+    case 0: return VariantOps<0>::pred(party, keys, xhat, n, z, status, st);
+    case 1: return VariantOps<1>::pred(party, keys, xhat, n, z, status, st);
+    case 2: return VariantOps<2>::pred(party, keys, xhat, n, z, status, st);
+    case 3: return VariantOps<3>::pred(party, keys, xhat, n, z, status, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_eval_coeff(int v, int party, const uint8_t* keys, const uint64_t* xhat, int64_t n,
+                             uint64_t* y, int* status, hipStream_t st) {
+  switch (v) {
+    case 0: return VariantOps<0>::coeff(party, keys, xhat, n, y, status, st);
+    case 1: return VariantOps<1>::coeff(party, keys, xhat, n, y, status, st);
+    case 2: return VariantOps<2>::coeff(party, keys, xhat, n, y, status, st);
+    case 3: return VariantOps<3>::coeff(party, keys, xhat, n, y, status, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fused(int v, const DevItem* items, const uint32_t* tiles, uint32_t n_tiles, uint32_t* counter,
+                        int* status, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (v) {
+    case 0: return VariantOps<0>::fused(items, tiles, n_tiles, counter, status, grid, st);
+    case 1: return VariantOps<1>::fused(items, tiles, n_tiles, counter, status, grid, st);
+    case 2: return VariantOps<2>::fused(items, tiles, n_tiles, counter, status, grid, st);
+    case 3: return VariantOps<3>::fused(items, tiles, n_tiles, counter, status, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int variant_block(int v) {
+  switch (v) {
+    case 0: return VariantOps<0>::block();
+    case 1: return VariantOps<1>::block();
+    case 2: return VariantOps<2>::block();
+    default: return VariantOps<3>::block();
+  }
+}
+
+int variant_lds_bytes(int v) {
+  switch (v) {
+    case 0: return VariantOps<0>::lds_bytes();
+    case 1: return VariantOps<1>::lds_bytes();
+    case 2: return VariantOps<2>::lds_bytes();
+    default: return VariantOps<3>::lds_bytes();
+  }
+}
+
+}  // namespace fss

@@ -1,0 +1,284 @@
+"""ctypes binding of libfusefss (include/fusefss.h), same names as the C ABI.
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device buffers are passed as integer addresses (for example
+``tensor.data_ptr()``) and streams as ``torch.cuda.current_stream().cuda_stream``.
+Importing this module loads the native library and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfusefss.so")
+
+FSS_OK = 0
+ERRORS = {-1: "FSS_E_INVALID_SPEC", -2: "FSS_E_UNSUPPORTED", -3: "FSS_E_NEEDS_PHI",
+          -4: "FSS_E_SHAPE", -5: "FSS_E_PARTY", -6: "FSS_E_HIP", -7: "FSS_E_OOM", -8: "FSS_E_ARG"}
+MAX_ATOMS = 16
+
+PRED_LT_SIGNED, PRED_LT_UNSIGNED, PRED_LOWBITS_LT, PRED_MSB_SHIFT = 0, 1, 2, 3
+COMBINE_XOR, COMBINE_AND, COMBINE_OR = 0, 1, 2
+
+
+class FssError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Interval(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double)]
+
+
+class Piece(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("coef", C.c_double * 4)]
+
+
+class Pred(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("negate", C.c_int32), ("out", C.c_int32),
+                ("combine", C.c_int32), ("f_bits", C.c_int32), ("reserved", C.c_int32),
+                ("thr", C.c_double), ("gamma", C.c_int64), ("c", C.c_int64)]
+
+
+class SpecInfo(C.Structure):
+    _fields_ = [("n_bits", C.c_int32), ("frac_bits", C.c_int32), ("m", C.c_int32),
+                ("degree", C.c_int32), ("p", C.c_int32), ("out_frac_bits", C.c_int32),
+                ("T", C.c_int32), ("ell", C.c_int32), ("atom_k", C.c_int32 * MAX_ATOMS),
+                ("atom_c", C.c_int64 * MAX_ATOMS), ("atom_is_mask", C.c_int32 * MAX_ATOMS)]
+
+
+class WorkItem(C.Structure):
+    _fields_ = [("party", C.c_int32), ("reserved", C.c_int32), ("keys", C.c_void_p),
+                ("xhat", C.c_void_p), ("y", C.c_void_p), ("zbits", C.c_void_p),
+                ("n_elems", C.c_int64)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("aes_variant", C.c_int32), ("order", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                          "(the HIP library is required; there is no fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    sig = {
+        "fss_compile_spec": [C.POINTER(Interval), i32, C.POINTER(Piece), C.POINTER(Pred), i32, i32,
+                             C.POINTER(vp)],
+        "fss_spec_free": [vp],
+        "fss_spec_query": [vp, i32, i32, C.POINTER(SpecInfo), vp, vp],
+        "fss_key_bytes": [vp, i32, i32, i64, C.POINTER(C.c_size_t)],
+        "fss_keygen": [vp, i32, i32, u64, i64, vp, vp, vp, vp, vp],
+        "fss_mask_input": [vp, vp, i64, vp, vp],
+        "fss_eval": [i32, vp, vp, i64, vp, vp, vp],
+        "fss_eval_pred": [i32, vp, vp, i64, vp, vp],
+        "fss_eval_coeff": [i32, vp, vp, i64, vp, vp],
+        "fss_plan_create": [C.POINTER(WorkItem), i32, C.POINTER(Tune), C.POINTER(vp)],
+        "fss_plan_launch": [vp, vp],
+        "fss_plan_free": [vp],
+        "fss_plan_aes_blocks": [vp],
+        "fss_plan_config": [vp, C.POINTER(Tune), C.POINTER(i32)],
+        "fss_graph_capture": [C.POINTER(vp), i32, C.POINTER(vp)],
+        "fss_graph_launch": [vp, vp],
+        "fss_graph_free": [vp],
+        "fss_autotune": [C.POINTER(WorkItem), i32, C.c_char_p, C.POINTER(Tune)],
+        "fss_aes_variants": [],
+        "fss_status": [vp, C.POINTER(i32)],
+        "fss_last_error": [],
+        "fss_version": [],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.fss_spec_free.restype = None
+    L.fss_plan_aes_blocks.restype = C.c_double
+    L.fss_last_error.restype = C.c_char_p
+    L.fss_version.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != FSS_OK:
+        raise FssError(rc, lib.fss_last_error().decode(errors="replace"))
+
+
+def _p(x) -> int | None:
+    """Device address of a tensor (or an int address / None)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        try:
+            import torch
+            return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            return None
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+# ---------------------------------------------------------------------------
+
+class Spec:
+    """An operator specification compiled by the library (fss_compile_spec)."""
+
+    def __init__(self, desc):
+        m = len(desc.intervals)
+        iv = (Interval * m)(*[Interval(lo, hi) for lo, hi in desc.intervals])
+        pcs = (Piece * m)()
+        for i, coefs in enumerate(desc.pieces):
+            pcs[i].degree = len(coefs) - 1
+            for l, c in enumerate(coefs[:4]):
+                pcs[i].coef[l] = c
+        np_ = len(desc.preds)
+        prs = (Pred * max(np_, 1))()
+        for j, q in enumerate(desc.preds):
+            prs[j] = Pred(q.kind, int(q.negate), q.out, getattr(q, "combine", 0), q.f_bits, 0,
+                          q.thr, q.gamma, q.c)
+        h = C.c_void_p()
+        _check(lib.fss_compile_spec(iv, m, pcs, prs if np_ else None, np_, desc.out_frac_bits,
+                                    C.byref(h)))
+        self.handle = h
+        self.name = desc.name
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.fss_spec_free(h)
+            self.handle = None
+
+    def query(self, n_bits: int, frac_bits: int) -> dict:
+        info = SpecInfo()
+        _check(lib.fss_spec_query(self.handle, n_bits, frac_bits, C.byref(info), None, None))
+        m, p = info.m, info.p
+        ap = (C.c_uint64 * (m + 1))()
+        co = (C.c_uint64 * (m * p))()
+        _check(lib.fss_spec_query(self.handle, n_bits, frac_bits, None, ap, co))
+        return {"n": info.n_bits, "f": info.frac_bits, "m": m, "d": info.degree, "p": p,
+                "F_out": info.out_frac_bits, "T": info.T, "ell": info.ell,
+                "atom_k": list(info.atom_k[:info.T]), "atom_c": list(info.atom_c[:info.T]),
+                "atom_is_mask": list(info.atom_is_mask[:info.T]),
+                "aprime": list(ap), "coef": [[co[i * p + l] for l in range(p)] for i in range(m)]}
+
+    def key_bytes(self, n_bits: int, frac_bits: int, n_elems: int) -> int:
+        out = C.c_size_t()
+        _check(lib.fss_key_bytes(self.handle, n_bits, frac_bits, n_elems, C.byref(out)))
+        return out.value
+
+
+def fss_keygen(spec: Spec, n_bits, frac_bits, seed, n_elems, key0, key1, r_in, r_out, stream=None):
+    _check(lib.fss_keygen(spec.handle, n_bits, frac_bits, seed & (2**64 - 1), n_elems, _p(key0),
+                          _p(key1), _p(r_in), _p(r_out), _stream(stream)))
+
+
+def fss_mask_input(x, r_in, n, xhat, stream=None):
+    _check(lib.fss_mask_input(_p(x), _p(r_in), n, _p(xhat), _stream(stream)))
+
+
+def fss_eval(party, keys, xhat, n, y, zbits, stream=None):
+    _check(lib.fss_eval(party, _p(keys), _p(xhat), n, _p(y), _p(zbits), _stream(stream)))
+
+
+def fss_eval_pred(party, keys, xhat, n, zbits, stream=None):
+    _check(lib.fss_eval_pred(party, _p(keys), _p(xhat), n, _p(zbits), _stream(stream)))
+
+
+def fss_eval_coeff(party, keys, xhat, n, y, stream=None):
+    _check(lib.fss_eval_coeff(party, _p(keys), _p(xhat), n, _p(y), _stream(stream)))
+
+
+def fss_status(stream=None) -> int:
+    code = C.c_int32()
+    _check(lib.fss_status(_stream(stream), C.byref(code)))
+    return code.value
+
+
+def work_items(items) -> C.Array:
+    """items: iterable of (party, keys, xhat, y, zbits, n_elems) with tensors or addresses."""
+    items = list(items)
+    arr = (WorkItem * max(len(items), 1))()
+    for i, (party, keys, xhat, y, z, n) in enumerate(items):
+        arr[i] = WorkItem(party, 0, _p(keys), _p(xhat), _p(y), _p(z), n)
+    return arr, len(items)
+
+
+class Plan:
+    """fss_plan: a work-list evaluated by one persistent fused launch."""
+
+    def __init__(self, items, tune: Tune | None = None):
+        arr, n = work_items(items)
+        h = C.c_void_p()
+        _check(lib.fss_plan_create(arr, n, C.byref(tune) if tune is not None else None, C.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib.fss_plan_launch(self.handle, _stream(stream)))
+
+    def aes_blocks(self) -> float:
+        return lib.fss_plan_aes_blocks(self.handle)
+
+    def config(self) -> dict:
+        t, g = Tune(), C.c_int32()
+        _check(lib.fss_plan_config(self.handle, C.byref(t), C.byref(g)))
+        return {"aes_variant": t.aes_variant, "block_threads": t.block_threads,
+                "blocks_per_cu": t.blocks_per_cu, "order": t.order, "grid": g.value}
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            lib.fss_plan_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None:
+            self.free()
+
+
+class Graph:
+    """fss_graph: the launches of several plans captured into one HIP graph."""
+
+    def __init__(self, plans):
+        plans = list(plans)
+        arr = (C.c_void_p * max(len(plans), 1))(*[p.handle.value for p in plans])
+        h = C.c_void_p()
+        _check(lib.fss_graph_capture(arr, len(plans), C.byref(h)))
+        self.handle = h
+        self._plans = plans
+
+    def launch(self, stream=None):
+        _check(lib.fss_graph_launch(self.handle, _stream(stream)))
+
+    def free(self):
+        if self.handle is not None and self.handle.value:
+            lib.fss_graph_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None:
+            self.free()
+
+
+def fss_autotune(items, cache_path: str | None = None) -> Tune:
+    arr, n = work_items(items)
+    best = Tune()
+    _check(lib.fss_autotune(arr, n, cache_path.encode() if cache_path else None, C.byref(best)))
+    return best
+
+
+def aes_variants() -> int:
+    return lib.fss_aes_variants()
+
+
+def version() -> str:
+    return lib.fss_version().decode()

@@ -1,0 +1,83 @@
+"""Decoder of the library's key-buffer format, written from its documentation
+(header struct and tile layout in paper_2606_09551_amd/csrc/fss_common.hpp),
+so tests can compare GPU-generated keys with the oracle's field by field."""
+import numpy as np
+
+HEADER_BYTES = 16384
+TILE = 64
+MAXA, MAXM, MAXP = 16, 64, 4
+
+HDR = np.dtype([
+    ("magic", "<u4"), ("version", "<u4"), ("party", "<u4"), ("layout", "<u4"),
+    ("n", "<u4"), ("f", "<u4"), ("m", "<u4"), ("d", "<u4"), ("p", "<u4"), ("T", "<u4"),
+    ("ell", "<u4"), ("F_out", "<u4"), ("n_prim", "<u4"), ("n_views", "<u4"), ("kmax", "<u4"),
+    ("pad0", "<u4"), ("n_elems", "<u8"), ("n_tiles", "<u8"), ("tile_bytes", "<u8"),
+    ("spec_hash", "<u8"), ("negate", "<u8"), ("atom_k", "<u4", MAXA), ("atom_out", "<u4", MAXA),
+    ("atom_rview", "<u4", MAXA), ("atom_c", "<u8", MAXA), ("atom_off", "<u8", MAXA),
+    ("off_w", "<u8"), ("off_croot", "<u8"), ("off_ccw", "<u8"), ("off_cvcw", "<u8"),
+    ("off_cfin", "<u8"), ("off_crho", "<u8"), ("off_crout", "<u8"),
+    ("aprime", "<u8", MAXM + 1), ("tab", "<u8", (MAXM, MAXP, MAXP)),
+])
+
+
+def header(buf: np.ndarray):
+    return np.frombuffer(buf[: HDR.itemsize].tobytes(), dtype=HDR)[0]
+
+
+class KeyView:
+    def __init__(self, buf: np.ndarray):
+        self.buf = buf
+        self.h = header(buf)
+
+    def _u64(self, off: int) -> int:
+        return int(np.frombuffer(self.buf[off:off + 8].tobytes(), dtype="<u8")[0])
+
+    def _blk(self, off: int):
+        return self._u64(off), self._u64(off + 8)
+
+    def tile_base(self, e: int) -> int:
+        return HEADER_BYTES + (e // TILE) * int(self.h["tile_bytes"])
+
+    def atom(self, e: int, t: int) -> dict:
+        lane, k = e % TILE, int(self.h["atom_k"][t])
+        base = self.tile_base(e) + int(self.h["atom_off"][t])
+        root = self._blk(base + lane * 16)
+        cws = [self._blk(base + TILE * 16 + (i * TILE + lane) * 16) for i in range(k)]
+        vb = self._u64(base + TILE * 16 * (1 + k) + lane * 8)
+        return {"root": root, "scw": [(lo & ~3, hi) for lo, hi in cws],
+                "tl": [lo & 1 for lo, _ in cws], "tr": [(lo >> 1) & 1 for lo, _ in cws],
+                "vcw": [(vb >> i) & 1 for i in range(k)], "fin": (vb >> 32) & 1}
+
+    def coeff(self, e: int) -> dict:
+        h, lane = self.h, e % TILE
+        n, p = int(h["n"]), int(h["p"])
+        tb = self.tile_base(e)
+        root = self._blk(tb + int(h["off_croot"]) + lane * 16)
+        cws = [self._blk(tb + int(h["off_ccw"]) + (i * TILE + lane) * 16) for i in range(n)]
+        vcw = [[self._u64(tb + int(h["off_cvcw"]) + ((i * p + q) * TILE + lane) * 8) for q in range(p)]
+               for i in range(n)]
+        fin = [self._u64(tb + int(h["off_cfin"]) + (q * TILE + lane) * 8) for q in range(p)]
+        rho = [self._u64(tb + int(h["off_crho"]) + (q * TILE + lane) * 8) for q in range(p)]
+        rout = self._u64(tb + int(h["off_crout"]) + lane * 8)
+        w = self._u64(tb + int(h["off_w"]) + lane * 8)
+        return {"root": root, "scw": [(lo & ~3, hi) for lo, hi in cws],
+                "tl": [lo & 1 for lo, _ in cws], "tr": [(lo >> 1) & 1 for lo, _ in cws],
+                "vcw": vcw, "fin": fin, "rho": rho, "rout": rout, "wshare": w}
+
+
+def oracle_atom(K, t: int) -> dict:
+    a = K.atom[t]
+    k = a.n
+    return {"root": (a.root.lo, a.root.hi), "scw": [(a.scw[i].lo, a.scw[i].hi) for i in range(k)],
+            "tl": [a.tl[i] for i in range(k)], "tr": [a.tr[i] for i in range(k)],
+            "vcw": [int(a.vcw[i][0]) for i in range(k)], "fin": int(a.fin[0])}
+
+
+def oracle_coeff(K) -> dict:
+    c = K.coeff
+    n, p = c.n, c.p
+    return {"root": (c.root.lo, c.root.hi), "scw": [(c.scw[i].lo, c.scw[i].hi) for i in range(n)],
+            "tl": [c.tl[i] for i in range(n)], "tr": [c.tr[i] for i in range(n)],
+            "vcw": [[int(c.vcw[i][q]) for q in range(p)] for i in range(n)],
+            "fin": [int(c.fin[q]) for q in range(p)], "rho": [int(K.rho[q]) for q in range(p)],
+            "rout": int(K.rout), "wshare": int(K.wshare)}

@@ -1,0 +1,125 @@
+"""Host-side checks of the C-ABI library (CPU only: no kernel is launched).
+
+The shared library must load, export every function include/fusefss.h
+declares, quantise specs to exactly the oracle's integer tables (two
+independent implementations of the same rules), reject invalid specs with
+the documented codes, and size keys independently of masks.
+"""
+import math
+import os
+import re
+
+import pytest
+
+import oracle as O
+from paper_2606_09551_amd import fss as F
+from paper_2606_09551_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            src = open(os.path.join(inc, fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\*?\s*(fss_\w+)\s*\(", src, flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(F.lib, n), n
+    assert "gfx950" in F.version()
+
+
+SPECS = [(W.clip_relu_spec(), 16, 8), (W.gelu_spec(), 24, 12), (W.exp_spec(), 24, 12),
+         (W.recip_spec(7), 24, 12), (W.recip_spec(9), 24, 12), (W.rsqrt_spec(), 24, 12),
+         (W.relu_worked_example_spec(), 10, 0), (W.gelu_spec(f=5), 10, 5)]
+
+
+@pytest.mark.parametrize("desc,n,f", SPECS, ids=lambda v: getattr(v, "name", str(v)))
+def test_quantised_tables_match_oracle(desc, n, f):
+    lib_t = F.Spec(desc).query(n, f)
+    orc = O.spec_tables(O.compile_spec(desc, n, f))
+    for k in ("m", "d", "p", "F_out", "T", "ell", "aprime", "coef"):
+        assert lib_t[k] == orc[k], k
+    atoms = [(k, c % 2**64, msk) for k, c, msk in zip(lib_t["atom_k"], lib_t["atom_c"], lib_t["atom_is_mask"])]
+    assert atoms == [(a[0], a[1], a[2]) for a in orc["atoms"]]
+
+
+def test_mixed_predicates_match_oracle():
+    P = W.PredDesc
+    preds = [P(W.LT_SIGNED, 0, thr=-1.0), P(W.LT_SIGNED, 0, thr=2.5), P(W.LT_UNSIGNED, 1, thr=5.0),
+             P(W.LOWBITS_LT, 2, f_bits=3, gamma=5, negate=True), P(W.MSB_SHIFT, 3, c=37),
+             P(W.LT_SIGNED, 4, thr=-math.inf), P(W.LOWBITS_LT, 5, f_bits=2, gamma=4)]
+    desc = W.SpecDesc("mixed", [(-math.inf, 0.5), (0.5, math.inf)], [[1.0, 2.0, 0.5, 0.25], [0.0]], preds)
+    lib_t = F.Spec(desc).query(12, 4)
+    orc = O.spec_tables(O.compile_spec(desc, 12, 4))
+    assert lib_t["T"] == orc["T"] and lib_t["ell"] == orc["ell"] and lib_t["coef"] == orc["coef"]
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(intervals=[(0.0, 1.0), (1.0, math.inf)], pieces=[[0.0], [0.0]]), -1),
+    (dict(intervals=[(-math.inf, 0.0), (0.5, math.inf)], pieces=[[0.0], [0.0]]), -1),
+    (dict(intervals=[(-math.inf, math.inf)], pieces=[[0.0, 0, 0, 0, 1.0]]), -1),
+])
+def test_compile_rejects_invalid(bad, code):
+    with pytest.raises(F.FssError) as e:
+        F.Spec(W.SpecDesc("bad", bad["intervals"], bad["pieces"]))
+    assert e.value.code == code
+
+
+def test_quantisation_errors_reported():
+    desc = W.SpecDesc("coll", [(-math.inf, 0.001), (0.001, 0.002), (0.002, math.inf)], [[0.0]] * 3)
+    s = F.Spec(desc)
+    with pytest.raises(F.FssError) as e:
+        s.query(16, 8)
+    assert e.value.code == -1
+    with pytest.raises(F.FssError) as e:
+        F.Spec(W.clip_relu_spec()).query(33, 8)
+    assert e.value.code == -2
+    big = W.SpecDesc("big", [(-math.inf, math.inf)], [[0.0, 0.0, 0.0, 1e6]])
+    with pytest.raises(F.FssError) as e:
+        F.Spec(big).query(16, 8)
+    assert e.value.code == -1
+
+
+def test_and_or_need_postprocessing():
+    desc = W.SpecDesc("andp", [(-math.inf, math.inf)], [[0.0]], [W.PredDesc(W.LT_SIGNED, 0, thr=1.0)])
+    desc.preds[0].__class__  # frozen dataclass; build one with combine = AND
+    from dataclasses import dataclass
+
+    @dataclass(frozen=True)
+    class PC(W.PredDesc):
+        combine: int = 1
+
+    desc.preds = [PC(W.LT_SIGNED, 0, thr=1.0)]
+    with pytest.raises(F.FssError) as e:
+        F.Spec(desc)
+    assert e.value.code == -3
+
+
+def test_key_bytes_shape():
+    """Key size is a function of (spec, n, f, N) only; tiles of 64 elements."""
+    s = F.Spec(W.gelu_spec())
+    per_tile = s.key_bytes(24, 12, 64) - s.key_bytes(24, 12, 0)
+    assert per_tile % 256 == 0
+    for N in (1, 63, 64, 65, 393216):
+        assert s.key_bytes(24, 12, N) == 16384 + ((N + 63) // 64) * per_tile
+    # 3 Z_2 atoms of 24 levels, one 24-level vector DCF with p = 3, shares
+    expect = 3 * (64 * 16 * 25 + 64 * 8) + 64 * 8 + 64 * 16 * 25 + 24 * 3 * 64 * 8 + 2 * 3 * 64 * 8 + 64 * 8
+    assert per_tile == (expect + 255) // 256 * 256
+    c = F.Spec(W.clip_relu_spec())
+    assert (c.key_bytes(16, 8, 4096) - 16384) // 4096 == pytest.approx(1416, abs=16)
+
+
+def test_argument_errors():
+    s = F.Spec(W.clip_relu_spec())
+    with pytest.raises(F.FssError) as e:
+        s.key_bytes(16, 8, -1)
+    assert e.value.code == -8
