@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the FSS hot path on one MI355X.
+
+Default workload: the GELU operator over one BERT-base FFN activation
+(128 x 3072 elements, 24-bit inputs with 12 fractional bits, 16 degree-2
+intervals on [-6, 6) plus two tails, outputs in Z_2^64).  One step is one
+pass of the whole hot path over the batch:
+    dealer key generation for both parties (fresh one-time keys every step)
+    -> masked opening xhat = x + r_in
+    -> both parties' evaluation of both FSS calls and the local combination.
+`value` counts element-evals (one party x one element x both calls) per second
+of the timed steps.  The plain evaluator (two launches per party) is timed on
+the same inputs for comparison.
+
+Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "element-evals/sec (GELU spec, Z_2^64) + p50/p99 latency, fused vs plain"
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz of 32-bit integer VALU issue.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# Algorithmic 32-bit integer ops of one T-table AES-128 block: 10 rounds x
+# (16 table-index extractions + 8 three-input XORs) + 16 for whitening,
+# last-round byte merge and the Matyas-Meyer-Oseas feed-forward.
+OPS_PER_AES = 256
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return 0.0
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def keygen_aes_per_elem(inst) -> int:
+    nb = (inst.p + 1) // 2
+    prg = sum(4 * k for k in inst.atom_k) + 2 * inst.n_bits * (2 + 2 * nb) + 2 * nb
+    rand = 2 * inst.T + 7
+    return prg + rand
+
+
+def cpu_baseline(op, n_bits, f_bits, seconds: float) -> dict:
+    """The oracle (keygen + both parties' evaluation) on a bounded sample."""
+    import numpy as np
+
+    import oracle as O
+
+    S = O.compile_spec(op.spec, n_bits, f_bits)
+    threads = O.hw_threads()
+    cal = max(2 * threads, 16)
+    t0 = time.perf_counter()
+    O.full(S, op.seed, np.arange(cal, dtype=np.int64), op.x[:cal])
+    per = (time.perf_counter() - t0) / cal
+    count = int(min(len(op.x), max(cal, seconds / max(per, 1e-9))))
+    elems = np.arange(count, dtype=np.int64)
+    t0 = time.perf_counter()
+    *_, used = O.full(S, op.seed, elems, op.x[:count])
+    dt = time.perf_counter() - t0
+    return {"value": round(2 * count / dt, 3), "unit": "element-evals/s", "cores": int(used),
+            "kind": "oracle",
+            "sample": f"first {count} of {len(op.x)} elements: dealer keygen + both parties' "
+                      f"evaluation, {dt:.1f} s wall on {used} threads"}
+
+
+def build_ops(workload: str):
+    from paper_2606_09551_amd import workloads as W
+
+    if workload == "c1":
+        return W.config1(), 16, 8, "clip_relu_4096"
+    if workload == "c2":
+        return W.config2(), W.N_BITS, W.F_BITS, "gelu_bert_base_ffn_128x3072"
+    if workload == "c3":
+        return W.config3(), W.N_BITS, W.F_BITS, "softmax_exp_12x128x128_recip_12x128"
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one copy kernel of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build evaluates on one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by element range across GPUs, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_09551_amd import fss as F
+    from paper_2606_09551_amd import runtime as R
+
+    torch.cuda.set_device(0)
+    ops, n_bits, f_bits, wname = build_ops(args.workload)
+    insts = []
+    for op in ops:
+        inst = R.OpInstanceGPU(F.Spec(op.spec), n_bits, f_bits, len(op.x))
+        inst.set_input(op.x)
+        insts.append(inst)
+    n_elems = sum(i.n for i in insts)
+    stream = torch.cuda.current_stream()
+    plan = F.Plan([inst.item(b) for inst in insts for b in (0, 1)])
+    cfg = plan.config()
+    eval_aes = plan.aes_blocks()
+    kg_aes = sum(keygen_aes_per_elem(i) * i.n for i in insts)
+
+    def step(k: int, fused: bool, ev):
+        base = 0xB3C4 + 7919 * k
+        ev[0].record(stream)
+        for j, (inst, op) in enumerate(zip(insts, ops)):
+            inst.keygen((op.seed ^ base) + j)
+            inst.mask()
+        ev[1].record(stream)
+        if fused:
+            plan.launch()
+        else:
+            for inst in insts:
+                inst.eval_plain(0)
+                inst.eval_plain(1)
+        ev[2].record(stream)
+
+    def run(fused: bool):
+        for k in range(args.warmup):
+            step(k, fused, [torch.cuda.Event(enable_timing=True) for _ in range(3)])
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(args.warmup + k, fused, evs[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        code = F.fss_status()
+        if code != 0:
+            raise SystemExit(f"device status {code}")
+        kg = [e[0].elapsed_time(e[1]) for e in evs]
+        ev = [e[1].elapsed_time(e[2]) for e in evs]
+        lat = [e[0].elapsed_time(e[2]) for e in evs]
+        return {"wall_s": wall, "keygen_ms": statistics.mean(kg), "eval_ms": statistics.mean(ev),
+                "lat": lat}
+
+    fused = run(True)
+    plain = None if args.no_plain else run(False)
+
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 0, out=dst)
+        torch.cuda.synchronize()
+
+    evals = 2 * n_elems
+    value = evals * args.steps / fused["wall_s"]
+    eval_s = fused["eval_ms"] / 1e3
+    achieved = eval_aes * OPS_PER_AES / eval_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "element-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fused["wall_s"] * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wname, "elements": n_elems, "parties": 2, "n_bits": n_bits,
+                   "frac_bits": f_bits, "path": "fused persistent work-list",
+                   "step": "keygen (both parties) + masked opening + eval (both parties)",
+                   "launch": cfg},
+        "latency_ms": {"p50": round(pct(fused["lat"], 0.5), 4), "p99": round(pct(fused["lat"], 0.99), 4)},
+        "breakdown_ms": {"keygen": round(fused["keygen_ms"], 4), "eval": round(fused["eval_ms"], 4)},
+        "aes_blocks_per_s": round((eval_aes + kg_aes) * args.steps / fused["wall_s"], 1),
+        "eval_only_element_evals_per_s": round(evals / eval_s, 1),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+                     "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": "k_fused", "ops_per_aes_block": OPS_PER_AES,
+                     "aes_blocks_per_launch": eval_aes},
+    }
+    if plain is not None:
+        out["plain"] = {"value": round(evals * args.steps / plain["wall_s"], 1),
+                        "ms_per_step": round(plain["wall_s"] * 1e3 / args.steps, 4),
+                        "latency_ms": {"p50": round(pct(plain["lat"], 0.5), 4),
+                                       "p99": round(pct(plain["lat"], 0.99), 4)},
+                        "eval_ms": round(plain["eval_ms"], 4)}
+        out["fused_over_plain"] = round(out["value"] / out["plain"]["value"], 4)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ops[0], n_bits, f_bits, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

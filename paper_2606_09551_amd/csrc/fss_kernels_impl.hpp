@@ -40,6 +40,9 @@ __device__ __forceinline__ void set_status(int* st, int code) { atomicCAS(st, 0,
 // ---------------------------------------------------------------------------
 // Byte-permute selector placing byte B of src0 at result byte 1 and keeping
 // bytes 0 and 2 of src1 (lane offset, table bank): one v_perm per address.
+// v_perm_b32 numbers the bytes of {src0, src1} with src1 as bytes 0..3, so the
+// result is (lane offset) | (table byte << 8) | (bank << 16): byte 0 < 128,
+// byte 2 in {0, 1}, byte 3 = 0, which keeps every address inside the table.
 template <int B>
 __device__ __forceinline__ uint32_t lane_addr(uint32_t w, uint32_t base) {
   constexpr uint32_t sel = (0x0cu << 24) | (0x02u << 16) | ((4u + B) << 8) | 0x00u;
@@ -71,7 +74,7 @@ struct Tab1 {
         base01((uint32_t)(lane & 31) * 4u), base23(((uint32_t)(lane & 31) * 4u) | 0x10000u) {}
   template <int TBL, int B>
   __device__ __forceinline__ uint32_t get(uint32_t w) const {
-    uint32_t a = lane_addr<B>(w, TBL < 2 ? base01 : base23) & 0x1ff7cu;  // < 128 KB - 131
+    const uint32_t a = lane_addr<B>(w, TBL < 2 ? base01 : base23);
     return *reinterpret_cast<const uint32_t*>(lds + a + (TBL & 1) * 128);
   }
   __device__ static void fill(uint32_t* lds, int tid, int nthr) {
@@ -92,7 +95,7 @@ struct Tab2 {
       : lds(reinterpret_cast<const uint8_t*>(l)), base((uint32_t)(lane & 31) * 4u) {}
   template <int TBL, int B>
   __device__ __forceinline__ uint32_t get(uint32_t w) const {
-    uint32_t a = lane_addr<B>(w, base) & 0xff7cu;  // < 64 KB - 131
+    const uint32_t a = lane_addr<B>(w, base);
     uint32_t v = *reinterpret_cast<const uint32_t*>(lds + a + (TBL >= 2 ? 128 : 0));
     return rotl8n(v, 8 * (TBL & 1));
   }
@@ -113,7 +116,7 @@ struct Tab3 {
       : lds(reinterpret_cast<const uint8_t*>(l)), base((uint32_t)(lane & 63) * 4u) {}
   template <int TBL, int B>
   __device__ __forceinline__ uint32_t get(uint32_t w) const {
-    uint32_t a = lane_addr<B>(w, base) & 0xfffcu;  // < 64 KB - 3
+    const uint32_t a = lane_addr<B>(w, base);
     return rotl8n(*reinterpret_cast<const uint32_t*>(lds + a), 8 * TBL);
   }
   __device__ static void fill(uint32_t* lds, int tid, int nthr) {

@@ -6,12 +6,14 @@
 
 namespace fss {
 
-// Copy the cached per-spec header into a key buffer, stamping size and party.
+// Copy the cached per-spec header into a key buffer, stamping size and party;
+// the rest of the header region is zeroed so key bytes are fully determined.
 __global__ void k_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
                               uint32_t party) {
   const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
   uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-  for (uint32_t i = threadIdx.x; i < sizeof(KeyHeader) / 4; i += blockDim.x) d[i] = s[i];
+  for (uint32_t i = threadIdx.x; i < kHeaderBytes / 4; i += blockDim.x)
+    d[i] = i < sizeof(KeyHeader) / 4 ? s[i] : 0u;
   __syncthreads();
   if (threadIdx.x == 0) {
     KeyHeader* h = reinterpret_cast<KeyHeader*>(dst);

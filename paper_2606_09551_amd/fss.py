@@ -153,10 +153,10 @@ class Spec:
         self.handle = h
         self.name = desc.name
 
-    def __del__(self):
+    def __del__(self, _free=lib.fss_spec_free):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
-            lib.fss_spec_free(h)
+            _free(h)
             self.handle = None
 
     def query(self, n_bits: int, frac_bits: int) -> dict:
@@ -235,9 +235,9 @@ class Plan:
         return {"aes_variant": t.aes_variant, "block_threads": t.block_threads,
                 "blocks_per_cu": t.blocks_per_cu, "order": t.order, "grid": g.value}
 
-    def free(self):
+    def free(self, _free=lib.fss_plan_free):
         if self.handle is not None and self.handle.value:
-            lib.fss_plan_free(self.handle)
+            _free(self.handle)
         self.handle = None
 
     def __del__(self):
@@ -259,9 +259,9 @@ class Graph:
     def launch(self, stream=None):
         _check(lib.fss_graph_launch(self.handle, _stream(stream)))
 
-    def free(self):
+    def free(self, _free=lib.fss_graph_free):
         if self.handle is not None and self.handle.value:
-            lib.fss_graph_free(self.handle)
+            _free(self.handle)
         self.handle = None
 
     def __del__(self):
