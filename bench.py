@@ -119,6 +119,9 @@ def main() -> None:
         insts.append(inst)
     n_elems = sum(i.n for i in insts)
     stream = torch.cuda.current_stream()
+    for inst, op in zip(insts, ops):       # the plan reads each key buffer's header
+        inst.keygen(op.seed)
+    torch.cuda.synchronize()
     plan = F.Plan([inst.item(b) for inst in insts for b in (0, 1)])
     cfg = plan.config()
     eval_aes = plan.aes_blocks()

@@ -53,7 +53,7 @@ int env_int(const char* name, int dflt) {
 // Default AES table layouts of the plain evaluator and of keygen (override
 // with FSS_AES_VARIANT / FSS_KEYGEN_VARIANT).
 int eval_variant() { return env_int("FSS_AES_VARIANT", 1); }
-int keygen_variant() { return env_int("FSS_KEYGEN_VARIANT", 0); }
+int keygen_variant() { return env_int("FSS_KEYGEN_VARIANT", 2); }
 
 // Per-device library state: the status word kernels report into.
 std::mutex g_mu;
