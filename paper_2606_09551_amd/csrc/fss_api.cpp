@@ -252,6 +252,15 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
   uint32_t kmax = 0;
   for (int t = 0; t < q->T; ++t) kmax = std::max(kmax, q->atom_k[t]);
   h.kmax = kmax;
+  // Lookup points u_i = (v - a'_i) mod 2^n span W = a'_{m-1} - a'_1 + 1
+  // consecutive values; with 2^K >= W they meet at most two aligned blocks of
+  // 2^K values, whose first n - K levels are shared.  Worth it when m >= 4.
+  {
+    const uint64_t W = (m >= 2) ? (q->aprime[m - 1] - q->aprime[1] + 1) : 1;
+    int K = 0;
+    while (K < n && ((uint64_t)1 << K) < W) ++K;
+    h.top_depth = (m >= 4) ? (uint32_t)(n - K) : 0u;
+  }
   h.tile_bytes = q->layout.tile_bytes;
   h.spec_hash = S->hash;
   h.negate = q->negate;
@@ -279,6 +288,7 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
     for (int k = 0; k < q->p; ++k) {
       h.tab[0][j][k] = A(m - 1, j, k);
       for (int i = 1; i < m; ++i) h.tab[i][j][k] = A(i - 1, j, k) - A(i, j, k);
+      h.tabv[j][k] = A(0, j, k) - A(m - 1, j, k);
     }
   *out = std::move(q);
   return FSS_OK;
@@ -546,12 +556,16 @@ int device_cus(int* cus, std::string* name) {
   return FSS_OK;
 }
 
-// Per-element AES count of one party's evaluation (both calls).
+// Per-element AES blocks of one party's evaluation (both calls) as the
+// kernels compute it: every atom walk, the full walk at v, the two shared
+// top walks of depth D and the m-1 point walks below depth D.
 double elem_aes(const KeyHeader& h) {
   double a = 0;
   for (uint32_t t = 0; t < h.T; ++t) a += h.atom_k[t];
-  const int nb = (int)(h.p + 1) / 2;
-  a += (double)h.m * ((double)h.n * (1 + nb) + nb);
+  const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb, n = h.n, D = h.top_depth;
+  a += n * lvl + nb;                                    // D(v)
+  a += 2 * D * lvl;                                     // shared tops
+  a += (double)(h.m - 1) * ((n - D) * lvl + nb);        // points
   return a;
 }
 

@@ -95,7 +95,7 @@ constexpr uint64_t kHeaderBytes = 16384;
 struct KeyHeader {
   uint32_t magic, version, party, layout;
   uint32_t n, f, m, d, p, T, ell, F_out;
-  uint32_t n_prim, n_views, kmax, pad0;
+  uint32_t n_prim, n_views, kmax, top_depth;  // top_depth: shared levels of the lookup points
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];
@@ -108,6 +108,7 @@ struct KeyHeader {
   // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
   // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
   uint64_t tab[kMaxM][kMaxP][kMaxP];
+  uint64_t tabv[kMaxP][kMaxP];             // sum_{i>=1} tab_i = A_0 - A_{m-1}
 };
 static_assert(sizeof(KeyHeader) <= kHeaderBytes, "header too large");
 

@@ -26,10 +26,27 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
 __device__ __forceinline__ uint32_t rotl8n(uint32_t x, int n8) {
   return n8 == 0 ? x : ((x << n8) | (x >> (32 - n8)));
 }
-__device__ __forceinline__ uint4 ld16(const uint8_t* p) { return *reinterpret_cast<const uint4*>(p); }
-__device__ __forceinline__ uint64_t ld8(const uint8_t* p) { return *reinterpret_cast<const uint64_t*>(p); }
-__device__ __forceinline__ void st16(uint8_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
-__device__ __forceinline__ void st8(uint8_t* p, uint64_t v) { *reinterpret_cast<uint64_t*>(p) = v; }
+// Every key, input and output access goes through global-address-space
+// pointers: pointers read from a work-list are otherwise generic, and generic
+// (flat) loads also count against the LDS wait counter, serialising them with
+// the T-table reads.
+#define FSS_GLOBAL __attribute__((address_space(1)))
+using GHdr = const FSS_GLOBAL KeyHeader*;
+__device__ __forceinline__ GHdr ghdr(const void* p) { return (GHdr)p; }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld16(const uint8_t* p) {
+  const u32x4 v = *(const FSS_GLOBAL u32x4*)p;
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint64_t ld8(const uint8_t* p) { return *(const FSS_GLOBAL uint64_t*)p; }
+__device__ __forceinline__ void st16(uint8_t* p, uint4 v) {
+  u32x4 w;
+  w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+  *(FSS_GLOBAL u32x4*)p = w;
+}
+__device__ __forceinline__ void st8(uint8_t* p, uint64_t v) { *(FSS_GLOBAL uint64_t*)p = v; }
+__device__ __forceinline__ uint64_t ldg64(const uint64_t* p) { return *(const FSS_GLOBAL uint64_t*)p; }
+__device__ __forceinline__ void stg64(uint64_t* p, uint64_t v) { *(FSS_GLOBAL uint64_t*)p = v; }
 __device__ __forceinline__ uint64_t mk64(uint32_t lo, uint32_t hi) { return (uint64_t)lo | ((uint64_t)hi << 32); }
 __device__ __forceinline__ void set_status(int* st, int code) { atomicCAS(st, 0, code); }
 
@@ -130,7 +147,7 @@ constexpr int kKeygenBlock = 256;
 
 template <int V> struct TabOf;
 template <> struct TabOf<0> { using T = Tab0; static constexpr int kBlock = 256; };
-template <> struct TabOf<1> { using T = Tab1; static constexpr int kBlock = 1024; };
+template <> struct TabOf<1> { using T = Tab1; static constexpr int kBlock = 768; };
 template <> struct TabOf<2> { using T = Tab2; static constexpr int kBlock = 512; };
 template <> struct TabOf<3> { using T = Tab3; static constexpr int kBlock = 512; };
 
@@ -191,6 +208,12 @@ __device__ __forceinline__ void aes_rounds(const Key& key, const TB& tb, uint32_
   (aes_round<Rs + 1>(key, tb, s), ...);
 }
 
+template <class Key, class TB, int K, int... Rs>
+__device__ __forceinline__ void aes_rounds_from2(const Key& key, const TB& tb, uint32_t (&s)[K][4],
+                                                 std::integer_sequence<int, Rs...>) {
+  (aes_round<Rs + 2>(key, tb, s), ...);
+}
+
 template <class Key, class TB, int K>
 __device__ __forceinline__ void aes_encrypt(const Key& key, const TB& tb, uint32_t (&s)[K][4]) {
 #pragma unroll
@@ -224,10 +247,45 @@ __device__ __forceinline__ void prg(const TB& tb, const uint32_t (&s)[K][4], con
     for (int c = 0; c < 4; ++c) o[k][c] ^= x[k][c];
 }
 
+// H(s, j_k) for K tweaks of one seed.  The inputs differ only in byte 15 (row 3
+// of column 3), which after round 1 reaches only column 0: round 1's columns
+// 1..3 and three of column 0's four lookups are computed once.
+template <class TB, int K>
+__device__ __forceinline__ void prg_shared(const TB& tb, const uint32_t (&s)[4], const uint32_t (&j)[K],
+                                           uint32_t (&o)[K][4]) {
+  constexpr PrgKey key{};
+  const uint32_t a0 = s[0] ^ key.template w<0>(), a1 = s[1] ^ key.template w<1>();
+  const uint32_t a2 = s[2] ^ key.template w<2>(), a3 = s[3] ^ key.template w<3>();
+  // a3 ^ (j << 24) has the same bytes 0..2 as a3
+  const uint32_t c0 = xor3(tb.template get<0, 0>(a0), tb.template get<1, 1>(a1), tb.template get<2, 2>(a2));
+  const uint32_t c1 = xor3(xor3(tb.template get<0, 0>(a1), tb.template get<1, 1>(a2), tb.template get<2, 2>(a3)),
+                           tb.template get<3, 3>(a0), key.template w<5>());
+  const uint32_t c2 = xor3(xor3(tb.template get<0, 0>(a2), tb.template get<1, 1>(a3), tb.template get<2, 2>(a0)),
+                           tb.template get<3, 3>(a1), key.template w<6>());
+  const uint32_t c3 = xor3(xor3(tb.template get<0, 0>(a3), tb.template get<1, 1>(a0), tb.template get<2, 2>(a1)),
+                           tb.template get<3, 3>(a2), key.template w<7>());
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    o[k][0] = xor3(c0, tb.template get<3, 3>(a3 ^ (j[k] << 24)), key.template w<4>());
+    o[k][1] = c1;
+    o[k][2] = c2;
+    o[k][3] = c3;
+  }
+  aes_rounds_from2(key, tb, o, std::make_integer_sequence<int, 8>{});
+  aes_final(key, tb, o);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    o[k][0] ^= s[0];
+    o[k][1] ^= s[1];
+    o[k][2] ^= s[2];
+    o[k][3] ^= s[3] ^ (j[k] << 24);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Header validation (uniform across the launch)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int header_check(const KeyHeader* h, int party, int64_t n) {
+__device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
   if (h->magic != kMagic || h->version != kVersion) return kStatusShape;
   if ((int)h->party != party) return kStatusParty;
   if (n < 0 || (uint64_t)n > h->n_elems) return kStatusShape;
@@ -238,7 +296,7 @@ __device__ __forceinline__ int header_check(const KeyHeader* h, int party, int64
 // Call 1: packed comparison.  Up to three Z_2 DCF atoms walk in lockstep.
 // ---------------------------------------------------------------------------
 template <class TB>
-__device__ __forceinline__ uint32_t eval_atoms(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+__device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8_t* tile,
                                                int lane, int b, uint64_t xhat) {
   const int T = (int)h->T;
   uint32_t bits = 0;
@@ -298,7 +356,7 @@ __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, const KeyHeader* h,
 // Combine atom shares into output-bit shares and ballot-pack 64 elements
 // per word: z_j = negate_j (party 0) ^ w_j ^ XOR over atoms of (A_t ^ A_r(t)).
 template <class TB>
-__device__ __forceinline__ void pred_tile(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+__device__ __forceinline__ void pred_tile(const TB& tb, GHdr h, const uint8_t* tile,
                                           int lane, int b, uint64_t xhat, bool valid, uint64_t* z,
                                           uint64_t tile_idx, uint64_t words) {
   const uint32_t A = eval_atoms(tb, h, tile, lane, b, xhat);
@@ -312,7 +370,7 @@ __device__ __forceinline__ void pred_tile(const TB& tb, const KeyHeader* h, cons
   const int ell = (int)h->ell;
   for (int j = 0; j < ell; ++j) {
     const uint64_t word = __ballot(valid && ((bits >> j) & 1ull));
-    if (lane == 0) z[(uint64_t)j * words + tile_idx] = word;
+    if (lane == 0) stg64(z + (uint64_t)j * words + tile_idx, word);
   }
 }
 
@@ -320,60 +378,85 @@ __device__ __forceinline__ void pred_tile(const TB& tb, const KeyHeader* h, cons
 // Call 2: vector interval lookup.  One vector DCF (payload rho in Z^P) is
 // evaluated at m points; 1 + ceil(P/2) AES per level, interleaved.
 // ---------------------------------------------------------------------------
+template <int P>
+struct VState {  // a node of the GGM tree: seed, control bit, partial sum
+  uint32_t s[4];
+  uint32_t t;
+  uint64_t V[P];
+};
+
+template <int P>
+__device__ __forceinline__ VState<P> vroot(GHdr h, const uint8_t* tile, int lane, int b) {
+  VState<P> st;
+  const uint4 r = ld16(tile + h->off_croot + lane * 16);
+  st.s[0] = r.x; st.s[1] = r.y; st.s[2] = r.z; st.s[3] = r.w;
+  st.t = (uint32_t)b;
+#pragma unroll
+  for (int q = 0; q < P; ++q) st.V[q] = 0;
+  return st;
+}
+
+template <int P>
+__device__ __forceinline__ VState<P> vselect(bool c, const VState<P>& a, const VState<P>& b) {
+  VState<P> r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.s[k] = c ? a.s[k] : b.s[k];
+  r.t = c ? a.t : b.t;
+#pragma unroll
+  for (int q = 0; q < P; ++q) r.V[q] = c ? a.V[q] : b.V[q];
+  return r;
+}
+
+// Advance `st` through levels [i0, i1) along the bits of the n-bit input x
+// (level i consumes bit n-1-i).
 template <int P, class TB>
-__device__ __forceinline__ void eval_vec(const TB& tb, const KeyHeader* h, const uint8_t* tile, int lane,
-                                         int b, uint32_t x, uint64_t (&out)[P]) {
+__device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
+                                         uint32_t x, int i0, int i1, VState<P>& st) {
   constexpr int NB = (P + 1) / 2;
   const int n = (int)h->n;
-  const uint4 r = ld16(tile + h->off_croot + lane * 16);
-  uint32_t s[4] = {r.x, r.y, r.z, r.w};
-  uint32_t t = (uint32_t)b;
-  uint64_t V[P];
-#pragma unroll
-  for (int q = 0; q < P; ++q) V[q] = 0;
   const uint8_t* cwp = tile + h->off_ccw + lane * 16;
   const uint8_t* vcp = tile + h->off_cvcw + lane * 8;
-  for (int i = 0; i < n; ++i) {
+  for (int i = i0; i < i1; ++i) {
     const uint32_t xi = (x >> (n - 1 - i)) & 1u;
-    uint32_t ss[1 + NB][4], jj[1 + NB], o[1 + NB][4];
-#pragma unroll
-    for (int q = 0; q <= NB; ++q) {
-      ss[q][0] = s[0]; ss[q][1] = s[1]; ss[q][2] = s[2]; ss[q][3] = s[3];
-    }
+    uint32_t jj[1 + NB], o[1 + NB][4];
     jj[0] = xi;
     jj[1] = 2u + 2u * xi;
     if (NB > 1) jj[NB > 1 ? 2 : 0] = 3u + 2u * xi;
-    prg<TB, 1 + NB>(tb, ss, jj, o);
+    prg_shared<TB, 1 + NB>(tb, st.s, jj, o);
     const uint4 cw = ld16(cwp + (uint64_t)i * kTile * 16);
+    const uint32_t t = st.t;
     const uint32_t msk = 0u - t;
     const uint64_t msk64 = 0ull - (uint64_t)t;
-    const uint32_t nt = (o[0][0] & 1u) ^ ((cw.x >> xi) & t & 1u);
-    s[0] = (o[0][0] & ~3u) ^ (cw.x & ~3u & msk);
-    s[1] = o[0][1] ^ (cw.y & msk);
-    s[2] = o[0][2] ^ (cw.z & msk);
-    s[3] = o[0][3] ^ (cw.w & msk);
+    st.t = (o[0][0] & 1u) ^ ((cw.x >> xi) & t & 1u);
+    st.s[0] = (o[0][0] & ~3u) ^ (cw.x & ~3u & msk);
+    st.s[1] = o[0][1] ^ (cw.y & msk);
+    st.s[2] = o[0][2] ^ (cw.z & msk);
+    st.s[3] = o[0][3] ^ (cw.w & msk);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
       v += ld8(vcp + ((uint64_t)i * P + q) * kTile * 8) & msk64;
-      V[q] += b ? (0ull - v) : v;
+      st.V[q] += b ? (0ull - v) : v;
     }
-    t = nt;
   }
-  // Convert(s) = the first P words of H(s, 6) || H(s, 7).
-  uint32_t ss[NB][4], jj[NB], o[NB][4];
+}
+
+// Leaf value: V + (-1)^b (Convert(s) + t * CW_{n+1}), Convert(s) = the first
+// P words of H(s, 6) || H(s, 7).
+template <int P, class TB>
+__device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
+                                          const VState<P>& st, uint64_t (&out)[P]) {
+  constexpr int NB = (P + 1) / 2;
+  uint32_t jj[NB], o[NB][4];
 #pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    ss[q][0] = s[0]; ss[q][1] = s[1]; ss[q][2] = s[2]; ss[q][3] = s[3];
-    jj[q] = 6u + q;
-  }
-  prg<TB, NB>(tb, ss, jj, o);
-  const uint64_t msk64 = 0ull - (uint64_t)t;
+  for (int q = 0; q < NB; ++q) jj[q] = 6u + q;
+  prg_shared<TB, NB>(tb, st.s, jj, o);
+  const uint64_t msk64 = 0ull - (uint64_t)st.t;
 #pragma unroll
   for (int q = 0; q < P; ++q) {
     uint64_t c = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
     c += ld8(tile + h->off_cfin + ((uint64_t)q * kTile + lane) * 8) & msk64;
-    out[q] = V[q] + (b ? (0ull - c) : c);
+    out[q] = st.V[q] + (b ? (0ull - c) : c);
   }
 }
 
@@ -382,39 +465,65 @@ __device__ __forceinline__ void eval_vec(const TB& tb, const KeyHeader* h, const
 // active piece's coefficients at xhat are
 //   q = tab_0 rho_b + sum_{i=1}^{m-1} tab_i g_i  (+ r_out share in q_0),
 // where tab_0 = A_{m-1}, tab_i = A_{i-1} - A_i and A_i maps a share of
-// 1[x in I_i] rho to the x-hat coefficients of piece i.  Then y = sum q_j xhat^j.
+// 1[x in I_i] rho to the x-hat coefficients of piece i.  Since
+// sum_{i>=1} tab_i = A_0 - A_{m-1} =: tabv, the D(v) terms enter once:
+//   q = sum_i tab_i (D(u_i) + 1[v < a'_i] rho_b) - tabv D(v) + tab_0 rho_b.
+// Then y = sum_j q_j xhat^j.  (Ring arithmetic mod 2^64: any order is exact.)
+//
+// Shared prefixes: the points u_1 > ... > u_{m-1} (cyclically) lie in a window
+// of W = a'_{m-1} - a'_1 + 1 consecutive values, which meets at most two
+// aligned blocks of 2^K >= W values.  Their first D = n - K levels are walked
+// once per block (A, the block of u_{m-1}, and its successor B) and each point
+// resumes from its block's state: same outputs, (m - 3) * D fewer levels.
 template <int P, class TB>
-__device__ __forceinline__ uint64_t coeff_tile(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+__device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8_t* tile,
                                                int lane, int b, uint64_t xhat) {
-  const int n = (int)h->n, m = (int)h->m;
+  const int n = (int)h->n, m = (int)h->m, D = (int)h->top_depth;
   const uint32_t Nmask = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
   const uint32_t half = 1u << (n - 1);
   const uint32_t v = ((uint32_t)xhat + half) & Nmask;
-  uint64_t Dv[P], rho[P], q[P];
-  eval_vec<P>(tb, h, tile, lane, b, v, Dv);
-#pragma unroll
-  for (int k = 0; k < P; ++k) {
-    rho[k] = ld8(tile + h->off_crho + ((uint64_t)k * kTile + lane) * 8);
-    q[k] = 0;
+  const uint8_t* rhop = tile + h->off_crho + lane * 8;
+  const int K = n - D;
+  const uint32_t top_mask = D >= 32 ? 0xffffffffu : ((1u << D) - 1u);
+  const uint32_t blkA = (uint32_t)(((uint64_t)((v - (uint32_t)h->aprime[m - 1]) & Nmask)) >> K);
+  const uint32_t blkB = (blkA + 1u) & top_mask;
+  VState<P> sa = vroot<P>(h, tile, lane, b), sb = sa;
+  if (D > 0) {
+    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkA << K), 0, D, sa);
+    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkB << K), 0, D, sb);
   }
+  uint64_t q[P];
+#pragma unroll
+  for (int k = 0; k < P; ++k) q[k] = 0;
   for (int i = 1; i < m; ++i) {
     const uint32_t ap = (uint32_t)h->aprime[i];
     const uint32_t u = (v - ap) & Nmask;
-    uint64_t D[P];
-    eval_vec<P>(tb, h, tile, lane, b, u, D);
-    const uint64_t lt = v < ap ? ~0ull : 0ull;
+    VState<P> st = vselect<P>((uint32_t)((uint64_t)u >> K) == blkA, sa, sb);
+    vec_walk<P>(tb, h, tile, lane, b, u, D, n, st);
     uint64_t g[P];
+    vec_final<P>(tb, h, tile, lane, b, st, g);
+    const uint64_t lt = v < ap ? ~0ull : 0ull;
 #pragma unroll
-    for (int k = 0; k < P; ++k) g[k] = D[k] - Dv[k] + (rho[k] & lt);
+    for (int k = 0; k < P; ++k) g[k] += ld8(rhop + (uint64_t)k * kTile * 8) & lt;
 #pragma unroll
     for (int j = 0; j < P; ++j)
 #pragma unroll
       for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * g[k];
   }
+  {
+    VState<P> st = vroot<P>(h, tile, lane, b);
+    vec_walk<P>(tb, h, tile, lane, b, v, 0, n, st);
+    uint64_t Dv[P];
+    vec_final<P>(tb, h, tile, lane, b, st, Dv);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int k = 0; j + k < P; ++k) q[j] -= h->tabv[j][k] * Dv[k];
+  }
 #pragma unroll
   for (int j = 0; j < P; ++j)
 #pragma unroll
-    for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * rho[k];
+    for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * ld8(rhop + (uint64_t)k * kTile * 8);
   q[0] += ld8(tile + h->off_crout + lane * 8);
   uint64_t y = q[P - 1];
 #pragma unroll
@@ -423,7 +532,7 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, const KeyHeader* h,
 }
 
 template <class TB>
-__device__ __forceinline__ uint64_t coeff_dispatch(const TB& tb, const KeyHeader* h, const uint8_t* tile,
+__device__ __forceinline__ uint64_t coeff_dispatch(const TB& tb, GHdr h, const uint8_t* tile,
                                                    int lane, int b, uint64_t xhat) {
   switch (h->p) {
     case 1: return coeff_tile<1>(tb, h, tile, lane, b, xhat);
@@ -443,7 +552,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_pred(const uint8_t* k
   __shared__ uint32_t lds[TB::kWords];
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
-  const KeyHeader* h = reinterpret_cast<const KeyHeader*>(keys);
+  const GHdr h = ghdr(keys);
   const int bad = header_check(h, party, n);
   if (bad) {
     if (threadIdx.x == 0) set_status(status, bad);
@@ -455,7 +564,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_pred(const uint8_t* k
   if (tile >= words) return;
   const uint64_t e = tile * kTile + lane;
   const bool valid = e < (uint64_t)n;
-  const uint64_t xh = valid ? xhat[e] : 0;
+  const uint64_t xh = valid ? ldg64(xhat + e) : 0;
   TB tb(lds, lane);
   const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
   pred_tile(tb, h, tp, lane, party, xh, valid, z, tile, words);
@@ -468,7 +577,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* 
   __shared__ uint32_t lds[TB::kWords];
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
-  const KeyHeader* h = reinterpret_cast<const KeyHeader*>(keys);
+  const GHdr h = ghdr(keys);
   const int bad = header_check(h, party, n);
   if (bad) {
     if (threadIdx.x == 0) set_status(status, bad);
@@ -479,11 +588,11 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* 
   if (tile * kTile >= (uint64_t)n) return;
   const uint64_t e = tile * kTile + lane;
   const bool valid = e < (uint64_t)n;
-  const uint64_t xh = valid ? xhat[e] : 0;
+  const uint64_t xh = valid ? ldg64(xhat + e) : 0;
   TB tb(lds, lane);
   const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
   const uint64_t out = coeff_dispatch(tb, h, tp, lane, party, xh);
-  if (valid) y[e] = out;
+  if (valid) stg64(y + e, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -506,10 +615,19 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     if (lane == 0) idx = atomicAdd(counter, 1u);
     idx = __builtin_amdgcn_readfirstlane(idx);
     if (idx >= n_tiles) break;
-    const uint32_t item = __builtin_amdgcn_readfirstlane(tiles[2 * idx]);
-    const uint64_t tile = __builtin_amdgcn_readfirstlane(tiles[2 * idx + 1]);
-    const DevItem it = items[item];
-    const KeyHeader* h = reinterpret_cast<const KeyHeader*>(it.keys);
+    const FSS_GLOBAL uint32_t* tl = (const FSS_GLOBAL uint32_t*)tiles;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(tl[2 * idx]);
+    const uint64_t tile = __builtin_amdgcn_readfirstlane(tl[2 * idx + 1]);
+    const FSS_GLOBAL DevItem* ip = (const FSS_GLOBAL DevItem*)items + item;
+    DevItem it;
+    it.keys = ip->keys;
+    it.xhat = ip->xhat;
+    it.y = ip->y;
+    it.z = ip->z;
+    it.n_elems = ip->n_elems;
+    it.party = ip->party;
+    it.words = ip->words;
+    const GHdr h = ghdr(it.keys);
     const int bad = header_check(h, it.party, it.n_elems);
     if (bad) {
       if (lane == 0) set_status(status, bad);
@@ -517,11 +635,11 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     }
     const uint64_t e = tile * kTile + lane;
     const bool valid = e < (uint64_t)it.n_elems;
-    const uint64_t xh = valid ? it.xhat[e] : 0;
+    const uint64_t xh = valid ? ldg64(it.xhat + e) : 0;
     const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
     if (h->T > 0) pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
     const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh);
-    if (valid) it.y[e] = out;
+    if (valid) stg64(it.y + e, out);
   }
 }
 
@@ -597,7 +715,7 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
 // Vector DCF Gen for f(x) = beta * 1[x < alpha] over n bits, beta in Z^P.
 // Per party, blocks are [keep seed, lose seed, keep values.., lose values..].
 template <int P, class TB>
-__device__ __forceinline__ void gen_vec(const TB& tb, const KeyHeader* h, int n, uint64_t alpha,
+__device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t alpha,
                                         const uint64_t (&beta)[P], const uint32_t (&r0)[4],
                                         const uint32_t (&r1)[4], uint8_t* k0, uint8_t* k1, int lane) {
   constexpr int NB = (P + 1) / 2;
@@ -615,11 +733,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, const KeyHeader* h, int n,
     uint64_t vk[2][P], vl[2][P];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      uint32_t in[KB][4], o[KB][4], jj[KB];
-#pragma unroll
-      for (int q = 0; q < KB; ++q) {
-        in[q][0] = s[b][0]; in[q][1] = s[b][1]; in[q][2] = s[b][2]; in[q][3] = s[b][3];
-      }
+      uint32_t o[KB][4], jj[KB];
       jj[0] = ai;
       jj[1] = ai ^ 1u;
 #pragma unroll
@@ -627,7 +741,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, const KeyHeader* h, int n,
         jj[2 + q] = 2u + 2u * ai + q;
         jj[2 + NB + q] = 2u + 2u * (ai ^ 1u) + q;
       }
-      prg<TB, KB>(tb, in, jj, o);
+      prg_shared<TB, KB>(tb, s[b], jj, o);
       tk[b] = o[0][0] & 1u;
       tl[b] = o[1][0] & 1u;
       sk[b][0] = o[0][0] & ~3u; sk[b][1] = o[0][1]; sk[b][2] = o[0][2]; sk[b][3] = o[0][3];
@@ -676,13 +790,10 @@ __device__ __forceinline__ void gen_vec(const TB& tb, const KeyHeader* h, int n,
   uint64_t cv[2][P];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
-    uint32_t in[NB][4], o[NB][4], jj[NB];
+    uint32_t o[NB][4], jj[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      in[q][0] = s[b][0]; in[q][1] = s[b][1]; in[q][2] = s[b][2]; in[q][3] = s[b][3];
-      jj[q] = 6u + q;
-    }
-    prg<TB, NB>(tb, in, jj, o);
+    for (int q = 0; q < NB; ++q) jj[q] = 6u + q;
+    prg_shared<TB, NB>(tb, s[b], jj, o);
 #pragma unroll
     for (int q = 0; q < P; ++q) cv[b][q] = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
   }
@@ -698,7 +809,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, const KeyHeader* h, int n,
 }
 
 template <int P, class TB>
-__device__ __forceinline__ void keygen_coeff(const TB& tb, const KeyHeader* h, const KgArgs& ga, uint64_t e,
+__device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs& ga, uint64_t e,
                                              uint64_t rin, uint8_t* t0, uint8_t* t1, int lane) {
   uint64_t rho[P];
   rho[0] = 1;
@@ -723,7 +834,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, const KeyHeader* h, c
 }
 
 template <int V>
-__global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* h, KgArgs ga, uint8_t* key0,
+__global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* hdr, KgArgs ga, uint8_t* key0,
                                                               uint8_t* key1, uint64_t* r_in, uint64_t* r_out) {
   using TB = typename TabOf<V>::T;
   __shared__ uint32_t lds[TB::kWords];
@@ -733,6 +844,7 @@ __global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* h, KgA
   const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (tile >= ga.n_tiles) return;
   TB tb(lds, lane);
+  const GHdr h = ghdr(hdr);
   const uint64_t e = tile * kTile + lane;
   const uint64_t tb_bytes = h->tile_bytes;
   uint8_t* t0 = key0 + kHeaderBytes + tile * tb_bytes;
@@ -742,8 +854,8 @@ __global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* h, KgA
   rand_blk(tb, ga.rk, e, 0, 0, r);
   const uint64_t rin = mk64(r[0], r[1]), rout = mk64(r[2], r[3]);
   if (e < (uint64_t)ga.n_elems) {
-    if (r_in) r_in[e] = rin;
-    if (r_out) r_out[e] = rout;
+    if (r_in) stg64(r_in + e, rin);
+    if (r_out) stg64(r_out + e, rout);
   }
   rand_blk(tb, ga.rk, e, 1, 0, r);
   const uint64_t rs = mk64(r[0], r[1]);
