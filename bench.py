@@ -75,6 +75,31 @@ def cpu_baseline(op, n_bits, f_bits, seconds: float) -> dict:
                       f"evaluation, {dt:.1f} s wall on {used} threads"}
 
 
+KERNEL_SOURCES = ["paper_2606_09551_amd/csrc/fss_kernels_impl.hpp", "paper_2606_09551_amd/csrc/fss_common.hpp",
+                  "paper_2606_09551_amd/csrc/fss_kernels.hpp"]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per fused launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    if workload != "c2":
+        return None
+    path = os.path.join(ROOT, "profiles", "k_fused_gelu_128x3072_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0].strip() in ("kernel_sources_sha256_16", "traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES)
+    if kv.get("kernel_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def build_ops(workload: str):
     from paper_2606_09551_amd import workloads as W
 
@@ -84,7 +109,21 @@ def build_ops(workload: str):
         return W.config2(), W.N_BITS, W.F_BITS, "gelu_bert_base_ffn_128x3072"
     if workload == "c3":
         return W.config3(), W.N_BITS, W.F_BITS, "softmax_exp_12x128x128_recip_12x128"
+    if workload == "c4":
+        return W.config4(), W.N_BITS, W.F_BITS, "gpt2_small_seq256_12_layers_gelu_exp_recip_rsqrt"
     raise SystemExit(f"unknown workload {workload}")
+
+
+def layer_groups(ops) -> list:
+    """Indices of ops grouped per transformer layer (name prefix 'L<k>.')."""
+    groups, keyed = [], {}
+    for i, op in enumerate(ops):
+        key = op.name.split(".")[0] if op.name.startswith("L") and "." in op.name else "all"
+        if key not in keyed:
+            keyed[key] = len(groups)
+            groups.append([])
+        groups[keyed[key]].append(i)
+    return groups
 
 
 def main() -> None:
@@ -92,7 +131,10 @@ def main() -> None:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--graphs", action="store_true", help="replay each layer's launch from a HIP graph")
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="autotune the fused launch on the first layer (cache file path)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -122,9 +164,14 @@ def main() -> None:
     for inst, op in zip(insts, ops):       # the plan reads each key buffer's header
         inst.keygen(op.seed)
     torch.cuda.synchronize()
-    plan = F.Plan([inst.item(b) for inst in insts for b in (0, 1)])
-    cfg = plan.config()
-    eval_aes = plan.aes_blocks()
+    groups = layer_groups(ops)
+    tune = None
+    if args.autotune:
+        tune = F.fss_autotune([insts[i].item(b) for i in groups[0] for b in (0, 1)], args.autotune)
+    plans = [F.Plan([insts[i].item(b) for i in g for b in (0, 1)], tune) for g in groups]
+    graphs = [F.Graph([p]) for p in plans] if args.graphs else None
+    cfg = plans[0].config()
+    eval_aes = sum(p.aes_blocks() for p in plans)
     kg_aes = sum(keygen_aes_per_elem(i) * i.n for i in insts)
 
     def step(k: int, fused: bool, ev):
@@ -135,7 +182,12 @@ def main() -> None:
             inst.mask()
         ev[1].record(stream)
         if fused:
-            plan.launch()
+            if graphs:
+                for g in graphs:
+                    g.launch()
+            else:
+                for p in plans:
+                    p.launch()
         else:
             for inst in insts:
                 inst.eval_plain(0)
@@ -190,17 +242,20 @@ def main() -> None:
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": wname, "elements": n_elems, "parties": 2, "n_bits": n_bits,
-                   "frac_bits": f_bits, "path": "fused persistent work-list",
+                   "frac_bits": f_bits, "ops": len(ops),
+                   "path": "fused persistent work-list" + (", HIP graph per layer" if graphs else ""),
+                   "launches_per_step": len(plans),
                    "step": "keygen (both parties) + masked opening + eval (both parties)",
-                   "launch": cfg},
+                   "launch": cfg, "autotuned": bool(args.autotune)},
         "latency_ms": {"p50": round(pct(fused["lat"], 0.5), 4), "p99": round(pct(fused["lat"], 0.99), 4)},
         "breakdown_ms": {"keygen": round(fused["keygen_ms"], 4), "eval": round(fused["eval_ms"], 4)},
         "aes_blocks_per_s": round((eval_aes + kg_aes) * args.steps / fused["wall_s"], 1),
         "eval_only_element_evals_per_s": round(evals / eval_s, 1),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                     "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                     "traffic": measured_traffic(args.workload),
                      "kernel": "k_fused", "ops_per_aes_block": OPS_PER_AES,
-                     "aes_blocks_per_launch": eval_aes},
+                     "aes_blocks_per_launch": eval_aes / len(plans)},
     }
     if plain is not None:
         out["plain"] = {"value": round(evals * args.steps / plain["wall_s"], 1),

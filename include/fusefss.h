@@ -187,6 +187,9 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
 /* One persistent launch evaluating both calls of every element of every item
  * in a single pass.  Enqueue-only and safe to capture into a HIP graph. */
 int fss_plan_launch(fss_plan* plan, void* stream);
+/* Waits for the plan's last launch (direct or through a graph), then returns
+ * its device buffers to the library's pool.  Free graphs that captured a plan
+ * before the plan itself. */
 int fss_plan_free(fss_plan* plan);
 /* Algorithmic AES-128 blocks one launch of `plan` evaluates (sum over items
  * of n_elems * (sum_t k_t + m * (n * (1 + ceil(p/2)) + ceil(p/2))));

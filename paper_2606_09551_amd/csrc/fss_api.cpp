@@ -294,6 +294,8 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
   return FSS_OK;
 }
 
+int aux_stream(hipStream_t* out);
+
 int get_qspec(const fss_spec* Sc, int n, int f, std::shared_ptr<QSpec>* out) {
   fss_spec* S = const_cast<fss_spec*>(Sc);
   std::lock_guard<std::mutex> lk(S->mu);
@@ -322,8 +324,12 @@ int device_header(const fss_spec* Sc, QSpec* q, uint8_t** out) {
     return FSS_OK;
   }
   uint8_t* p = nullptr;
+  hipStream_t up;
+  int rc = aux_stream(&up);
+  if (rc) return rc;
   HIP_TRY(hipMalloc(&p, sizeof(KeyHeader)), "hipMalloc(header)");
-  HIP_TRY(hipMemcpy(p, &q->hdr, sizeof(KeyHeader), hipMemcpyHostToDevice), "hipMemcpy(header)");
+  HIP_TRY(hipMemcpyAsync(p, &q->hdr, sizeof(KeyHeader), hipMemcpyHostToDevice, up), "hipMemcpyAsync(header)");
+  HIP_TRY(hipStreamSynchronize(up), "hipStreamSynchronize(header)");
   q->dev_hdr[dev] = p;
   *out = p;
   return FSS_OK;
@@ -530,6 +536,8 @@ int fss_status(void* stream, int32_t* device_code) {
 // ===========================================================================
 struct fss_plan {
   int device = 0;
+  hipEvent_t done = nullptr;  // recorded after every launch; freeing waits on it
+  bool launched = false;
   DevItem* d_items = nullptr;
   uint32_t* d_tiles = nullptr;
   uint32_t* d_counter = nullptr;
@@ -539,9 +547,49 @@ struct fss_plan {
   double aes_per_launch = 0;  // algorithmic AES blocks of one launch
 };
 
+namespace {
+// Device buffers of freed plans are kept per device and reused, so building a
+// plan per scheduling step does not allocate once the pool is warm.
+struct PoolBuf { int dev; size_t bytes; void* p; };
+std::mutex g_pool_mu;
+std::vector<PoolBuf> g_pool_free;
+std::map<void*, PoolBuf> g_pool_all;
+
+int pool_get(size_t bytes, void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    int bi = -1;
+    for (size_t i = 0; i < g_pool_free.size(); ++i)
+      if (g_pool_free[i].dev == dev && g_pool_free[i].bytes >= bytes &&
+          (bi < 0 || g_pool_free[i].bytes < g_pool_free[bi].bytes))
+        bi = (int)i;
+    if (bi >= 0) {
+      *out = g_pool_free[bi].p;
+      g_pool_free.erase(g_pool_free.begin() + bi);
+      return FSS_OK;
+    }
+  }
+  const size_t cap = std::max<size_t>(256, bytes + bytes / 2);
+  HIP_TRY(hipMalloc(out, cap), "hipMalloc(plan)");
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool_all[*out] = PoolBuf{dev, cap, *out};
+  return FSS_OK;
+}
+
+void pool_put(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pool_all.find(p);
+  if (it != g_pool_all.end()) g_pool_free.push_back(it->second);
+}
+}  // namespace
+
 struct fss_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<fss_plan*> plans;  // captured plans: their events mark each replay
 };
 
 namespace {
@@ -569,8 +617,29 @@ double elem_aes(const KeyHeader& h) {
   return a;
 }
 
+// Header reads go through a library-owned non-blocking stream so they never
+// wait for kernels running on other streams (the caller orders keygen first).
+int aux_stream(hipStream_t* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = streams.find(dev);
+  if (it == streams.end()) {
+    hipStream_t s;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+    it = streams.emplace(dev, s).first;
+  }
+  *out = it->second;
+  return FSS_OK;
+}
+
 int read_header(const void* keys, KeyHeader* h) {
-  HIP_TRY(hipMemcpy(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost), "hipMemcpy(header)");
+  hipStream_t s;
+  int rc = aux_stream(&s);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(header)");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(header)");
   if (h->magic != kMagic || h->version != kVersion) return fail(FSS_E_SHAPE, "not a key buffer");
   return FSS_OK;
 }
@@ -639,13 +708,23 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   std::unique_ptr<fss_plan> P(new (std::nothrow) fss_plan());
   if (!P) return fail(FSS_E_OOM, "out of host memory");
   HIP_TRY(hipGetDevice(&P->device), "hipGetDevice");
-  HIP_TRY(hipMalloc(&P->d_items, sizeof(DevItem) * std::max<size_t>(1, dev.size())), "hipMalloc(items)");
-  HIP_TRY(hipMalloc(&P->d_tiles, sizeof(uint32_t) * std::max<size_t>(2, flat.size())), "hipMalloc(tiles)");
-  HIP_TRY(hipMalloc(&P->d_counter, sizeof(uint32_t)), "hipMalloc(counter)");
+  void *pi = nullptr, *pt = nullptr, *pc = nullptr;
+  if ((rc = pool_get(sizeof(DevItem) * std::max<size_t>(1, dev.size()), &pi))) return rc;
+  P->d_items = (DevItem*)pi;
+  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(2, flat.size()), &pt))) return rc;
+  P->d_tiles = (uint32_t*)pt;
+  if ((rc = pool_get(sizeof(uint32_t), &pc))) return rc;
+  P->d_counter = (uint32_t*)pc;
+  hipStream_t up;
+  if ((rc = aux_stream(&up))) return rc;
   if (!dev.empty())
-    HIP_TRY(hipMemcpy(P->d_items, dev.data(), sizeof(DevItem) * dev.size(), hipMemcpyHostToDevice), "upload items");
+    HIP_TRY(hipMemcpyAsync(P->d_items, dev.data(), sizeof(DevItem) * dev.size(), hipMemcpyHostToDevice, up),
+            "upload items");
   if (!flat.empty())
-    HIP_TRY(hipMemcpy(P->d_tiles, flat.data(), sizeof(uint32_t) * flat.size(), hipMemcpyHostToDevice), "upload tiles");
+    HIP_TRY(hipMemcpyAsync(P->d_tiles, flat.data(), sizeof(uint32_t) * flat.size(), hipMemcpyHostToDevice, up),
+            "upload tiles");
+  HIP_TRY(hipStreamSynchronize(up), "hipStreamSynchronize(upload)");
+  HIP_TRY(hipEventCreateWithFlags(&P->done, hipEventDisableTiming), "hipEventCreate(plan)");
   P->n_tiles = (uint32_t)tl.size();
   P->tune = tn;
   P->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
@@ -664,14 +743,23 @@ int fss_plan_launch(fss_plan* plan, void* stream) {
   HIP_TRY(launch_fused(plan->tune.aes_variant, plan->d_items, plan->d_tiles, plan->n_tiles, plan->d_counter, st,
                        plan->grid, (hipStream_t)stream),
           "fused launch");
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIP_TRY(hipStreamIsCapturing((hipStream_t)stream, &cs), "hipStreamIsCapturing");
+  if (cs == hipStreamCaptureStatusNone) {
+    HIP_TRY(hipEventRecord(plan->done, (hipStream_t)stream), "hipEventRecord(plan)");
+    plan->launched = true;
+  }
   return FSS_OK;
 }
 
 int fss_plan_free(fss_plan* plan) {
   if (!plan) return FSS_OK;
-  (void)hipFree(plan->d_items);
-  (void)hipFree(plan->d_tiles);
-  (void)hipFree(plan->d_counter);
+  // Wait for the last enqueued launch before the buffers can be handed out again.
+  if (plan->launched) (void)hipEventSynchronize(plan->done);
+  if (plan->done) (void)hipEventDestroy(plan->done);
+  pool_put(plan->d_items);
+  pool_put(plan->d_tiles);
+  pool_put(plan->d_counter);
   delete plan;
   return FSS_OK;
 }
@@ -691,6 +779,7 @@ int fss_graph_capture(fss_plan* const* plans, int32_t n_plans, fss_graph** out) 
     return hip_fail(e, "hipStreamBeginCapture");
   }
   for (int i = 0; i < n_plans && rc == FSS_OK; ++i) rc = fss_plan_launch(plans[i], s);
+  if (rc == FSS_OK) G->plans.assign(plans, plans + n_plans);
   e = hipStreamEndCapture(s, &G->graph);
   (void)hipStreamDestroy(s);
   if (rc) return rc;
@@ -707,6 +796,10 @@ int fss_graph_capture(fss_plan* const* plans, int32_t n_plans, fss_graph** out) 
 int fss_graph_launch(fss_graph* graph, void* stream) {
   if (!graph) return fail(FSS_E_ARG, "graph NULL");
   HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream), "hipGraphLaunch");
+  for (fss_plan* p : graph->plans) {
+    HIP_TRY(hipEventRecord(p->done, (hipStream_t)stream), "hipEventRecord(graph)");
+    p->launched = true;
+  }
   return FSS_OK;
 }
 

@@ -284,3 +284,53 @@ def test_keygen_single_party_matches():
     torch.cuda.synchronize()
     assert torch.equal(a.keys[0], b.keys[0])
     assert torch.equal(a.r_in, b.r_in)
+
+
+def test_c4_layer_worklist_autotuned_graph(tmp_path):
+    """One GPT-2-small layer (GELU, exp, reciprocal, rsqrt) x both parties as one
+    autotuned work-list, replayed from a HIP graph: equal to the plain path,
+    sampled elements equal to the oracle."""
+    ops = W.config4(layers=1)
+    _flush("c4 layer 0 work-list")
+    insts = []
+    for op in ops:
+        inst = R.OpInstanceGPU(F.Spec(op.spec), W.N_BITS, W.F_BITS, len(op.x))
+        inst.set_input(op.x)
+        inst.keygen(op.seed)
+        inst.mask()
+        insts.append(inst)
+    for inst in insts:
+        for b in (0, 1):
+            inst.eval_plain(b)
+    torch.cuda.synchronize()
+    plain = [inst.host() for inst in insts]
+    items = [inst.item(b) for inst in insts for b in (0, 1)]
+    tune = F.fss_autotune(items, str(tmp_path / "tune.txt"))
+    again = F.fss_autotune(items, str(tmp_path / "tune.txt"))      # served from the cache
+    assert (tune.aes_variant, tune.blocks_per_cu, tune.order) == (again.aes_variant, again.blocks_per_cu,
+                                                                  again.order)
+    plan = F.Plan(items, tune)
+    graph = F.Graph([plan])
+    for rep in range(2):
+        for inst in insts:
+            for b in (0, 1):
+                inst.y[b].fill_(7)
+                inst.z[b].fill_(7)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        for a, inst in zip(plain, insts):
+            c = inst.host()
+            for k in ("y0", "y1", "z0", "z1"):
+                assert np.array_equal(a[k], c[k]), (rep, k)
+    assert F.fss_status() == 0
+    graph.free()
+    plan.free()
+    for op, inst, out in zip(ops, insts, plain):
+        N = len(op.x)
+        elems = np.unique(np.r_[np.linspace(0, N - 1, 48).astype(np.int64), [63, 64, N - 1]])
+        elems = elems[elems < N]
+        o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems)
+        out["keys0"] = inst.keys[0].cpu().numpy()
+        out["keys1"] = inst.keys[1].cpu().numpy()
+        compare(out, o, elems, N)
