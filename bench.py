@@ -131,7 +131,9 @@ def main() -> None:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=64, help="c5: requests in the Poisson stream")
+    ap.add_argument("--rate", type=float, default=50.0, help="c5: mean arrival rate (req/s)")
     ap.add_argument("--graphs", action="store_true", help="replay each layer's launch from a HIP graph")
     ap.add_argument("--autotune", default=None, metavar="CACHE",
                     help="autotune the fused launch on the first layer (cache file path)")
@@ -153,6 +155,9 @@ def main() -> None:
     from paper_2606_09551_amd import runtime as R
 
     torch.cuda.set_device(0)
+    if args.workload == "c5":
+        serve_bench(args)
+        return
     ops, n_bits, f_bits, wname = build_ops(args.workload)
     insts = []
     for op in ops:
@@ -267,6 +272,62 @@ def main() -> None:
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ops[0], n_bits, f_bits, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(args) -> None:
+    """Config 5: a Poisson stream of BERT-base requests (L ~ U{16..512}) served
+    by the continuous-batching server, fused and plain evaluators on the same
+    stream.  Party 0's server is evaluated; each request's keys are generated
+    on the device at admission (dealer time reported separately)."""
+    import gc
+
+    import torch
+
+    from paper_2606_09551_amd import serving as S
+    from paper_2606_09551_amd import workloads as W
+
+    reqs = W.config5_requests(args.requests, args.rate)
+    stream = [(r.rid, r.L, r.arrival) for r in reqs]
+    free, total = torch.cuda.mem_get_info()
+    arena = int(min(free * 0.85, 230 * 2**30))
+    out = {}
+    for path in ("fused", "plain"):
+        srv = S.Server(arena, layers=12, path=path)
+        st = srv.run(stream)
+        st.pop("_requests")
+        out[path] = st
+        del srv
+        gc.collect()
+        torch.cuda.empty_cache()
+    f, p = out["fused"], out["plain"]
+    line = {
+        "metric": METRIC,
+        "value": round(f["element_evals_per_s"], 1),
+        "unit": "element-evals/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(f["makespan_s"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"serving_bert_base_poisson_{args.rate:g}rps_{args.requests}req_L16_512",
+                   "party": 0, "layers": 12, "ops_per_layer": "gelu, exp, reciprocal, rsqrt x2 tokens",
+                   "arena_bytes": arena, "keys": "generated on the device at admission"},
+        "latency_s": f["latency_s"],
+        "admission_to_done_s": f["admission_to_done_s"],
+        "requests_per_s": round(f["requests_per_s"], 3),
+        "dealer_s": round(f["dealer_s"], 3),
+        "mean_batch_requests": round(f["mean_batch_requests"], 3),
+        "batches": f["batches"],
+        "plain": {"value": round(p["element_evals_per_s"], 1), "latency_s": p["latency_s"],
+                  "admission_to_done_s": p["admission_to_done_s"], "makespan_s": round(p["makespan_s"], 3)},
+        "fused_over_plain": round(f["element_evals_per_s"] / p["element_evals_per_s"], 4),
+        "offered_rps": args.rate,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -291,3 +291,48 @@ def request_ops(req: Request, layers: int = 12, seed: int = 0xC5) -> list:
 def all_specs() -> list:
     return [clip_relu_spec(), gelu_spec(), exp_spec(), recip_spec(7), recip_spec(8),
             recip_spec(9), rsqrt_spec(), relu_worked_example_spec()]
+
+
+# ---------------------------------------------------------------------------
+# Device-side inputs for served requests (too large to draw on the host):
+# the same distributions as above, drawn with torch's seeded CUDA generator.
+# ---------------------------------------------------------------------------
+
+REQUEST_OPS = ("gelu", "exp", "recip", "rsqrt")
+
+
+def request_op_sizes(L: int) -> dict:
+    """Elements of each nonlinearity call of one BERT-base layer at length L."""
+    return {"gelu": L * 3072, "exp": 12 * L * L, "recip": 12 * L, "rsqrt": 2 * L}
+
+
+def request_specs(L: int) -> dict:
+    recip_log2 = 7 if L <= 128 else (8 if L <= 256 else 9)
+    return {"gelu": gelu_spec(), "exp": exp_spec(), "recip": recip_spec(recip_log2),
+            "rsqrt": rsqrt_spec()}
+
+
+def request_layer_inputs_device(rid: int, L: int, layer: int, device="cuda", seed: int = 0xC5) -> dict:
+    """int64 plaintext inputs of one layer's four calls, generated on `device`."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(splitmix64(seed ^ (rid << 16) ^ layer) & ((1 << 63) - 1))
+    scale = float(1 << F_BITS)
+    lim = 1 << (N_BITS - 1)
+
+    def q(t):
+        return torch.clamp(torch.round(t * scale), -lim, lim - 1).to(torch.int64)
+
+    gelu = torch.randn(L * 3072, generator=g, device=device, dtype=torch.float64) * 1.5
+    logits = torch.randn(12, L, L, generator=g, device=device, dtype=torch.float64) * 3.0
+    centred = logits - logits.max(dim=-1, keepdim=True).values
+    sums = torch.exp(centred).sum(dim=-1)
+    sig = torch.pow(2.0, torch.rand(2 * L, generator=g, device=device, dtype=torch.float64) * 5.0 - 1.5)
+    vals = torch.randn(2 * L, 768, generator=g, device=device, dtype=torch.float64) * sig[:, None]
+    var = vals.var(dim=-1)
+    return {"gelu": q(gelu), "exp": q(centred.reshape(-1)), "recip": q(sums.reshape(-1)), "rsqrt": q(var)}
+
+
+def request_dealer_seed(rid: int, layer: int, op_index: int, seed: int = 0xC5) -> int:
+    return splitmix64(seed ^ (rid << 24) ^ (layer << 8) ^ op_index)

@@ -1,0 +1,86 @@
+"""Serving: each request's results are the same alone and in the continuous-
+batching mix (bit-exact), for the fused and the plain evaluator, and sampled
+party-0 shares equal the oracle's."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as O  # noqa: E402
+from paper_2606_09551_amd import serving as S  # noqa: E402
+from paper_2606_09551_amd import workloads as W  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+STREAM = [(0, 40, 0.0), (1, 16, 0.002), (2, 32, 0.004), (3, 24, 0.006), (4, 48, 0.008), (5, 20, 0.010)]
+KEEP = {1, 3}
+
+
+def _serve(stream, path, keep):
+    srv = S.Server(arena_bytes=3 * 2**30 // 2, layers=2, path=path)
+    stats = srv.run(stream, keep=keep)
+    return srv, stats, {r.rid: r for r in stats["_requests"]}
+
+
+def test_served_equals_alone_and_oracle():
+    print("serving mix (fused)", flush=True)
+    srv, stats, mix = _serve(STREAM, "fused", KEEP)
+    assert stats["requests"] == len(STREAM)
+    assert all(r.done >= r.admitted >= r.arrival for r in mix.values())
+    assert stats["mean_batch_requests"] > 1.0          # requests shared launches
+    # the arena (1.5 GB) cannot hold all six requests at once: admission queued some
+    assert stats["max_footprint_bytes"] * 3 > srv.arena.nbytes
+    assert srv.arena.free_bytes() == srv.arena.nbytes  # everything released
+    for rid in KEEP:
+        print(f"request {rid} alone", flush=True)
+        L = next(L for r, L, _ in STREAM if r == rid)
+        for path in ("fused", "plain"):
+            _, _, alone = _serve([(rid, L, 0.0)], path, {rid})
+            a, b = mix[rid].outputs, alone[rid].outputs
+            assert a.keys() == b.keys() and len(a) == 2 * len(W.REQUEST_OPS)
+            for k in a:
+                for u, v in zip(a[k], b[k]):
+                    assert np.array_equal(u, v), (rid, path, k)
+    # oracle: party-0 shares of sampled elements of every op of request 1, layer 1
+    rid, layer = 1, 1
+    L = 16
+    descs = W.request_specs(L)
+    for j, name in enumerate(W.REQUEST_OPS):
+        y, z, x = mix[rid].outputs[(layer, name)]
+        n = len(x)
+        elems = np.unique(np.r_[np.linspace(0, n - 1, 24).astype(np.int64), [n - 1]])
+        Sp = O.compile_spec(descs[name], W.N_BITS, W.F_BITS)
+        K0, _, r_in, _ = O.keygen(Sp, W.request_dealer_seed(rid, layer, j), elems)
+        xhat = x[elems].view(np.uint64) + r_in
+        y0, z0 = O.evaluate(0, Sp, K0, xhat)
+        assert np.array_equal(y[elems], y0), name
+        ell = Sp.ell
+        words = (n + 63) // 64
+        zp = z[: ell * words].reshape(ell, words)
+        got = np.zeros(len(elems), np.uint64)
+        for bit in range(ell):
+            got |= ((zp[bit][elems >> 6] >> (elems & 63).astype(np.uint64)) & np.uint64(1)) << np.uint64(bit)
+        assert np.array_equal(got, z0), name
+
+
+def test_arena_first_fit_and_coalescing():
+    a = S.KeyArena(4096, "cuda")
+    x = a.alloc(1000)
+    y = a.alloc(1000)
+    z = a.alloc(1000)
+    assert (x, y, z) == (0, 1024, 2048)
+    assert a.alloc(2000) is None
+    a.release(y, 1000)
+    a.release(x, 1000)
+    assert a.alloc(2000) == 0
+    a.release(0, 2000)
+    a.release(z, 1000)
+    assert a.free_bytes() == 4096 and a.free == [(0, 4096)]
