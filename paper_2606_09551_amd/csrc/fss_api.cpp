@@ -53,7 +53,7 @@ int env_int(const char* name, int dflt) {
 // Default AES table layouts of the plain evaluator and of keygen (override
 // with FSS_AES_VARIANT / FSS_KEYGEN_VARIANT).
 int eval_variant() { return env_int("FSS_AES_VARIANT", 1); }
-int keygen_variant() { return env_int("FSS_KEYGEN_VARIANT", 2); }
+int keygen_variant() { return env_int("FSS_KEYGEN_VARIANT", 1); }
 
 // Per-device library state: the status word kernels report into.
 std::mutex g_mu;
@@ -465,7 +465,7 @@ int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t
   for (int t = 0; t < kMaxAtoms; ++t) ga.bprime[t] = q->bprime[t];
   ga.n_elems = n_elems;
   ga.n_tiles = tiles;
-  HIP_TRY(launch_keygen(keygen_variant(), reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
+  HIP_TRY(launch_keygen(keygen_variant(), q->p, reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
                         (uint8_t*)key1, r_in, r_out, st),
           "keygen launch");
   return FSS_OK;

@@ -141,9 +141,9 @@ struct Tab3 {
   }
 };
 
-// Keygen holds both parties' walk state (about 250 VGPRs), so it always runs
-// 256-thread blocks whatever the table layout.
-constexpr int kKeygenBlock = 256;
+// Keygen holds both parties' walk state (up to about 190 VGPRs), so it runs
+// 512-thread blocks (two waves per SIMD) whatever the table layout.
+constexpr int kKeygenBlock = 512;
 
 template <int V> struct TabOf;
 template <> struct TabOf<0> { using T = Tab0; static constexpr int kBlock = 256; };
@@ -719,7 +719,6 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
                                         const uint64_t (&beta)[P], const uint32_t (&r0)[4],
                                         const uint32_t (&r1)[4], uint8_t* k0, uint8_t* k1, int lane) {
   constexpr int NB = (P + 1) / 2;
-  constexpr int KB = 2 * (1 + NB);  // blocks per party per level
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
   uint32_t t[2] = {0u, 1u};
   uint64_t Va[P];
@@ -729,42 +728,51 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   if (k1) st16(k1 + h->off_croot + lane * 16, make_uint4(s[1][0], s[1][1], s[1][2], s[1][3]));
   for (int i = 0; i < n; ++i) {
     const uint32_t ai = (uint32_t)(alpha >> (n - 1 - i)) & 1u;
-    uint32_t sk[2][4], sl[2][4], tk[2], tl[2];
-    uint64_t vk[2][P], vl[2][P];
+    // Per party: the child on alpha's path ("keep") and the other ("lose").
+    // Only what the correction words need is accumulated across the two
+    // parties: the lost seeds' XOR, v_lose(1) - v_lose(0), v_keep(0) - v_keep(1).
+    uint32_t sk[2][4], tk[2], scw[4] = {0u, 0u, 0u, 0u}, tkx = 0u, tlx = 0u;
+    uint64_t dl[P], dk[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) dl[q] = dk[q] = 0;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      uint32_t o[KB][4], jj[KB];
+      uint32_t o[1 + NB][4], jj[1 + NB];
       jj[0] = ai;
-      jj[1] = ai ^ 1u;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        jj[2 + q] = 2u + 2u * ai + q;
-        jj[2 + NB + q] = 2u + 2u * (ai ^ 1u) + q;
-      }
-      prg_shared<TB, KB>(tb, s[b], jj, o);
+      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * ai + q;
+      prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
       tk[b] = o[0][0] & 1u;
-      tl[b] = o[1][0] & 1u;
+      tkx ^= tk[b];
       sk[b][0] = o[0][0] & ~3u; sk[b][1] = o[0][1]; sk[b][2] = o[0][2]; sk[b][3] = o[0][3];
-      sl[b][0] = o[1][0] & ~3u; sl[b][1] = o[1][1]; sl[b][2] = o[1][2]; sl[b][3] = o[1][3];
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        vk[b][q] = mk64(o[2 + q / 2][2 * (q & 1)], o[2 + q / 2][2 * (q & 1) + 1]);
-        vl[b][q] = mk64(o[2 + NB + q / 2][2 * (q & 1)], o[2 + NB + q / 2][2 * (q & 1) + 1]);
+        const uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
+        dk[q] += b ? (0ull - v) : v;
       }
-    }
-    uint32_t scw[4];
+      __builtin_amdgcn_sched_barrier(0);
+      jj[0] = ai ^ 1u;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) scw[c] = sl[0][c] ^ sl[1][c];
+      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * (ai ^ 1u) + q;
+      prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
+      tlx ^= o[0][0] & 1u;
+      scw[0] ^= o[0][0] & ~3u; scw[1] ^= o[0][1]; scw[2] ^= o[0][2]; scw[3] ^= o[0][3];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
+        dl[q] += b ? v : (0ull - v);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
     const uint64_t neg = 0ull - (uint64_t)t[1];  // (-1)^{t_1} as a mask
     const uint64_t badd = 0ull - (uint64_t)ai;   // beta enters when the lost child is L
     uint64_t vcw[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      const uint64_t w = vl[1][q] - vl[0][q] - Va[q] + (beta[q] & badd);
+      const uint64_t w = dl[q] - Va[q] + (beta[q] & badd);
       vcw[q] = (w ^ neg) - neg;
-      Va[q] = Va[q] - vk[1][q] + vk[0][q] + ((vcw[q] ^ neg) - neg);
+      Va[q] = Va[q] + dk[q] + ((vcw[q] ^ neg) - neg);
     }
-    const uint32_t tkx = tk[0] ^ tk[1], tlx = tl[0] ^ tl[1];
     const uint32_t tL = (ai ? tlx : tkx) ^ ai ^ 1u;
     const uint32_t tR = (ai ? tkx : tlx) ^ ai;
     const uint4 cw = make_uint4(scw[0] | tL | (tR << 1), scw[1], scw[2], scw[3]);
@@ -833,7 +841,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
   }
 }
 
-template <int V>
+template <int V, int P>
 __global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* hdr, KgArgs ga, uint8_t* key0,
                                                               uint8_t* key1, uint64_t* r_in, uint64_t* r_out) {
   using TB = typename TabOf<V>::T;
@@ -887,12 +895,7 @@ __global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* hdr, K
   st8(t0 + h->off_w + lane * 8, W);
   if (t1) st8(t1 + h->off_w + lane * 8, W ^ wout);
 
-  switch (h->p) {
-    case 1: keygen_coeff<1>(tb, h, ga, e, rin, t0, t1, lane); break;
-    case 2: keygen_coeff<2>(tb, h, ga, e, rin, t0, t1, lane); break;
-    case 3: keygen_coeff<3>(tb, h, ga, e, rin, t0, t1, lane); break;
-    default: keygen_coeff<4>(tb, h, ga, e, rin, t0, t1, lane); break;
-  }
+  keygen_coeff<P>(tb, h, ga, e, rin, t0, t1, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -905,13 +908,19 @@ template <int V>
 int VariantOps<V>::lds_bytes() { return TabOf<V>::T::kWords * 4; }
 
 template <int V>
-hipError_t VariantOps<V>::keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
+hipError_t VariantOps<V>::keygen(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
                                  uint64_t* ri, uint64_t* ro, hipStream_t st) {
   constexpr int B = kKeygenBlock;
   const uint64_t per = B / 64;
   const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_keygen<V>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro);
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_keygen<V, 1>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
+    case 2: hipLaunchKernelGGL((k_keygen<V, 2>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
+    case 3: hipLaunchKernelGGL((k_keygen<V, 3>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
+    case 4: hipLaunchKernelGGL((k_keygen<V, 4>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -48,13 +48,13 @@ hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64
   return hipGetLastError();
 }
 
-hipError_t launch_keygen(int v, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
-                         uint64_t* ro, hipStream_t st) {
+hipError_t launch_keygen(int v, int p, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
+                         uint64_t* ri, uint64_t* ro, hipStream_t st) {
   switch (v) {
-    case 0: return VariantOps<0>::keygen(h, ga, k0, k1, ri, ro, st);
-    case 1: return VariantOps<1>::keygen(h, ga, k0, k1, ri, ro, st);
-    case 2: return VariantOps<2>::keygen(h, ga, k0, k1, ri, ro, st);
-    case 3: return VariantOps<3>::keygen(h, ga, k0, k1, ri, ro, st);
+    case 0: return VariantOps<0>::keygen(h, p, ga, k0, k1, ri, ro, st);
+    case 1: return VariantOps<1>::keygen(h, p, ga, k0, k1, ri, ro, st);
+    case 2: return VariantOps<2>::keygen(h, p, ga, k0, k1, ri, ro, st);
+    case 3: return VariantOps<3>::keygen(h, p, ga, k0, k1, ri, ro, st);
     default: return hipErrorInvalidValue;
   }
 }

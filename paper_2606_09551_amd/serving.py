@@ -10,8 +10,9 @@ server:
 * generates the admitted request's inputs, keys and masked inputs on a dealer
   stream, so dealer work overlaps evaluation of requests already admitted;
 * every scheduling step launches ONE fused work-list over the next layer of
-  every ready request that has no layer in flight (iteration-level continuous
-  batching); requests that arrive meanwhile join at the next step;
+  every ready request (iteration-level continuous batching): the next step
+  starts when the previous one completes, so everything that became ready
+  meanwhile (new arrivals whose keys are in place) joins it;
 * frees a request's arena block as soon as its last layer completes.
 
 All FSS work goes through the C ABI (`fss`); torch provides the arena, the
@@ -99,6 +100,7 @@ class Request:
     admitted: float = -1.0
     done: float = -1.0
     ready_event: object = None
+    layer_ready: list = field(default_factory=list)  # per-layer dealer completion events
     next_layer: int = 0
     in_flight: bool = False
     keep_outputs: bool = False
@@ -109,7 +111,7 @@ class Request:
 
 
 class Server:
-    def __init__(self, arena_bytes: int, layers: int = 12, path: str = "fused", max_in_flight: int = 2,
+    def __init__(self, arena_bytes: int, layers: int = 12, path: str = "fused", max_in_flight: int = 1,
                  tune: F.Tune | None = None, device: str = "cuda"):
         self.arena = KeyArena(arena_bytes, device)
         self.layers = layers
@@ -167,6 +169,7 @@ class Server:
         req.admitted = now
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
+        req.layer_ready = []
         with torch.cuda.stream(self.dealer):
             ev0.record(self.dealer)
             st = self.dealer.cuda_stream
@@ -178,6 +181,10 @@ class Server:
                                  self._addr(req, s.r_in), None, st)
                     F.fss_mask_input(self._addr(req, s.x), self._addr(req, s.r_in), s.n,
                                      self._addr(req, s.xhat), st)
+                # a layer can be evaluated as soon as its own keys are in place
+                ev = torch.cuda.Event()
+                ev.record(self.dealer)
+                req.layer_ready.append(ev)
             ev1.record(self.dealer)
         req.ready_event = ev1
         req._dealer_events = (ev0, ev1)
@@ -252,7 +259,7 @@ class Server:
             active = [r for r in active if r.done < 0]
             if len(inflight) < self.max_in_flight:
                 batch = [r for r in active if not r.in_flight and r.next_layer < self.layers
-                         and r.ready_event.query()]
+                         and r.layer_ready[r.next_layer].query()]
                 if batch:
                     inflight.append(self._launch(batch))
                     progressed = True
