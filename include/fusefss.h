@@ -191,10 +191,17 @@ int fss_plan_launch(fss_plan* plan, void* stream);
  * its device buffers to the library's pool.  Free graphs that captured a plan
  * before the plan itself. */
 int fss_plan_free(fss_plan* plan);
-/* Algorithmic AES-128 blocks one launch of `plan` evaluates (sum over items
- * of n_elems * (sum_t k_t + m * (n * (1 + ceil(p/2)) + ceil(p/2))));
- * used for throughput and roofline reporting. */
+/* AES-128 blocks one launch of `plan` evaluates, as the kernels compute them
+ * (per element and party, with B = 1 + ceil(p/2) blocks per tree level and
+ * D the shared top depth: sum_t k_t + (n + 2D + (m-1)(n-D)) B + m ceil(p/2);
+ * the m-1 lookup points share their first D levels, walked once for each of
+ * the two aligned blocks they fall in).  Used for throughput reporting. */
 double fss_plan_aes_blocks(const fss_plan* plan);
+/* T-table lookups of one launch: 16 per AES round, less the 24 lookups of
+ * rounds 1-2 that the blocks expanding one seed under K tweaks share
+ * (160 K - 24 (K - 1) per expansion).  The table-lookup rate of the CUs'
+ * local memory bounds the evaluation, so this is the roofline's work figure. */
+double fss_plan_table_lookups(const fss_plan* plan);
 /* Resolved launch configuration of a plan (host out-params). */
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid);
 

@@ -545,6 +545,7 @@ struct fss_plan {
   fss_tune tune{};
   int grid = 0;
   double aes_per_launch = 0;  // algorithmic AES blocks of one launch
+  double lookups_per_launch = 0;  // T-table lookups of one launch
 };
 
 namespace {
@@ -617,6 +618,20 @@ double elem_aes(const KeyHeader& h) {
   return a;
 }
 
+// Per-element T-table lookups of one party's evaluation: 16 per AES round.
+// Blocks that expand one seed under K tweaks differ only in byte 15, so they
+// share 12 lookups of round 1 and 12 of round 2 (identical addresses in the
+// unchanging table; round 2's are merged by the compiler).
+double elem_lookups(const KeyHeader& h) {
+  auto shared = [](double K) { return 160.0 * K - 24.0 * (K - 1.0); };
+  double a = 0;
+  for (uint32_t t = 0; t < h.T; ++t) a += 160.0 * h.atom_k[t];
+  const double nb = (double)((h.p + 1) / 2), n = h.n, D = h.top_depth;
+  const double levels = n + 2 * D + (double)(h.m - 1) * (n - D);
+  a += levels * shared(1 + nb) + (double)h.m * shared(nb);
+  return a;
+}
+
 // Header reads go through a library-owned non-blocking stream so they never
 // wait for kernels running on other streams (the caller orders keygen first).
 int aux_stream(hipStream_t* out) {
@@ -680,7 +695,7 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   std::vector<DevItem> dev(n_items);
   struct T { uint32_t item, tile; double cost; };
   std::vector<T> tl;
-  double aes_total = 0;
+  double aes_total = 0, lookups_total = 0;
   for (int i = 0; i < n_items; ++i) {
     const fss_work_item& it = items[i];
     if ((rc = check_party(it.party))) return rc;
@@ -695,6 +710,7 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
     dev[i] = DevItem{(const uint8_t*)it.keys, it.xhat, it.y, it.zbits, it.n_elems, it.party, (int32_t)tiles};
     const double c = elem_aes(h);
     aes_total += c * (double)it.n_elems;
+    lookups_total += elem_lookups(h) * (double)it.n_elems;
     for (uint64_t t = 0; t < tiles; ++t) tl.push_back({(uint32_t)i, (uint32_t)t, c});
   }
   if (tl.size() > 0xffffffffull) return fail(FSS_E_UNSUPPORTED, "work-list too long");
@@ -730,6 +746,7 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   P->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
                                       (int)((tl.size() * 64 + tn.block_threads - 1) / tn.block_threads)));
   P->aes_per_launch = aes_total;
+  P->lookups_per_launch = lookups_total;
   *out = P.release();
   return FSS_OK;
 }
@@ -895,6 +912,7 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
 // Extra introspection used by the benchmark: algorithmic AES blocks of one
 // launch of a plan, and its resolved launch configuration.
 double fss_plan_aes_blocks(const fss_plan* plan) { return plan ? plan->aes_per_launch : 0.0; }
+double fss_plan_table_lookups(const fss_plan* plan) { return plan ? plan->lookups_per_launch : 0.0; }
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid) {
   if (!plan || !tune || !grid) return fail(FSS_E_ARG, "NULL argument");
   *tune = plan->tune;

@@ -141,10 +141,6 @@ struct Tab3 {
   }
 };
 
-// Keygen holds both parties' walk state (up to about 190 VGPRs), so it runs
-// 512-thread blocks (two waves per SIMD) whatever the table layout.
-constexpr int kKeygenBlock = 512;
-
 template <int V> struct TabOf;
 template <> struct TabOf<0> { using T = Tab0; static constexpr int kBlock = 256; };
 template <> struct TabOf<1> { using T = Tab1; static constexpr int kBlock = 768; };
@@ -841,8 +837,16 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
   }
 }
 
+// Keygen runs the table layout's block size, like evaluation: the layout's
+// tables fill one CU's local memory, so the block size sets the waves per CU.
+// With P <= 3, both parties' walk state exceeds that register budget by a few
+// values live across a whole level (spilled: a handful of accesses per level);
+// P = 4 would spill inside the AES rounds, so it keeps two waves per SIMD.
 template <int V, int P>
-__global__ __launch_bounds__(kKeygenBlock) void k_keygen(const KeyHeader* hdr, KgArgs ga, uint8_t* key0,
+constexpr int keygen_block() { return (P >= 4 && TabOf<V>::kBlock > 512) ? 512 : TabOf<V>::kBlock; }
+
+template <int V, int P>
+__global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHeader* hdr, KgArgs ga, uint8_t* key0,
                                                               uint8_t* key1, uint64_t* r_in, uint64_t* r_out) {
   using TB = typename TabOf<V>::T;
   __shared__ uint32_t lds[TB::kWords];
@@ -907,21 +911,27 @@ int VariantOps<V>::block() { return TabOf<V>::kBlock; }
 template <int V>
 int VariantOps<V>::lds_bytes() { return TabOf<V>::T::kWords * 4; }
 
+template <int V, int P>
+hipError_t launch_keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
+                         uint64_t* ro, hipStream_t st) {
+  constexpr int B = keygen_block<V, P>();
+  const uint64_t per = B / 64;
+  const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
+  hipLaunchKernelGGL((k_keygen<V, P>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro);
+  return hipGetLastError();
+}
+
 template <int V>
 hipError_t VariantOps<V>::keygen(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
                                  uint64_t* ri, uint64_t* ro, hipStream_t st) {
-  constexpr int B = kKeygenBlock;
-  const uint64_t per = B / 64;
-  const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
-  if (grid == 0) return hipSuccess;
+  if (ga.n_tiles == 0) return hipSuccess;
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_keygen<V, 1>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
-    case 2: hipLaunchKernelGGL((k_keygen<V, 2>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
-    case 3: hipLaunchKernelGGL((k_keygen<V, 3>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
-    case 4: hipLaunchKernelGGL((k_keygen<V, 4>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro); break;
+    case 1: return launch_keygen<V, 1>(h, ga, k0, k1, ri, ro, st);
+    case 2: return launch_keygen<V, 2>(h, ga, k0, k1, ri, ro, st);
+    case 3: return launch_keygen<V, 3>(h, ga, k0, k1, ri, ro, st);
+    case 4: return launch_keygen<V, 4>(h, ga, k0, k1, ri, ro, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <int V>

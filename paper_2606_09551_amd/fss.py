@@ -4,14 +4,25 @@ Argument marshalling only: every step of the hot path runs in the library's
 HIP kernels.  Device buffers are passed as integer addresses (for example
 ``tensor.data_ptr()``) and streams as ``torch.cuda.current_stream().cuda_stream``.
 Importing this module loads the native library and raises if it is missing.
+
+The library links the HIP runtime by soname.  torch brings its own copy of
+that runtime, and a process must hold only one (two HSA runtimes in one
+process do not share the device), so torch is imported first: the library
+then binds to the runtime torch already loaded.  ``FUSEFSS_LIB`` names
+another build of the library to load instead of the in-tree one.
 """
 from __future__ import annotations
 
 import ctypes as C
 import os
 
+try:  # load torch's HIP runtime before the library resolves its own
+    import torch  # noqa: F401
+except ImportError:  # the C ABI stays usable without torch
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libfusefss.so")
+LIB_PATH = os.environ.get("FUSEFSS_LIB") or os.path.join(_HERE, "_lib", "libfusefss.so")
 
 FSS_OK = 0
 ERRORS = {-1: "FSS_E_INVALID_SPEC", -2: "FSS_E_UNSUPPORTED", -3: "FSS_E_NEEDS_PHI",
@@ -81,6 +92,7 @@ def _load():
         "fss_plan_launch": [vp, vp],
         "fss_plan_free": [vp],
         "fss_plan_aes_blocks": [vp],
+        "fss_plan_table_lookups": [vp],
         "fss_plan_config": [vp, C.POINTER(Tune), C.POINTER(i32)],
         "fss_graph_capture": [C.POINTER(vp), i32, C.POINTER(vp)],
         "fss_graph_launch": [vp, vp],
@@ -97,6 +109,7 @@ def _load():
         f.restype = C.c_int
     L.fss_spec_free.restype = None
     L.fss_plan_aes_blocks.restype = C.c_double
+    L.fss_plan_table_lookups.restype = C.c_double
     L.fss_last_error.restype = C.c_char_p
     L.fss_version.restype = C.c_char_p
     return L
@@ -228,6 +241,9 @@ class Plan:
 
     def aes_blocks(self) -> float:
         return lib.fss_plan_aes_blocks(self.handle)
+
+    def table_lookups(self) -> float:
+        return lib.fss_plan_table_lookups(self.handle)
 
     def config(self) -> dict:
         t, g = Tune(), C.c_int32()

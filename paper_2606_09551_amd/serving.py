@@ -112,8 +112,12 @@ class Request:
 
 class Server:
     def __init__(self, arena_bytes: int, layers: int = 12, path: str = "fused", max_in_flight: int = 1,
-                 tune: F.Tune | None = None, device: str = "cuda"):
+                 tune: F.Tune | None = None, device: str = "cuda", dealer_sync: bool = False):
+        """`dealer_sync` makes admission wait until the request's keys are in
+        place (deterministic batching, e.g. for tests); by default dealer work
+        overlaps evaluation."""
         self.arena = KeyArena(arena_bytes, device)
+        self.dealer_sync = dealer_sync
         self.layers = layers
         self.path = path
         self.max_in_flight = max_in_flight
@@ -188,6 +192,8 @@ class Server:
             ev1.record(self.dealer)
         req.ready_event = ev1
         req._dealer_events = (ev0, ev1)
+        if self.dealer_sync:
+            ev1.synchronize()
         return True
 
     # -- evaluation --------------------------------------------------------------

