@@ -184,12 +184,29 @@ def main() -> None:
     eval_lookups = sum(p.table_lookups() for p in plans)
     kg_aes = sum(keygen_aes_per_elem(i) * i.n for i in insts)
 
+    # Dealer work of different operators is independent: with several operators
+    # it is spread over side streams (joined before evaluation), so the
+    # keygen of a small operator overlaps that of a large one.
+    dealers = [torch.cuda.Stream() for _ in range(min(4, len(insts)))] if len(insts) > 1 else []
+
     def step(k: int, fused: bool, ev):
         base = 0xB3C4 + 7919 * k
         ev[0].record(stream)
-        for j, (inst, op) in enumerate(zip(insts, ops)):
-            inst.keygen((op.seed ^ base) + j)
-            inst.mask()
+        if dealers:
+            for d in dealers:
+                d.wait_event(ev[0])
+            for j, (inst, op) in enumerate(zip(insts, ops)):
+                with torch.cuda.stream(dealers[j % len(dealers)]):
+                    inst.keygen((op.seed ^ base) + j)
+                    inst.mask()
+            for d in dealers:
+                done = torch.cuda.Event()
+                done.record(d)
+                stream.wait_event(done)
+        else:
+            for j, (inst, op) in enumerate(zip(insts, ops)):
+                inst.keygen((op.seed ^ base) + j)
+                inst.mask()
         ev[1].record(stream)
         if fused:
             if graphs:

@@ -59,6 +59,24 @@ int keygen_variant() { return env_int("FSS_KEYGEN_VARIANT", 1); }
 std::mutex g_mu;
 std::map<int, int*> g_status_buf;
 
+// Compute units of the current device (cached per device): launch shapes of
+// the per-operator kernels spread small batches over all CUs.
+std::map<int, int> g_cus;
+
+int current_cus(int* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_cus.find(dev);
+  if (it == g_cus.end()) {
+    int c = 0;
+    HIP_TRY(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    it = g_cus.emplace(dev, c > 0 ? c : 1).first;
+  }
+  *out = it->second;
+  return FSS_OK;
+}
+
 int device_status_ptr(int** out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
@@ -465,8 +483,10 @@ int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t
   for (int t = 0; t < kMaxAtoms; ++t) ga.bprime[t] = q->bprime[t];
   ga.n_elems = n_elems;
   ga.n_tiles = tiles;
+  int cus = 0;
+  if ((rc = current_cus(&cus))) return rc;
   HIP_TRY(launch_keygen(keygen_variant(), q->p, reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
-                        (uint8_t*)key1, r_in, r_out, st),
+                        (uint8_t*)key1, r_in, r_out, cus, st),
           "keygen launch");
   return FSS_OK;
 }
@@ -485,7 +505,9 @@ int fss_eval_pred(int32_t party, const void* keys, const uint64_t* xhat, int64_t
   if (!keys || n_elems < 0 || (n_elems > 0 && (!xhat || !zbits))) return fail(FSS_E_ARG, "bad arguments");
   int* st = nullptr;
   if ((rc = device_status_ptr(&st))) return rc;
-  HIP_TRY(launch_eval_pred(eval_variant(), party, (const uint8_t*)keys, xhat, n_elems, zbits, st,
+  int cus = 0;
+  if ((rc = current_cus(&cus))) return rc;
+  HIP_TRY(launch_eval_pred(eval_variant(), party, (const uint8_t*)keys, xhat, n_elems, zbits, st, cus,
                            (hipStream_t)stream),
           "pred launch");
   return FSS_OK;
@@ -498,7 +520,9 @@ int fss_eval_coeff(int32_t party, const void* keys, const uint64_t* xhat, int64_
   if (!keys || n_elems < 0 || (n_elems > 0 && (!xhat || !y))) return fail(FSS_E_ARG, "bad arguments");
   int* st = nullptr;
   if ((rc = device_status_ptr(&st))) return rc;
-  HIP_TRY(launch_eval_coeff(eval_variant(), party, (const uint8_t*)keys, xhat, n_elems, y, st,
+  int cus = 0;
+  if ((rc = current_cus(&cus))) return rc;
+  HIP_TRY(launch_eval_coeff(eval_variant(), party, (const uint8_t*)keys, xhat, n_elems, y, st, cus,
                             (hipStream_t)stream),
           "coeff launch");
   return FSS_OK;

@@ -37,12 +37,14 @@ template <int V>
 struct VariantOps {
   static int block();
   static int lds_bytes();
+  // `cus`: compute units of the device; batches with fewer tiles than a full
+  // grid get smaller blocks so their tiles spread over the CUs.
   static hipError_t keygen(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
-                           uint64_t* ro, hipStream_t st);
+                           uint64_t* ro, int cus, hipStream_t st);
   static hipError_t pred(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* z,
-                         int* status, hipStream_t st);
+                         int* status, int cus, hipStream_t st);
   static hipError_t coeff(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* y,
-                          int* status, hipStream_t st);
+                          int* status, int cus, hipStream_t st);
   static hipError_t fused(const DevItem* items, const uint32_t* tiles, uint32_t n_tiles, uint32_t* counter,
                           int* status, int grid, hipStream_t st);
 };
@@ -54,13 +56,13 @@ extern template struct VariantOps<3>;
 hipError_t launch_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
                               uint32_t party, hipStream_t st);
 hipError_t launch_keygen(int variant, int p, const KeyHeader* dev_hdr, const KgArgs& ga, uint8_t* key0,
-                         uint8_t* key1, uint64_t* r_in, uint64_t* r_out, hipStream_t st);
+                         uint8_t* key1, uint64_t* r_in, uint64_t* r_out, int cus, hipStream_t st);
 hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat,
                        hipStream_t st);
 hipError_t launch_eval_pred(int variant, int party, const uint8_t* keys, const uint64_t* xhat,
-                            int64_t n, uint64_t* z, int* status, hipStream_t st);
+                            int64_t n, uint64_t* z, int* status, int cus, hipStream_t st);
 hipError_t launch_eval_coeff(int variant, int party, const uint8_t* keys, const uint64_t* xhat,
-                             int64_t n, uint64_t* y, int* status, hipStream_t st);
+                             int64_t n, uint64_t* y, int* status, int cus, hipStream_t st);
 // Resets the work counter with a kernel (graph-safe), then launches the
 // persistent kernel with `grid` blocks of the variant's block size.
 hipError_t launch_fused(int variant, const DevItem* items, const uint32_t* tiles, uint32_t n_tiles,

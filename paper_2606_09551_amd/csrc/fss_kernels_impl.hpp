@@ -95,10 +95,11 @@ struct Tab1 {
     return *reinterpret_cast<const uint32_t*>(lds + a + (TBL & 1) * 128);
   }
   __device__ static void fill(uint32_t* lds, int tid, int nthr) {
-    for (int i = tid; i < 32768; i += nthr) {
-      int sub = (i >> 5) & 1, x = (i >> 6) & 255, bank = i >> 14;
-      int tbl = bank * 2 + sub;
-      lds[i] = rotl8n(c_aes.te0[x], 8 * tbl);
+    // 16-byte chunk j covers words 4j..4j+3: one table entry, 4 of its 32 copies
+    for (int j = tid; j < 8192; j += nthr) {
+      const int sub = (j >> 3) & 1, x = (j >> 4) & 255, bank = j >> 12;
+      const uint32_t v = rotl8n(c_aes.te0[x], 8 * (bank * 2 + sub));
+      reinterpret_cast<uint4*>(lds)[j] = make_uint4(v, v, v, v);
     }
   }
 };
@@ -117,9 +118,9 @@ struct Tab2 {
     return rotl8n(v, 8 * (TBL & 1));
   }
   __device__ static void fill(uint32_t* lds, int tid, int nthr) {
-    for (int i = tid; i < 16384; i += nthr) {
-      int sub = (i >> 5) & 1, x = i >> 6;
-      lds[i] = rotl8n(c_aes.te0[x], 16 * sub);
+    for (int j = tid; j < 4096; j += nthr) {
+      const uint32_t v = rotl8n(c_aes.te0[j >> 4], 16 * ((j >> 3) & 1));
+      reinterpret_cast<uint4*>(lds)[j] = make_uint4(v, v, v, v);
     }
   }
 };
@@ -137,7 +138,10 @@ struct Tab3 {
     return rotl8n(*reinterpret_cast<const uint32_t*>(lds + a), 8 * TBL);
   }
   __device__ static void fill(uint32_t* lds, int tid, int nthr) {
-    for (int i = tid; i < 16384; i += nthr) lds[i] = c_aes.te0[i >> 6];
+    for (int j = tid; j < 4096; j += nthr) {
+      const uint32_t v = c_aes.te0[j >> 4];
+      reinterpret_cast<uint4*>(lds)[j] = make_uint4(v, v, v, v);
+    }
   }
 };
 
@@ -545,7 +549,7 @@ template <int V>
 __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_pred(const uint8_t* keys, const uint64_t* xhat,
                                                                  int64_t n, uint64_t* z, int party, int* status) {
   using TB = typename TabOf<V>::T;
-  __shared__ uint32_t lds[TB::kWords];
+  __shared__ __align__(16) uint32_t lds[TB::kWords];
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
   const GHdr h = ghdr(keys);
@@ -570,7 +574,7 @@ template <int V>
 __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* keys, const uint64_t* xhat,
                                                                   int64_t n, uint64_t* y, int party, int* status) {
   using TB = typename TabOf<V>::T;
-  __shared__ uint32_t lds[TB::kWords];
+  __shared__ __align__(16) uint32_t lds[TB::kWords];
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
   const GHdr h = ghdr(keys);
@@ -601,7 +605,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
                                                              uint32_t n_tiles, uint32_t* counter,
                                                              int* status) {
   using TB = typename TabOf<V>::T;
-  __shared__ uint32_t lds[TB::kWords];
+  __shared__ __align__(16) uint32_t lds[TB::kWords];
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -849,7 +853,7 @@ template <int V, int P>
 __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHeader* hdr, KgArgs ga, uint8_t* key0,
                                                               uint8_t* key1, uint64_t* r_in, uint64_t* r_out) {
   using TB = typename TabOf<V>::T;
-  __shared__ uint32_t lds[TB::kWords];
+  __shared__ __align__(16) uint32_t lds[TB::kWords];
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -911,48 +915,59 @@ int VariantOps<V>::block() { return TabOf<V>::kBlock; }
 template <int V>
 int VariantOps<V>::lds_bytes() { return TabOf<V>::T::kWords * 4; }
 
+// Waves (tiles) per block: the full block when there are enough tiles to give
+// every CU one, otherwise ceil(tiles / CUs), so a small batch runs on as many
+// CUs as it has tiles instead of queueing its tiles on a few of them.
+inline uint64_t waves_per_block(uint64_t tiles, int cus, int block) {
+  const uint64_t full = (uint64_t)block / 64;
+  const uint64_t c = cus > 0 ? (uint64_t)cus : 1;
+  const uint64_t w = (tiles + c - 1) / c;
+  return w < 1 ? 1 : (w > full ? full : w);
+}
+
 template <int V, int P>
 hipError_t launch_keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
-                         uint64_t* ro, hipStream_t st) {
-  constexpr int B = keygen_block<V, P>();
-  const uint64_t per = B / 64;
+                         uint64_t* ro, int cus, hipStream_t st) {
+  const uint64_t per = waves_per_block(ga.n_tiles, cus, keygen_block<V, P>());
   const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
-  hipLaunchKernelGGL((k_keygen<V, P>), dim3(grid), dim3(B), 0, st, h, ga, k0, k1, ri, ro);
+  hipLaunchKernelGGL((k_keygen<V, P>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, h, ga, k0, k1, ri, ro);
   return hipGetLastError();
 }
 
 template <int V>
 hipError_t VariantOps<V>::keygen(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
-                                 uint64_t* ri, uint64_t* ro, hipStream_t st) {
+                                 uint64_t* ri, uint64_t* ro, int cus, hipStream_t st) {
   if (ga.n_tiles == 0) return hipSuccess;
   switch (p) {
-    case 1: return launch_keygen<V, 1>(h, ga, k0, k1, ri, ro, st);
-    case 2: return launch_keygen<V, 2>(h, ga, k0, k1, ri, ro, st);
-    case 3: return launch_keygen<V, 3>(h, ga, k0, k1, ri, ro, st);
-    case 4: return launch_keygen<V, 4>(h, ga, k0, k1, ri, ro, st);
+    case 1: return launch_keygen<V, 1>(h, ga, k0, k1, ri, ro, cus, st);
+    case 2: return launch_keygen<V, 2>(h, ga, k0, k1, ri, ro, cus, st);
+    case 3: return launch_keygen<V, 3>(h, ga, k0, k1, ri, ro, cus, st);
+    case 4: return launch_keygen<V, 4>(h, ga, k0, k1, ri, ro, cus, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int V>
 hipError_t VariantOps<V>::pred(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* z,
-                               int* status, hipStream_t st) {
-  constexpr int B = TabOf<V>::kBlock;
-  const uint64_t tiles = ((uint64_t)n + 63) / 64, per = B / 64;
+                               int* status, int cus, hipStream_t st) {
+  const uint64_t tiles = ((uint64_t)n + 63) / 64;
+  if (tiles == 0) return hipSuccess;
+  const uint64_t per = waves_per_block(tiles, cus, TabOf<V>::kBlock);
   const unsigned grid = (unsigned)((tiles + per - 1) / per);
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_eval_pred<V>), dim3(grid), dim3(B), 0, st, keys, xhat, n, z, party, status);
+  hipLaunchKernelGGL((k_eval_pred<V>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, keys, xhat, n, z, party,
+                     status);
   return hipGetLastError();
 }
 
 template <int V>
 hipError_t VariantOps<V>::coeff(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* y,
-                                int* status, hipStream_t st) {
-  constexpr int B = TabOf<V>::kBlock;
-  const uint64_t tiles = ((uint64_t)n + 63) / 64, per = B / 64;
+                                int* status, int cus, hipStream_t st) {
+  const uint64_t tiles = ((uint64_t)n + 63) / 64;
+  if (tiles == 0) return hipSuccess;
+  const uint64_t per = waves_per_block(tiles, cus, TabOf<V>::kBlock);
   const unsigned grid = (unsigned)((tiles + per - 1) / per);
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_eval_coeff<V>), dim3(grid), dim3(B), 0, st, keys, xhat, n, y, party, status);
+  hipLaunchKernelGGL((k_eval_coeff<V>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, keys, xhat, n, y, party,
+                     status);
   return hipGetLastError();
 }
 

@@ -49,34 +49,34 @@ hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64
 }
 
 hipError_t launch_keygen(int v, int p, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
-                         uint64_t* ri, uint64_t* ro, hipStream_t st) {
+                         uint64_t* ri, uint64_t* ro, int cus, hipStream_t st) {
   switch (v) {
-    case 0: return VariantOps<0>::keygen(h, p, ga, k0, k1, ri, ro, st);
-    case 1: return VariantOps<1>::keygen(h, p, ga, k0, k1, ri, ro, st);
-    case 2: return VariantOps<2>::keygen(h, p, ga, k0, k1, ri, ro, st);
-    case 3: return VariantOps<3>::keygen(h, p, ga, k0, k1, ri, ro, st);
+    case 0: return VariantOps<0>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
+    case 1: return VariantOps<1>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
+    case 2: return VariantOps<2>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
+    case 3: return VariantOps<3>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_eval_pred(int v, int party, const uint8_t* keys, const uint64_t* xhat, int64_t n,
-                            uint64_t* z, int* status, hipStream_t st) {
+                            uint64_t* z, int* status, int cus, hipStream_t st) {
   switch (v) {
-    case 0: return VariantOps<0>::pred(party, keys, xhat, n, z, status, st);
-    case 1: return VariantOps<1>::pred(party, keys, xhat, n, z, status, st);
-    case 2: return VariantOps<2>::pred(party, keys, xhat, n, z, status, st);
-    case 3: return VariantOps<3>::pred(party, keys, xhat, n, z, status, st);
+    case 0: return VariantOps<0>::pred(party, keys, xhat, n, z, status, cus, st);
+    case 1: return VariantOps<1>::pred(party, keys, xhat, n, z, status, cus, st);
+    case 2: return VariantOps<2>::pred(party, keys, xhat, n, z, status, cus, st);
+    case 3: return VariantOps<3>::pred(party, keys, xhat, n, z, status, cus, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_eval_coeff(int v, int party, const uint8_t* keys, const uint64_t* xhat, int64_t n,
-                             uint64_t* y, int* status, hipStream_t st) {
+                             uint64_t* y, int* status, int cus, hipStream_t st) {
   switch (v) {
-    case 0: return VariantOps<0>::coeff(party, keys, xhat, n, y, status, st);
-    case 1: return VariantOps<1>::coeff(party, keys, xhat, n, y, status, st);
-    case 2: return VariantOps<2>::coeff(party, keys, xhat, n, y, status, st);
-    case 3: return VariantOps<3>::coeff(party, keys, xhat, n, y, status, st);
+    case 0: return VariantOps<0>::coeff(party, keys, xhat, n, y, status, cus, st);
+    case 1: return VariantOps<1>::coeff(party, keys, xhat, n, y, status, cus, st);
+    case 2: return VariantOps<2>::coeff(party, keys, xhat, n, y, status, cus, st);
+    case 3: return VariantOps<3>::coeff(party, keys, xhat, n, y, status, cus, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -7,8 +7,10 @@ server:
 * admits arrived requests in FIFO order when the key arena has room for the
   request's whole footprint (all of its layers' keys are preloaded: one-time
   key material stays device-resident until the request finishes);
-* generates the admitted request's inputs, keys and masked inputs on a dealer
-  stream, so dealer work overlaps evaluation of requests already admitted;
+* generates the admitted request's inputs, keys and masked inputs on dealer
+  streams (the operators of a layer spread over several, so a small
+  operator's keygen overlaps a large one's), overlapping evaluation of
+  requests already admitted;
 * every scheduling step launches ONE fused work-list over the next layer of
   every ready request (iteration-level continuous batching): the next step
   starts when the previous one completes, so everything that became ready
@@ -112,7 +114,8 @@ class Request:
 
 class Server:
     def __init__(self, arena_bytes: int, layers: int = 12, path: str = "fused", max_in_flight: int = 1,
-                 tune: F.Tune | None = None, device: str = "cuda", dealer_sync: bool = False):
+                 tune: F.Tune | None = None, device: str = "cuda", dealer_sync: bool = False,
+                 dealer_streams: int = 4):
         """`dealer_sync` makes admission wait until the request's keys are in
         place (deterministic batching, e.g. for tests); by default dealer work
         overlaps evaluation."""
@@ -123,7 +126,7 @@ class Server:
         self.max_in_flight = max_in_flight
         self.tune = tune
         self.device = device
-        self.dealer = torch.cuda.Stream(device=device)
+        self.dealers = [torch.cuda.Stream(device=device) for _ in range(max(1, dealer_streams))]
         self.evals = torch.cuda.Stream(device=device)
         self.specs: dict = {}
         self.dealer_ms = 0.0
@@ -174,22 +177,39 @@ class Server:
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         req.layer_ready = []
-        with torch.cuda.stream(self.dealer):
-            ev0.record(self.dealer)
-            st = self.dealer.cuda_stream
-            for layer in range(self.layers):
+        lead = self.dealers[0]
+        ev0.record(lead)
+        for d in self.dealers[1:]:
+            d.wait_event(ev0)
+        for layer in range(self.layers):
+            with torch.cuda.stream(lead):
                 xs = W.request_layer_inputs_device(req.rid, req.L, layer, self.device)
-                for s in req.slots[layer]:
+            inputs_ready = torch.cuda.Event()
+            inputs_ready.record(lead)
+            evs = []
+            for j, s in enumerate(req.slots[layer]):
+                d = self.dealers[j % len(self.dealers)]
+                if d is not lead:
+                    d.wait_event(inputs_ready)
+                with torch.cuda.stream(d):
                     self._view(req, s.x, s.n).copy_(xs[s.name])
                     F.fss_keygen(s.spec, W.N_BITS, W.F_BITS, s.seed, s.n, self._addr(req, s.key), None,
-                                 self._addr(req, s.r_in), None, st)
+                                 self._addr(req, s.r_in), None, d.cuda_stream)
                     F.fss_mask_input(self._addr(req, s.x), self._addr(req, s.r_in), s.n,
-                                     self._addr(req, s.xhat), st)
-                # a layer can be evaluated as soon as its own keys are in place
-                ev = torch.cuda.Event()
-                ev.record(self.dealer)
-                req.layer_ready.append(ev)
-            ev1.record(self.dealer)
+                                     self._addr(req, s.xhat), d.cuda_stream)
+                    ev = torch.cuda.Event()
+                    ev.record(d)
+                    evs.append(ev)
+                # the generated inputs are read on this side stream
+                for t in xs.values():
+                    t.record_stream(d)
+            # a layer can be evaluated as soon as its own keys are in place
+            req.layer_ready.append(evs)
+        for d in self.dealers[1:]:
+            done = torch.cuda.Event()
+            done.record(d)
+            lead.wait_event(done)
+        ev1.record(lead)
         req.ready_event = ev1
         req._dealer_events = (ev0, ev1)
         if self.dealer_sync:
@@ -265,7 +285,7 @@ class Server:
             active = [r for r in active if r.done < 0]
             if len(inflight) < self.max_in_flight:
                 batch = [r for r in active if not r.in_flight and r.next_layer < self.layers
-                         and r.layer_ready[r.next_layer].query()]
+                         and all(e.query() for e in r.layer_ready[r.next_layer])]
                 if batch:
                     inflight.append(self._launch(batch))
                     progressed = True
