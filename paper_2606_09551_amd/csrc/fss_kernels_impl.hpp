@@ -670,13 +670,17 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
   if (a1) st16(a1 + lane * 16, make_uint4(s1[0], s1[1], s1[2], s1[3]));
   for (int i = 0; i < k; ++i) {
     const uint32_t ai = (uint32_t)(alpha >> (k - 1 - i)) & 1u;
-    uint32_t in[4][4], o[4][4];
-    const uint32_t jj[4] = {ai, ai ^ 1u, ai, ai ^ 1u};  // p0 keep, p0 lose, p1 keep, p1 lose
+    uint32_t o[4][4];  // p0 keep, p0 lose, p1 keep, p1 lose
+    {
+      const uint32_t jj[2] = {ai, ai ^ 1u};
+      uint32_t oa[2][4], ob[2][4];
+      prg_shared<TB, 2>(tb, s0, jj, oa);
+      prg_shared<TB, 2>(tb, s1, jj, ob);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      in[0][c] = s0[c]; in[1][c] = s0[c]; in[2][c] = s1[c]; in[3][c] = s1[c];
+      for (int c = 0; c < 4; ++c) {
+        o[0][c] = oa[0][c]; o[1][c] = oa[1][c]; o[2][c] = ob[0][c]; o[3][c] = ob[1][c];
+      }
     }
-    prg<TB, 4>(tb, in, jj, o);
     const uint32_t tk0 = o[0][0] & 1u, tl0 = o[1][0] & 1u, tk1 = o[2][0] & 1u, tl1 = o[3][0] & 1u;
     const uint32_t vk0 = (o[0][0] >> 1) & 1u, vl0 = (o[1][0] >> 1) & 1u;
     const uint32_t vk1 = (o[2][0] >> 1) & 1u, vl1 = (o[3][0] >> 1) & 1u;
@@ -719,41 +723,36 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
                                         const uint64_t (&beta)[P], const uint32_t (&r0)[4],
                                         const uint32_t (&r1)[4], uint8_t* k0, uint8_t* k1, int lane) {
   constexpr int NB = (P + 1) / 2;
+  // Header offsets are read before the first key store: the compiler cannot
+  // tell the key stores from header memory, and a header read after a store
+  // would wait for the store to complete.
+  const uint64_t off_croot = h->off_croot, off_ccw = h->off_ccw, off_cvcw = h->off_cvcw;
+  const uint64_t off_cfin = h->off_cfin;
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
   uint32_t t[2] = {0u, 1u};
   uint64_t Va[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) Va[q] = 0;
-  st16(k0 + h->off_croot + lane * 16, make_uint4(s[0][0], s[0][1], s[0][2], s[0][3]));
-  if (k1) st16(k1 + h->off_croot + lane * 16, make_uint4(s[1][0], s[1][1], s[1][2], s[1][3]));
+  st16(k0 + off_croot + lane * 16, make_uint4(s[0][0], s[0][1], s[0][2], s[0][3]));
+  if (k1) st16(k1 + off_croot + lane * 16, make_uint4(s[1][0], s[1][1], s[1][2], s[1][3]));
   for (int i = 0; i < n; ++i) {
-    const uint32_t ai = (uint32_t)(alpha >> (n - 1 - i)) & 1u;
-    // Per party: the child on alpha's path ("keep") and the other ("lose").
-    // Only what the correction words need is accumulated across the two
-    // parties: the lost seeds' XOR, v_lose(1) - v_lose(0), v_keep(0) - v_keep(1).
-    uint32_t sk[2][4], tk[2], scw[4] = {0u, 0u, 0u, 0u}, tkx = 0u, tlx = 0u;
-    uint64_t dl[P], dk[P];
+    const uint32_t ai = (uint32_t)(alpha >> (n - 1 - i)) & 1u, al = ai ^ 1u;
+    const uint64_t neg = 0ull - (uint64_t)t[1];  // (-1)^{t_1} as a mask
+    const uint64_t badd = 0ull - (uint64_t)ai;   // beta enters when the lost child is L
+    // The child off alpha's path ("lose") of both parties first: their seeds'
+    // XOR is the seed correction, v_lose(1) - v_lose(0) gives V_CW.  The live
+    // set then stays small: V_CW enters V_alpha at once, and each party's child
+    // on the path ("keep") becomes its next seed as soon as it is expanded.
+    uint32_t scw[4] = {0u, 0u, 0u, 0u}, tlx = 0u;
+    uint64_t dl[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) dl[q] = dk[q] = 0;
+    for (int q = 0; q < P; ++q) dl[q] = 0;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       uint32_t o[1 + NB][4], jj[1 + NB];
-      jj[0] = ai;
+      jj[0] = al;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * ai + q;
-      prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
-      tk[b] = o[0][0] & 1u;
-      tkx ^= tk[b];
-      sk[b][0] = o[0][0] & ~3u; sk[b][1] = o[0][1]; sk[b][2] = o[0][2]; sk[b][3] = o[0][3];
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
-        dk[q] += b ? (0ull - v) : v;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      jj[0] = ai ^ 1u;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * (ai ^ 1u) + q;
+      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * al + q;
       prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
       tlx ^= o[0][0] & 1u;
       scw[0] ^= o[0][0] & ~3u; scw[1] ^= o[0][1]; scw[2] ^= o[0][2]; scw[3] ^= o[0][3];
@@ -764,35 +763,46 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    const uint64_t neg = 0ull - (uint64_t)t[1];  // (-1)^{t_1} as a mask
-    const uint64_t badd = 0ull - (uint64_t)ai;   // beta enters when the lost child is L
-    uint64_t vcw[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const uint64_t w = dl[q] - Va[q] + (beta[q] & badd);
-      vcw[q] = (w ^ neg) - neg;
-      Va[q] = Va[q] + dk[q] + ((vcw[q] ^ neg) - neg);
+      const uint64_t vcw = (w ^ neg) - neg;
+      Va[q] += (vcw ^ neg) - neg;
+      const uint64_t vo = off_cvcw + (((uint64_t)i * P + q) * kTile + lane) * 8;
+      st8(k0 + vo, vcw);
+      if (k1) st8(k1 + vo, vcw);
     }
+    uint32_t tk[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      uint32_t o[1 + NB][4], jj[1 + NB];
+      jj[0] = ai;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * ai + q;
+      prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
+      tk[b] = o[0][0] & 1u;
+      const uint32_t m = 0u - t[b];  // the parent's control bit applies the correction
+      s[b][0] = (o[0][0] & ~3u) ^ (scw[0] & ~3u & m);
+      s[b][1] = o[0][1] ^ (scw[1] & m);
+      s[b][2] = o[0][2] ^ (scw[2] & m);
+      s[b][3] = o[0][3] ^ (scw[3] & m);
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
+        Va[q] += b ? (0ull - v) : v;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const uint32_t tkx = tk[0] ^ tk[1];
     const uint32_t tL = (ai ? tlx : tkx) ^ ai ^ 1u;
     const uint32_t tR = (ai ? tkx : tlx) ^ ai;
     const uint4 cw = make_uint4(scw[0] | tL | (tR << 1), scw[1], scw[2], scw[3]);
-    const uint64_t cwoff = h->off_ccw + ((uint64_t)i * kTile + lane) * 16;
+    const uint64_t cwoff = off_ccw + ((uint64_t)i * kTile + lane) * 16;
     st16(k0 + cwoff, cw);
     if (k1) st16(k1 + cwoff, cw);
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const uint64_t vo = h->off_cvcw + (((uint64_t)i * P + q) * kTile + lane) * 8;
-      st8(k0 + vo, vcw[q]);
-      if (k1) st8(k1 + vo, vcw[q]);
-    }
     const uint32_t tkc = ai ? tR : tL;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const uint32_t m = 0u - t[b];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) s[b][c] = sk[b][c] ^ (scw[c] & m);
-      t[b] = tk[b] ^ (t[b] & tkc);
-    }
+    for (int b = 0; b < 2; ++b) t[b] = tk[b] ^ (t[b] & tkc);
   }
   // CW_{n+1} = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha)
   uint64_t cv[2][P];
@@ -810,7 +820,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   for (int q = 0; q < P; ++q) {
     const uint64_t w = cv[1][q] - cv[0][q] - Va[q];
     const uint64_t f = (w ^ neg) - neg;
-    const uint64_t fo = h->off_cfin + ((uint64_t)q * kTile + lane) * 8;
+    const uint64_t fo = off_cfin + ((uint64_t)q * kTile + lane) * 8;
     st8(k0 + fo, f);
     if (k1) st8(k1 + fo, f);
   }
@@ -827,6 +837,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
   rand_blk(tb, ga.rk, e, 64, 0, c0);
   rand_blk(tb, ga.rk, e, 65, 0, c1);
   const int n = (int)h->n;
+  const uint64_t off_crho = h->off_crho;
   const uint64_t nmask = n >= 64 ? ~0ull : ((1ull << n) - 1);
   gen_vec<P>(tb, h, n, rin & nmask, rho, c0, c1, t0, t1, lane);
   uint32_t ra[4], rb[4];
@@ -835,7 +846,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
   const uint64_t sh[4] = {mk64(ra[0], ra[1]), mk64(ra[2], ra[3]), mk64(rb[0], rb[1]), mk64(rb[2], rb[3])};
 #pragma unroll
   for (int q = 0; q < P; ++q) {
-    const uint64_t o = h->off_crho + ((uint64_t)q * kTile + lane) * 8;
+    const uint64_t o = off_crho + ((uint64_t)q * kTile + lane) * 8;
     st8(t0 + o, sh[q]);
     if (t1) st8(t1 + o, rho[q] - sh[q]);
   }
