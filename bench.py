@@ -180,6 +180,7 @@ def main() -> None:
     plans = [F.Plan([insts[i].item(b) for i in g for b in (0, 1)], tune) for g in groups]
     graphs = [F.Graph([p]) for p in plans] if args.graphs else None
     cfg = plans[0].config()
+    cfg["parts"] = max(p.parts() for p in plans)
     eval_aes = sum(p.aes_blocks() for p in plans)
     eval_lookups = sum(p.table_lookups() for p in plans)
     kg_aes = sum(keygen_aes_per_elem(i) * i.n for i in insts)

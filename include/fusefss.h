@@ -195,13 +195,20 @@ int fss_plan_free(fss_plan* plan);
  * (per element and party, with B = 1 + ceil(p/2) blocks per tree level and
  * D the shared top depth: sum_t k_t + (n + 2D + (m-1)(n-D)) B + m ceil(p/2);
  * the m-1 lookup points share their first D levels, walked once for each of
- * the two aligned blocks they fall in).  Used for throughput reporting. */
+ * the two aligned blocks they fall in; a tile run in parts walks them once per
+ * part).  Used for throughput reporting. */
 double fss_plan_aes_blocks(const fss_plan* plan);
 /* T-table lookups of one launch: 16 per AES round, less the 24 lookups of
  * rounds 1-2 that the blocks expanding one seed under K tweaks share
  * (160 K - 24 (K - 1) per expansion).  The table-lookup rate of the CUs'
  * local memory bounds the evaluation, so this is the roofline's work figure. */
 double fss_plan_table_lookups(const fss_plan* plan);
+/* Parts per tile the planner chose (1 = every tile runs whole).  When the
+ * tiles do not divide evenly over the resident waves, the planner splits each
+ * tile's lookup points into up to 4 parts run by different waves; each part
+ * adds its share of y (mod 2^64, exact) into y, which the launch zeroes first.
+ * Returns 0 for a NULL plan. */
+int fss_plan_parts(const fss_plan* plan);
 /* Resolved launch configuration of a plan (host out-params). */
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid);
 

@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <queue>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -563,9 +564,13 @@ struct fss_plan {
   hipEvent_t done = nullptr;  // recorded after every launch; freeing waits on it
   bool launched = false;
   DevItem* d_items = nullptr;
-  uint32_t* d_tiles = nullptr;
+  uint32_t* d_tiles = nullptr;    // work-list units, kUnitWords u32 each
   uint32_t* d_counter = nullptr;
-  uint32_t n_tiles = 0;
+  uint32_t* d_split = nullptr;    // items whose tiles run in parts
+  uint32_t n_tiles = 0;           // units
+  uint32_t n_split = 0;
+  uint64_t max_split_elems = 0;
+  int parts = 1;                  // parts per tile chosen by the planner
   fss_tune tune{};
   int grid = 0;
   double aes_per_launch = 0;  // algorithmic AES blocks of one launch
@@ -629,31 +634,84 @@ int device_cus(int* cus, std::string* name) {
   return FSS_OK;
 }
 
-// Per-element AES blocks of one party's evaluation (both calls) as the
-// kernels compute it: every atom walk, the full walk at v, the two shared
-// top walks of depth D and the m-1 point walks below depth D.
-double elem_aes(const KeyHeader& h) {
-  double a = 0;
-  for (uint32_t t = 0; t < h.T; ++t) a += h.atom_k[t];
+// Per-element cost of one party's evaluation as the kernels compute it, in
+// pieces a work-list unit is made of: call 1 (every atom walk), the base of
+// call 2 (the full walk at v), the two shared top walks of depth D (repeated by
+// every unit that evaluates lookup points) and one lookup point below depth D.
+// AES blocks, and T-table lookups: 16 per round, less the 12 + 12 lookups of
+// rounds 1-2 shared by every block after the first of a seed's K tweaks.
+struct ElemCost {
+  double aes_pred = 0, aes_base = 0, aes_tops = 0, aes_point = 0;
+  double lk_pred = 0, lk_base = 0, lk_tops = 0, lk_point = 0;
+  int points = 0;  // m - 1
+};
+
+ElemCost elem_cost(const KeyHeader& h) {
+  auto shared = [](double K) { return 160.0 * K - 24.0 * (K - 1.0); };
+  ElemCost c;
+  for (uint32_t t = 0; t < h.T; ++t) c.aes_pred += h.atom_k[t];
+  c.lk_pred = 160.0 * c.aes_pred;
   const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb, n = h.n, D = h.top_depth;
-  a += n * lvl + nb;                                    // D(v)
-  a += 2 * D * lvl;                                     // shared tops
-  a += (double)(h.m - 1) * ((n - D) * lvl + nb);        // points
-  return a;
+  c.aes_base = n * lvl + nb;
+  c.lk_base = n * shared(lvl) + shared(nb);
+  c.aes_tops = 2 * D * lvl;
+  c.lk_tops = 2 * D * shared(lvl);
+  c.aes_point = (n - D) * lvl + nb;
+  c.lk_point = (n - D) * shared(lvl) + shared(nb);
+  c.points = (int)h.m - 1;
+  return c;
 }
 
-// Per-element T-table lookups of one party's evaluation: 16 per AES round.
-// Blocks that expand one seed under K tweaks differ only in byte 15, so they
-// share 12 lookups of round 1 and 12 of round 2 (identical addresses in the
-// unchanging table; round 2's are merged by the compiler).
-double elem_lookups(const KeyHeader& h) {
-  auto shared = [](double K) { return 160.0 * K - 24.0 * (K - 1.0); };
-  double a = 0;
-  for (uint32_t t = 0; t < h.T; ++t) a += 160.0 * h.atom_k[t];
-  const double nb = (double)((h.p + 1) / 2), n = h.n, D = h.top_depth;
-  const double levels = n + 2 * D + (double)(h.m - 1) * (n - D);
-  a += levels * shared(1 + nb) + (double)h.m * shared(nb);
-  return a;
+// One work-list unit before upload.
+struct Unit {
+  uint32_t item, tile, range, flags;
+  double aes, lookups;
+};
+
+// The units of one tile split into `parts` (at most one per lookup point).
+// Part 0 carries call 1 and the base of call 2 and so takes fewer points.
+void tile_units(const ElemCost& c, uint32_t item, uint32_t tile, int parts, std::vector<Unit>& out) {
+  const int S = std::max(1, std::min(parts, c.points));
+  if (S == 1) {
+    const double tops = c.points > 0 ? 1.0 : 0.0;
+    out.push_back({item, tile, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitPred | kUnitBase,
+                   c.aes_pred + c.aes_base + tops * c.aes_tops + c.points * c.aes_point,
+                   c.lk_pred + c.lk_base + tops * c.lk_tops + c.points * c.lk_point});
+    return;
+  }
+  const double total = c.aes_pred + c.aes_base + c.points * c.aes_point;
+  int k0 = (int)std::lround((total / S - c.aes_pred - c.aes_base) / c.aes_point);
+  k0 = std::max(0, std::min(k0, c.points - (S - 1)));
+  const int rest = c.points - k0;
+  int i = 1;
+  for (int part = 0; part < S; ++part) {
+    const int k = part == 0 ? k0 : rest / (S - 1) + (part - 1 < rest % (S - 1) ? 1 : 0);
+    const double tops = k > 0 ? 1.0 : 0.0;
+    Unit u{item, tile, (uint32_t)i | ((uint32_t)(i + k) << 16), kUnitAccumulate,
+           tops * c.aes_tops + k * c.aes_point, tops * c.lk_tops + k * c.lk_point};
+    if (part == 0) {
+      u.flags |= kUnitPred | kUnitBase;
+      u.aes += c.aes_pred + c.aes_base;
+      u.lookups += c.lk_pred + c.lk_base;
+    }
+    out.push_back(u);
+    i += k;
+  }
+}
+
+// Makespan of the fused kernel's schedule: waves take units in work-list
+// order as they finish (list scheduling over `waves` identical waves).
+double simulate_makespan(const std::vector<Unit>& units, int waves) {
+  std::priority_queue<double, std::vector<double>, std::greater<double>> q;
+  for (int w = 0; w < waves; ++w) q.push(0.0);
+  double end = 0;
+  for (const Unit& u : units) {
+    const double t = q.top() + u.aes;
+    q.pop();
+    q.push(t);
+    end = std::max(end, t);
+  }
+  return end;
 }
 
 // Header reads go through a library-owned non-blocking stream so they never
@@ -717,9 +775,8 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   if (rc) return rc;
 
   std::vector<DevItem> dev(n_items);
-  struct T { uint32_t item, tile; double cost; };
-  std::vector<T> tl;
-  double aes_total = 0, lookups_total = 0;
+  std::vector<ElemCost> cost(n_items);
+  uint64_t total_tiles = 0;
   for (int i = 0; i < n_items; ++i) {
     const fss_work_item& it = items[i];
     if ((rc = check_party(it.party))) return rc;
@@ -732,29 +789,71 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
     if (h.ell > 0 && it.n_elems > 0 && !it.zbits) return fail(FSS_E_ARG, "item %d: zbits NULL", i);
     const uint64_t tiles = ((uint64_t)it.n_elems + kTile - 1) / kTile;
     dev[i] = DevItem{(const uint8_t*)it.keys, it.xhat, it.y, it.zbits, it.n_elems, it.party, (int32_t)tiles};
-    const double c = elem_aes(h);
-    aes_total += c * (double)it.n_elems;
-    lookups_total += elem_lookups(h) * (double)it.n_elems;
-    for (uint64_t t = 0; t < tiles; ++t) tl.push_back({(uint32_t)i, (uint32_t)t, c});
+    cost[i] = elem_cost(h);
+    total_tiles += tiles;
   }
-  if (tl.size() > 0xffffffffull) return fail(FSS_E_UNSUPPORTED, "work-list too long");
-  if (tn.order == 0)
-    std::stable_sort(tl.begin(), tl.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
-  std::vector<uint32_t> flat(2 * tl.size());
-  for (size_t k = 0; k < tl.size(); ++k) {
-    flat[2 * k] = tl[k].item;
-    flat[2 * k + 1] = tl[k].tile;
+  if (total_tiles * 4 > 0xffffffffull) return fail(FSS_E_UNSUPPORTED, "work-list too long");
+  const int waves_per_block = tn.block_threads / 64;
+  // Split tiles into parts only where that shortens the schedule: when the
+  // tiles do not divide evenly over the resident waves, whole tiles leave some
+  // waves a tile behind the others, and parts even that out at the price of
+  // repeating the shared top walks.  Candidates: 1..4 parts for every tile.
+  std::vector<Unit> best;
+  int best_parts = 1;
+  double best_span = 0;
+  for (int parts = 1; parts <= 4; ++parts) {
+    std::vector<Unit> units;
+    units.reserve(total_tiles * parts);
+    for (int i = 0; i < n_items; ++i)
+      for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t) tile_units(cost[i], (uint32_t)i, (uint32_t)t, parts, units);
+    if (parts > 1 && units.size() == best.size()) break;  // nothing left to split
+    if (tn.order == 0)
+      std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.aes > b.aes; });
+    const int grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
+                                               (int)((units.size() + waves_per_block - 1) / waves_per_block)));
+    const double span = simulate_makespan(units, grid * waves_per_block);
+    // a split has to win clearly: the simulation does not see that the last
+    // waves run faster once the others have finished
+    if (parts == 1 || span < best_span * 0.97) {
+      best_span = span;
+      best_parts = parts;
+      best.swap(units);
+    }
+    if (total_tiles > 64ull * (uint64_t)cus * tn.blocks_per_cu * waves_per_block) break;  // tail already small
   }
+  double aes_total = 0, lookups_total = 0;
+  std::vector<uint32_t> flat((size_t)kUnitWords * best.size());
+  std::vector<uint32_t> split;
+  std::vector<char> is_split(n_items, 0);
+  for (size_t k = 0; k < best.size(); ++k) {
+    const Unit& u = best[k];
+    flat[kUnitWords * k] = u.item;
+    flat[kUnitWords * k + 1] = u.tile;
+    flat[kUnitWords * k + 2] = u.range;
+    flat[kUnitWords * k + 3] = u.flags;
+    const uint64_t e0 = (uint64_t)u.tile * kTile;
+    const double elems = (double)std::min<uint64_t>(kTile, (uint64_t)dev[u.item].n_elems - e0);
+    aes_total += u.aes * elems;
+    lookups_total += u.lookups * elems;
+    if ((u.flags & kUnitAccumulate) && !is_split[u.item]) {
+      is_split[u.item] = 1;
+      split.push_back(u.item);
+    }
+  }
+  uint64_t max_split_elems = 0;
+  for (uint32_t i : split) max_split_elems = std::max<uint64_t>(max_split_elems, (uint64_t)dev[i].n_elems);
   std::unique_ptr<fss_plan> P(new (std::nothrow) fss_plan());
   if (!P) return fail(FSS_E_OOM, "out of host memory");
   HIP_TRY(hipGetDevice(&P->device), "hipGetDevice");
-  void *pi = nullptr, *pt = nullptr, *pc = nullptr;
+  void *pi = nullptr, *pt = nullptr, *pc = nullptr, *ps = nullptr;
   if ((rc = pool_get(sizeof(DevItem) * std::max<size_t>(1, dev.size()), &pi))) return rc;
   P->d_items = (DevItem*)pi;
-  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(2, flat.size()), &pt))) return rc;
+  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(kUnitWords, flat.size()), &pt))) return rc;
   P->d_tiles = (uint32_t*)pt;
   if ((rc = pool_get(sizeof(uint32_t), &pc))) return rc;
   P->d_counter = (uint32_t*)pc;
+  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(1, split.size()), &ps))) return rc;
+  P->d_split = (uint32_t*)ps;
   hipStream_t up;
   if ((rc = aux_stream(&up))) return rc;
   if (!dev.empty())
@@ -762,13 +861,19 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
             "upload items");
   if (!flat.empty())
     HIP_TRY(hipMemcpyAsync(P->d_tiles, flat.data(), sizeof(uint32_t) * flat.size(), hipMemcpyHostToDevice, up),
-            "upload tiles");
+            "upload work-list");
+  if (!split.empty())
+    HIP_TRY(hipMemcpyAsync(P->d_split, split.data(), sizeof(uint32_t) * split.size(), hipMemcpyHostToDevice, up),
+            "upload split items");
   HIP_TRY(hipStreamSynchronize(up), "hipStreamSynchronize(upload)");
   HIP_TRY(hipEventCreateWithFlags(&P->done, hipEventDisableTiming), "hipEventCreate(plan)");
-  P->n_tiles = (uint32_t)tl.size();
+  P->n_tiles = (uint32_t)best.size();
+  P->n_split = (uint32_t)split.size();
+  P->max_split_elems = max_split_elems;
+  P->parts = best_parts;
   P->tune = tn;
   P->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
-                                      (int)((tl.size() * 64 + tn.block_threads - 1) / tn.block_threads)));
+                                      (int)((best.size() + waves_per_block - 1) / waves_per_block)));
   P->aes_per_launch = aes_total;
   P->lookups_per_launch = lookups_total;
   *out = P.release();
@@ -782,7 +887,7 @@ int fss_plan_launch(fss_plan* plan, void* stream) {
   int rc = device_status_ptr(&st);
   if (rc) return rc;
   HIP_TRY(launch_fused(plan->tune.aes_variant, plan->d_items, plan->d_tiles, plan->n_tiles, plan->d_counter, st,
-                       plan->grid, (hipStream_t)stream),
+                       plan->grid, plan->d_split, plan->n_split, plan->max_split_elems, (hipStream_t)stream),
           "fused launch");
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing((hipStream_t)stream, &cs), "hipStreamIsCapturing");
@@ -801,6 +906,7 @@ int fss_plan_free(fss_plan* plan) {
   pool_put(plan->d_items);
   pool_put(plan->d_tiles);
   pool_put(plan->d_counter);
+  pool_put(plan->d_split);
   delete plan;
   return FSS_OK;
 }
@@ -937,6 +1043,7 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
 // launch of a plan, and its resolved launch configuration.
 double fss_plan_aes_blocks(const fss_plan* plan) { return plan ? plan->aes_per_launch : 0.0; }
 double fss_plan_table_lookups(const fss_plan* plan) { return plan ? plan->lookups_per_launch : 0.0; }
+int fss_plan_parts(const fss_plan* plan) { return plan ? plan->parts : 0; }
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid) {
   if (!plan || !tune || !grid) return fail(FSS_E_ARG, "NULL argument");
   *tune = plan->tune;

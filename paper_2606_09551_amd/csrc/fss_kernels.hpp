@@ -32,6 +32,14 @@ struct DevItem {
   int32_t words;  // ceil(n_elems / 64): stride of the z bit-planes
 };
 
+// One unit of the fused kernel's work-list, kUnitWords u32: item, tile,
+// lookup-point range (i0 | i1 << 16) and flags.  A tile either runs whole
+// (call 1 + all of call 2, y stored) or in parts whose shares of y are added.
+constexpr int kUnitWords = 4;
+constexpr uint32_t kUnitPred = 1u;        // call 1 (the predicate bits)
+constexpr uint32_t kUnitBase = 2u;        // the walk at v, tab_0 rho and r_out terms of call 2
+constexpr uint32_t kUnitAccumulate = 4u;  // add the part's y to memory zeroed before the launch
+
 // Launchers of one AES table layout V (0 .. kNumAesVariants-1).
 template <int V>
 struct VariantOps {
@@ -45,7 +53,7 @@ struct VariantOps {
                          int* status, int cus, hipStream_t st);
   static hipError_t coeff(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* y,
                           int* status, int cus, hipStream_t st);
-  static hipError_t fused(const DevItem* items, const uint32_t* tiles, uint32_t n_tiles, uint32_t* counter,
+  static hipError_t fused(const DevItem* items, const uint32_t* units, uint32_t n_units, uint32_t* counter,
                           int* status, int grid, hipStream_t st);
 };
 extern template struct VariantOps<0>;
@@ -63,10 +71,12 @@ hipError_t launch_eval_pred(int variant, int party, const uint8_t* keys, const u
                             int64_t n, uint64_t* z, int* status, int cus, hipStream_t st);
 hipError_t launch_eval_coeff(int variant, int party, const uint8_t* keys, const uint64_t* xhat,
                              int64_t n, uint64_t* y, int* status, int cus, hipStream_t st);
-// Resets the work counter with a kernel (graph-safe), then launches the
-// persistent kernel with `grid` blocks of the variant's block size.
-hipError_t launch_fused(int variant, const DevItem* items, const uint32_t* tiles, uint32_t n_tiles,
-                        uint32_t* counter, int* status, int grid, hipStream_t st);
+// Resets the work counter and zeroes y of the split items with kernels
+// (graph-safe), then launches the persistent kernel with `grid` blocks of the
+// variant's block size over `n_units` work-list units.
+hipError_t launch_fused(int variant, const DevItem* items, const uint32_t* units, uint32_t n_units,
+                        uint32_t* counter, int* status, int grid, const uint32_t* split_items,
+                        uint32_t n_split, uint64_t max_split_elems, hipStream_t st);
 int variant_block(int variant);
 int variant_lds_bytes(int variant);
 

@@ -475,10 +475,17 @@ __device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* t
 // aligned blocks of 2^K >= W values.  Their first D = n - K levels are walked
 // once per block (A, the block of u_{m-1}, and its successor B) and each point
 // resumes from its block's state: same outputs, (m - 3) * D fewer levels.
+//
+// Every term of q, and so of y = sum_j q_j xhat^j, is linear: a tile's work can
+// be split into parts that each return their share of y (mod 2^64).  This call
+// covers the points i in [i0, min(i1, m)) and, when `base` is set, the walk at
+// v with the tabv, tab_0 rho and r_out terms; i0 = 1, i1 >= m, base = true is
+// the whole of call 2.
 template <int P, class TB>
 __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8_t* tile,
-                                               int lane, int b, uint64_t xhat) {
+                                               int lane, int b, uint64_t xhat, int i0, int i1, bool base) {
   const int n = (int)h->n, m = (int)h->m, D = (int)h->top_depth;
+  const int iend = i1 < m ? i1 : m;
   const uint32_t Nmask = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
   const uint32_t half = 1u << (n - 1);
   const uint32_t v = ((uint32_t)xhat + half) & Nmask;
@@ -487,15 +494,15 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   const uint32_t top_mask = D >= 32 ? 0xffffffffu : ((1u << D) - 1u);
   const uint32_t blkA = (uint32_t)(((uint64_t)((v - (uint32_t)h->aprime[m - 1]) & Nmask)) >> K);
   const uint32_t blkB = (blkA + 1u) & top_mask;
-  VState<P> sa = vroot<P>(h, tile, lane, b), sb = sa;
-  if (D > 0) {
-    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkA << K), 0, D, sa);
-    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkB << K), 0, D, sb);
-  }
   uint64_t q[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) q[k] = 0;
-  for (int i = 1; i < m; ++i) {
+  VState<P> sa = vroot<P>(h, tile, lane, b), sb = sa;
+  if (D > 0 && iend > i0) {
+    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkA << K), 0, D, sa);
+    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkB << K), 0, D, sb);
+  }
+  for (int i = i0; i < iend; ++i) {
     const uint32_t ap = (uint32_t)h->aprime[i];
     const uint32_t u = (v - ap) & Nmask;
     VState<P> st = vselect<P>((uint32_t)((uint64_t)u >> K) == blkA, sa, sb);
@@ -510,7 +517,7 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
 #pragma unroll
       for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * g[k];
   }
-  {
+  if (base) {
     VState<P> st = vroot<P>(h, tile, lane, b);
     vec_walk<P>(tb, h, tile, lane, b, v, 0, n, st);
     uint64_t Dv[P];
@@ -519,12 +526,12 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
     for (int j = 0; j < P; ++j)
 #pragma unroll
       for (int k = 0; j + k < P; ++k) q[j] -= h->tabv[j][k] * Dv[k];
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * ld8(rhop + (uint64_t)k * kTile * 8);
+    q[0] += ld8(tile + h->off_crout + lane * 8);
   }
-#pragma unroll
-  for (int j = 0; j < P; ++j)
-#pragma unroll
-    for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * ld8(rhop + (uint64_t)k * kTile * 8);
-  q[0] += ld8(tile + h->off_crout + lane * 8);
   uint64_t y = q[P - 1];
 #pragma unroll
   for (int j = P - 2; j >= 0; --j) y = y * xhat + q[j];
@@ -533,12 +540,13 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
 
 template <class TB>
 __device__ __forceinline__ uint64_t coeff_dispatch(const TB& tb, GHdr h, const uint8_t* tile,
-                                                   int lane, int b, uint64_t xhat) {
+                                                   int lane, int b, uint64_t xhat, int i0 = 1,
+                                                   int i1 = kMaxM + 1, bool base = true) {
   switch (h->p) {
-    case 1: return coeff_tile<1>(tb, h, tile, lane, b, xhat);
-    case 2: return coeff_tile<2>(tb, h, tile, lane, b, xhat);
-    case 3: return coeff_tile<3>(tb, h, tile, lane, b, xhat);
-    default: return coeff_tile<4>(tb, h, tile, lane, b, xhat);
+    case 1: return coeff_tile<1>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 2: return coeff_tile<2>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 3: return coeff_tile<3>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    default: return coeff_tile<4>(tb, h, tile, lane, b, xhat, i0, i1, base);
   }
 }
 
@@ -615,9 +623,11 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     if (lane == 0) idx = atomicAdd(counter, 1u);
     idx = __builtin_amdgcn_readfirstlane(idx);
     if (idx >= n_tiles) break;
-    const FSS_GLOBAL uint32_t* tl = (const FSS_GLOBAL uint32_t*)tiles;
-    const uint32_t item = __builtin_amdgcn_readfirstlane(tl[2 * idx]);
-    const uint64_t tile = __builtin_amdgcn_readfirstlane(tl[2 * idx + 1]);
+    const FSS_GLOBAL uint32_t* tl = (const FSS_GLOBAL uint32_t*)tiles + (uint64_t)kUnitWords * idx;
+    const uint32_t item = __builtin_amdgcn_readfirstlane(tl[0]);
+    const uint64_t tile = __builtin_amdgcn_readfirstlane(tl[1]);
+    const uint32_t range = __builtin_amdgcn_readfirstlane(tl[2]);
+    const uint32_t flags = __builtin_amdgcn_readfirstlane(tl[3]);
     const FSS_GLOBAL DevItem* ip = (const FSS_GLOBAL DevItem*)items + item;
     DevItem it;
     it.keys = ip->keys;
@@ -637,11 +647,20 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     const bool valid = e < (uint64_t)it.n_elems;
     const uint64_t xh = valid ? ldg64(it.xhat + e) : 0;
     const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
-    if (h->T > 0) pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
-    const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh);
-    if (valid) stg64(it.y + e, out);
+    if ((flags & kUnitPred) && h->T > 0)
+      pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
+    const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),
+                                        (flags & kUnitBase) != 0);
+    if (valid) {
+      if (flags & kUnitAccumulate)  // parts of one tile add their shares of y (mod 2^64)
+        __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)out,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else
+        stg64(it.y + e, out);
+    }
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // Dealer key generation.  Lane = element; every random value is

@@ -2,6 +2,8 @@
 // table-layout index to its launchers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fss_kernels.hpp"
 
 namespace fss {
@@ -81,11 +83,29 @@ hipError_t launch_eval_coeff(int v, int party, const uint8_t* keys, const uint64
   }
 }
 
+// Zeroes y of the items whose tiles run in parts (the parts add into it).
+__global__ void k_zero_split(const DevItem* items, const uint32_t* split_items, uint32_t n_split) {
+  for (uint32_t s = blockIdx.y; s < n_split; s += gridDim.y) {
+    const DevItem* ip = items + split_items[s];
+    uint64_t* y = ip->y;
+    const int64_t n = ip->n_elems;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+      y[e] = 0;
+  }
+}
+
 hipError_t launch_fused(int v, const DevItem* items, const uint32_t* tiles, uint32_t n_tiles, uint32_t* counter,
-                        int* status, int grid, hipStream_t st) {
+                        int* status, int grid, const uint32_t* split_items, uint32_t n_split,
+                        uint64_t max_split_elems, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (n_split > 0 && max_split_elems > 0) {
+    const uint64_t bx = std::min<uint64_t>((max_split_elems + 255) / 256, 1024);
+    const unsigned by = std::min<uint32_t>(n_split, 1024);
+    hipLaunchKernelGGL(k_zero_split, dim3((unsigned)bx, by), dim3(256), 0, st, items, split_items, n_split);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   switch (v) {
     case 0: return VariantOps<0>::fused(items, tiles, n_tiles, counter, status, grid, st);
     case 1: return VariantOps<1>::fused(items, tiles, n_tiles, counter, status, grid, st);

@@ -93,6 +93,7 @@ def _load():
         "fss_plan_free": [vp],
         "fss_plan_aes_blocks": [vp],
         "fss_plan_table_lookups": [vp],
+        "fss_plan_parts": [vp],
         "fss_plan_config": [vp, C.POINTER(Tune), C.POINTER(i32)],
         "fss_graph_capture": [C.POINTER(vp), i32, C.POINTER(vp)],
         "fss_graph_launch": [vp, vp],
@@ -244,6 +245,9 @@ class Plan:
 
     def table_lookups(self) -> float:
         return lib.fss_plan_table_lookups(self.handle)
+
+    def parts(self) -> int:
+        return lib.fss_plan_parts(self.handle)
 
     def config(self) -> dict:
         t, g = Tune(), C.c_int32()
