@@ -12,7 +12,6 @@
 #include <map>
 #include <memory>
 #include <mutex>
-#include <queue>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -668,16 +667,19 @@ struct Unit {
   double aes, lookups;
 };
 
-// The units of one tile split into `parts` (at most one per lookup point).
-// Part 0 carries call 1 and the base of call 2 and so takes fewer points.
-void tile_units(const ElemCost& c, uint32_t item, uint32_t tile, int parts, std::vector<Unit>& out) {
+// The units of one tile split into `parts` (at most one per lookup point):
+// per part, its flags, point range and per-element cost.  Part 0 carries
+// call 1 and the base of call 2 and so takes fewer points.  Every tile of an
+// item splits the same way.
+std::vector<Unit> tile_parts(const ElemCost& c, int parts) {
+  std::vector<Unit> out;
   const int S = std::max(1, std::min(parts, c.points));
   if (S == 1) {
     const double tops = c.points > 0 ? 1.0 : 0.0;
-    out.push_back({item, tile, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitPred | kUnitBase,
+    out.push_back({0, 0, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitPred | kUnitBase,
                    c.aes_pred + c.aes_base + tops * c.aes_tops + c.points * c.aes_point,
                    c.lk_pred + c.lk_base + tops * c.lk_tops + c.points * c.lk_point});
-    return;
+    return out;
   }
   const double total = c.aes_pred + c.aes_base + c.points * c.aes_point;
   int k0 = (int)std::lround((total / S - c.aes_pred - c.aes_base) / c.aes_point);
@@ -687,8 +689,8 @@ void tile_units(const ElemCost& c, uint32_t item, uint32_t tile, int parts, std:
   for (int part = 0; part < S; ++part) {
     const int k = part == 0 ? k0 : rest / (S - 1) + (part - 1 < rest % (S - 1) ? 1 : 0);
     const double tops = k > 0 ? 1.0 : 0.0;
-    Unit u{item, tile, (uint32_t)i | ((uint32_t)(i + k) << 16), kUnitAccumulate,
-           tops * c.aes_tops + k * c.aes_point, tops * c.lk_tops + k * c.lk_point};
+    Unit u{0, 0, (uint32_t)i | ((uint32_t)(i + k) << 16), kUnitAccumulate, tops * c.aes_tops + k * c.aes_point,
+           tops * c.lk_tops + k * c.lk_point};
     if (part == 0) {
       u.flags |= kUnitPred | kUnitBase;
       u.aes += c.aes_pred + c.aes_base;
@@ -697,22 +699,30 @@ void tile_units(const ElemCost& c, uint32_t item, uint32_t tile, int parts, std:
     out.push_back(u);
     i += k;
   }
+  return out;
 }
 
 // Makespan of the fused kernel's schedule: waves take units in work-list
-// order as they finish (list scheduling over `waves` identical waves).
-double simulate_makespan(const std::vector<Unit>& units, int waves) {
-  std::priority_queue<double, std::vector<double>, std::greater<double>> q;
-  for (int w = 0; w < waves; ++w) q.push(0.0);
-  double end = 0;
-  for (const Unit& u : units) {
-    const double t = q.top() + u.aes;
-    q.pop();
-    q.push(t);
-    end = std::max(end, t);
+// order as they finish, i.e. list scheduling over `waves` identical waves.
+// Runs of equal-cost units are assigned together to the earliest-free waves,
+// tracked as (finish time -> number of waves): exact, and a few map
+// operations per run.
+struct ScheduleSim {
+  std::map<double, uint64_t> fin;
+  explicit ScheduleSim(uint64_t waves) { fin[0.0] = waves; }
+  void run(double cost, uint64_t count) {
+    while (count > 0) {
+      auto it = fin.begin();
+      const double t = it->first;
+      const uint64_t take = std::min(it->second, count);
+      if (take == it->second) fin.erase(it);
+      else it->second -= take;
+      fin[t + cost] += take;
+      count -= take;
+    }
   }
-  return end;
-}
+  double makespan() const { return fin.rbegin()->first; }
+};
 
 // Header reads go through a library-owned non-blocking stream so they never
 // wait for kernels running on other streams (the caller orders keygen first).
@@ -797,29 +807,68 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   // Split tiles into parts only where that shortens the schedule: when the
   // tiles do not divide evenly over the resident waves, whole tiles leave some
   // waves a tile behind the others, and parts even that out at the price of
-  // repeating the shared top walks.  Candidates: 1..4 parts for every tile.
-  std::vector<Unit> best;
+  // repeating the shared top walks.  Candidates: 1..4 parts for every tile,
+  // compared by the simulated schedule (all tiles of an item cost the same).
+  struct Group { double cost; uint32_t item, part; uint64_t count; };
+  auto groups_for = [&](int parts, std::vector<std::vector<Unit>>& tp, std::vector<Group>& g) {
+    tp.assign(n_items, {});
+    g.clear();
+    for (int i = 0; i < n_items; ++i) {
+      if (dev[i].words == 0) continue;
+      tp[i] = tile_parts(cost[i], parts);
+      for (uint32_t q = 0; q < tp[i].size(); ++q) g.push_back({tp[i][q].aes, (uint32_t)i, q, (uint64_t)dev[i].words});
+    }
+    if (tn.order == 0)
+      std::stable_sort(g.begin(), g.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
+  };
   int best_parts = 1;
   double best_span = 0;
+  uint64_t best_units = 0;
+  std::vector<std::vector<Unit>> tp;
+  std::vector<Group> groups;
   for (int parts = 1; parts <= 4; ++parts) {
-    std::vector<Unit> units;
-    units.reserve(total_tiles * parts);
-    for (int i = 0; i < n_items; ++i)
-      for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t) tile_units(cost[i], (uint32_t)i, (uint32_t)t, parts, units);
-    if (parts > 1 && units.size() == best.size()) break;  // nothing left to split
-    if (tn.order == 0)
-      std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.aes > b.aes; });
-    const int grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
-                                               (int)((units.size() + waves_per_block - 1) / waves_per_block)));
-    const double span = simulate_makespan(units, grid * waves_per_block);
+    groups_for(parts, tp, groups);
+    uint64_t n_units = 0;
+    for (const Group& g : groups) n_units += g.count;
+    if (parts > 1 && n_units == best_units) break;  // nothing left to split
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * tn.blocks_per_cu,
+                                                                  (n_units + waves_per_block - 1) / waves_per_block));
+    ScheduleSim sim((uint64_t)grid * waves_per_block);
+    if (tn.order == 0) {
+      for (const Group& g : groups) sim.run(g.cost, g.count);
+    } else {  // natural order: tile by tile, parts in turn
+      for (int i = 0; i < n_items; ++i)
+        for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t)
+          for (const Unit& u : tp[i]) sim.run(u.aes, 1);
+    }
+    const double span = sim.makespan();
     // a split has to win clearly: the simulation does not see that the last
     // waves run faster once the others have finished
     if (parts == 1 || span < best_span * 0.97) {
       best_span = span;
       best_parts = parts;
-      best.swap(units);
+      best_units = n_units;
     }
-    if (total_tiles > 64ull * (uint64_t)cus * tn.blocks_per_cu * waves_per_block) break;  // tail already small
+  }
+  groups_for(best_parts, tp, groups);
+  std::vector<Unit> best;
+  best.reserve(best_units);
+  if (tn.order == 0) {
+    for (const Group& g : groups)
+      for (uint64_t t = 0; t < g.count; ++t) {
+        Unit u = tp[g.item][g.part];
+        u.item = g.item;
+        u.tile = (uint32_t)t;
+        best.push_back(u);
+      }
+  } else {
+    for (int i = 0; i < n_items; ++i)
+      for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t)
+        for (Unit u : tp[i]) {
+          u.item = (uint32_t)i;
+          u.tile = (uint32_t)t;
+          best.push_back(u);
+        }
   }
   double aes_total = 0, lookups_total = 0;
   std::vector<uint32_t> flat((size_t)kUnitWords * best.size());
