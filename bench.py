@@ -324,6 +324,7 @@ def serve_bench(args) -> None:
         st = srv.run(stream)
         st.pop("_requests")
         out[path] = st
+        print(f"served {len(stream)} requests ({path}): {st['makespan_s']:.1f} s", file=sys.stderr, flush=True)
         del srv
         gc.collect()
         torch.cuda.empty_cache()
