@@ -43,8 +43,17 @@ class DcfKey(C.Structure):
                 ("vcw", (C.c_uint64 * MAXP) * MAXN), ("fin", C.c_uint64 * MAXP)]
 
 
+MAXL4 = (MAXN + 1) // 2
+
+
+class Dcf4Key(C.Structure):
+    _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("root", Blk), ("scw", (Blk * 4) * MAXL4),
+                ("tcw", (C.c_uint8 * 4) * MAXL4), ("vcw", ((C.c_uint64 * MAXP) * 4) * MAXL4),
+                ("fin", C.c_uint64 * MAXP)]
+
+
 class ElemKey(C.Structure):
-    _fields_ = [("atom", DcfKey * MAXT), ("wshare", C.c_uint64), ("coeff", DcfKey),
+    _fields_ = [("atom", DcfKey * MAXT), ("wshare", C.c_uint64), ("coeff", Dcf4Key),
                 ("rho", C.c_uint64 * MAXP), ("rout", C.c_uint64)]
 
 
@@ -99,6 +108,9 @@ def lib():
         L.orc_dcf_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk,
                                   C.POINTER(DcfKey), C.POINTER(DcfKey)]
         L.orc_dcf_eval.argtypes = [C.c_int, C.POINTER(DcfKey), C.c_uint64, u64p]
+        L.orc_dcf4_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk, C.POINTER(Blk),
+                                   C.POINTER(Dcf4Key), C.POINTER(Dcf4Key)]
+        L.orc_dcf4_eval.argtypes = [C.c_int, C.POINTER(Dcf4Key), C.c_uint64, u64p]
         L.orc_spec_compile.argtypes = [C.POINTER(Interval), C.c_int32, C.POINTER(Piece),
                                        C.POINTER(Pred), C.c_int32, C.c_int32, C.c_int32,
                                        C.c_int32, C.POINTER(Spec)]
@@ -112,7 +124,7 @@ def lib():
         L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
                                     C.POINTER(C.c_int32)]
         for name, cls in (("orc_sizeof_elem_key", ElemKey), ("orc_sizeof_dcf_key", DcfKey),
-                          ("orc_sizeof_spec", Spec)):
+                          ("orc_sizeof_dcf4_key", Dcf4Key), ("orc_sizeof_spec", Spec)):
             got = getattr(L, name)()
             if got != C.sizeof(cls):
                 raise RuntimeError(f"oracle struct layout mismatch: {name} {got} != {C.sizeof(cls)}")
@@ -171,6 +183,22 @@ def dcf_gen(n: int, p: int, alpha: int, beta, root0, root1):
 def dcf_eval(b: int, key: DcfKey, x: int):
     out = (C.c_uint64 * MAXP)()
     lib().orc_dcf_eval(b, C.byref(key), x, out)
+    return out[0] if key.p == 0 else list(out[: key.p])
+
+
+def dcf4_gen(n: int, p: int, alpha: int, beta, root0, root1, keep_rand):
+    """Four children per level.  keep_rand: (ceil(n/2) * (1 + ceil(p/2))) (lo, hi)
+    blocks, the on-path child's corrections level by level."""
+    b = (C.c_uint64 * MAXP)(*([int(v) & (2**64 - 1) for v in (beta if p else [beta])]))
+    kr = (Blk * max(1, len(keep_rand)))(*[Blk(lo, hi) for lo, hi in keep_rand])
+    k0, k1 = Dcf4Key(), Dcf4Key()
+    lib().orc_dcf4_gen(n, p, alpha, b, Blk(*root0), Blk(*root1), kr, C.byref(k0), C.byref(k1))
+    return k0, k1
+
+
+def dcf4_eval(b: int, key: Dcf4Key, x: int):
+    out = (C.c_uint64 * MAXP)()
+    lib().orc_dcf4_eval(b, C.byref(key), x, out)
     return out[0] if key.p == 0 else list(out[: key.p])
 
 

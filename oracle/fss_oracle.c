@@ -336,6 +336,145 @@ void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out) {
 }
 
 /* ========================================================================= */
+/* DCF with four children per level: two input bits (one base-4 digit) per   */
+/* level, the per-child form of the corrections above.                       */
+/* ========================================================================= */
+
+/* Child c (0..3) of seed s: next seed, control bit t, and group value v. */
+static void expand4(int p, orc_blk s, int c, orc_blk* s_out, int* t_out, uint64_t* v_out) {
+  orc_blk n = orc_prg(s, c);
+  *t_out = (int)(n.lo & 1);
+  *s_out = clear2(n);
+  if (p == 0) {
+    v_out[0] = (n.lo >> 1) & 1;
+  } else {
+    uint64_t w[4];
+    orc_blk a = orc_prg(s, 4 + 2 * c);
+    w[0] = a.lo; w[1] = a.hi;
+    if (p > 2) { orc_blk b = orc_prg(s, 5 + 2 * c); w[2] = b.lo; w[3] = b.hi; }
+    for (int k = 0; k < p; k++) v_out[k] = w[k];
+  }
+}
+
+static void convert4(int p, orc_blk s, uint64_t* out) {
+  if (p == 0) {
+    out[0] = (s.lo >> 2) & 1;
+  } else {
+    uint64_t w[4];
+    orc_blk a = orc_prg(s, 12);
+    w[0] = a.lo; w[1] = a.hi;
+    if (p > 2) { orc_blk b = orc_prg(s, 13); w[2] = b.lo; w[3] = b.hi; }
+    for (int k = 0; k < p; k++) out[k] = w[k];
+  }
+}
+
+/* Base-4 digit i (most significant first) of x over `levels` digits. */
+static int digit4(uint64_t x, int levels, int i) { return (int)((x >> (2 * (levels - 1 - i))) & 3); }
+
+void orc_dcf4_gen(int n, int p, uint64_t alpha, const uint64_t* beta, orc_blk root0, orc_blk root1,
+                  const orc_blk* keep_rand, orc_dcf4_key* k0, orc_dcf4_key* k1) {
+  memset(k0, 0, sizeof *k0);
+  memset(k1, 0, sizeof *k1);
+  k0->n = k1->n = n;
+  k0->p = k1->p = p;
+  const int levels = (n + 1) / 2, nr = 1 + (p + 1) / 2;
+  orc_blk s[2] = {clear2(root0), clear2(root1)};
+  int t[2] = {0, 1};
+  k0->root = s[0];
+  k1->root = s[1];
+  uint64_t Va[ORC_MAXP];
+  g_zero(p, Va);
+
+  for (int i = 0; i < levels; i++) {
+    const int a = digit4(alpha, levels, i);   /* the child on alpha's path */
+    orc_blk sc[2][4];
+    int tc[2][4];
+    uint64_t vc[2][4][ORC_MAXP];
+    for (int b = 0; b < 2; b++)
+      for (int c = 0; c < 4; c++) expand4(p, s[b], c, &sc[b][c], &tc[b][c], vc[b][c]);
+    const orc_blk* kr = keep_rand + (size_t)i * nr;
+    for (int c = 0; c < 4; c++) {
+      orc_blk scw;
+      uint64_t vcw[ORC_MAXP];
+      if (c != a) {
+        /* the parties' children become equal: seeds, control bits and, for
+         * the value, V_CW = (-1)^{t1} (v1^c - v0^c - V_alpha [+ beta if c < a]) */
+        scw.lo = sc[0][c].lo ^ sc[1][c].lo;
+        scw.hi = sc[0][c].hi ^ sc[1][c].hi;
+        memcpy(vcw, vc[1][c], sizeof vcw);
+        g_sub(p, vcw, vc[0][c]);
+        g_sub(p, vcw, Va);
+        if (c < a) g_add(p, vcw, beta);
+        g_sign(p, t[1], vcw);
+      } else {
+        /* random corrections on alpha's child hide which child it is */
+        scw = clear2(kr[0]);
+        uint64_t w[4] = {kr[1].lo, kr[1].hi, nr > 2 ? kr[2].lo : 0, nr > 2 ? kr[2].hi : 0};
+        g_zero(p, vcw);
+        for (int k = 0; k < glen(p); k++) vcw[k] = (p == 0) ? (w[k] & 1) : w[k];
+      }
+      const int tcw = tc[0][c] ^ tc[1][c] ^ (c == a);
+      k0->scw[i][c] = k1->scw[i][c] = scw;
+      k0->tcw[i][c] = k1->tcw[i][c] = (uint8_t)tcw;
+      for (int k = 0; k < glen(p); k++) k0->vcw[i][c][k] = k1->vcw[i][c][k] = vcw[k];
+    }
+    /* V_alpha = V_alpha - v1^a + v0^a + (-1)^{t1} V_CW^a */
+    uint64_t tmp[ORC_MAXP];
+    g_sub(p, Va, vc[1][a]);
+    g_add(p, Va, vc[0][a]);
+    memcpy(tmp, k0->vcw[i][a], sizeof tmp);
+    g_sign(p, t[1], tmp);
+    g_add(p, Va, tmp);
+    for (int b = 0; b < 2; b++) {
+      orc_blk ns = sc[b][a];
+      if (t[b]) { ns.lo ^= k0->scw[i][a].lo; ns.hi ^= k0->scw[i][a].hi; }
+      const int nt = tc[b][a] ^ (t[b] & k0->tcw[i][a]);
+      s[b] = ns;
+      t[b] = nt;
+    }
+  }
+  /* CW_final = (-1)^{t1} (Convert(s1) - Convert(s0) - V_alpha) */
+  uint64_t c0[ORC_MAXP], c1[ORC_MAXP];
+  convert4(p, s[0], c0);
+  convert4(p, s[1], c1);
+  g_sub(p, c1, c0);
+  g_sub(p, c1, Va);
+  g_sign(p, t[1], c1);
+  for (int k = 0; k < glen(p); k++) k0->fin[k] = k1->fin[k] = c1[k];
+}
+
+void orc_dcf4_eval(int b, const orc_dcf4_key* k, uint64_t x, uint64_t* out) {
+  const int p = k->p, levels = (k->n + 1) / 2;
+  orc_blk s = k->root;
+  int t = b;
+  uint64_t V[ORC_MAXP], tmp[ORC_MAXP];
+  g_zero(p, V);
+  for (int i = 0; i < levels; i++) {
+    const int d = digit4(x, levels, i);
+    orc_blk ns;
+    int nt;
+    uint64_t v[ORC_MAXP];
+    expand4(p, s, d, &ns, &nt, v);
+    if (t) {
+      ns.lo ^= k->scw[i][d].lo;
+      ns.hi ^= k->scw[i][d].hi;
+      nt ^= k->tcw[i][d];
+      g_add(p, v, k->vcw[i][d]);   /* v + t * V_CW^d, with the parent's t */
+    }
+    memcpy(tmp, v, sizeof tmp);
+    g_sign(p, b, tmp);
+    g_add(p, V, tmp);
+    s = ns;
+    t = nt;
+  }
+  convert4(p, s, tmp);
+  if (t) g_add(p, tmp, k->fin);
+  g_sign(p, b, tmp);
+  g_add(p, V, tmp);
+  for (int q = 0; q < glen(p); q++) out[q] = V[q];
+}
+
+/* ========================================================================= */
 /* Operator specification                                                    */
 /* ========================================================================= */
 
@@ -519,7 +658,12 @@ void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
   for (int k = 1; k < S->p; k++) rho[k] = rho[k - 1] * ((uint64_t)0 - r_in);
   orc_blk c0 = orc_rand(kseed, e, 64, 0);
   orc_blk c1 = orc_rand(kseed, e, 65, 0);
-  orc_dcf_gen(S->n, S->p, r_in & lowmask(S->n), rho, c0, c1, &k0->coeff, &k1->coeff);
+  /* the on-path child's corrections at level i: R(e, 69 + k, i) */
+  orc_blk kr[ORC_MAXL4 * 3];
+  const int levels = (S->n + 1) / 2, nr = 1 + (S->p + 1) / 2;
+  for (int i = 0; i < levels; i++)
+    for (int k = 0; k < nr; k++) kr[i * nr + k] = orc_rand(kseed, e, 69 + k, i);
+  orc_dcf4_gen(S->n, S->p, r_in & lowmask(S->n), rho, c0, c1, kr, &k0->coeff, &k1->coeff);
   orc_blk ra = orc_rand(kseed, e, 67, 0), rb = orc_rand(kseed, e, 68, 0);
   uint64_t sh[4] = {ra.lo, ra.hi, rb.lo, rb.hi};
   for (int k = 0; k < S->p; k++) {
@@ -568,13 +712,13 @@ void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xha
   const uint64_t N = (uint64_t)1 << n, s = N / 2;
   uint64_t v = ((xhat & (N - 1)) + s) & (N - 1);
   uint64_t Dv[ORC_MAXP];
-  orc_dcf_eval(b, &K->coeff, v, Dv);
+  orc_dcf4_eval(b, &K->coeff, v, Dv);
   uint64_t g[ORC_MAXM + 1][ORC_MAXP];
   for (int k = 0; k < p; k++) { g[0][k] = 0; g[m][k] = K->rho[k]; }
   for (int i = 1; i < m; i++) {
     uint64_t u = (v - S->aprime[i]) & (N - 1);
     uint64_t D[ORC_MAXP];
-    orc_dcf_eval(b, &K->coeff, u, D);
+    orc_dcf4_eval(b, &K->coeff, u, D);
     for (int k = 0; k < p; k++)
       g[i][k] = D[k] - Dv[k] + (v < S->aprime[i] ? K->rho[k] : 0);
   }
@@ -681,6 +825,7 @@ int orc_hw_threads(void) {
 }
 int orc_sizeof_elem_key(void) { return (int)sizeof(orc_elem_key); }
 int orc_sizeof_dcf_key(void) { return (int)sizeof(orc_dcf_key); }
+int orc_sizeof_dcf4_key(void) { return (int)sizeof(orc_dcf4_key); }
 int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
 
 typedef struct {

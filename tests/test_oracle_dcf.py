@@ -69,3 +69,81 @@ def test_dcf_keys_share_corrections_and_differ_in_roots():
         assert k0.scw[i].lo & 3 == 0
         assert list(k0.vcw[i][:3]) == list(k1.vcw[i][:3])
     assert list(k0.fin[:3]) == list(k1.fin[:3])
+
+
+# ---- four children per level (call 2's vector DCF) -------------------------
+
+def _keep_rand(rnd, n, p):
+    levels, per = (n + 1) // 2, 1 + (p + 1) // 2
+    return [(rnd.getrandbits(64), rnd.getrandbits(64)) for _ in range(levels * per)]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
+def test_dcf4_z2_bruteforce(n):
+    rnd = random.Random(300 + n)
+    for alpha in range(2**n):
+        for beta in (0, 1):
+            k0, k1 = O.dcf4_gen(n, 0, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, 0))
+            for x in range(2**n):
+                got = O.dcf4_eval(0, k0, x) ^ O.dcf4_eval(1, k1, x)
+                assert got == (beta if x < alpha else 0), (n, alpha, beta, x)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", [1, 3, 4, 6])
+def test_dcf4_vector_bruteforce(n, p):
+    rnd = random.Random(3000 * n + p)
+    for alpha in range(2**n):
+        beta = [rnd.getrandbits(64) for _ in range(p)]
+        k0, k1 = O.dcf4_gen(n, p, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, p))
+        for x in range(2**n):
+            a, b = O.dcf4_eval(0, k0, x), O.dcf4_eval(1, k1, x)
+            got = [(u + v) & M64 for u, v in zip(a, b)]
+            assert got == (beta if x < alpha else [0] * p), (n, p, alpha, x)
+
+
+def test_dcf4_wide_domain_sampled():
+    """n = 23, 24 and 32: sampled points around alpha and across the domain."""
+    rnd = random.Random(15)
+    for n in (23, 24, 32):
+        for _ in range(6):
+            alpha = rnd.getrandbits(n)
+            beta = [rnd.getrandbits(64) for _ in range(3)]
+            k0, k1 = O.dcf4_gen(n, 3, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, 3))
+            pts = {0, 2**n - 1, alpha, (alpha - 1) % 2**n, (alpha + 1) % 2**n}
+            pts |= {alpha ^ (1 << j) for j in range(n)}
+            pts |= {rnd.getrandbits(n) for _ in range(20)}
+            for x in pts:
+                got = [(u + v) & M64 for u, v in zip(O.dcf4_eval(0, k0, x), O.dcf4_eval(1, k1, x))]
+                assert got == (beta if x < alpha else [0, 0, 0]), (n, alpha, x)
+
+
+def test_dcf4_corrections():
+    """Both keys carry the same corrections; alpha's child gets the supplied
+    randomness at every level, every other child corrects the parties'
+    children to equal seeds (checked on the first level, where both parties
+    expand their roots)."""
+    rnd = random.Random(21)
+    n, p, alpha = 8, 3, 0b10_01_11_00
+    kr = _keep_rand(rnd, n, p)
+    r0, r1 = _roots(rnd)
+    k0, k1 = O.dcf4_gen(n, p, alpha, [5, 6, 7], r0, r1, kr)
+    assert k0.root.lo & 3 == 0 and k1.root.lo & 3 == 0
+    per = 1 + (p + 1) // 2
+    for i in range(n // 2):
+        a = (alpha >> (2 * (n // 2 - 1 - i))) & 3
+        for c in range(4):
+            assert (k0.scw[i][c].lo, k0.scw[i][c].hi) == (k1.scw[i][c].lo, k1.scw[i][c].hi)
+            assert k0.tcw[i][c] == k1.tcw[i][c] and k0.scw[i][c].lo & 3 == 0
+            assert list(k0.vcw[i][c][:p]) == list(k1.vcw[i][c][:p])
+        lo, hi = kr[i * per]
+        assert (k0.scw[i][a].lo, k0.scw[i][a].hi) == (lo & ~3, hi)
+        assert list(k0.vcw[i][a][:p]) == [kr[i * per + 1][0], kr[i * per + 1][1], kr[i * per + 2][0]]
+    # level 0: child seeds are H(root, c) with bits 0..1 cleared, t = bit 0
+    a0 = (alpha >> (n - 2)) & 3
+    for c in range(4):
+        if c == a0:
+            continue
+        c0, c1 = O.prg(k0.root.lo, k0.root.hi, c), O.prg(k1.root.lo, k1.root.hi, c)
+        assert k0.scw[0][c].lo == (c0[0] ^ c1[0]) & ~3 and k0.scw[0][c].hi == c0[1] ^ c1[1]
+        assert k0.tcw[0][c] == (c0[0] ^ c1[0]) & 1
