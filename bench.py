@@ -50,9 +50,14 @@ def pct(xs, q):
 
 
 def keygen_aes_per_elem(inst) -> int:
+    """Dealer AES blocks per element: both parties' children of every Z_2 DCF
+    level (2 each), of every lookup-DCF level (4 children of 1 + ceil(p/2)
+    blocks each, L = ceil(n/2) levels) and the leaf conversions, plus the
+    counter-mode randomness (1 + ceil(p/2) blocks per lookup level)."""
     nb = (inst.p + 1) // 2
-    prg = sum(4 * k for k in inst.atom_k) + 2 * inst.n_bits * (2 + 2 * nb) + 2 * nb
-    rand = 2 * inst.T + 7
+    L = (inst.n_bits + 1) // 2
+    prg = sum(4 * k for k in inst.atom_k) + 2 * L * 4 * (1 + nb) + 2 * nb
+    rand = 2 * inst.T + 7 + L * (1 + nb)
     return prg + rand
 
 

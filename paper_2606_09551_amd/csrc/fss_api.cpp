@@ -272,12 +272,16 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
   h.kmax = kmax;
   // Lookup points u_i = (v - a'_i) mod 2^n span W = a'_{m-1} - a'_1 + 1
   // consecutive values; with 2^K >= W they meet at most two aligned blocks of
-  // 2^K values, whose first n - K levels are shared.  Worth it when m >= 4.
+  // 2^K values, whose first levels are shared.  The lookup DCF walks
+  // 2L = 2 ceil(n / 2) bits, two per level, so K is raised until 2L - K is
+  // even and the shared levels are (2L - K) / 2.  Worth it when m >= 4.
   {
     const uint64_t W = (m >= 2) ? (q->aprime[m - 1] - q->aprime[1] + 1) : 1;
+    const int bits4 = 2 * ((n + 1) / 2);
     int K = 0;
     while (K < n && ((uint64_t)1 << K) < W) ++K;
-    h.top_depth = (m >= 4) ? (uint32_t)(n - K) : 0u;
+    if ((bits4 - K) & 1) ++K;
+    h.top_depth = (m >= 4 && K < bits4) ? (uint32_t)((bits4 - K) / 2) : 0u;
   }
   h.tile_bytes = q->layout.tile_bytes;
   h.spec_hash = S->hash;
@@ -650,13 +654,14 @@ ElemCost elem_cost(const KeyHeader& h) {
   ElemCost c;
   for (uint32_t t = 0; t < h.T; ++t) c.aes_pred += h.atom_k[t];
   c.lk_pred = 160.0 * c.aes_pred;
-  const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb, n = h.n, D = h.top_depth;
-  c.aes_base = n * lvl + nb;
-  c.lk_base = n * shared(lvl) + shared(nb);
+  // the lookup DCF has L = ceil(n / 2) levels of four children; D of them shared
+  const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb, L = (double)((h.n + 1) / 2), D = h.top_depth;
+  c.aes_base = L * lvl + nb;
+  c.lk_base = L * shared(lvl) + shared(nb);
   c.aes_tops = 2 * D * lvl;
   c.lk_tops = 2 * D * shared(lvl);
-  c.aes_point = (n - D) * lvl + nb;
-  c.lk_point = (n - D) * shared(lvl) + shared(nb);
+  c.aes_point = (L - D) * lvl + nb;
+  c.lk_point = (L - D) * shared(lvl) + shared(nb);
   c.points = (int)h.m - 1;
   return c;
 }

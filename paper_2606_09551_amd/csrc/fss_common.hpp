@@ -81,11 +81,14 @@ constexpr AesConst kAes = make_aes_const();
 //   atom t : root[64] (16 B) | cw[k_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
 //            | vbits[64] (u64: bit i = value corr. of level i, bit 32 = final)
 //   wshare[64] (u64: bit j = this party's share of the carry of output j)
-//   coeff  : root[64] | cw[n][64] | vcw[n][p][64] (u64) | fin[p][64]
+//   coeff  : root[64] | cw[L][4][64] (16 B: seed corr., bit0 = control-bit
+//            corr.) | vcw[L][4][p][64] (u64) | fin[p][64]
 //            | rho[p][64] (share of rho) | rout[64] (share of r_out)
+//   The lookup's vector DCF has four children per level (two input bits), so
+//   it has L = ceil(n / 2) levels with a correction for each child.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -95,7 +98,7 @@ constexpr uint64_t kHeaderBytes = 16384;
 struct KeyHeader {
   uint32_t magic, version, party, layout;
   uint32_t n, f, m, d, p, T, ell, F_out;
-  uint32_t n_prim, n_views, kmax, top_depth;  // top_depth: shared levels of the lookup points
+  uint32_t n_prim, n_views, kmax, top_depth;  // top_depth: shared lookup-DCF levels of the lookup points
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];
@@ -127,8 +130,9 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p) {
   }
   L.off_w = o;     o += kTile * 8;
   L.off_croot = o; o += kTile * 16;
-  L.off_ccw = o;   o += (uint64_t)n * kTile * 16;
-  L.off_cvcw = o;  o += (uint64_t)n * p * kTile * 8;
+  const uint64_t levels = (uint64_t)(n + 1) / 2;  // four children per level
+  L.off_ccw = o;   o += levels * 4 * kTile * 16;
+  L.off_cvcw = o;  o += levels * 4 * p * kTile * 8;
   L.off_cfin = o;  o += (uint64_t)p * kTile * 8;
   L.off_crho = o;  o += (uint64_t)p * kTile * 8;
   L.off_crout = o; o += kTile * 8;

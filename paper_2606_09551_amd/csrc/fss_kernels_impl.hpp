@@ -407,27 +407,30 @@ __device__ __forceinline__ VState<P> vselect(bool c, const VState<P>& a, const V
   return r;
 }
 
-// Advance `st` through levels [i0, i1) along the bits of the n-bit input x
-// (level i consumes bit n-1-i).
+// Advance `st` through levels [i0, i1) of the lookup DCF along the base-4
+// digits of the input x: the DCF has L = ceil(n / 2) levels of four children
+// and level i consumes digit L - 1 - i (an odd n has a leading zero bit).
+// Child d of seed s is H(s, d), its value the first P words of H(s, 4 + 2d + k).
 template <int P, class TB>
 __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
                                          uint32_t x, int i0, int i1, VState<P>& st) {
   constexpr int NB = (P + 1) / 2;
-  const int n = (int)h->n;
+  const int L = ((int)h->n + 1) / 2;
   const uint8_t* cwp = tile + h->off_ccw + lane * 16;
   const uint8_t* vcp = tile + h->off_cvcw + lane * 8;
   for (int i = i0; i < i1; ++i) {
-    const uint32_t xi = (x >> (n - 1 - i)) & 1u;
+    const uint32_t d = (x >> (2 * (L - 1 - i))) & 3u;
     uint32_t jj[1 + NB], o[1 + NB][4];
-    jj[0] = xi;
-    jj[1] = 2u + 2u * xi;
-    if (NB > 1) jj[NB > 1 ? 2 : 0] = 3u + 2u * xi;
+    jj[0] = d;
+    jj[1] = 4u + 2u * d;
+    if (NB > 1) jj[NB > 1 ? 2 : 0] = 5u + 2u * d;
     prg_shared<TB, 1 + NB>(tb, st.s, jj, o);
-    const uint4 cw = ld16(cwp + (uint64_t)i * kTile * 16);
+    const uint64_t row = (uint64_t)i * 4 + d;  // child d's corrections at level i
+    const uint4 cw = ld16(cwp + row * kTile * 16);
     const uint32_t t = st.t;
     const uint32_t msk = 0u - t;
     const uint64_t msk64 = 0ull - (uint64_t)t;
-    st.t = (o[0][0] & 1u) ^ ((cw.x >> xi) & t & 1u);
+    st.t = (o[0][0] & 1u) ^ (cw.x & t & 1u);
     st.s[0] = (o[0][0] & ~3u) ^ (cw.x & ~3u & msk);
     st.s[1] = o[0][1] ^ (cw.y & msk);
     st.s[2] = o[0][2] ^ (cw.z & msk);
@@ -435,21 +438,21 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
-      v += ld8(vcp + ((uint64_t)i * P + q) * kTile * 8) & msk64;
+      v += ld8(vcp + (row * P + q) * kTile * 8) & msk64;
       st.V[q] += b ? (0ull - v) : v;
     }
   }
 }
 
-// Leaf value: V + (-1)^b (Convert(s) + t * CW_{n+1}), Convert(s) = the first
-// P words of H(s, 6) || H(s, 7).
+// Leaf value: V + (-1)^b (Convert(s) + t * CW_fin), Convert(s) = the first
+// P words of H(s, 12) || H(s, 13).
 template <int P, class TB>
 __device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
                                           const VState<P>& st, uint64_t (&out)[P]) {
   constexpr int NB = (P + 1) / 2;
   uint32_t jj[NB], o[NB][4];
 #pragma unroll
-  for (int q = 0; q < NB; ++q) jj[q] = 6u + q;
+  for (int q = 0; q < NB; ++q) jj[q] = 12u + q;
   prg_shared<TB, NB>(tb, st.s, jj, o);
   const uint64_t msk64 = 0ull - (uint64_t)st.t;
 #pragma unroll
@@ -472,8 +475,9 @@ __device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* t
 //
 // Shared prefixes: the points u_1 > ... > u_{m-1} (cyclically) lie in a window
 // of W = a'_{m-1} - a'_1 + 1 consecutive values, which meets at most two
-// aligned blocks of 2^K >= W values.  Their first D = n - K levels are walked
-// once per block (A, the block of u_{m-1}, and its successor B) and each point
+// aligned blocks of 2^K >= W values.  With K = 2L - 2D the first D levels of
+// the lookup DCF are walked once per block (A, the block of u_{m-1}, and its
+// successor B, modulo the 2^(n-K) blocks of the n-bit domain) and each point
 // resumes from its block's state: same outputs, (m - 3) * D fewer levels.
 //
 // Every term of q, and so of y = sum_j q_j xhat^j, is linear: a tile's work can
@@ -485,15 +489,16 @@ template <int P, class TB>
 __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8_t* tile,
                                                int lane, int b, uint64_t xhat, int i0, int i1, bool base) {
   const int n = (int)h->n, m = (int)h->m, D = (int)h->top_depth;
+  const int L = (n + 1) / 2;
   const int iend = i1 < m ? i1 : m;
   const uint32_t Nmask = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
   const uint32_t half = 1u << (n - 1);
   const uint32_t v = ((uint32_t)xhat + half) & Nmask;
   const uint8_t* rhop = tile + h->off_crho + lane * 8;
-  const int K = n - D;
-  const uint32_t top_mask = D >= 32 ? 0xffffffffu : ((1u << D) - 1u);
-  const uint32_t blkA = (uint32_t)(((uint64_t)((v - (uint32_t)h->aprime[m - 1]) & Nmask)) >> K);
-  const uint32_t blkB = (blkA + 1u) & top_mask;
+  const int K = D > 0 ? 2 * (L - D) : 0;  // input bits below the shared levels (D > 0: 2 <= K < n)
+  const uint32_t blk_mask = D > 0 ? (1u << (n - K)) - 1u : 0u;
+  const uint32_t blkA = D > 0 ? (((v - (uint32_t)h->aprime[m - 1]) & Nmask) >> K) : 0u;
+  const uint32_t blkB = (blkA + 1u) & blk_mask;
   uint64_t q[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) q[k] = 0;
@@ -505,8 +510,8 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   for (int i = i0; i < iend; ++i) {
     const uint32_t ap = (uint32_t)h->aprime[i];
     const uint32_t u = (v - ap) & Nmask;
-    VState<P> st = vselect<P>((uint32_t)((uint64_t)u >> K) == blkA, sa, sb);
-    vec_walk<P>(tb, h, tile, lane, b, u, D, n, st);
+    VState<P> st = vselect<P>((u >> K) == blkA, sa, sb);  // D = 0: both are the root
+    vec_walk<P>(tb, h, tile, lane, b, u, D, L, st);
     uint64_t g[P];
     vec_final<P>(tb, h, tile, lane, b, st, g);
     const uint64_t lt = v < ap ? ~0ull : 0ull;
@@ -519,7 +524,7 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   }
   if (base) {
     VState<P> st = vroot<P>(h, tile, lane, b);
-    vec_walk<P>(tb, h, tile, lane, b, v, 0, n, st);
+    vec_walk<P>(tb, h, tile, lane, b, v, 0, L, st);
     uint64_t Dv[P];
     vec_final<P>(tb, h, tile, lane, b, st, Dv);
 #pragma unroll
@@ -675,6 +680,20 @@ __device__ __forceinline__ void rand_blk(const TB& tb, const RoundKeys& rk, uint
   o[0] = s[0][0]; o[1] = s[0][1]; o[2] = s[0][2]; o[3] = s[0][3];
 }
 
+// R(e, purpose_k, ctr) for K purposes at once (one interleaved AES).
+template <class TB, int K>
+__device__ __forceinline__ void rand_blks(const TB& tb, const RoundKeys& rk, uint64_t e, const uint32_t (&purpose)[K],
+                                          uint32_t ctr, uint32_t (&o)[K][4]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    o[k][0] = (uint32_t)e;
+    o[k][1] = (uint32_t)(e >> 32);
+    o[k][2] = (purpose[k] & 0xffffu) | (ctr << 16);
+    o[k][3] = 0u;
+  }
+  aes_encrypt(RtKey{rk}, tb, o);
+}
+
 // Z_2 DCF Gen for f(x) = 1[x < alpha] over k bits; writes root, cw, vbits.
 // The PRG tweaks are chosen so block 0/1 of each party is the child on /
 // off alpha's path ("keep" / "lose"); no register array is indexed at run time.
@@ -735,18 +754,25 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
   if (a1) st8(a1 + (vbo - a0), vbits);
 }
 
-// Vector DCF Gen for f(x) = beta * 1[x < alpha] over n bits, beta in Z^P.
-// Per party, blocks are [keep seed, lose seed, keep values.., lose values..].
+// Vector DCF Gen for f(x) = beta * 1[x < alpha] over n bits, beta in Z^P,
+// with four children per level (L = ceil(n / 2) levels, base-4 digits of
+// alpha).  At every level both parties expand all four children; for the
+// child off alpha's path the corrections make the parties' children equal:
+// seed XOR, control bits t0 ^ t1, V_CW = (-1)^{t_1} (v_1 - v_0 - V_alpha
+// [+ beta below alpha's digit]).  Alpha's child gets random corrections
+// R(e, 69 + k, level), carries the parties on, and updates V_alpha.
 template <int P, class TB>
 __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t alpha,
                                         const uint64_t (&beta)[P], const uint32_t (&r0)[4],
-                                        const uint32_t (&r1)[4], uint8_t* k0, uint8_t* k1, int lane) {
+                                        const uint32_t (&r1)[4], const RoundKeys& rk, uint64_t e,
+                                        uint8_t* k0, uint8_t* k1, int lane) {
   constexpr int NB = (P + 1) / 2;
   // Header offsets are read before the first key store: the compiler cannot
   // tell the key stores from header memory, and a header read after a store
   // would wait for the store to complete.
   const uint64_t off_croot = h->off_croot, off_ccw = h->off_ccw, off_cvcw = h->off_cvcw;
   const uint64_t off_cfin = h->off_cfin;
+  const int L = (n + 1) / 2;
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
   uint32_t t[2] = {0u, 1u};
   uint64_t Va[P];
@@ -754,82 +780,96 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   for (int q = 0; q < P; ++q) Va[q] = 0;
   st16(k0 + off_croot + lane * 16, make_uint4(s[0][0], s[0][1], s[0][2], s[0][3]));
   if (k1) st16(k1 + off_croot + lane * 16, make_uint4(s[1][0], s[1][1], s[1][2], s[1][3]));
-  for (int i = 0; i < n; ++i) {
-    const uint32_t ai = (uint32_t)(alpha >> (n - 1 - i)) & 1u, al = ai ^ 1u;
+  for (int i = 0; i < L; ++i) {
+    const uint32_t a = (uint32_t)(alpha >> (2 * (L - 1 - i))) & 3u;
     const uint64_t neg = 0ull - (uint64_t)t[1];  // (-1)^{t_1} as a mask
-    const uint64_t badd = 0ull - (uint64_t)ai;   // beta enters when the lost child is L
-    // The child off alpha's path ("lose") of both parties first: their seeds'
-    // XOR is the seed correction, v_lose(1) - v_lose(0) gives V_CW.  The live
-    // set then stays small: V_CW enters V_alpha at once, and each party's child
-    // on the path ("keep") becomes its next seed as soon as it is expanded.
-    uint32_t scw[4] = {0u, 0u, 0u, 0u}, tlx = 0u;
-    uint64_t dl[P];
+    // Children off alpha's path: corrections written as they are expanded.
+    // Alpha's child: the parties' children kept for after the loop.
+    uint32_t ks[2][4] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}}, kt[2] = {0u, 0u};
+    uint64_t dk[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) dl[q] = 0;
+    for (int q = 0; q < P; ++q) dk[q] = 0;
+#pragma unroll 1
+    for (uint32_t c = 0; c < 4; ++c) {
+      uint32_t o0[1 + NB][4], o1[1 + NB][4], jj[1 + NB];
+      jj[0] = c;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      uint32_t o[1 + NB][4], jj[1 + NB];
-      jj[0] = al;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * al + q;
-      prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
-      tlx ^= o[0][0] & 1u;
-      scw[0] ^= o[0][0] & ~3u; scw[1] ^= o[0][1]; scw[2] ^= o[0][2]; scw[3] ^= o[0][3];
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
-        dl[q] += b ? v : (0ull - v);
-      }
+      for (int k = 0; k < NB; ++k) jj[1 + k] = 4u + 2u * c + k;
+      prg_shared<TB, 1 + NB>(tb, s[0], jj, o0);
       __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-      const uint64_t w = dl[q] - Va[q] + (beta[q] & badd);
-      const uint64_t vcw = (w ^ neg) - neg;
-      Va[q] += (vcw ^ neg) - neg;
-      const uint64_t vo = off_cvcw + (((uint64_t)i * P + q) * kTile + lane) * 8;
-      st8(k0 + vo, vcw);
-      if (k1) st8(k1 + vo, vcw);
-    }
-    uint32_t tk[2];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      uint32_t o[1 + NB][4], jj[1 + NB];
-      jj[0] = ai;
-#pragma unroll
-      for (int q = 0; q < NB; ++q) jj[1 + q] = 2u + 2u * ai + q;
-      prg_shared<TB, 1 + NB>(tb, s[b], jj, o);
-      tk[b] = o[0][0] & 1u;
-      const uint32_t m = 0u - t[b];  // the parent's control bit applies the correction
-      s[b][0] = (o[0][0] & ~3u) ^ (scw[0] & ~3u & m);
-      s[b][1] = o[0][1] ^ (scw[1] & m);
-      s[b][2] = o[0][2] ^ (scw[2] & m);
-      s[b][3] = o[0][3] ^ (scw[3] & m);
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
-        Va[q] += b ? (0ull - v) : v;
-      }
+      prg_shared<TB, 1 + NB>(tb, s[1], jj, o1);
       __builtin_amdgcn_sched_barrier(0);
+      const uint32_t t0c = o0[0][0] & 1u, t1c = o1[0][0] & 1u;
+      if (c == a) {
+        ks[0][0] = o0[0][0] & ~3u;
+        ks[1][0] = o1[0][0] & ~3u;
+#pragma unroll
+        for (int w = 1; w < 4; ++w) {
+          ks[0][w] = o0[0][w];
+          ks[1][w] = o1[0][w];
+        }
+        kt[0] = t0c;
+        kt[1] = t1c;
+#pragma unroll
+        for (int q = 0; q < P; ++q)
+          dk[q] = mk64(o0[1 + q / 2][2 * (q & 1)], o0[1 + q / 2][2 * (q & 1) + 1]) -
+                  mk64(o1[1 + q / 2][2 * (q & 1)], o1[1 + q / 2][2 * (q & 1) + 1]);
+      } else {
+        const uint4 cw = make_uint4(((o0[0][0] ^ o1[0][0]) & ~3u) | (t0c ^ t1c), o0[0][1] ^ o1[0][1],
+                                    o0[0][2] ^ o1[0][2], o0[0][3] ^ o1[0][3]);
+        const uint64_t cwoff = off_ccw + (((uint64_t)i * 4 + c) * kTile + lane) * 16;
+        st16(k0 + cwoff, cw);
+        if (k1) st16(k1 + cwoff, cw);
+        const uint64_t below = c < a ? ~0ull : 0ull;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const uint64_t v0 = mk64(o0[1 + q / 2][2 * (q & 1)], o0[1 + q / 2][2 * (q & 1) + 1]);
+          const uint64_t v1 = mk64(o1[1 + q / 2][2 * (q & 1)], o1[1 + q / 2][2 * (q & 1) + 1]);
+          const uint64_t w = v1 - v0 - Va[q] + (beta[q] & below);
+          const uint64_t vo = off_cvcw + ((((uint64_t)i * 4 + c) * P + q) * kTile + lane) * 8;
+          st8(k0 + vo, (w ^ neg) - neg);
+          if (k1) st8(k1 + vo, (w ^ neg) - neg);
+        }
+      }
     }
-    const uint32_t tkx = tk[0] ^ tk[1];
-    const uint32_t tL = (ai ? tlx : tkx) ^ ai ^ 1u;
-    const uint32_t tR = (ai ? tkx : tlx) ^ ai;
-    const uint4 cw = make_uint4(scw[0] | tL | (tR << 1), scw[1], scw[2], scw[3]);
-    const uint64_t cwoff = off_ccw + ((uint64_t)i * kTile + lane) * 16;
+    // Alpha's child: random seed and value corrections R(e, 69 + k, level);
+    // the parties' next seeds and V_alpha.
+    uint32_t kr[1 + NB][4];
+    {
+      uint32_t pur[1 + NB];
+#pragma unroll
+      for (int k = 0; k <= NB; ++k) pur[k] = 69u + k;
+      rand_blks<TB, 1 + NB>(tb, rk, e, pur, (uint32_t)i, kr);
+    }
+    const uint32_t tcw_a = kt[0] ^ kt[1] ^ 1u;
+    const uint32_t scw_a[4] = {kr[0][0] & ~3u, kr[0][1], kr[0][2], kr[0][3]};
+    const uint64_t cwoff = off_ccw + (((uint64_t)i * 4 + a) * kTile + lane) * 16;
+    const uint4 cw = make_uint4(scw_a[0] | tcw_a, scw_a[1], scw_a[2], scw_a[3]);
     st16(k0 + cwoff, cw);
     if (k1) st16(k1 + cwoff, cw);
-    const uint32_t tkc = ai ? tR : tL;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) t[b] = tk[b] ^ (t[b] & tkc);
+    for (int q = 0; q < P; ++q) {
+      const uint64_t vcw = mk64(kr[1 + q / 2][2 * (q & 1)], kr[1 + q / 2][2 * (q & 1) + 1]);
+      const uint64_t vo = off_cvcw + ((((uint64_t)i * 4 + a) * P + q) * kTile + lane) * 8;
+      st8(k0 + vo, vcw);
+      if (k1) st8(k1 + vo, vcw);
+      Va[q] += dk[q] + ((vcw ^ neg) - neg);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const uint32_t m = 0u - t[b];  // the parent's control bit applies the correction
+#pragma unroll
+      for (int w = 0; w < 4; ++w) s[b][w] = ks[b][w] ^ (scw_a[w] & m);
+      t[b] = kt[b] ^ (t[b] & tcw_a);
+    }
   }
-  // CW_{n+1} = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha)
+  // CW_fin = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha), Convert = H(s, 12 + k)
   uint64_t cv[2][P];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     uint32_t o[NB][4], jj[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) jj[q] = 6u + q;
+    for (int q = 0; q < NB; ++q) jj[q] = 12u + q;
     prg_shared<TB, NB>(tb, s[b], jj, o);
 #pragma unroll
     for (int q = 0; q < P; ++q) cv[b][q] = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
@@ -858,7 +898,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
   const int n = (int)h->n;
   const uint64_t off_crho = h->off_crho;
   const uint64_t nmask = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  gen_vec<P>(tb, h, n, rin & nmask, rho, c0, c1, t0, t1, lane);
+  gen_vec<P>(tb, h, n, rin & nmask, rho, c0, c1, ga.rk, e, t0, t1, lane);
   uint32_t ra[4], rb[4];
   rand_blk(tb, ga.rk, e, 67, 0, ra);
   rand_blk(tb, ga.rk, e, 68, 0, rb);

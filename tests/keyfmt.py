@@ -49,19 +49,23 @@ class KeyView:
                 "vcw": [(vb >> i) & 1 for i in range(k)], "fin": (vb >> 32) & 1}
 
     def coeff(self, e: int) -> dict:
+        """The lookup DCF: L = ceil(n / 2) levels of four children, each child's
+        seed correction (bit 0 = control-bit correction) and value corrections."""
         h, lane = self.h, e % TILE
         n, p = int(h["n"]), int(h["p"])
+        L = (n + 1) // 2
         tb = self.tile_base(e)
         root = self._blk(tb + int(h["off_croot"]) + lane * 16)
-        cws = [self._blk(tb + int(h["off_ccw"]) + (i * TILE + lane) * 16) for i in range(n)]
-        vcw = [[self._u64(tb + int(h["off_cvcw"]) + ((i * p + q) * TILE + lane) * 8) for q in range(p)]
-               for i in range(n)]
+        cws = [[self._blk(tb + int(h["off_ccw"]) + ((i * 4 + c) * TILE + lane) * 16) for c in range(4)]
+               for i in range(L)]
+        vcw = [[[self._u64(tb + int(h["off_cvcw"]) + (((i * 4 + c) * p + q) * TILE + lane) * 8)
+                 for q in range(p)] for c in range(4)] for i in range(L)]
         fin = [self._u64(tb + int(h["off_cfin"]) + (q * TILE + lane) * 8) for q in range(p)]
         rho = [self._u64(tb + int(h["off_crho"]) + (q * TILE + lane) * 8) for q in range(p)]
         rout = self._u64(tb + int(h["off_crout"]) + lane * 8)
         w = self._u64(tb + int(h["off_w"]) + lane * 8)
-        return {"root": root, "scw": [(lo & ~3, hi) for lo, hi in cws],
-                "tl": [lo & 1 for lo, _ in cws], "tr": [(lo >> 1) & 1 for lo, _ in cws],
+        return {"root": root, "scw": [[(lo & ~3, hi) for lo, hi in lv] for lv in cws],
+                "tcw": [[lo & 1 for lo, _ in lv] for lv in cws],
                 "vcw": vcw, "fin": fin, "rho": rho, "rout": rout, "wshare": w}
 
 
@@ -75,9 +79,10 @@ def oracle_atom(K, t: int) -> dict:
 
 def oracle_coeff(K) -> dict:
     c = K.coeff
-    n, p = c.n, c.p
-    return {"root": (c.root.lo, c.root.hi), "scw": [(c.scw[i].lo, c.scw[i].hi) for i in range(n)],
-            "tl": [c.tl[i] for i in range(n)], "tr": [c.tr[i] for i in range(n)],
-            "vcw": [[int(c.vcw[i][q]) for q in range(p)] for i in range(n)],
+    L, p = (c.n + 1) // 2, c.p
+    return {"root": (c.root.lo, c.root.hi),
+            "scw": [[(c.scw[i][ch].lo, c.scw[i][ch].hi) for ch in range(4)] for i in range(L)],
+            "tcw": [[c.tcw[i][ch] for ch in range(4)] for i in range(L)],
+            "vcw": [[[int(c.vcw[i][ch][q]) for q in range(p)] for ch in range(4)] for i in range(L)],
             "fin": [int(c.fin[q]) for q in range(p)], "rho": [int(K.rho[q]) for q in range(p)],
             "rout": int(K.rout), "wshare": int(K.wshare)}

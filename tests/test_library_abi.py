@@ -111,11 +111,14 @@ def test_key_bytes_shape():
     assert per_tile % 256 == 0
     for N in (1, 63, 64, 65, 393216):
         assert s.key_bytes(24, 12, N) == 16384 + ((N + 63) // 64) * per_tile
-    # 3 Z_2 atoms of 24 levels, one 24-level vector DCF with p = 3, shares
-    expect = 3 * (64 * 16 * 25 + 64 * 8) + 64 * 8 + 64 * 16 * 25 + 24 * 3 * 64 * 8 + 2 * 3 * 64 * 8 + 64 * 8
+    # 3 Z_2 atoms of 24 levels, w shares, then the lookup DCF: root, 12 levels x 4
+    # children of seed (16 B) and p = 3 value corrections, fin, rho and r_out shares
+    expect = (3 * (64 * 16 * 25 + 64 * 8) + 64 * 8 + 64 * 16 + 12 * 4 * 64 * 16 + 12 * 4 * 3 * 64 * 8
+              + 2 * 3 * 64 * 8 + 64 * 8)
     assert per_tile == (expect + 255) // 256 * 256
     c = F.Spec(W.clip_relu_spec())
-    assert (c.key_bytes(16, 8, 4096) - 16384) // 4096 == pytest.approx(1416, abs=16)
+    # n = 16, p = 2: atoms 3 * (17 * 16 + 8), w 8, root 16, 8 levels x 4 x (16 + 16), fin/rho 32, r_out 8
+    assert (c.key_bytes(16, 8, 4096) - 16384) // 4096 == 3 * (17 * 16 + 8) + 8 + 16 + 8 * 4 * 32 + 32 + 8
 
 
 def test_argument_errors():
