@@ -796,9 +796,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
 #pragma unroll
       for (int k = 0; k < NB; ++k) jj[1 + k] = 4u + 2u * c + k;
       prg_shared<TB, 1 + NB>(tb, s[0], jj, o0);
-      __builtin_amdgcn_sched_barrier(0);
       prg_shared<TB, 1 + NB>(tb, s[1], jj, o1);
-      __builtin_amdgcn_sched_barrier(0);
       const uint32_t t0c = o0[0][0] & 1u, t1c = o1[0][0] & 1u;
       if (c == a) {
         ks[0][0] = o0[0][0] & ~3u;
