@@ -192,11 +192,12 @@ int fss_plan_launch(fss_plan* plan, void* stream);
  * before the plan itself. */
 int fss_plan_free(fss_plan* plan);
 /* AES-128 blocks one launch of `plan` evaluates, as the kernels compute them
- * (per element and party, with B = 1 + ceil(p/2) blocks per tree level and
- * D the shared top depth: sum_t k_t + (n + 2D + (m-1)(n-D)) B + m ceil(p/2);
- * the m-1 lookup points share their first D levels, walked once for each of
- * the two aligned blocks they fall in; a tile run in parts walks them once per
- * part).  Used for throughput reporting. */
+ * (per element and party, with B = 1 + ceil(p/2) blocks per level of the
+ * lookup DCF, L = ceil(n/2) such levels of four children, and D shared top
+ * levels: sum_t k_t + (L + 2D + (m-1)(L-D)) B + m ceil(p/2); the m-1 lookup
+ * points share their first D levels, walked once for each of the two aligned
+ * blocks they fall in; a tile run in parts walks them once per part).  Used
+ * for throughput reporting. */
 double fss_plan_aes_blocks(const fss_plan* plan);
 /* T-table lookups of one launch: 16 per AES round, less the 24 lookups of
  * rounds 1-2 that the blocks expanding one seed under K tweaks share

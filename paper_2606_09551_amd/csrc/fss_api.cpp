@@ -578,6 +578,9 @@ struct fss_plan {
   int grid = 0;
   double aes_per_launch = 0;  // algorithmic AES blocks of one launch
   double lookups_per_launch = 0;  // T-table lookups of one launch
+  // Waits for the last launch, then returns the device buffers to the pool
+  // (also on a failed creation, for whatever was already taken).
+  ~fss_plan();
 };
 
 namespace {
@@ -618,6 +621,16 @@ void pool_put(void* p) {
   if (it != g_pool_all.end()) g_pool_free.push_back(it->second);
 }
 }  // namespace
+
+fss_plan::~fss_plan() {
+  // Buffers may be handed to another plan only after the last enqueued launch.
+  if (launched) (void)hipEventSynchronize(done);
+  if (done) (void)hipEventDestroy(done);
+  pool_put(d_items);
+  pool_put(d_tiles);
+  pool_put(d_counter);
+  pool_put(d_split);
+}
 
 struct fss_graph {
   hipGraph_t graph = nullptr;
@@ -786,7 +799,7 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   tn.block_threads = variant_block(tn.aes_variant);
   if (tn.blocks_per_cu <= 0) tn.blocks_per_cu = blocks_per_cu_default(tn.aes_variant);
   int cus = 0;
-  int rc = device_cus(&cus, nullptr);
+  int rc = current_cus(&cus);
   if (rc) return rc;
 
   std::vector<DevItem> dev(n_items);
@@ -953,15 +966,7 @@ int fss_plan_launch(fss_plan* plan, void* stream) {
 }
 
 int fss_plan_free(fss_plan* plan) {
-  if (!plan) return FSS_OK;
-  // Wait for the last enqueued launch before the buffers can be handed out again.
-  if (plan->launched) (void)hipEventSynchronize(plan->done);
-  if (plan->done) (void)hipEventDestroy(plan->done);
-  pool_put(plan->d_items);
-  pool_put(plan->d_tiles);
-  pool_put(plan->d_counter);
-  pool_put(plan->d_split);
-  delete plan;
+  delete plan;  // waits for the plan's last launch, returns its buffers
   return FSS_OK;
 }
 
