@@ -147,3 +147,28 @@ def test_dcf4_corrections():
         c0, c1 = O.prg(k0.root.lo, k0.root.hi, c), O.prg(k1.root.lo, k1.root.hi, c)
         assert k0.scw[0][c].lo == (c0[0] ^ c1[0]) & ~3 and k0.scw[0][c].hi == c0[1] ^ c1[1]
         assert k0.tcw[0][c] == (c0[0] ^ c1[0]) & 1
+
+
+def test_dcf4_corrections_do_not_single_out_alpha_child():
+    """The per-child corrections must not show which child lies on alpha's
+    path: over 600 keys, the control-bit correction of alpha's child and of
+    the other children are each 1 about half the time (a constant on alpha's
+    child would single it out; its seed correction is the supplied randomness,
+    checked in test_dcf4_corrections)."""
+    rnd = random.Random(77)
+    n, p = 6, 3
+    on = [0, 0]
+    off = [0, 0]
+    for _ in range(600):
+        alpha = rnd.getrandbits(n)
+        k0, _ = O.dcf4_gen(n, p, alpha, [1, 2, 3], *_roots(rnd), _keep_rand(rnd, n, p))
+        for i in range(n // 2):
+            a = (alpha >> (2 * (n // 2 - 1 - i))) & 3
+            for c in range(4):
+                bucket = on if c == a else off
+                bucket[0] += k0.tcw[i][c]
+                bucket[1] += 1
+    frac_on, frac_off = on[0] / on[1], off[0] / off[1]
+    # 1800 and 5400 Bernoulli(1/2) samples: 5 sigma is about 0.06 and 0.034
+    assert abs(frac_on - 0.5) < 0.06, frac_on
+    assert abs(frac_off - 0.5) < 0.034, frac_off
