@@ -685,38 +685,41 @@ struct Unit {
   double aes, lookups;
 };
 
-// The units of one tile split into `parts` (at most one per lookup point):
-// per part, its flags, point range and per-element cost.  Part 0 carries
-// call 1 and the base of call 2 and so takes fewer points.  Every tile of an
-// item splits the same way.
+// The units of one tile: call 1 on its own (when the spec has atoms), and
+// call 2 whole or split into `parts` (at most one per lookup point), with
+// flags, point range and per-element cost.  Call 2's part 0 carries the base
+// (the walk at v) and so takes fewer points.  Every tile of an item splits the
+// same way.  Call 1 as a unit of its own lets the costlier call-2 units run
+// first and the short call-1 units fill the end of the schedule.
 std::vector<Unit> tile_parts(const ElemCost& c, int parts) {
   std::vector<Unit> out;
   const int S = std::max(1, std::min(parts, c.points));
   if (S == 1) {
     const double tops = c.points > 0 ? 1.0 : 0.0;
-    out.push_back({0, 0, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitPred | kUnitBase,
-                   c.aes_pred + c.aes_base + tops * c.aes_tops + c.points * c.aes_point,
-                   c.lk_pred + c.lk_base + tops * c.lk_tops + c.points * c.lk_point});
-    return out;
-  }
-  const double total = c.aes_pred + c.aes_base + c.points * c.aes_point;
-  int k0 = (int)std::lround((total / S - c.aes_pred - c.aes_base) / c.aes_point);
-  k0 = std::max(0, std::min(k0, c.points - (S - 1)));
-  const int rest = c.points - k0;
-  int i = 1;
-  for (int part = 0; part < S; ++part) {
-    const int k = part == 0 ? k0 : rest / (S - 1) + (part - 1 < rest % (S - 1) ? 1 : 0);
-    const double tops = k > 0 ? 1.0 : 0.0;
-    Unit u{0, 0, (uint32_t)i | ((uint32_t)(i + k) << 16), kUnitAccumulate, tops * c.aes_tops + k * c.aes_point,
-           tops * c.lk_tops + k * c.lk_point};
-    if (part == 0) {
-      u.flags |= kUnitPred | kUnitBase;
-      u.aes += c.aes_pred + c.aes_base;
-      u.lookups += c.lk_pred + c.lk_base;
+    out.push_back({0, 0, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitBase,
+                   c.aes_base + tops * c.aes_tops + c.points * c.aes_point,
+                   c.lk_base + tops * c.lk_tops + c.points * c.lk_point});
+  } else {
+    const double total = c.aes_base + c.points * c.aes_point;
+    int k0 = (int)std::lround((total / S - c.aes_base) / c.aes_point);
+    k0 = std::max(0, std::min(k0, c.points - (S - 1)));
+    const int rest = c.points - k0;
+    int i = 1;
+    for (int part = 0; part < S; ++part) {
+      const int k = part == 0 ? k0 : rest / (S - 1) + (part - 1 < rest % (S - 1) ? 1 : 0);
+      const double tops = k > 0 ? 1.0 : 0.0;
+      Unit u{0, 0, (uint32_t)i | ((uint32_t)(i + k) << 16), kUnitAccumulate, tops * c.aes_tops + k * c.aes_point,
+             tops * c.lk_tops + k * c.lk_point};
+      if (part == 0) {
+        u.flags |= kUnitBase;
+        u.aes += c.aes_base;
+        u.lookups += c.lk_base;
+      }
+      out.push_back(u);
+      i += k;
     }
-    out.push_back(u);
-    i += k;
   }
+  if (c.aes_pred > 0) out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred, c.lk_pred});
   return out;
 }
 

@@ -33,8 +33,8 @@ struct DevItem {
 };
 
 // One unit of the fused kernel's work-list, kUnitWords u32: item, tile,
-// lookup-point range (i0 | i1 << 16) and flags.  A tile either runs whole
-// (call 1 + all of call 2, y stored) or in parts whose shares of y are added.
+// lookup-point range (i0 | i1 << 16) and flags.  A tile has a call-1 unit and
+// call 2 either whole (y stored) or in parts whose shares of y are added.
 constexpr int kUnitWords = 4;
 constexpr uint32_t kUnitPred = 1u;        // call 1 (the predicate bits)
 constexpr uint32_t kUnitBase = 2u;        // the walk at v, tab_0 rho and r_out terms of call 2

@@ -654,6 +654,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
     if ((flags & kUnitPred) && h->T > 0)
       pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
+    if (!(flags & kUnitBase) && (range & 0xffffu) >= (range >> 16)) continue;  // a call-1 unit
     const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),
                                         (flags & kUnitBase) != 0);
     if (valid) {

@@ -139,9 +139,10 @@ def test_small_specs_all_elements(name):
         g = gpu_run(desc, n, f, x, 0x5EED + len(name), path=path)
         o = oracle_run(desc, n, f, x, 0x5EED + len(name), np.arange(N))
         compare(g, o, np.arange(N), N, check_keys=16 if path == "plain" else 0)
-        if path == "fused" and o["S"].m >= 3:
-            # 32 tiles cannot fill the GPU: the planner runs them in parts
-            # that add their shares of y, which must not change any output
+        if path == "fused" and name in ("gelu_small", "exp_small"):
+            # 32 tiles cannot fill the GPU and call 2 dominates their cost: the
+            # planner runs call 2 in parts that add their shares of y, which
+            # must not change any output
             assert g["parts"] > 1, g["parts"]
 
 
