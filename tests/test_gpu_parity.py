@@ -146,6 +146,27 @@ def test_small_specs_all_elements(name):
             assert g["parts"] > 1, g["parts"]
 
 
+@pytest.mark.parametrize("n", [31, 32])
+@pytest.mark.parametrize("name", ["clip", "gelu"])
+def test_widest_domains(n, name):
+    """The widest comparison domains: n = 32 (16 lookup-DCF levels, full 32-bit
+    masks) and n = 31 (odd: a leading zero bit), every element of 200 inputs
+    spread over the whole domain plus its ends, keys sampled, both paths."""
+    desc = {"clip": W.clip_relu_spec(), "gelu": W.gelu_spec(f=8)}[name]
+    f = 8
+    N = 200
+    g_ = np.random.Generator(np.random.PCG64(1000 * n + len(name)))
+    s = 2 ** (n - 1)
+    x = g_.integers(-s, s, size=N).astype(np.int64)
+    x[:6] = [-s, s - 1, 0, -1, 1, -(1 << f)]
+    x[6:40] = g_.integers(-8 << f, 8 << f, size=34)  # where the pieces change
+    _flush(f"widest domain {name} n={n} N={N}")
+    for path in ("plain", "fused"):
+        g = gpu_run(desc, n, f, x, 0xD0 + n, path=path)
+        o = oracle_run(desc, n, f, x, 0xD0 + n, np.arange(N))
+        compare(g, o, np.arange(N), N, check_keys=8 if path == "plain" else 0)
+
+
 @pytest.mark.parametrize("N", [1, 63, 64, 65, 129])
 def test_edge_sizes(N):
     op = W.config1()[0]
