@@ -151,6 +151,8 @@ def main() -> None:
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one copy kernel of this size (HBM counter calibration)")
+    ap.add_argument("--ablation", choices=["reuse"], default=None,
+                    help="reuse: compiled program cached vs rebuilt per layer (12 GELU layers)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -164,6 +166,9 @@ def main() -> None:
     from paper_2606_09551_amd import runtime as R
 
     torch.cuda.set_device(0)
+    if args.ablation == "reuse":
+        reuse_ablation(args)
+        return
     if args.workload == "c5":
         serve_bench(args)
         return
@@ -362,6 +367,65 @@ def serve_bench(args) -> None:
         "offered_rps": args.rate,
     }
     print(json.dumps(line), flush=True)
+
+
+def reuse_ablation(args) -> None:
+    """Program reuse across layers (the paper's ablation "Program Reuse Across
+    Layers"): 12 BERT-base GELU layers of 128x3072, both parties, fresh keys for
+    every layer.  `cached` compiles the spec, builds the work-list plan and
+    captures its HIP graph once and replays it for every layer (the key, input
+    and output buffers are reused; keys are regenerated into them);
+    `per_layer` compiles, plans and captures again for every layer.  Init is
+    the host wall time of compile + spec tables + plan + capture; eval is the
+    HIP-event time of the layers' fused launches."""
+    import torch
+
+    from paper_2606_09551_amd import fss as F
+    from paper_2606_09551_amd import runtime as R
+    from paper_2606_09551_amd import workloads as W
+
+    op = W.config2()[0]
+    n_bits, f_bits, layers = W.N_BITS, W.F_BITS, 12
+    stream = torch.cuda.current_stream()
+    inst = R.OpInstanceGPU(F.Spec(op.spec), n_bits, f_bits, len(op.x))
+    inst.set_input(op.x)
+
+    def run(cached: bool) -> dict:
+        init_s, eval_ms, keep = 0.0, [], []
+        spec = plan = graph = None
+        for layer in range(layers):
+            if not cached or spec is None:
+                t0 = time.perf_counter()
+                spec = F.Spec(op.spec)
+                spec.query(n_bits, f_bits)
+                init_s += time.perf_counter() - t0
+                inst.spec = spec
+            inst.keygen(op.seed + 7919 * layer)
+            inst.mask()
+            torch.cuda.synchronize()
+            if not cached or plan is None:
+                t0 = time.perf_counter()
+                plan = F.Plan([inst.item(0), inst.item(1)])
+                graph = F.Graph([plan])
+                torch.cuda.synchronize()
+                init_s += time.perf_counter() - t0
+                keep.append((spec, plan, graph))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            graph.launch()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            eval_ms.append(e0.elapsed_time(e1))
+        for _, p, g in keep:
+            g.free()
+            p.free()
+        return {"program_inits": len(keep), "init_ms": round(init_s * 1e3, 3),
+                "eval_ms_total": round(sum(eval_ms), 3), "eval_ms_per_layer": round(statistics.mean(eval_ms), 4)}
+
+    run(True)  # warm-up: first compile, first launch, allocator
+    out = {"ablation": "program_reuse", "workload": "gelu_bert_base_ffn_128x3072_x12_layers",
+           "parties": 2, "cached": run(True), "per_layer": run(False)}
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
