@@ -295,8 +295,8 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
   }
   h.off_w = q->layout.off_w;
   h.off_croot = q->layout.off_croot;
-  h.off_ccw = q->layout.off_ccw;
-  h.off_cvcw = q->layout.off_cvcw;
+  h.off_crec = q->layout.off_crec;
+  h.rec_bytes = q->layout.rec_bytes;
   h.off_cfin = q->layout.off_cfin;
   h.off_crho = q->layout.off_crho;
   h.off_crout = q->layout.off_crout;

@@ -76,19 +76,23 @@ constexpr AesConst kAes = make_aes_const();
 
 // ---------------------------------------------------------------------------
 // Key buffer: a header, then n_tiles tiles of 64 elements.  Inside a tile
-// every field is stored structure-of-arrays over the 64 lanes, so a wave that
-// owns a tile reads each field with one coalesced access per level.
+// the fields are stored over the 64 lanes, so a wave that owns a tile reads
+// each field with one coalesced access per level.
 //   atom t : root[64] (16 B) | cw[k_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
 //            | vbits[64] (u64: bit i = value corr. of level i, bit 32 = final)
 //   wshare[64] (u64: bit j = this party's share of the carry of output j)
-//   coeff  : root[64] | cw[L][4][64] (16 B: seed corr., bit0 = control-bit
-//            corr.) | vcw[L][4][p][64] (u64) | fin[p][64]
+//   coeff  : root[64] | rec[L][4][64] | fin[p][64]
 //            | rho[p][64] (share of rho) | rout[64] (share of r_out)
 //   The lookup's vector DCF has four children per level (two input bits), so
-//   it has L = ceil(n / 2) levels with a correction for each child.
+//   it has L = ceil(n / 2) levels with corrections for each child.  A record
+//   rec[i][c][lane] (16 + 8p bytes) holds child c's seed correction (bit 0 =
+//   control-bit correction) followed by its p value corrections: the lanes of
+//   a wave pick different children, and a lane's child is one contiguous
+//   record, so a level's load touches fewer cache lines than separate seed and
+//   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -106,7 +110,7 @@ struct KeyHeader {
   uint32_t atom_rview[kMaxAtoms];          // theta atoms: index of their view's mask atom
   uint64_t atom_c[kMaxAtoms];              // view shift
   uint64_t atom_off[kMaxAtoms];            // byte offset of the atom section in a tile
-  uint64_t off_w, off_croot, off_ccw, off_cvcw, off_cfin, off_crho, off_crout;
+  uint64_t off_w, off_croot, off_crec, rec_bytes, off_cfin, off_crho, off_crout;  // rec_bytes = 16 + 8 p
   uint64_t aprime[kMaxM + 1];              // offset-binary boundaries
   // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
   // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
@@ -117,7 +121,7 @@ static_assert(sizeof(KeyHeader) <= kHeaderBytes, "header too large");
 
 struct Layout {
   uint64_t atom_off[kMaxAtoms];
-  uint64_t off_w, off_croot, off_ccw, off_cvcw, off_cfin, off_crho, off_crout;
+  uint64_t off_w, off_croot, off_crec, rec_bytes, off_cfin, off_crho, off_crout;
   uint64_t tile_bytes;
 };
 
@@ -131,8 +135,8 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p) {
   L.off_w = o;     o += kTile * 8;
   L.off_croot = o; o += kTile * 16;
   const uint64_t levels = (uint64_t)(n + 1) / 2;  // four children per level
-  L.off_ccw = o;   o += levels * 4 * kTile * 16;
-  L.off_cvcw = o;  o += levels * 4 * p * kTile * 8;
+  L.rec_bytes = 16 + 8 * (uint64_t)p;       // seed correction, then p value corrections
+  L.off_crec = o;  o += levels * 4 * kTile * L.rec_bytes;
   L.off_cfin = o;  o += (uint64_t)p * kTile * 8;
   L.off_crho = o;  o += (uint64_t)p * kTile * 8;
   L.off_crout = o; o += kTile * 8;

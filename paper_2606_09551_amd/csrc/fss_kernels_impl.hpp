@@ -165,19 +165,28 @@ struct RtKey {   // a key known at launch (the dealer seed), read from kernel ar
   __device__ __forceinline__ uint32_t w() const { return rk.w[I]; }
 };
 
+// One middle round of K blocks.  All 16 K table lookups are written before
+// any of their XORs: where the scheduler keeps the source order (it reverts
+// regions whose reordered form needs more registers), that order still has
+// the round's lookups in flight together instead of one column's at a time.
 template <int R, class Key, class TB, int K>
 __device__ __forceinline__ void aes_round(const Key& key, const TB& tb, uint32_t (&s)[K][4]) {
+  uint32_t t[K][4][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      t[k][c][0] = tb.template get<0, 0>(s[k][c]);
+      t[k][c][1] = tb.template get<1, 1>(s[k][(c + 1) & 3]);
+      t[k][c][2] = tb.template get<2, 2>(s[k][(c + 2) & 3]);
+      t[k][c][3] = tb.template get<3, 3>(s[k][(c + 3) & 3]);
+    }
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const uint32_t a0 = s[k][0], a1 = s[k][1], a2 = s[k][2], a3 = s[k][3];
-    uint32_t t0 = xor3(tb.template get<0, 0>(a0), tb.template get<1, 1>(a1), tb.template get<2, 2>(a2));
-    uint32_t t1 = xor3(tb.template get<0, 0>(a1), tb.template get<1, 1>(a2), tb.template get<2, 2>(a3));
-    uint32_t t2 = xor3(tb.template get<0, 0>(a2), tb.template get<1, 1>(a3), tb.template get<2, 2>(a0));
-    uint32_t t3 = xor3(tb.template get<0, 0>(a3), tb.template get<1, 1>(a0), tb.template get<2, 2>(a1));
-    s[k][0] = xor3(t0, tb.template get<3, 3>(a3), key.template w<4 * R + 0>());
-    s[k][1] = xor3(t1, tb.template get<3, 3>(a0), key.template w<4 * R + 1>());
-    s[k][2] = xor3(t2, tb.template get<3, 3>(a1), key.template w<4 * R + 2>());
-    s[k][3] = xor3(t3, tb.template get<3, 3>(a2), key.template w<4 * R + 3>());
+    s[k][0] = xor3(xor3(t[k][0][0], t[k][0][1], t[k][0][2]), t[k][0][3], key.template w<4 * R + 0>());
+    s[k][1] = xor3(xor3(t[k][1][0], t[k][1][1], t[k][1][2]), t[k][1][3], key.template w<4 * R + 1>());
+    s[k][2] = xor3(xor3(t[k][2][0], t[k][2][1], t[k][2][2]), t[k][2][3], key.template w<4 * R + 2>());
+    s[k][3] = xor3(xor3(t[k][3][0], t[k][3][1], t[k][3][2]), t[k][3][3], key.template w<4 * R + 3>());
   }
 }
 
@@ -287,6 +296,7 @@ __device__ __forceinline__ void prg_shared(const TB& tb, const uint32_t (&s)[4],
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
   if (h->magic != kMagic || h->version != kVersion) return kStatusShape;
+  if (h->rec_bytes != 16 + 8 * (uint64_t)h->p) return kStatusShape;
   if ((int)h->party != party) return kStatusParty;
   if (n < 0 || (uint64_t)n > h->n_elems) return kStatusShape;
   return 0;
@@ -416,8 +426,8 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
                                          uint32_t x, int i0, int i1, VState<P>& st) {
   constexpr int NB = (P + 1) / 2;
   const int L = ((int)h->n + 1) / 2;
-  const uint8_t* cwp = tile + h->off_ccw + lane * 16;
-  const uint8_t* vcp = tile + h->off_cvcw + lane * 8;
+  constexpr uint64_t REC = 16 + 8 * P;
+  const uint8_t* recp = tile + h->off_crec + lane * REC;
   for (int i = i0; i < i1; ++i) {
     const uint32_t d = (x >> (2 * (L - 1 - i))) & 3u;
     uint32_t jj[1 + NB], o[1 + NB][4];
@@ -425,8 +435,9 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
     jj[1] = 4u + 2u * d;
     if (NB > 1) jj[NB > 1 ? 2 : 0] = 5u + 2u * d;
     prg_shared<TB, 1 + NB>(tb, st.s, jj, o);
-    const uint64_t row = (uint64_t)i * 4 + d;  // child d's corrections at level i
-    const uint4 cw = ld16(cwp + row * kTile * 16);
+    const uint8_t* rp = recp + ((uint64_t)i * 4 + d) * kTile * REC;  // child d's record at level i
+    const uint64_t c01 = ld8(rp), c23 = ld8(rp + 8);
+    const uint4 cw = make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
     const uint32_t t = st.t;
     const uint32_t msk = 0u - t;
     const uint64_t msk64 = 0ull - (uint64_t)t;
@@ -438,7 +449,7 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
-      v += ld8(vcp + (row * P + q) * kTile * 8) & msk64;
+      v += ld8(rp + 16 + 8 * q) & msk64;
       st.V[q] += b ? (0ull - v) : v;
     }
   }
@@ -771,7 +782,8 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   // Header offsets are read before the first key store: the compiler cannot
   // tell the key stores from header memory, and a header read after a store
   // would wait for the store to complete.
-  const uint64_t off_croot = h->off_croot, off_ccw = h->off_ccw, off_cvcw = h->off_cvcw;
+  constexpr uint64_t REC = 16 + 8 * P;
+  const uint64_t off_croot = h->off_croot, off_crec = h->off_crec;
   const uint64_t off_cfin = h->off_cfin;
   const int L = (n + 1) / 2;
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
@@ -816,18 +828,21 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
       } else {
         const uint4 cw = make_uint4(((o0[0][0] ^ o1[0][0]) & ~3u) | (t0c ^ t1c), o0[0][1] ^ o1[0][1],
                                     o0[0][2] ^ o1[0][2], o0[0][3] ^ o1[0][3]);
-        const uint64_t cwoff = off_ccw + (((uint64_t)i * 4 + c) * kTile + lane) * 16;
-        st16(k0 + cwoff, cw);
-        if (k1) st16(k1 + cwoff, cw);
+        const uint64_t ro = off_crec + (((uint64_t)i * 4 + c) * kTile + lane) * REC;
+        st8(k0 + ro, mk64(cw.x, cw.y));
+        st8(k0 + ro + 8, mk64(cw.z, cw.w));
+        if (k1) {
+          st8(k1 + ro, mk64(cw.x, cw.y));
+          st8(k1 + ro + 8, mk64(cw.z, cw.w));
+        }
         const uint64_t below = c < a ? ~0ull : 0ull;
 #pragma unroll
         for (int q = 0; q < P; ++q) {
           const uint64_t v0 = mk64(o0[1 + q / 2][2 * (q & 1)], o0[1 + q / 2][2 * (q & 1) + 1]);
           const uint64_t v1 = mk64(o1[1 + q / 2][2 * (q & 1)], o1[1 + q / 2][2 * (q & 1) + 1]);
           const uint64_t w = v1 - v0 - Va[q] + (beta[q] & below);
-          const uint64_t vo = off_cvcw + ((((uint64_t)i * 4 + c) * P + q) * kTile + lane) * 8;
-          st8(k0 + vo, (w ^ neg) - neg);
-          if (k1) st8(k1 + vo, (w ^ neg) - neg);
+          st8(k0 + ro + 16 + 8 * q, (w ^ neg) - neg);
+          if (k1) st8(k1 + ro + 16 + 8 * q, (w ^ neg) - neg);
         }
       }
     }
@@ -842,16 +857,18 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
     }
     const uint32_t tcw_a = kt[0] ^ kt[1] ^ 1u;
     const uint32_t scw_a[4] = {kr[0][0] & ~3u, kr[0][1], kr[0][2], kr[0][3]};
-    const uint64_t cwoff = off_ccw + (((uint64_t)i * 4 + a) * kTile + lane) * 16;
-    const uint4 cw = make_uint4(scw_a[0] | tcw_a, scw_a[1], scw_a[2], scw_a[3]);
-    st16(k0 + cwoff, cw);
-    if (k1) st16(k1 + cwoff, cw);
+    const uint64_t ro = off_crec + (((uint64_t)i * 4 + a) * kTile + lane) * REC;
+    st8(k0 + ro, mk64(scw_a[0] | tcw_a, scw_a[1]));
+    st8(k0 + ro + 8, mk64(scw_a[2], scw_a[3]));
+    if (k1) {
+      st8(k1 + ro, mk64(scw_a[0] | tcw_a, scw_a[1]));
+      st8(k1 + ro + 8, mk64(scw_a[2], scw_a[3]));
+    }
 #pragma unroll
     for (int q = 0; q < P; ++q) {
       const uint64_t vcw = mk64(kr[1 + q / 2][2 * (q & 1)], kr[1 + q / 2][2 * (q & 1) + 1]);
-      const uint64_t vo = off_cvcw + ((((uint64_t)i * 4 + a) * P + q) * kTile + lane) * 8;
-      st8(k0 + vo, vcw);
-      if (k1) st8(k1 + vo, vcw);
+      st8(k0 + ro + 16 + 8 * q, vcw);
+      if (k1) st8(k1 + ro + 16 + 8 * q, vcw);
       Va[q] += dk[q] + ((vcw ^ neg) - neg);
     }
 #pragma unroll

@@ -14,7 +14,7 @@ HDR = np.dtype([
     ("top_depth", "<u4"), ("n_elems", "<u8"), ("n_tiles", "<u8"), ("tile_bytes", "<u8"),
     ("spec_hash", "<u8"), ("negate", "<u8"), ("atom_k", "<u4", MAXA), ("atom_out", "<u4", MAXA),
     ("atom_rview", "<u4", MAXA), ("atom_c", "<u8", MAXA), ("atom_off", "<u8", MAXA),
-    ("off_w", "<u8"), ("off_croot", "<u8"), ("off_ccw", "<u8"), ("off_cvcw", "<u8"),
+    ("off_w", "<u8"), ("off_croot", "<u8"), ("off_crec", "<u8"), ("rec_bytes", "<u8"),
     ("off_cfin", "<u8"), ("off_crho", "<u8"), ("off_crout", "<u8"),
     ("aprime", "<u8", MAXM + 1), ("tab", "<u8", (MAXM, MAXP, MAXP)), ("tabv", "<u8", (MAXP, MAXP)),
 ])
@@ -49,17 +49,19 @@ class KeyView:
                 "vcw": [(vb >> i) & 1 for i in range(k)], "fin": (vb >> 32) & 1}
 
     def coeff(self, e: int) -> dict:
-        """The lookup DCF: L = ceil(n / 2) levels of four children, each child's
-        seed correction (bit 0 = control-bit correction) and value corrections."""
+        """The lookup DCF: L = ceil(n / 2) levels of four children; child c of
+        level i has a record rec[i][c][lane] of 16 + 8p bytes: its seed
+        correction (bit 0 = control-bit correction), then its p value corrections."""
         h, lane = self.h, e % TILE
         n, p = int(h["n"]), int(h["p"])
         L = (n + 1) // 2
+        rec = 16 + 8 * p
+        assert int(h["rec_bytes"]) == rec
         tb = self.tile_base(e)
         root = self._blk(tb + int(h["off_croot"]) + lane * 16)
-        cws = [[self._blk(tb + int(h["off_ccw"]) + ((i * 4 + c) * TILE + lane) * 16) for c in range(4)]
-               for i in range(L)]
-        vcw = [[[self._u64(tb + int(h["off_cvcw"]) + (((i * 4 + c) * p + q) * TILE + lane) * 8)
-                 for q in range(p)] for c in range(4)] for i in range(L)]
+        recs = [[tb + int(h["off_crec"]) + ((i * 4 + c) * TILE + lane) * rec for c in range(4)] for i in range(L)]
+        cws = [[self._blk(r) for r in lv] for lv in recs]
+        vcw = [[[self._u64(r + 16 + 8 * q) for q in range(p)] for r in lv] for lv in recs]
         fin = [self._u64(tb + int(h["off_cfin"]) + (q * TILE + lane) * 8) for q in range(p)]
         rho = [self._u64(tb + int(h["off_crho"]) + (q * TILE + lane) * 8) for q in range(p)]
         rout = self._u64(tb + int(h["off_crout"]) + lane * 8)
