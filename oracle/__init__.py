@@ -43,17 +43,18 @@ class DcfKey(C.Structure):
                 ("vcw", (C.c_uint64 * MAXP) * MAXN), ("fin", C.c_uint64 * MAXP)]
 
 
-MAXL4 = (MAXN + 1) // 2
+MAXLR = (MAXN + 1) // 2  # lookup-DCF levels at r = 2
+MAXC = 16                # children per level at r = 4
 
 
-class Dcf4Key(C.Structure):
-    _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("root", Blk), ("scw", (Blk * 4) * MAXL4),
-                ("tcw", (C.c_uint8 * 4) * MAXL4), ("vcw", ((C.c_uint64 * MAXP) * 4) * MAXL4),
-                ("fin", C.c_uint64 * MAXP)]
+class DcfRKey(C.Structure):
+    _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("r", C.c_int32), ("root", Blk),
+                ("scw", (Blk * MAXC) * MAXLR), ("tcw", (C.c_uint8 * MAXC) * MAXLR),
+                ("vcw", ((C.c_uint64 * MAXP) * MAXC) * MAXLR), ("fin", C.c_uint64 * MAXP)]
 
 
 class ElemKey(C.Structure):
-    _fields_ = [("atom", DcfKey * MAXT), ("wshare", C.c_uint64), ("coeff", Dcf4Key),
+    _fields_ = [("atom", DcfKey * MAXT), ("wshare", C.c_uint64), ("coeff", DcfRKey),
                 ("rho", C.c_uint64 * MAXP), ("rout", C.c_uint64)]
 
 
@@ -85,7 +86,7 @@ class Spec(C.Structure):
                 ("prim_out", C.c_int32 * MAXPRED), ("prim_bprime", C.c_uint64 * MAXPRED),
                 ("n_views", C.c_int32), ("view_k", C.c_int32 * MAXPRED),
                 ("view_c", C.c_uint64 * MAXPRED), ("T", C.c_int32),
-                ("negate", C.c_uint8 * MAXL)]
+                ("negate", C.c_uint8 * MAXL), ("lookup_r", C.c_int32)]
 
 
 _lib = None
@@ -108,9 +109,9 @@ def lib():
         L.orc_dcf_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk,
                                   C.POINTER(DcfKey), C.POINTER(DcfKey)]
         L.orc_dcf_eval.argtypes = [C.c_int, C.POINTER(DcfKey), C.c_uint64, u64p]
-        L.orc_dcf4_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk, C.POINTER(Blk),
-                                   C.POINTER(Dcf4Key), C.POINTER(Dcf4Key)]
-        L.orc_dcf4_eval.argtypes = [C.c_int, C.POINTER(Dcf4Key), C.c_uint64, u64p]
+        L.orc_dcfr_gen.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk, C.POINTER(Blk),
+                                   C.POINTER(DcfRKey), C.POINTER(DcfRKey)]
+        L.orc_dcfr_eval.argtypes = [C.c_int, C.POINTER(DcfRKey), C.c_uint64, u64p]
         L.orc_spec_compile.argtypes = [C.POINTER(Interval), C.c_int32, C.POINTER(Piece),
                                        C.POINTER(Pred), C.c_int32, C.c_int32, C.c_int32,
                                        C.c_int32, C.POINTER(Spec)]
@@ -124,7 +125,7 @@ def lib():
         L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
                                     C.POINTER(C.c_int32)]
         for name, cls in (("orc_sizeof_elem_key", ElemKey), ("orc_sizeof_dcf_key", DcfKey),
-                          ("orc_sizeof_dcf4_key", Dcf4Key), ("orc_sizeof_spec", Spec)):
+                          ("orc_sizeof_dcfr_key", DcfRKey), ("orc_sizeof_spec", Spec)):
             got = getattr(L, name)()
             if got != C.sizeof(cls):
                 raise RuntimeError(f"oracle struct layout mismatch: {name} {got} != {C.sizeof(cls)}")
@@ -186,19 +187,19 @@ def dcf_eval(b: int, key: DcfKey, x: int):
     return out[0] if key.p == 0 else list(out[: key.p])
 
 
-def dcf4_gen(n: int, p: int, alpha: int, beta, root0, root1, keep_rand):
-    """Four children per level.  keep_rand: (ceil(n/2) * (1 + ceil(p/2))) (lo, hi)
+def dcfr_gen(n: int, r: int, p: int, alpha: int, beta, root0, root1, keep_rand):
+    """2^r children per level.  keep_rand: (ceil(n/r) * (1 + ceil(p/2))) (lo, hi)
     blocks, the on-path child's corrections level by level."""
     b = (C.c_uint64 * MAXP)(*([int(v) & (2**64 - 1) for v in (beta if p else [beta])]))
     kr = (Blk * max(1, len(keep_rand)))(*[Blk(lo, hi) for lo, hi in keep_rand])
-    k0, k1 = Dcf4Key(), Dcf4Key()
-    lib().orc_dcf4_gen(n, p, alpha, b, Blk(*root0), Blk(*root1), kr, C.byref(k0), C.byref(k1))
+    k0, k1 = DcfRKey(), DcfRKey()
+    lib().orc_dcfr_gen(n, r, p, alpha, b, Blk(*root0), Blk(*root1), kr, C.byref(k0), C.byref(k1))
     return k0, k1
 
 
-def dcf4_eval(b: int, key: Dcf4Key, x: int):
+def dcfr_eval(b: int, key: DcfRKey, x: int):
     out = (C.c_uint64 * MAXP)()
-    lib().orc_dcf4_eval(b, C.byref(key), x, out)
+    lib().orc_dcfr_eval(b, C.byref(key), x, out)
     return out[0] if key.p == 0 else list(out[: key.p])
 
 
@@ -208,8 +209,9 @@ class SpecError(ValueError):
     pass
 
 
-def compile_spec(desc, n_bits: int, frac_bits: int) -> Spec:
-    """desc: paper_2606_09551_amd.workloads.SpecDesc (real-valued spec)."""
+def compile_spec(desc, n_bits: int, frac_bits: int, lookup_r: int = 2) -> Spec:
+    """desc: paper_2606_09551_amd.workloads.SpecDesc (real-valued spec);
+    lookup_r: input bits per level of call 2's DCF (2, 3 or 4)."""
     m = len(desc.intervals)
     iv = (Interval * m)(*[Interval(lo, hi) for lo, hi in desc.intervals])
     pcs = (Piece * m)()
@@ -226,6 +228,9 @@ def compile_spec(desc, n_bits: int, frac_bits: int) -> Spec:
                                 C.byref(S))
     if rc != 0:
         raise SpecError(f"oracle rejected spec {getattr(desc, 'name', '?')}: rc={rc}")
+    if lookup_r not in (2, 3, 4):
+        raise SpecError(f"lookup_r must be 2, 3 or 4, got {lookup_r}")
+    S.lookup_r = lookup_r
     return S
 
 

@@ -336,12 +336,12 @@ void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out) {
 }
 
 /* ========================================================================= */
-/* DCF with four children per level: two input bits (one base-4 digit) per   */
+/* DCF with 2^r children per level: r input bits (one base-2^r digit) per    */
 /* level, the per-child form of the corrections above.                       */
 /* ========================================================================= */
 
-/* Child c (0..3) of seed s: next seed, control bit t, and group value v. */
-static void expand4(int p, orc_blk s, int c, orc_blk* s_out, int* t_out, uint64_t* v_out) {
+/* Child c (0..2^r-1) of seed s: next seed, control bit t, and group value v. */
+static void expand_r(int r, int p, orc_blk s, int c, orc_blk* s_out, int* t_out, uint64_t* v_out) {
   orc_blk n = orc_prg(s, c);
   *t_out = (int)(n.lo & 1);
   *s_out = clear2(n);
@@ -349,35 +349,38 @@ static void expand4(int p, orc_blk s, int c, orc_blk* s_out, int* t_out, uint64_
     v_out[0] = (n.lo >> 1) & 1;
   } else {
     uint64_t w[4];
-    orc_blk a = orc_prg(s, 4 + 2 * c);
+    orc_blk a = orc_prg(s, (1 << r) + 2 * c);
     w[0] = a.lo; w[1] = a.hi;
-    if (p > 2) { orc_blk b = orc_prg(s, 5 + 2 * c); w[2] = b.lo; w[3] = b.hi; }
+    if (p > 2) { orc_blk b = orc_prg(s, (1 << r) + 2 * c + 1); w[2] = b.lo; w[3] = b.hi; }
     for (int k = 0; k < p; k++) v_out[k] = w[k];
   }
 }
 
-static void convert4(int p, orc_blk s, uint64_t* out) {
+static void convert_r(int r, int p, orc_blk s, uint64_t* out) {
   if (p == 0) {
     out[0] = (s.lo >> 2) & 1;
   } else {
     uint64_t w[4];
-    orc_blk a = orc_prg(s, 12);
+    orc_blk a = orc_prg(s, 3 * (1 << r));
     w[0] = a.lo; w[1] = a.hi;
-    if (p > 2) { orc_blk b = orc_prg(s, 13); w[2] = b.lo; w[3] = b.hi; }
+    if (p > 2) { orc_blk b = orc_prg(s, 3 * (1 << r) + 1); w[2] = b.lo; w[3] = b.hi; }
     for (int k = 0; k < p; k++) out[k] = w[k];
   }
 }
 
-/* Base-4 digit i (most significant first) of x over `levels` digits. */
-static int digit4(uint64_t x, int levels, int i) { return (int)((x >> (2 * (levels - 1 - i))) & 3); }
+/* Base-2^r digit i (most significant first) of x over `levels` digits. */
+static int digit_r(int r, uint64_t x, int levels, int i) {
+  return (int)((x >> (r * (levels - 1 - i))) & (((uint64_t)1 << r) - 1));
+}
 
-void orc_dcf4_gen(int n, int p, uint64_t alpha, const uint64_t* beta, orc_blk root0, orc_blk root1,
-                  const orc_blk* keep_rand, orc_dcf4_key* k0, orc_dcf4_key* k1) {
+void orc_dcfr_gen(int n, int r, int p, uint64_t alpha, const uint64_t* beta, orc_blk root0, orc_blk root1,
+                  const orc_blk* keep_rand, orc_dcfr_key* k0, orc_dcfr_key* k1) {
   memset(k0, 0, sizeof *k0);
   memset(k1, 0, sizeof *k1);
   k0->n = k1->n = n;
   k0->p = k1->p = p;
-  const int levels = (n + 1) / 2, nr = 1 + (p + 1) / 2;
+  k0->r = k1->r = r;
+  const int levels = (n + r - 1) / r, nr = 1 + (p + 1) / 2, C = 1 << r;
   orc_blk s[2] = {clear2(root0), clear2(root1)};
   int t[2] = {0, 1};
   k0->root = s[0];
@@ -386,14 +389,14 @@ void orc_dcf4_gen(int n, int p, uint64_t alpha, const uint64_t* beta, orc_blk ro
   g_zero(p, Va);
 
   for (int i = 0; i < levels; i++) {
-    const int a = digit4(alpha, levels, i);   /* the child on alpha's path */
-    orc_blk sc[2][4];
-    int tc[2][4];
-    uint64_t vc[2][4][ORC_MAXP];
+    const int a = digit_r(r, alpha, levels, i);   /* the child on alpha's path */
+    orc_blk sc[2][ORC_MAXC];
+    int tc[2][ORC_MAXC];
+    uint64_t vc[2][ORC_MAXC][ORC_MAXP];
     for (int b = 0; b < 2; b++)
-      for (int c = 0; c < 4; c++) expand4(p, s[b], c, &sc[b][c], &tc[b][c], vc[b][c]);
+      for (int c = 0; c < C; c++) expand_r(r, p, s[b], c, &sc[b][c], &tc[b][c], vc[b][c]);
     const orc_blk* kr = keep_rand + (size_t)i * nr;
-    for (int c = 0; c < 4; c++) {
+    for (int c = 0; c < C; c++) {
       orc_blk scw;
       uint64_t vcw[ORC_MAXP];
       if (c != a) {
@@ -407,11 +410,16 @@ void orc_dcf4_gen(int n, int p, uint64_t alpha, const uint64_t* beta, orc_blk ro
         if (c < a) g_add(p, vcw, beta);
         g_sign(p, t[1], vcw);
       } else {
-        /* random corrections on alpha's child hide which child it is */
+        /* random corrections on alpha's child hide which child it is; with
+         * p = 0 (one block per level) the value bit is bit 1 of that block */
         scw = clear2(kr[0]);
-        uint64_t w[4] = {kr[1].lo, kr[1].hi, nr > 2 ? kr[2].lo : 0, nr > 2 ? kr[2].hi : 0};
         g_zero(p, vcw);
-        for (int k = 0; k < glen(p); k++) vcw[k] = (p == 0) ? (w[k] & 1) : w[k];
+        if (p == 0) {
+          vcw[0] = (kr[0].lo >> 1) & 1;
+        } else {
+          uint64_t w[4] = {kr[1].lo, kr[1].hi, nr > 2 ? kr[2].lo : 0, nr > 2 ? kr[2].hi : 0};
+          for (int k = 0; k < p; k++) vcw[k] = w[k];
+        }
       }
       const int tcw = tc[0][c] ^ tc[1][c] ^ (c == a);
       k0->scw[i][c] = k1->scw[i][c] = scw;
@@ -435,26 +443,26 @@ void orc_dcf4_gen(int n, int p, uint64_t alpha, const uint64_t* beta, orc_blk ro
   }
   /* CW_final = (-1)^{t1} (Convert(s1) - Convert(s0) - V_alpha) */
   uint64_t c0[ORC_MAXP], c1[ORC_MAXP];
-  convert4(p, s[0], c0);
-  convert4(p, s[1], c1);
+  convert_r(r, p, s[0], c0);
+  convert_r(r, p, s[1], c1);
   g_sub(p, c1, c0);
   g_sub(p, c1, Va);
   g_sign(p, t[1], c1);
   for (int k = 0; k < glen(p); k++) k0->fin[k] = k1->fin[k] = c1[k];
 }
 
-void orc_dcf4_eval(int b, const orc_dcf4_key* k, uint64_t x, uint64_t* out) {
-  const int p = k->p, levels = (k->n + 1) / 2;
+void orc_dcfr_eval(int b, const orc_dcfr_key* k, uint64_t x, uint64_t* out) {
+  const int p = k->p, r = k->r, levels = (k->n + k->r - 1) / k->r;
   orc_blk s = k->root;
   int t = b;
   uint64_t V[ORC_MAXP], tmp[ORC_MAXP];
   g_zero(p, V);
   for (int i = 0; i < levels; i++) {
-    const int d = digit4(x, levels, i);
+    const int d = digit_r(r, x, levels, i);
     orc_blk ns;
     int nt;
     uint64_t v[ORC_MAXP];
-    expand4(p, s, d, &ns, &nt, v);
+    expand_r(r, p, s, d, &ns, &nt, v);
     if (t) {
       ns.lo ^= k->scw[i][d].lo;
       ns.hi ^= k->scw[i][d].hi;
@@ -467,7 +475,7 @@ void orc_dcf4_eval(int b, const orc_dcf4_key* k, uint64_t x, uint64_t* out) {
     s = ns;
     t = nt;
   }
-  convert4(p, s, tmp);
+  convert_r(r, p, s, tmp);
   if (t) g_add(p, tmp, k->fin);
   g_sign(p, b, tmp);
   g_add(p, V, tmp);
@@ -505,6 +513,7 @@ int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
   const int n = n_bits, f = frac_bits;
   const int64_t N = (int64_t)1 << n, s = N / 2;
   S->n = n; S->f = f; S->m = m;
+  S->lookup_r = 2;
 
   /* Partition: contiguous half-open real intervals, tails at -inf / +inf. */
   if (!(isinf(iv[0].lo) && iv[0].lo < 0)) return -1;
@@ -659,11 +668,11 @@ void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
   orc_blk c0 = orc_rand(kseed, e, 64, 0);
   orc_blk c1 = orc_rand(kseed, e, 65, 0);
   /* the on-path child's corrections at level i: R(e, 69 + k, i) */
-  orc_blk kr[ORC_MAXL4 * 3];
-  const int levels = (S->n + 1) / 2, nr = 1 + (S->p + 1) / 2;
+  orc_blk kr[ORC_MAXLR * 3];
+  const int levels = (S->n + S->lookup_r - 1) / S->lookup_r, nr = 1 + (S->p + 1) / 2;
   for (int i = 0; i < levels; i++)
     for (int k = 0; k < nr; k++) kr[i * nr + k] = orc_rand(kseed, e, 69 + k, i);
-  orc_dcf4_gen(S->n, S->p, r_in & lowmask(S->n), rho, c0, c1, kr, &k0->coeff, &k1->coeff);
+  orc_dcfr_gen(S->n, S->lookup_r, S->p, r_in & lowmask(S->n), rho, c0, c1, kr, &k0->coeff, &k1->coeff);
   orc_blk ra = orc_rand(kseed, e, 67, 0), rb = orc_rand(kseed, e, 68, 0);
   uint64_t sh[4] = {ra.lo, ra.hi, rb.lo, rb.hi};
   for (int k = 0; k < S->p; k++) {
@@ -712,13 +721,13 @@ void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xha
   const uint64_t N = (uint64_t)1 << n, s = N / 2;
   uint64_t v = ((xhat & (N - 1)) + s) & (N - 1);
   uint64_t Dv[ORC_MAXP];
-  orc_dcf4_eval(b, &K->coeff, v, Dv);
+  orc_dcfr_eval(b, &K->coeff, v, Dv);
   uint64_t g[ORC_MAXM + 1][ORC_MAXP];
   for (int k = 0; k < p; k++) { g[0][k] = 0; g[m][k] = K->rho[k]; }
   for (int i = 1; i < m; i++) {
     uint64_t u = (v - S->aprime[i]) & (N - 1);
     uint64_t D[ORC_MAXP];
-    orc_dcf4_eval(b, &K->coeff, u, D);
+    orc_dcfr_eval(b, &K->coeff, u, D);
     for (int k = 0; k < p; k++)
       g[i][k] = D[k] - Dv[k] + (v < S->aprime[i] ? K->rho[k] : 0);
   }
@@ -825,7 +834,7 @@ int orc_hw_threads(void) {
 }
 int orc_sizeof_elem_key(void) { return (int)sizeof(orc_elem_key); }
 int orc_sizeof_dcf_key(void) { return (int)sizeof(orc_dcf_key); }
-int orc_sizeof_dcf4_key(void) { return (int)sizeof(orc_dcf4_key); }
+int orc_sizeof_dcfr_key(void) { return (int)sizeof(orc_dcfr_key); }
 int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
 
 typedef struct {
@@ -883,6 +892,7 @@ static int run_jobs(job_t proto, int64_t count, int threads) {
 int orc_keygen_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
                      orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in, uint64_t* r_out,
                      int threads) {
+  if (S->lookup_r < 2 || S->lookup_r > 4) return -3;
   job_t J;
   memset(&J, 0, sizeof J);
   J.kind = 0; J.S = S; J.seed = seed; J.elems = elems;
@@ -901,6 +911,7 @@ int orc_eval_batch(int b, const orc_spec* S, const orc_elem_key* K, const uint64
 int orc_full_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
                    const int64_t* x, uint64_t* y0, uint64_t* y1, uint64_t* z0, uint64_t* z1,
                    int threads) {
+  if (S->lookup_r < 2 || S->lookup_r > 4) return -3;
   job_t J;
   memset(&J, 0, sizeof J);
   J.kind = 2; J.S = S; J.seed = seed; J.elems = elems; J.x = x;

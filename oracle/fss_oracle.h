@@ -65,29 +65,31 @@ void orc_dcf_gen(int n, int p, uint64_t alpha, const uint64_t* beta,
                  orc_blk root0, orc_blk root1, orc_dcf_key* k0, orc_dcf_key* k1);
 void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out);
 
-/* ---- DCF with four children per level ------------------------------------- */
-/* The same construction with two input bits per level: each level has four
- * children, and the key carries a seed, control-bit and value correction for
- * each child.  For a child off alpha's path they are the corrections above
- * (with beta entering when that child's digit is below alpha's); for the child
- * on the path they are fresh dealer randomness (`keep_rand`, 1 + ceil(p/2)
- * blocks per level), so the key does not show which child alpha takes.  An odd
- * n is walked as n + 1 bits with a leading zero digit.  Child c of seed s is
- * H(s, c) (seed and control bit), its value the first p words of
- * H(s, 4 + 2c + k), and Convert(s) the first p words of H(s, 12 + k). */
-#define ORC_MAXL4 ((ORC_MAXN + 1) / 2)
+/* ---- DCF with 2^r children per level --------------------------------------- */
+/* The same construction with r input bits (one base-2^r digit) per level, r in
+ * {2, 3, 4}: each level has 2^r children, and the key carries a seed,
+ * control-bit and value correction for each child.  For a child off alpha's
+ * path they are the corrections above (with beta entering when that child's
+ * digit is below alpha's); for the child on the path they are fresh dealer
+ * randomness (`keep_rand`, 1 + ceil(p/2) blocks per level), so the key does
+ * not show which child alpha takes.  The input is walked as r * ceil(n / r)
+ * bits with leading zeros.  Child c of seed s is H(s, c) (seed and control
+ * bit), its value the first p words of H(s, 2^r + 2c + k), and Convert(s)
+ * the first p words of H(s, 3 * 2^r + k). */
+#define ORC_MAXLR ((ORC_MAXN + 1) / 2) /* levels at r = 2 */
+#define ORC_MAXC 16                    /* children at r = 4 */
 typedef struct {
-  int32_t n, p;                         /* n: input bits; levels = ceil(n / 2) */
+  int32_t n, p, r;                      /* levels = ceil(n / r) */
   orc_blk root;
-  orc_blk scw[ORC_MAXL4][4];            /* seed corrections (bits 0..1 zero) */
-  uint8_t tcw[ORC_MAXL4][4];            /* control-bit corrections */
-  uint64_t vcw[ORC_MAXL4][4][ORC_MAXP]; /* value corrections */
+  orc_blk scw[ORC_MAXLR][ORC_MAXC];            /* seed corrections (bits 0..1 zero) */
+  uint8_t tcw[ORC_MAXLR][ORC_MAXC];            /* control-bit corrections */
+  uint64_t vcw[ORC_MAXLR][ORC_MAXC][ORC_MAXP]; /* value corrections */
   uint64_t fin[ORC_MAXP];
-} orc_dcf4_key;
+} orc_dcfr_key;
 
-void orc_dcf4_gen(int n, int p, uint64_t alpha, const uint64_t* beta, orc_blk root0, orc_blk root1,
-                  const orc_blk* keep_rand, orc_dcf4_key* k0, orc_dcf4_key* k1);
-void orc_dcf4_eval(int b, const orc_dcf4_key* k, uint64_t x, uint64_t* out);
+void orc_dcfr_gen(int n, int r, int p, uint64_t alpha, const uint64_t* beta, orc_blk root0, orc_blk root1,
+                  const orc_blk* keep_rand, orc_dcfr_key* k0, orc_dcfr_key* k1);
+void orc_dcfr_eval(int b, const orc_dcfr_key* k, uint64_t x, uint64_t* out);
 
 /* ---- operator specification ------------------------------------------------ */
 typedef struct { double lo, hi; } orc_interval;
@@ -119,9 +121,11 @@ typedef struct {
   uint64_t view_c[ORC_MAXPRED];
   int32_t T;                            /* atoms: n_prim thresholds, then n_views mask atoms */
   uint8_t negate[ORC_MAXL];             /* public constant flip per output bit */
+  int32_t lookup_r;                     /* input bits per level of call 2's DCF (2, 3 or 4) */
 } orc_spec;
 
-/* Returns 0 on success, negative on an invalid or unsupported spec. */
+/* Returns 0 on success, negative on an invalid or unsupported spec.  Sets
+ * lookup_r = 2; a caller may change it before keygen. */
 int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
                      const orc_pred* pr, int32_t n_pred, int32_t n_bits,
                      int32_t frac_bits, int32_t out_frac_bits, orc_spec* S);
@@ -130,7 +134,7 @@ int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
 typedef struct {
   orc_dcf_key atom[ORC_MAXT];
   uint64_t wshare;                      /* bit j: this party's share of the carry of output j */
-  orc_dcf4_key coeff;                   /* call 2's vector DCF, four children per level */
+  orc_dcfr_key coeff;                   /* call 2's vector DCF, 2^r children per level */
   uint64_t rho[ORC_MAXP];               /* additive share of rho = ((-r_in)^k)_k */
   uint64_t rout;                        /* additive share of r_out */
 } orc_elem_key;
@@ -155,7 +159,7 @@ int orc_full_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64
 int orc_hw_threads(void);
 int orc_sizeof_elem_key(void);
 int orc_sizeof_dcf_key(void);
-int orc_sizeof_dcf4_key(void);
+int orc_sizeof_dcfr_key(void);
 int orc_sizeof_spec(void);
 
 /* ---- Protocol "Compile a scalar gate instance", lookup part ---------------- */

@@ -71,104 +71,117 @@ def test_dcf_keys_share_corrections_and_differ_in_roots():
     assert list(k0.fin[:3]) == list(k1.fin[:3])
 
 
-# ---- four children per level (call 2's vector DCF) -------------------------
+# ---- 2^r children per level (call 2's vector DCF) ---------------------------
 
-def _keep_rand(rnd, n, p):
-    levels, per = (n + 1) // 2, 1 + (p + 1) // 2
+def _keep_rand(rnd, n, p, r):
+    levels, per = -(-n // r), 1 + (p + 1) // 2
     return [(rnd.getrandbits(64), rnd.getrandbits(64)) for _ in range(levels * per)]
 
 
+@pytest.mark.parametrize("r", [2, 3, 4])
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 6])
-def test_dcf4_z2_bruteforce(n):
-    rnd = random.Random(300 + n)
+def test_dcfr_z2_bruteforce(n, r):
+    rnd = random.Random(300 + 10 * n + r)
     for alpha in range(2**n):
         for beta in (0, 1):
-            k0, k1 = O.dcf4_gen(n, 0, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, 0))
+            k0, k1 = O.dcfr_gen(n, r, 0, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, 0, r))
             for x in range(2**n):
-                got = O.dcf4_eval(0, k0, x) ^ O.dcf4_eval(1, k1, x)
-                assert got == (beta if x < alpha else 0), (n, alpha, beta, x)
+                got = O.dcfr_eval(0, k0, x) ^ O.dcfr_eval(1, k1, x)
+                assert got == (beta if x < alpha else 0), (n, r, alpha, beta, x)
 
 
+@pytest.mark.parametrize("r", [2, 3, 4])
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
-@pytest.mark.parametrize("n", [1, 3, 4, 6])
-def test_dcf4_vector_bruteforce(n, p):
-    rnd = random.Random(3000 * n + p)
+@pytest.mark.parametrize("n", [1, 3, 4, 6, 7])
+def test_dcfr_vector_bruteforce(n, p, r):
+    rnd = random.Random(3000 * n + 10 * p + r)
     for alpha in range(2**n):
         beta = [rnd.getrandbits(64) for _ in range(p)]
-        k0, k1 = O.dcf4_gen(n, p, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, p))
+        k0, k1 = O.dcfr_gen(n, r, p, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, p, r))
         for x in range(2**n):
-            a, b = O.dcf4_eval(0, k0, x), O.dcf4_eval(1, k1, x)
+            a, b = O.dcfr_eval(0, k0, x), O.dcfr_eval(1, k1, x)
             got = [(u + v) & M64 for u, v in zip(a, b)]
-            assert got == (beta if x < alpha else [0] * p), (n, p, alpha, x)
+            assert got == (beta if x < alpha else [0] * p), (n, p, r, alpha, x)
 
 
-def test_dcf4_wide_domain_sampled():
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_dcfr_wide_domain_sampled(r):
     """n = 23, 24 and 32: sampled points around alpha and across the domain."""
-    rnd = random.Random(15)
+    rnd = random.Random(15 + r)
     for n in (23, 24, 32):
         for _ in range(6):
             alpha = rnd.getrandbits(n)
             beta = [rnd.getrandbits(64) for _ in range(3)]
-            k0, k1 = O.dcf4_gen(n, 3, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, 3))
+            k0, k1 = O.dcfr_gen(n, r, 3, alpha, beta, *_roots(rnd), _keep_rand(rnd, n, 3, r))
             pts = {0, 2**n - 1, alpha, (alpha - 1) % 2**n, (alpha + 1) % 2**n}
             pts |= {alpha ^ (1 << j) for j in range(n)}
             pts |= {rnd.getrandbits(n) for _ in range(20)}
             for x in pts:
-                got = [(u + v) & M64 for u, v in zip(O.dcf4_eval(0, k0, x), O.dcf4_eval(1, k1, x))]
-                assert got == (beta if x < alpha else [0, 0, 0]), (n, alpha, x)
+                got = [(u + v) & M64 for u, v in zip(O.dcfr_eval(0, k0, x), O.dcfr_eval(1, k1, x))]
+                assert got == (beta if x < alpha else [0, 0, 0]), (n, r, alpha, x)
 
 
-def test_dcf4_corrections():
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_dcfr_corrections(r):
     """Both keys carry the same corrections; alpha's child gets the supplied
     randomness at every level, every other child corrects the parties'
-    children to equal seeds (checked on the first level, where both parties
-    expand their roots)."""
-    rnd = random.Random(21)
-    n, p, alpha = 8, 3, 0b10_01_11_00
-    kr = _keep_rand(rnd, n, p)
+    children to equal seeds and values (checked on the first level, where both
+    parties expand their roots: child c is H(root, c), its value H(root, 2^r + 2c))."""
+    rnd = random.Random(21 + r)
+    n, p = 12, 3
+    alpha = rnd.getrandbits(n)
+    beta = [5, 6, 7]
+    kr = _keep_rand(rnd, n, p, r)
     r0, r1 = _roots(rnd)
-    k0, k1 = O.dcf4_gen(n, p, alpha, [5, 6, 7], r0, r1, kr)
+    k0, k1 = O.dcfr_gen(n, r, p, alpha, beta, r0, r1, kr)
     assert k0.root.lo & 3 == 0 and k1.root.lo & 3 == 0
-    per = 1 + (p + 1) // 2
-    for i in range(n // 2):
-        a = (alpha >> (2 * (n // 2 - 1 - i))) & 3
-        for c in range(4):
+    levels, per, C = n // r, 1 + (p + 1) // 2, 1 << r
+    for i in range(levels):
+        a = (alpha >> (r * (levels - 1 - i))) & (C - 1)
+        for c in range(C):
             assert (k0.scw[i][c].lo, k0.scw[i][c].hi) == (k1.scw[i][c].lo, k1.scw[i][c].hi)
             assert k0.tcw[i][c] == k1.tcw[i][c] and k0.scw[i][c].lo & 3 == 0
             assert list(k0.vcw[i][c][:p]) == list(k1.vcw[i][c][:p])
         lo, hi = kr[i * per]
         assert (k0.scw[i][a].lo, k0.scw[i][a].hi) == (lo & ~3, hi)
         assert list(k0.vcw[i][a][:p]) == [kr[i * per + 1][0], kr[i * per + 1][1], kr[i * per + 2][0]]
-    # level 0: child seeds are H(root, c) with bits 0..1 cleared, t = bit 0
-    a0 = (alpha >> (n - 2)) & 3
-    for c in range(4):
+    # level 0: the parties' roots carry t = 0 and t = 1, V_alpha = 0
+    a0 = alpha >> (n - r)
+    for c in range(C):
         if c == a0:
             continue
         c0, c1 = O.prg(k0.root.lo, k0.root.hi, c), O.prg(k1.root.lo, k1.root.hi, c)
         assert k0.scw[0][c].lo == (c0[0] ^ c1[0]) & ~3 and k0.scw[0][c].hi == c0[1] ^ c1[1]
         assert k0.tcw[0][c] == (c0[0] ^ c1[0]) & 1
+        v0 = O.prg(k0.root.lo, k0.root.hi, C + 2 * c) + O.prg(k0.root.lo, k0.root.hi, C + 2 * c + 1)
+        v1 = O.prg(k1.root.lo, k1.root.hi, C + 2 * c) + O.prg(k1.root.lo, k1.root.hi, C + 2 * c + 1)
+        for q in range(p):
+            w = (v1[q] - v0[q] + (beta[q] if c < a0 else 0)) & M64
+            assert k0.vcw[0][c][q] == (-w) & M64, (r, c, q)   # (-1)^{t_1}, t_1 = 1 at the root
 
 
-def test_dcf4_corrections_do_not_single_out_alpha_child():
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_dcfr_corrections_do_not_single_out_alpha_child(r):
     """The per-child corrections must not show which child lies on alpha's
     path: over 600 keys, the control-bit correction of alpha's child and of
     the other children are each 1 about half the time (a constant on alpha's
     child would single it out; its seed correction is the supplied randomness,
-    checked in test_dcf4_corrections)."""
-    rnd = random.Random(77)
-    n, p = 6, 3
+    checked in test_dcfr_corrections)."""
+    rnd = random.Random(77 + r)
+    n, p = 12, 3
+    C, levels = 1 << r, 12 // r
     on = [0, 0]
     off = [0, 0]
     for _ in range(600):
         alpha = rnd.getrandbits(n)
-        k0, _ = O.dcf4_gen(n, p, alpha, [1, 2, 3], *_roots(rnd), _keep_rand(rnd, n, p))
-        for i in range(n // 2):
-            a = (alpha >> (2 * (n // 2 - 1 - i))) & 3
-            for c in range(4):
+        k0, _ = O.dcfr_gen(n, r, p, alpha, [1, 2, 3], *_roots(rnd), _keep_rand(rnd, n, p, r))
+        for i in range(levels):
+            a = (alpha >> (r * (levels - 1 - i))) & (C - 1)
+            for c in range(C):
                 bucket = on if c == a else off
                 bucket[0] += k0.tcw[i][c]
                 bucket[1] += 1
     frac_on, frac_off = on[0] / on[1], off[0] / off[1]
-    # 1800 and 5400 Bernoulli(1/2) samples: 5 sigma is about 0.06 and 0.034
+    # at least 1800 and 5400 Bernoulli(1/2) samples: 5 sigma is about 0.06 and 0.034
     assert abs(frac_on - 0.5) < 0.06, frac_on
     assert abs(frac_off - 0.5) < 0.034, frac_off

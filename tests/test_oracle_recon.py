@@ -48,9 +48,10 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("r", [2, 3, 4])
 @pytest.mark.parametrize("desc,n,f", CASES, ids=lambda v: getattr(v, "name", str(v)))
-def test_reconstruction_exhaustive(desc, n, f):
-    S = O.compile_spec(desc, n, f)
+def test_reconstruction_exhaustive(desc, n, f, r):
+    S = O.compile_spec(desc, n, f, lookup_r=r)
     s = 2**(n - 1)
     xs = np.arange(-s, s, dtype=np.int64)
     yp, zp = O.plain_many(S, xs)
