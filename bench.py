@@ -51,12 +51,13 @@ def pct(xs, q):
 
 def keygen_aes_per_elem(inst) -> int:
     """Dealer AES blocks per element: both parties' children of every Z_2 DCF
-    level (2 each), of every lookup-DCF level (4 children of 1 + ceil(p/2)
-    blocks each, L = ceil(n/2) levels) and the leaf conversions, plus the
+    level (2 each), of every lookup-DCF level (2^r children of 1 + ceil(p/2)
+    blocks each, L = ceil(n/r) levels) and the leaf conversions, plus the
     counter-mode randomness (1 + ceil(p/2) blocks per lookup level)."""
     nb = (inst.p + 1) // 2
-    L = (inst.n_bits + 1) // 2
-    prg = sum(4 * k for k in inst.atom_k) + 2 * L * 4 * (1 + nb) + 2 * nb
+    r = inst.lookup_r
+    L = -(-inst.n_bits // r)
+    prg = sum(4 * k for k in inst.atom_k) + 2 * L * (1 << r) * (1 + nb) + 2 * nb
     rand = 2 * inst.T + 7 + L * (1 + nb)
     return prg + rand
 
@@ -88,9 +89,10 @@ KERNEL_SOURCES = ["paper_2606_09551_amd/csrc/fss_kernels_impl.hpp", "paper_2606_
                   "paper_2606_09551_amd/csrc/fss_kernels.hpp"]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, lookup_r: int):
     """HBM bytes per fused launch from the committed rocprofv3 counter summary,
-    or None when the kernel sources changed since the counters were taken."""
+    or None when the kernel sources or the lookup radix differ from those the
+    counters were taken with."""
     import hashlib
 
     if workload != "c2":
@@ -100,11 +102,14 @@ def measured_traffic(workload: str):
         return None
     kv = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0].strip() in ("kernel_sources_sha256_16", "traffic_bytes_per_launch"):
+        if ":" in line and line.split(":")[0].strip() in ("kernel_sources_sha256_16", "traffic_bytes_per_launch",
+                                                          "lookup_r"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES)
     if kv.get("kernel_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    if kv.get("lookup_r") != str(lookup_r):
         return None
     return int(kv["traffic_bytes_per_launch"])
 
@@ -149,6 +154,8 @@ def main() -> None:
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--lookup-r", type=int, default=None, choices=[2, 3, 4],
+                    help="input bits per level of call 2's DCF (default: the library's)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one copy kernel of this size (HBM counter calibration)")
     ap.add_argument("--ablation", choices=["reuse"], default=None,
@@ -175,7 +182,7 @@ def main() -> None:
     ops, n_bits, f_bits, wname = build_ops(args.workload)
     insts = []
     for op in ops:
-        inst = R.OpInstanceGPU(F.Spec(op.spec), n_bits, f_bits, len(op.x))
+        inst = R.OpInstanceGPU(F.Spec(op.spec, args.lookup_r), n_bits, f_bits, len(op.x))
         inst.set_input(op.x)
         insts.append(inst)
     n_elems = sum(i.n for i in insts)
@@ -285,14 +292,16 @@ def main() -> None:
                    "path": "fused persistent work-list" + (", HIP graph per layer" if graphs else ""),
                    "launches_per_step": len(plans),
                    "step": "keygen (both parties) + masked opening + eval (both parties)",
-                   "launch": cfg, "autotuned": bool(args.autotune)},
+                   "launch": cfg, "autotuned": bool(args.autotune),
+                   "lookup_r": insts[0].lookup_r,
+                   "key_bytes_per_party": sum(i.key_bytes for i in insts)},
         "latency_ms": {"p50": round(pct(fused["lat"], 0.5), 4), "p99": round(pct(fused["lat"], 0.99), 4)},
         "breakdown_ms": {"keygen": round(fused["keygen_ms"], 4), "eval": round(fused["eval_ms"], 4)},
         "aes_blocks_per_s": round((eval_aes + kg_aes) * args.steps / fused["wall_s"], 1),
         "eval_only_element_evals_per_s": round(evals / eval_s, 1),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(LOOKUP_PEAK_T, 3),
                      "unit": "T table-lookups/s", "frac": round(achieved / LOOKUP_PEAK_T, 4),
-                     "traffic": measured_traffic(args.workload),
+                     "traffic": measured_traffic(args.workload, insts[0].lookup_r),
                      "kernel": "k_fused", "ceiling": "CU local-memory lookup rate (T-table AES)",
                      "lookups_per_launch": eval_lookups / len(plans),
                      "aes_blocks_per_launch": eval_aes / len(plans),

@@ -101,6 +101,20 @@ int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces,
                      fss_spec** out);
 void fss_spec_free(fss_spec* spec);
 
+/* Input bits per level of call 2's vector DCF (the interval lookup of
+ * Definition "Interval lookup with vector payload", realised as one DCF
+ * evaluated at m points): 2, 3 or 4, i.e. 4, 8 or 16 children per level and
+ * ceil(n_bits / bits) levels.  More bits per level walk fewer levels at each
+ * lookup point (fewer AES blocks in evaluation) and generate and store more
+ * children per level (more AES in keygen, larger keys).  The paper leaves
+ * the DCF open; this is the 2^k-ary form.  Applies to keys generated and
+ * sizes queried after the call (each setting is cached separately); keys
+ * record it in their header, so evaluation needs no setting.  Returns
+ * FSS_E_ARG for other values.  The default is 3 until changed. */
+int fss_spec_set_lookup_radix(fss_spec* spec, int32_t bits);
+/* The current setting (or a negative FSS_E_* code for a NULL spec). */
+int fss_spec_get_lookup_radix(const fss_spec* spec);
+
 /* Public, mask-independent shape of a quantised spec (leakage L_shape of
  * the appendix "A standard real/ideal security statement"). */
 typedef struct {
@@ -110,6 +124,8 @@ typedef struct {
   int32_t atom_k[FSS_MAX_ATOMS];    /* bit width of each atom's view */
   int64_t atom_c[FSS_MAX_ATOMS];    /* public shift of each atom's view */
   int32_t atom_is_mask[FSS_MAX_ATOMS]; /* 1: the 1[view < r_k] atom of its view */
+  int32_t lookup_r;  /* input bits per level of call 2's DCF */
+  int32_t top_depth; /* its levels walked once per block of lookup points */
 } fss_spec_info;
 
 /* Quantise at (n_bits, frac_bits) and report the shape and integer tables.

@@ -209,7 +209,7 @@ class SpecError(ValueError):
     pass
 
 
-def compile_spec(desc, n_bits: int, frac_bits: int, lookup_r: int = 2) -> Spec:
+def compile_spec(desc, n_bits: int, frac_bits: int, lookup_r: int = 3) -> Spec:
     """desc: paper_2606_09551_amd.workloads.SpecDesc (real-valued spec);
     lookup_r: input bits per level of call 2's DCF (2, 3 or 4)."""
     m = len(desc.intervals)

@@ -513,7 +513,7 @@ int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
   const int n = n_bits, f = frac_bits;
   const int64_t N = (int64_t)1 << n, s = N / 2;
   S->n = n; S->f = f; S->m = m;
-  S->lookup_r = 2;
+  S->lookup_r = 3;
 
   /* Partition: contiguous half-open real intervals, tails at -inf / +inf. */
   if (!(isinf(iv[0].lo) && iv[0].lo < 0)) return -1;

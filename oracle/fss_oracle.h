@@ -125,7 +125,7 @@ typedef struct {
 } orc_spec;
 
 /* Returns 0 on success, negative on an invalid or unsupported spec.  Sets
- * lookup_r = 2; a caller may change it before keygen. */
+ * lookup_r = 3; a caller may change it before keygen. */
 int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
                      const orc_pred* pr, int32_t n_pred, int32_t n_bits,
                      int32_t frac_bits, int32_t out_frac_bits, orc_spec* S);

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <sstream>
@@ -134,9 +135,10 @@ struct fss_spec {
   std::vector<fss_piece> pc;
   std::vector<fss_pred> pr;
   int32_t out_frac_bits = -1;
+  int32_t lookup_r = kDefaultLookupR;  // input bits per level of call 2's DCF
   uint64_t hash = 0;
   std::mutex mu;
-  std::map<std::pair<int, int>, std::shared_ptr<QSpec>> cache;
+  std::map<std::tuple<int, int, int>, std::shared_ptr<QSpec>> cache;  // by (n, f, lookup_r)
 };
 
 namespace {
@@ -150,7 +152,7 @@ uint64_t fnv1a(const void* data, size_t len, uint64_t h = 0xcbf29ce484222325ull)
   return h;
 }
 
-int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
+int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out) {
   if (n < 2 || n > 32) return fail(FSS_E_UNSUPPORTED, "n_bits=%d outside [2,32]", n);
   if (f < 0 || f >= n) return fail(FSS_E_UNSUPPORTED, "frac_bits=%d must be in [0,n_bits)", f);
   auto q = std::make_shared<QSpec>();
@@ -256,7 +258,7 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
     q->atom_c[q->n_prim + v] = views[v].c;
   }
   for (int t = 0; t < q->n_prim; ++t) q->atom_rview[t] = (uint32_t)(q->n_prim + prim_view[t]);
-  q->layout = make_layout(q->T, q->atom_k, n, q->p);
+  q->layout = make_layout(q->T, q->atom_k, n, q->p, r);
 
   // Header template (party, n_elems and n_tiles are stamped per buffer).
   KeyHeader& h = q->hdr;
@@ -273,15 +275,17 @@ int quantize(const fss_spec* S, int n, int f, std::shared_ptr<QSpec>* out) {
   // Lookup points u_i = (v - a'_i) mod 2^n span W = a'_{m-1} - a'_1 + 1
   // consecutive values; with 2^K >= W they meet at most two aligned blocks of
   // 2^K values, whose first levels are shared.  The lookup DCF walks
-  // 2L = 2 ceil(n / 2) bits, two per level, so K is raised until 2L - K is
-  // even and the shared levels are (2L - K) / 2.  Worth it when m >= 4.
+  // rL = r ceil(n / r) bits, r per level, so K is raised to a multiple of r
+  // and the shared levels are (rL - K) / r; they need K < n (at least two
+  // blocks).  Worth it when m >= 4.
+  h.lookup_r = (uint32_t)r;
   {
     const uint64_t W = (m >= 2) ? (q->aprime[m - 1] - q->aprime[1] + 1) : 1;
-    const int bits4 = 2 * ((n + 1) / 2);
+    const int L = (n + r - 1) / r;
     int K = 0;
     while (K < n && ((uint64_t)1 << K) < W) ++K;
-    if ((bits4 - K) & 1) ++K;
-    h.top_depth = (m >= 4 && K < bits4) ? (uint32_t)((bits4 - K) / 2) : 0u;
+    K = (K + r - 1) / r * r;
+    h.top_depth = (m >= 4 && K < n) ? (uint32_t)(L - K / r) : 0u;
   }
   h.tile_bytes = q->layout.tile_bytes;
   h.spec_hash = S->hash;
@@ -321,14 +325,14 @@ int aux_stream(hipStream_t* out);
 int get_qspec(const fss_spec* Sc, int n, int f, std::shared_ptr<QSpec>* out) {
   fss_spec* S = const_cast<fss_spec*>(Sc);
   std::lock_guard<std::mutex> lk(S->mu);
-  auto key = std::make_pair(n, f);
+  auto key = std::make_tuple(n, f, (int)S->lookup_r);
   auto it = S->cache.find(key);
   if (it != S->cache.end()) {
     *out = it->second;
     return FSS_OK;
   }
   std::shared_ptr<QSpec> q;
-  int rc = quantize(S, n, f, &q);
+  int rc = quantize(S, n, f, (int)S->lookup_r, &q);
   if (rc != FSS_OK) return rc;
   S->cache[key] = q;
   *out = q;
@@ -419,6 +423,21 @@ int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces,
   return FSS_OK;
 }
 
+int fss_spec_set_lookup_radix(fss_spec* spec, int32_t bits) {
+  if (!spec) return fail(FSS_E_ARG, "spec NULL");
+  if (bits < 2 || bits > 4) return fail(FSS_E_ARG, "lookup radix bits=%d not in {2, 3, 4}", bits);
+  std::lock_guard<std::mutex> lk(spec->mu);
+  spec->lookup_r = bits;
+  return FSS_OK;
+}
+
+int fss_spec_get_lookup_radix(const fss_spec* spec) {
+  if (!spec) return fail(FSS_E_ARG, "spec NULL");
+  fss_spec* S = const_cast<fss_spec*>(spec);
+  std::lock_guard<std::mutex> lk(S->mu);
+  return S->lookup_r;
+}
+
 void fss_spec_free(fss_spec* spec) {
   if (!spec) return;
   for (auto& kv : spec->cache)
@@ -442,6 +461,8 @@ int fss_spec_query(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, fss_
     memset(info, 0, sizeof *info);
     info->n_bits = q->n; info->frac_bits = q->f; info->m = q->m; info->degree = q->d; info->p = q->p;
     info->out_frac_bits = q->F_out; info->T = q->T; info->ell = q->ell;
+    info->lookup_r = (int32_t)q->hdr.lookup_r;
+    info->top_depth = (int32_t)q->hdr.top_depth;
     for (int t = 0; t < q->T; ++t) {
       info->atom_k[t] = (int32_t)q->atom_k[t];
       info->atom_c[t] = (int64_t)q->atom_c[t];
@@ -489,7 +510,7 @@ int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t
   ga.n_tiles = tiles;
   int cus = 0;
   if ((rc = current_cus(&cus))) return rc;
-  HIP_TRY(launch_keygen(keygen_variant(), q->p, reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
+  HIP_TRY(launch_keygen(keygen_variant(), q->p, (int)q->hdr.lookup_r, reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
                         (uint8_t*)key1, r_in, r_out, cus, st),
           "keygen launch");
   return FSS_OK;
@@ -667,8 +688,9 @@ ElemCost elem_cost(const KeyHeader& h) {
   ElemCost c;
   for (uint32_t t = 0; t < h.T; ++t) c.aes_pred += h.atom_k[t];
   c.lk_pred = 160.0 * c.aes_pred;
-  // the lookup DCF has L = ceil(n / 2) levels of four children; D of them shared
-  const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb, L = (double)((h.n + 1) / 2), D = h.top_depth;
+  // the lookup DCF has L = ceil(n / r) levels of 2^r children; D of them shared
+  const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb;
+  const double L = (double)((h.n + h.lookup_r - 1) / h.lookup_r), D = h.top_depth;
   c.aes_base = L * lvl + nb;
   c.lk_base = L * shared(lvl) + shared(nb);
   c.aes_tops = 2 * D * lvl;
@@ -769,6 +791,8 @@ int read_header(const void* keys, KeyHeader* h) {
   HIP_TRY(hipMemcpyAsync(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(header)");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(header)");
   if (h->magic != kMagic || h->version != kVersion) return fail(FSS_E_SHAPE, "not a key buffer");
+  if (h->lookup_r < 2 || h->lookup_r > 4 || h->rec_bytes != 16 + 8 * (uint64_t)h->p)
+    return fail(FSS_E_SHAPE, "key buffer with an unknown lookup layout");
   return FSS_OK;
 }
 

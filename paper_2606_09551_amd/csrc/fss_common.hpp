@@ -81,10 +81,10 @@ constexpr AesConst kAes = make_aes_const();
 //   atom t : root[64] (16 B) | cw[k_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
 //            | vbits[64] (u64: bit i = value corr. of level i, bit 32 = final)
 //   wshare[64] (u64: bit j = this party's share of the carry of output j)
-//   coeff  : root[64] | rec[L][4][64] | fin[p][64]
+//   coeff  : root[64] | rec[L][2^r][64] | fin[p][64]
 //            | rho[p][64] (share of rho) | rout[64] (share of r_out)
-//   The lookup's vector DCF has four children per level (two input bits), so
-//   it has L = ceil(n / 2) levels with corrections for each child.  A record
+//   The lookup's vector DCF takes r input bits per level (2^r children), so
+//   it has L = ceil(n / r) levels with corrections for each child.  A record
 //   rec[i][c][lane] (16 + 8p bytes) holds child c's seed correction (bit 0 =
 //   control-bit correction) followed by its p value corrections: the lanes of
 //   a wave pick different children, and a lane's child is one contiguous
@@ -97,12 +97,14 @@ constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
 constexpr int kMaxP = 4;
+constexpr int kDefaultLookupR = 3;  // input bits per lookup-DCF level unless a spec sets it
 constexpr uint64_t kHeaderBytes = 16384;
 
 struct KeyHeader {
   uint32_t magic, version, party, layout;
   uint32_t n, f, m, d, p, T, ell, F_out;
   uint32_t n_prim, n_views, kmax, top_depth;  // top_depth: shared lookup-DCF levels of the lookup points
+  uint32_t lookup_r, reserved0;            // lookup_r: input bits per lookup-DCF level (2, 3 or 4)
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];
@@ -125,7 +127,7 @@ struct Layout {
   uint64_t tile_bytes;
 };
 
-FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p) {
+FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p, int r) {
   Layout L{};
   uint64_t o = 0;
   for (int t = 0; t < T; ++t) {
@@ -134,9 +136,9 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p) {
   }
   L.off_w = o;     o += kTile * 8;
   L.off_croot = o; o += kTile * 16;
-  const uint64_t levels = (uint64_t)(n + 1) / 2;  // four children per level
+  const uint64_t levels = (uint64_t)(n + r - 1) / r;  // 2^r children per level
   L.rec_bytes = 16 + 8 * (uint64_t)p;       // seed correction, then p value corrections
-  L.off_crec = o;  o += levels * 4 * kTile * L.rec_bytes;
+  L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
   L.off_cfin = o;  o += (uint64_t)p * kTile * 8;
   L.off_crho = o;  o += (uint64_t)p * kTile * 8;
   L.off_crout = o; o += kTile * 8;

@@ -47,7 +47,7 @@ struct VariantOps {
   static int lds_bytes();
   // `cus`: compute units of the device; batches with fewer tiles than a full
   // grid get smaller blocks so their tiles spread over the CUs.
-  static hipError_t keygen(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
+  static hipError_t keygen(const KeyHeader* h, int p, int r, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
                            uint64_t* ro, int cus, hipStream_t st);
   static hipError_t pred(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* z,
                          int* status, int cus, hipStream_t st);
@@ -63,7 +63,7 @@ extern template struct VariantOps<3>;
 
 hipError_t launch_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
                               uint32_t party, hipStream_t st);
-hipError_t launch_keygen(int variant, int p, const KeyHeader* dev_hdr, const KgArgs& ga, uint8_t* key0,
+hipError_t launch_keygen(int variant, int p, int r, const KeyHeader* dev_hdr, const KgArgs& ga, uint8_t* key0,
                          uint8_t* key1, uint64_t* r_in, uint64_t* r_out, int cus, hipStream_t st);
 hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat,
                        hipStream_t st);

@@ -297,6 +297,7 @@ __device__ __forceinline__ void prg_shared(const TB& tb, const uint32_t (&s)[4],
 __device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
   if (h->magic != kMagic || h->version != kVersion) return kStatusShape;
   if (h->rec_bytes != 16 + 8 * (uint64_t)h->p) return kStatusShape;
+  if (h->lookup_r < 2 || h->lookup_r > 4) return kStatusShape;
   if ((int)h->party != party) return kStatusParty;
   if (n < 0 || (uint64_t)n > h->n_elems) return kStatusShape;
   return 0;
@@ -417,25 +418,26 @@ __device__ __forceinline__ VState<P> vselect(bool c, const VState<P>& a, const V
   return r;
 }
 
-// Advance `st` through levels [i0, i1) of the lookup DCF along the base-4
-// digits of the input x: the DCF has L = ceil(n / 2) levels of four children
-// and level i consumes digit L - 1 - i (an odd n has a leading zero bit).
-// Child d of seed s is H(s, d), its value the first P words of H(s, 4 + 2d + k).
-template <int P, class TB>
+// Advance `st` through levels [i0, i1) of the lookup DCF along the base-2^R
+// digits of the input x: the DCF has L = ceil(n / R) levels of 2^R children
+// and level i consumes digit L - 1 - i (R L - n leading zero bits).
+// Child d of seed s is H(s, d), its value the first P words of H(s, 2^R + 2d + k).
+template <int P, int R, class TB>
 __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
                                          uint32_t x, int i0, int i1, VState<P>& st) {
   constexpr int NB = (P + 1) / 2;
-  const int L = ((int)h->n + 1) / 2;
+  constexpr uint32_t C = 1u << R;
+  const int L = ((int)h->n + R - 1) / R;
   constexpr uint64_t REC = 16 + 8 * P;
   const uint8_t* recp = tile + h->off_crec + lane * REC;
   for (int i = i0; i < i1; ++i) {
-    const uint32_t d = (x >> (2 * (L - 1 - i))) & 3u;
+    const uint32_t d = (x >> (R * (L - 1 - i))) & (C - 1u);
     uint32_t jj[1 + NB], o[1 + NB][4];
     jj[0] = d;
-    jj[1] = 4u + 2u * d;
-    if (NB > 1) jj[NB > 1 ? 2 : 0] = 5u + 2u * d;
+    jj[1] = C + 2u * d;
+    if (NB > 1) jj[NB > 1 ? 2 : 0] = C + 1u + 2u * d;
     prg_shared<TB, 1 + NB>(tb, st.s, jj, o);
-    const uint8_t* rp = recp + ((uint64_t)i * 4 + d) * kTile * REC;  // child d's record at level i
+    const uint8_t* rp = recp + ((uint64_t)i * C + d) * kTile * REC;  // child d's record at level i
     const uint64_t c01 = ld8(rp), c23 = ld8(rp + 8);
     const uint4 cw = make_uint4((uint32_t)c01, (uint32_t)(c01 >> 32), (uint32_t)c23, (uint32_t)(c23 >> 32));
     const uint32_t t = st.t;
@@ -456,14 +458,14 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
 }
 
 // Leaf value: V + (-1)^b (Convert(s) + t * CW_fin), Convert(s) = the first
-// P words of H(s, 12) || H(s, 13).
-template <int P, class TB>
+// P words of H(s, 3 * 2^R) || H(s, 3 * 2^R + 1).
+template <int P, int R, class TB>
 __device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
                                           const VState<P>& st, uint64_t (&out)[P]) {
   constexpr int NB = (P + 1) / 2;
   uint32_t jj[NB], o[NB][4];
 #pragma unroll
-  for (int q = 0; q < NB; ++q) jj[q] = 12u + q;
+  for (int q = 0; q < NB; ++q) jj[q] = 3u * (1u << R) + q;
   prg_shared<TB, NB>(tb, st.s, jj, o);
   const uint64_t msk64 = 0ull - (uint64_t)st.t;
 #pragma unroll
@@ -496,17 +498,17 @@ __device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* t
 // covers the points i in [i0, min(i1, m)) and, when `base` is set, the walk at
 // v with the tabv, tab_0 rho and r_out terms; i0 = 1, i1 >= m, base = true is
 // the whole of call 2.
-template <int P, class TB>
+template <int P, int R, class TB>
 __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8_t* tile,
                                                int lane, int b, uint64_t xhat, int i0, int i1, bool base) {
   const int n = (int)h->n, m = (int)h->m, D = (int)h->top_depth;
-  const int L = (n + 1) / 2;
+  const int L = (n + R - 1) / R;
   const int iend = i1 < m ? i1 : m;
   const uint32_t Nmask = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
   const uint32_t half = 1u << (n - 1);
   const uint32_t v = ((uint32_t)xhat + half) & Nmask;
   const uint8_t* rhop = tile + h->off_crho + lane * 8;
-  const int K = D > 0 ? 2 * (L - D) : 0;  // input bits below the shared levels (D > 0: 2 <= K < n)
+  const int K = D > 0 ? R * (L - D) : 0;  // input bits below the shared levels (D > 0: R <= K < n)
   const uint32_t blk_mask = D > 0 ? (1u << (n - K)) - 1u : 0u;
   const uint32_t blkA = D > 0 ? (((v - (uint32_t)h->aprime[m - 1]) & Nmask) >> K) : 0u;
   const uint32_t blkB = (blkA + 1u) & blk_mask;
@@ -515,16 +517,16 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   for (int k = 0; k < P; ++k) q[k] = 0;
   VState<P> sa = vroot<P>(h, tile, lane, b), sb = sa;
   if (D > 0 && iend > i0) {
-    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkA << K), 0, D, sa);
-    vec_walk<P>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkB << K), 0, D, sb);
+    vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkA << K), 0, D, sa);
+    vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkB << K), 0, D, sb);
   }
   for (int i = i0; i < iend; ++i) {
     const uint32_t ap = (uint32_t)h->aprime[i];
     const uint32_t u = (v - ap) & Nmask;
     VState<P> st = vselect<P>((u >> K) == blkA, sa, sb);  // D = 0: both are the root
-    vec_walk<P>(tb, h, tile, lane, b, u, D, L, st);
+    vec_walk<P, R>(tb, h, tile, lane, b, u, D, L, st);
     uint64_t g[P];
-    vec_final<P>(tb, h, tile, lane, b, st, g);
+    vec_final<P, R>(tb, h, tile, lane, b, st, g);
     const uint64_t lt = v < ap ? ~0ull : 0ull;
 #pragma unroll
     for (int k = 0; k < P; ++k) g[k] += ld8(rhop + (uint64_t)k * kTile * 8) & lt;
@@ -535,9 +537,9 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   }
   if (base) {
     VState<P> st = vroot<P>(h, tile, lane, b);
-    vec_walk<P>(tb, h, tile, lane, b, v, 0, L, st);
+    vec_walk<P, R>(tb, h, tile, lane, b, v, 0, L, st);
     uint64_t Dv[P];
-    vec_final<P>(tb, h, tile, lane, b, st, Dv);
+    vec_final<P, R>(tb, h, tile, lane, b, st, Dv);
 #pragma unroll
     for (int j = 0; j < P; ++j)
 #pragma unroll
@@ -554,15 +556,25 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   return y;
 }
 
+template <int R, class TB>
+__device__ __forceinline__ uint64_t coeff_dispatch_r(const TB& tb, GHdr h, const uint8_t* tile,
+                                                     int lane, int b, uint64_t xhat, int i0, int i1, bool base) {
+  switch (h->p) {
+    case 1: return coeff_tile<1, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 2: return coeff_tile<2, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 3: return coeff_tile<3, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    default: return coeff_tile<4, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
+  }
+}
+
 template <class TB>
 __device__ __forceinline__ uint64_t coeff_dispatch(const TB& tb, GHdr h, const uint8_t* tile,
                                                    int lane, int b, uint64_t xhat, int i0 = 1,
                                                    int i1 = kMaxM + 1, bool base = true) {
-  switch (h->p) {
-    case 1: return coeff_tile<1>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    case 2: return coeff_tile<2>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    case 3: return coeff_tile<3>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    default: return coeff_tile<4>(tb, h, tile, lane, b, xhat, i0, i1, base);
+  switch (h->lookup_r) {
+    case 2: return coeff_dispatch_r<2>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 3: return coeff_dispatch_r<3>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    default: return coeff_dispatch_r<4>(tb, h, tile, lane, b, xhat, i0, i1, base);
   }
 }
 
@@ -773,7 +785,7 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
 // seed XOR, control bits t0 ^ t1, V_CW = (-1)^{t_1} (v_1 - v_0 - V_alpha
 // [+ beta below alpha's digit]).  Alpha's child gets random corrections
 // R(e, 69 + k, level), carries the parties on, and updates V_alpha.
-template <int P, class TB>
+template <int P, int R, class TB>
 __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t alpha,
                                         const uint64_t (&beta)[P], const uint32_t (&r0)[4],
                                         const uint32_t (&r1)[4], const RoundKeys& rk, uint64_t e,
@@ -785,7 +797,8 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   constexpr uint64_t REC = 16 + 8 * P;
   const uint64_t off_croot = h->off_croot, off_crec = h->off_crec;
   const uint64_t off_cfin = h->off_cfin;
-  const int L = (n + 1) / 2;
+  constexpr uint32_t C = 1u << R;
+  const int L = (n + R - 1) / R;
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
   uint32_t t[2] = {0u, 1u};
   uint64_t Va[P];
@@ -794,7 +807,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   st16(k0 + off_croot + lane * 16, make_uint4(s[0][0], s[0][1], s[0][2], s[0][3]));
   if (k1) st16(k1 + off_croot + lane * 16, make_uint4(s[1][0], s[1][1], s[1][2], s[1][3]));
   for (int i = 0; i < L; ++i) {
-    const uint32_t a = (uint32_t)(alpha >> (2 * (L - 1 - i))) & 3u;
+    const uint32_t a = (uint32_t)(alpha >> (R * (L - 1 - i))) & (C - 1u);
     const uint64_t neg = 0ull - (uint64_t)t[1];  // (-1)^{t_1} as a mask
     // Children off alpha's path: corrections written as they are expanded.
     // Alpha's child: the parties' children kept for after the loop.
@@ -803,11 +816,11 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
 #pragma unroll
     for (int q = 0; q < P; ++q) dk[q] = 0;
 #pragma unroll 1
-    for (uint32_t c = 0; c < 4; ++c) {
+    for (uint32_t c = 0; c < C; ++c) {
       uint32_t o0[1 + NB][4], o1[1 + NB][4], jj[1 + NB];
       jj[0] = c;
 #pragma unroll
-      for (int k = 0; k < NB; ++k) jj[1 + k] = 4u + 2u * c + k;
+      for (int k = 0; k < NB; ++k) jj[1 + k] = C + 2u * c + k;
       prg_shared<TB, 1 + NB>(tb, s[0], jj, o0);
       prg_shared<TB, 1 + NB>(tb, s[1], jj, o1);
       const uint32_t t0c = o0[0][0] & 1u, t1c = o1[0][0] & 1u;
@@ -828,7 +841,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
       } else {
         const uint4 cw = make_uint4(((o0[0][0] ^ o1[0][0]) & ~3u) | (t0c ^ t1c), o0[0][1] ^ o1[0][1],
                                     o0[0][2] ^ o1[0][2], o0[0][3] ^ o1[0][3]);
-        const uint64_t ro = off_crec + (((uint64_t)i * 4 + c) * kTile + lane) * REC;
+        const uint64_t ro = off_crec + (((uint64_t)i * C + c) * kTile + lane) * REC;
         st8(k0 + ro, mk64(cw.x, cw.y));
         st8(k0 + ro + 8, mk64(cw.z, cw.w));
         if (k1) {
@@ -857,7 +870,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
     }
     const uint32_t tcw_a = kt[0] ^ kt[1] ^ 1u;
     const uint32_t scw_a[4] = {kr[0][0] & ~3u, kr[0][1], kr[0][2], kr[0][3]};
-    const uint64_t ro = off_crec + (((uint64_t)i * 4 + a) * kTile + lane) * REC;
+    const uint64_t ro = off_crec + (((uint64_t)i * C + a) * kTile + lane) * REC;
     st8(k0 + ro, mk64(scw_a[0] | tcw_a, scw_a[1]));
     st8(k0 + ro + 8, mk64(scw_a[2], scw_a[3]));
     if (k1) {
@@ -879,13 +892,13 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
       t[b] = kt[b] ^ (t[b] & tcw_a);
     }
   }
-  // CW_fin = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha), Convert = H(s, 12 + k)
+  // CW_fin = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha), Convert = H(s, 3 * 2^R + k)
   uint64_t cv[2][P];
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     uint32_t o[NB][4], jj[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) jj[q] = 12u + q;
+    for (int q = 0; q < NB; ++q) jj[q] = 3u * C + q;
     prg_shared<TB, NB>(tb, s[b], jj, o);
 #pragma unroll
     for (int q = 0; q < P; ++q) cv[b][q] = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
@@ -901,7 +914,7 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   }
 }
 
-template <int P, class TB>
+template <int P, int R, class TB>
 __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs& ga, uint64_t e,
                                              uint64_t rin, uint8_t* t0, uint8_t* t1, int lane) {
   uint64_t rho[P];
@@ -914,7 +927,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
   const int n = (int)h->n;
   const uint64_t off_crho = h->off_crho;
   const uint64_t nmask = n >= 64 ? ~0ull : ((1ull << n) - 1);
-  gen_vec<P>(tb, h, n, rin & nmask, rho, c0, c1, ga.rk, e, t0, t1, lane);
+  gen_vec<P, R>(tb, h, n, rin & nmask, rho, c0, c1, ga.rk, e, t0, t1, lane);
   uint32_t ra[4], rb[4];
   rand_blk(tb, ga.rk, e, 67, 0, ra);
   rand_blk(tb, ga.rk, e, 68, 0, rb);
@@ -935,7 +948,7 @@ __device__ __forceinline__ void keygen_coeff(const TB& tb, GHdr h, const KgArgs&
 template <int V, int P>
 constexpr int keygen_block() { return (P >= 4 && TabOf<V>::kBlock > 512) ? 512 : TabOf<V>::kBlock; }
 
-template <int V, int P>
+template <int V, int P, int R>
 __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHeader* hdr, KgArgs ga, uint8_t* key0,
                                                               uint8_t* key1, uint64_t* r_in, uint64_t* r_out) {
   using TB = typename TabOf<V>::T;
@@ -989,7 +1002,7 @@ __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHead
   st8(t0 + h->off_w + lane * 8, W);
   if (t1) st8(t1 + h->off_w + lane * 8, W ^ wout);
 
-  keygen_coeff<P>(tb, h, ga, e, rin, t0, t1, lane);
+  keygen_coeff<P, R>(tb, h, ga, e, rin, t0, t1, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,24 +1024,35 @@ inline uint64_t waves_per_block(uint64_t tiles, int cus, int block) {
   return w < 1 ? 1 : (w > full ? full : w);
 }
 
-template <int V, int P>
+template <int V, int P, int R>
 hipError_t launch_keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
                          uint64_t* ro, int cus, hipStream_t st) {
   const uint64_t per = waves_per_block(ga.n_tiles, cus, keygen_block<V, P>());
   const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
-  hipLaunchKernelGGL((k_keygen<V, P>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, h, ga, k0, k1, ri, ro);
+  hipLaunchKernelGGL((k_keygen<V, P, R>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, h, ga, k0, k1, ri, ro);
   return hipGetLastError();
 }
 
+template <int V, int R>
+hipError_t launch_keygen_p(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
+                           uint64_t* ro, int cus, hipStream_t st) {
+  switch (p) {
+    case 1: return launch_keygen<V, 1, R>(h, ga, k0, k1, ri, ro, cus, st);
+    case 2: return launch_keygen<V, 2, R>(h, ga, k0, k1, ri, ro, cus, st);
+    case 3: return launch_keygen<V, 3, R>(h, ga, k0, k1, ri, ro, cus, st);
+    case 4: return launch_keygen<V, 4, R>(h, ga, k0, k1, ri, ro, cus, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int V>
-hipError_t VariantOps<V>::keygen(const KeyHeader* h, int p, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
+hipError_t VariantOps<V>::keygen(const KeyHeader* h, int p, int r, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
                                  uint64_t* ri, uint64_t* ro, int cus, hipStream_t st) {
   if (ga.n_tiles == 0) return hipSuccess;
-  switch (p) {
-    case 1: return launch_keygen<V, 1>(h, ga, k0, k1, ri, ro, cus, st);
-    case 2: return launch_keygen<V, 2>(h, ga, k0, k1, ri, ro, cus, st);
-    case 3: return launch_keygen<V, 3>(h, ga, k0, k1, ri, ro, cus, st);
-    case 4: return launch_keygen<V, 4>(h, ga, k0, k1, ri, ro, cus, st);
+  switch (r) {
+    case 2: return launch_keygen_p<V, 2>(h, p, ga, k0, k1, ri, ro, cus, st);
+    case 3: return launch_keygen_p<V, 3>(h, p, ga, k0, k1, ri, ro, cus, st);
+    case 4: return launch_keygen_p<V, 4>(h, p, ga, k0, k1, ri, ro, cus, st);
     default: return hipErrorInvalidValue;
   }
 }

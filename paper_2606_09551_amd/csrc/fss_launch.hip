@@ -50,13 +50,13 @@ hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64
   return hipGetLastError();
 }
 
-hipError_t launch_keygen(int v, int p, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
+hipError_t launch_keygen(int v, int p, int r, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,
                          uint64_t* ri, uint64_t* ro, int cus, hipStream_t st) {
   switch (v) {
-    case 0: return VariantOps<0>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
-    case 1: return VariantOps<1>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
-    case 2: return VariantOps<2>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
-    case 3: return VariantOps<3>::keygen(h, p, ga, k0, k1, ri, ro, cus, st);
+    case 0: return VariantOps<0>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
+    case 1: return VariantOps<1>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
+    case 2: return VariantOps<2>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
+    case 3: return VariantOps<3>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
     default: return hipErrorInvalidValue;
   }
 }

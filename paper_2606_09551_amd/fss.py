@@ -57,7 +57,8 @@ class SpecInfo(C.Structure):
     _fields_ = [("n_bits", C.c_int32), ("frac_bits", C.c_int32), ("m", C.c_int32),
                 ("degree", C.c_int32), ("p", C.c_int32), ("out_frac_bits", C.c_int32),
                 ("T", C.c_int32), ("ell", C.c_int32), ("atom_k", C.c_int32 * MAX_ATOMS),
-                ("atom_c", C.c_int64 * MAX_ATOMS), ("atom_is_mask", C.c_int32 * MAX_ATOMS)]
+                ("atom_c", C.c_int64 * MAX_ATOMS), ("atom_is_mask", C.c_int32 * MAX_ATOMS),
+                ("lookup_r", C.c_int32), ("top_depth", C.c_int32)]
 
 
 class WorkItem(C.Structure):
@@ -81,6 +82,8 @@ def _load():
         "fss_compile_spec": [C.POINTER(Interval), i32, C.POINTER(Piece), C.POINTER(Pred), i32, i32,
                              C.POINTER(vp)],
         "fss_spec_free": [vp],
+        "fss_spec_set_lookup_radix": [vp, i32],
+        "fss_spec_get_lookup_radix": [vp],
         "fss_spec_query": [vp, i32, i32, C.POINTER(SpecInfo), vp, vp],
         "fss_key_bytes": [vp, i32, i32, i64, C.POINTER(C.c_size_t)],
         "fss_keygen": [vp, i32, i32, u64, i64, vp, vp, vp, vp, vp],
@@ -148,7 +151,7 @@ def _stream(stream) -> int | None:
 class Spec:
     """An operator specification compiled by the library (fss_compile_spec)."""
 
-    def __init__(self, desc):
+    def __init__(self, desc, lookup_r: int | None = None):
         m = len(desc.intervals)
         iv = (Interval * m)(*[Interval(lo, hi) for lo, hi in desc.intervals])
         pcs = (Piece * m)()
@@ -166,6 +169,15 @@ class Spec:
                                     C.byref(h)))
         self.handle = h
         self.name = desc.name
+        if lookup_r is not None:
+            _check(lib.fss_spec_set_lookup_radix(h, lookup_r))
+
+    @property
+    def lookup_r(self) -> int:
+        rc = lib.fss_spec_get_lookup_radix(self.handle)
+        if rc < 0:
+            _check(rc)
+        return rc
 
     def __del__(self, _free=lib.fss_spec_free):
         h = getattr(self, "handle", None)
@@ -184,6 +196,7 @@ class Spec:
                 "F_out": info.out_frac_bits, "T": info.T, "ell": info.ell,
                 "atom_k": list(info.atom_k[:info.T]), "atom_c": list(info.atom_c[:info.T]),
                 "atom_is_mask": list(info.atom_is_mask[:info.T]),
+                "lookup_r": info.lookup_r, "top_depth": info.top_depth,
                 "aprime": list(ap), "coef": [[co[i * p + l] for l in range(p)] for i in range(m)]}
 
     def key_bytes(self, n_bits: int, frac_bits: int, n_elems: int) -> int:

@@ -28,6 +28,7 @@ class OpInstanceGPU:
         q = spec.query(n_bits, frac_bits)
         self.ell, self.m, self.p, self.T = q["ell"], q["m"], q["p"], q["T"]
         self.atom_k = q["atom_k"]
+        self.lookup_r = q["lookup_r"]
         self.key_bytes = spec.key_bytes(n_bits, frac_bits, n)
         self.parties = tuple(parties)
         dev = torch.device(device)
@@ -38,11 +39,6 @@ class OpInstanceGPU:
         self.x, self.xhat = mk(n), mk(n)
         self.y = {b: mk(n) for b in self.parties}
         self.z = {b: mk(self.ell * words(n)) for b in self.parties}
-
-    # AES blocks of one party's evaluation of one element (both calls).
-    def aes_per_elem(self) -> int:
-        nb = (self.p + 1) // 2
-        return sum(self.atom_k) + self.m * (self.n_bits * (1 + nb) + nb)
 
     def set_input(self, x: np.ndarray):
         assert x.shape == (self.n,)

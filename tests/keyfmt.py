@@ -11,7 +11,7 @@ HDR = np.dtype([
     ("magic", "<u4"), ("version", "<u4"), ("party", "<u4"), ("layout", "<u4"),
     ("n", "<u4"), ("f", "<u4"), ("m", "<u4"), ("d", "<u4"), ("p", "<u4"), ("T", "<u4"),
     ("ell", "<u4"), ("F_out", "<u4"), ("n_prim", "<u4"), ("n_views", "<u4"), ("kmax", "<u4"),
-    ("top_depth", "<u4"), ("n_elems", "<u8"), ("n_tiles", "<u8"), ("tile_bytes", "<u8"),
+    ("top_depth", "<u4"), ("lookup_r", "<u4"), ("reserved0", "<u4"), ("n_elems", "<u8"), ("n_tiles", "<u8"), ("tile_bytes", "<u8"),
     ("spec_hash", "<u8"), ("negate", "<u8"), ("atom_k", "<u4", MAXA), ("atom_out", "<u4", MAXA),
     ("atom_rview", "<u4", MAXA), ("atom_c", "<u8", MAXA), ("atom_off", "<u8", MAXA),
     ("off_w", "<u8"), ("off_croot", "<u8"), ("off_crec", "<u8"), ("rec_bytes", "<u8"),
@@ -49,17 +49,17 @@ class KeyView:
                 "vcw": [(vb >> i) & 1 for i in range(k)], "fin": (vb >> 32) & 1}
 
     def coeff(self, e: int) -> dict:
-        """The lookup DCF: L = ceil(n / 2) levels of four children; child c of
+        """The lookup DCF: L = ceil(n / r) levels of 2^r children; child c of
         level i has a record rec[i][c][lane] of 16 + 8p bytes: its seed
         correction (bit 0 = control-bit correction), then its p value corrections."""
         h, lane = self.h, e % TILE
-        n, p = int(h["n"]), int(h["p"])
-        L = (n + 1) // 2
+        n, p, r = int(h["n"]), int(h["p"]), int(h["lookup_r"])
+        L, C = -(-n // r), 1 << r
         rec = 16 + 8 * p
         assert int(h["rec_bytes"]) == rec
         tb = self.tile_base(e)
         root = self._blk(tb + int(h["off_croot"]) + lane * 16)
-        recs = [[tb + int(h["off_crec"]) + ((i * 4 + c) * TILE + lane) * rec for c in range(4)] for i in range(L)]
+        recs = [[tb + int(h["off_crec"]) + ((i * C + c) * TILE + lane) * rec for c in range(C)] for i in range(L)]
         cws = [[self._blk(r) for r in lv] for lv in recs]
         vcw = [[[self._u64(r + 16 + 8 * q) for q in range(p)] for r in lv] for lv in recs]
         fin = [self._u64(tb + int(h["off_cfin"]) + (q * TILE + lane) * 8) for q in range(p)]
@@ -81,10 +81,10 @@ def oracle_atom(K, t: int) -> dict:
 
 def oracle_coeff(K) -> dict:
     c = K.coeff
-    L, p = (c.n + 1) // 2, c.p
+    L, p, C = -(-c.n // c.r), c.p, 1 << c.r
     return {"root": (c.root.lo, c.root.hi),
-            "scw": [[(c.scw[i][ch].lo, c.scw[i][ch].hi) for ch in range(4)] for i in range(L)],
-            "tcw": [[c.tcw[i][ch] for ch in range(4)] for i in range(L)],
-            "vcw": [[[int(c.vcw[i][ch][q]) for q in range(p)] for ch in range(4)] for i in range(L)],
+            "scw": [[(c.scw[i][ch].lo, c.scw[i][ch].hi) for ch in range(C)] for i in range(L)],
+            "tcw": [[c.tcw[i][ch] for ch in range(C)] for i in range(L)],
+            "vcw": [[[int(c.vcw[i][ch][q]) for q in range(p)] for ch in range(C)] for i in range(L)],
             "fin": [int(c.fin[q]) for q in range(p)], "rho": [int(K.rho[q]) for q in range(p)],
             "rout": int(K.rout), "wshare": int(K.wshare)}

@@ -54,8 +54,8 @@ def _flush(msg):
     print(msg, flush=True)
 
 
-def gpu_run(desc, n_bits, f, x, seed, path="plain", variant=None):
-    spec = F.Spec(desc)
+def gpu_run(desc, n_bits, f, x, seed, path="plain", variant=None, lookup_r=None):
+    spec = F.Spec(desc, lookup_r)
     op = R.OpInstanceGPU(spec, n_bits, f, len(x))
     op.set_input(x)
     op.keygen(seed)
@@ -73,14 +73,15 @@ def gpu_run(desc, n_bits, f, x, seed, path="plain", variant=None):
     torch.cuda.synchronize()
     out = op.host()
     out["parts"] = plan.parts() if path != "plain" else 1
+    out["lookup_r"] = spec.lookup_r
     out["keys0"] = op.keys[0].cpu().numpy()
     out["keys1"] = op.keys[1].cpu().numpy()
     out["op"] = op
     return out
 
 
-def oracle_run(desc, n_bits, f, x, seed, elems):
-    S = O.compile_spec(desc, n_bits, f)
+def oracle_run(desc, n_bits, f, x, seed, elems, lookup_r):
+    S = O.compile_spec(desc, n_bits, f, lookup_r=lookup_r)
     elems = np.asarray(elems, dtype=np.int64)
     K0, K1, r_in, r_out = O.keygen(S, seed, elems)
     xhat = (x[elems].astype(np.int64).view(np.uint64) + r_in).astype(np.uint64)
@@ -113,15 +114,16 @@ def test_c1_clip_relu_full_parity():
     _flush("c1 clip-relu n=4096")
     g = gpu_run(op.spec, 16, 8, op.x, op.seed)
     elems = np.arange(len(op.x))
-    o = oracle_run(op.spec, 16, 8, op.x, op.seed, elems)
+    o = oracle_run(op.spec, 16, 8, op.x, op.seed, elems, g["lookup_r"])
     compare(g, o, elems, len(op.x), check_keys=64)
     S = o["S"]
     yp, zp = O.plain_many(S, op.x)
     assert np.array_equal(g["y0"] + g["y1"] - g["r_out"], yp)
 
 
+@pytest.mark.parametrize("r", [2, 3, 4])
 @pytest.mark.parametrize("name", ["mixed", "steps", "relu", "gelu_small", "exp_small"])
-def test_small_specs_all_elements(name):
+def test_small_specs_all_elements(name, r):
     desc, n, f = {
         "mixed": (_mixed_spec(), 12, 4),
         "steps": (_steps_spec(), 10, 3),
@@ -134,10 +136,11 @@ def test_small_specs_all_elements(name):
     s = 2 ** (n - 1)
     x = g_.integers(-s, s, size=N).astype(np.int64)
     x[:4] = [-s, s - 1, 0, -1]
-    _flush(f"small spec {name} n={n} N={N}")
+    _flush(f"small spec {name} n={n} r={r} N={N}")
     for path in ("plain", "fused"):
-        g = gpu_run(desc, n, f, x, 0x5EED + len(name), path=path)
-        o = oracle_run(desc, n, f, x, 0x5EED + len(name), np.arange(N))
+        g = gpu_run(desc, n, f, x, 0x5EED + len(name), path=path, lookup_r=r)
+        assert g["lookup_r"] == r
+        o = oracle_run(desc, n, f, x, 0x5EED + len(name), np.arange(N), r)
         compare(g, o, np.arange(N), N, check_keys=16 if path == "plain" else 0)
         if path == "fused" and name in ("gelu_small", "exp_small"):
             # 32 tiles cannot fill the GPU and call 2 dominates their cost: the
@@ -146,12 +149,14 @@ def test_small_specs_all_elements(name):
             assert g["parts"] > 1, g["parts"]
 
 
+@pytest.mark.parametrize("r", [2, 3, 4])
 @pytest.mark.parametrize("n", [31, 32])
 @pytest.mark.parametrize("name", ["clip", "gelu"])
-def test_widest_domains(n, name):
-    """The widest comparison domains: n = 32 (16 lookup-DCF levels, full 32-bit
-    masks) and n = 31 (odd: a leading zero bit), every element of 200 inputs
-    spread over the whole domain plus its ends, keys sampled, both paths."""
+def test_widest_domains(n, name, r):
+    """The widest comparison domains: n = 32 (full 32-bit masks; 16, 11 or 8
+    lookup-DCF levels at r = 2, 3, 4) and n = 31 (leading zero bits at every
+    r), every element of 200 inputs spread over the whole domain plus its ends,
+    keys sampled, both paths."""
     desc = {"clip": W.clip_relu_spec(), "gelu": W.gelu_spec(f=8)}[name]
     f = 8
     N = 200
@@ -160,10 +165,10 @@ def test_widest_domains(n, name):
     x = g_.integers(-s, s, size=N).astype(np.int64)
     x[:6] = [-s, s - 1, 0, -1, 1, -(1 << f)]
     x[6:40] = g_.integers(-8 << f, 8 << f, size=34)  # where the pieces change
-    _flush(f"widest domain {name} n={n} N={N}")
+    _flush(f"widest domain {name} n={n} r={r} N={N}")
     for path in ("plain", "fused"):
-        g = gpu_run(desc, n, f, x, 0xD0 + n, path=path)
-        o = oracle_run(desc, n, f, x, 0xD0 + n, np.arange(N))
+        g = gpu_run(desc, n, f, x, 0xD0 + n, path=path, lookup_r=r)
+        o = oracle_run(desc, n, f, x, 0xD0 + n, np.arange(N), r)
         compare(g, o, np.arange(N), N, check_keys=8 if path == "plain" else 0)
 
 
@@ -173,7 +178,7 @@ def test_edge_sizes(N):
     x = op.x[:N]
     _flush(f"edge size N={N}")
     g = gpu_run(op.spec, 16, 8, x, 77, path="fused")
-    o = oracle_run(op.spec, 16, 8, x, 77, np.arange(N))
+    o = oracle_run(op.spec, 16, 8, x, 77, np.arange(N), g["lookup_r"])
     compare(g, o, np.arange(N), N)
 
 
@@ -199,7 +204,7 @@ def test_c2_gelu_full_size_fused():
     assert np.array_equal(R.unpack_bits(g["z0"], N) ^ R.unpack_bits(g["z1"], N), zp)
     rng = np.random.Generator(np.random.PCG64(2))
     elems = np.unique(np.concatenate([rng.integers(0, N, 160), [0, 63, 64, 65, N - 65, N - 64, N - 1]]))
-    o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems)
+    o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems, g["lookup_r"])
     compare(g, o, elems, N, check_keys=4)
 
 
@@ -249,7 +254,7 @@ def test_plain_fused_graph_identical_c3():
     for op, inst, out in zip(ops, insts, plain):
         N = len(op.x)
         elems = np.unique(np.r_[np.arange(0, N, max(1, N // 97)), N - 1])
-        o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems)
+        o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems, inst.spec.lookup_r)
         out["keys0"] = inst.keys[0].cpu().numpy()
         out["keys1"] = inst.keys[1].cpu().numpy()
         compare(out, o, elems, N)
@@ -274,7 +279,7 @@ def test_all_aes_table_layouts_identical():
             assert np.array_equal(cur[k], g2[k])
         if ref is None:
             ref = cur
-            o = oracle_run(op.spec, W.N_BITS, W.F_BITS, x, op.seed, np.arange(0, 5000, 97))
+            o = oracle_run(op.spec, W.N_BITS, W.F_BITS, x, op.seed, np.arange(0, 5000, 97), g["lookup_r"])
             compare(g, o, np.arange(0, 5000, 97), 5000)
         else:
             for k in ref:
@@ -357,7 +362,7 @@ def test_c4_layer_worklist_autotuned_graph(tmp_path):
         N = len(op.x)
         elems = np.unique(np.r_[np.linspace(0, N - 1, 48).astype(np.int64), [63, 64, N - 1]])
         elems = elems[elems < N]
-        o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems)
+        o = oracle_run(op.spec, W.N_BITS, W.F_BITS, op.x, op.seed, elems, inst.spec.lookup_r)
         out["keys0"] = inst.keys[0].cpu().numpy()
         out["keys1"] = inst.keys[1].cpu().numpy()
         compare(out, o, elems, N)

@@ -9,6 +9,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle as O  # noqa: E402
+from paper_2606_09551_amd import fss as F  # noqa: E402
 from paper_2606_09551_amd import serving as S  # noqa: E402
 from paper_2606_09551_amd import workloads as W  # noqa: E402
 
@@ -56,7 +57,7 @@ def test_served_equals_alone_and_oracle():
         y, z, x = mix[rid].outputs[(layer, name)]
         n = len(x)
         elems = np.unique(np.r_[np.linspace(0, n - 1, 24).astype(np.int64), [n - 1]])
-        Sp = O.compile_spec(descs[name], W.N_BITS, W.F_BITS)
+        Sp = O.compile_spec(descs[name], W.N_BITS, W.F_BITS, lookup_r=F.Spec(descs[name]).lookup_r)
         K0, _, r_in, _ = O.keygen(Sp, W.request_dealer_seed(rid, layer, j), elems)
         xhat = x[elems].view(np.uint64) + r_in
         y0, z0 = O.evaluate(0, Sp, K0, xhat)

@@ -104,21 +104,45 @@ def test_and_or_need_postprocessing():
     assert e.value.code == -3
 
 
-def test_key_bytes_shape():
-    """Key size is a function of (spec, n, f, N) only; tiles of 64 elements."""
-    s = F.Spec(W.gelu_spec())
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_key_bytes_shape(r):
+    """Key size is a function of (spec, n, f, N, lookup radix) only; tiles of 64 elements."""
+    s = F.Spec(W.gelu_spec(), lookup_r=r)
+    assert s.lookup_r == r
     per_tile = s.key_bytes(24, 12, 64) - s.key_bytes(24, 12, 0)
     assert per_tile % 256 == 0
     for N in (1, 63, 64, 65, 393216):
         assert s.key_bytes(24, 12, N) == 16384 + ((N + 63) // 64) * per_tile
-    # 3 Z_2 atoms of 24 levels, w shares, then the lookup DCF: root, 12 levels x 4
+    # 3 Z_2 atoms of 24 levels, w shares, then the lookup DCF: root, 24 / r levels x 2^r
     # children of seed (16 B) and p = 3 value corrections, fin, rho and r_out shares
-    expect = (3 * (64 * 16 * 25 + 64 * 8) + 64 * 8 + 64 * 16 + 12 * 4 * 64 * 16 + 12 * 4 * 3 * 64 * 8
+    expect = (3 * (64 * 16 * 25 + 64 * 8) + 64 * 8 + 64 * 16 + (24 // r) * 2**r * 64 * (16 + 3 * 8)
               + 2 * 3 * 64 * 8 + 64 * 8)
     assert per_tile == (expect + 255) // 256 * 256
-    c = F.Spec(W.clip_relu_spec())
-    # n = 16, p = 2: atoms 3 * (17 * 16 + 8), w 8, root 16, 8 levels x 4 x (16 + 16), fin/rho 32, r_out 8
-    assert (c.key_bytes(16, 8, 4096) - 16384) // 4096 == 3 * (17 * 16 + 8) + 8 + 16 + 8 * 4 * 32 + 32 + 8
+    c = F.Spec(W.clip_relu_spec(), lookup_r=r)
+    # n = 16, p = 2: atoms 3 * (17 * 16 + 8), w 8, root 16, ceil(16 / r) levels x 2^r x (16 + 16),
+    # fin/rho 32, r_out 8
+    assert (c.key_bytes(16, 8, 4096) - 16384) // 4096 == \
+        3 * (17 * 16 + 8) + 8 + 16 + (-(-16 // r)) * 2**r * 32 + 32 + 8
+
+
+def test_lookup_radix_setting():
+    """The radix is per spec; shared levels of the lookup points follow it: GELU at
+    n = 24 has its lookup window in 2^16 values, so K = 16 (r = 2, 4) or 18 (r = 3)
+    input bits lie below the shared levels."""
+    s = F.Spec(W.gelu_spec())
+    default = s.lookup_r
+    assert default in (2, 3, 4)
+    for r, depth in ((2, 4), (3, 2), (4, 2)):
+        s2 = F.Spec(W.gelu_spec(), lookup_r=r)
+        q = s2.query(24, 12)
+        assert (q["lookup_r"], q["top_depth"]) == (r, depth)
+    assert s.query(24, 12)["lookup_r"] == default
+    for bad in (0, 1, 5, -2):
+        with pytest.raises(F.FssError) as e:
+            F.Spec(W.gelu_spec(), lookup_r=bad)
+        assert e.value.code == -8
+    # clip-ReLU has m = 3: no shared levels at any radix
+    assert F.Spec(W.clip_relu_spec(), lookup_r=3).query(16, 8)["top_depth"] == 0
 
 
 def test_argument_errors():
