@@ -126,6 +126,7 @@ typedef struct {
   int32_t atom_is_mask[FSS_MAX_ATOMS]; /* 1: the 1[view < r_k] atom of its view */
   int32_t lookup_r;  /* input bits per level of call 2's DCF */
   int32_t top_depth; /* its levels walked once per block of lookup points */
+  int32_t top_blocks; /* aligned blocks of lookup points that share them */
 } fss_spec_info;
 
 /* Quantise at (n_bits, frac_bits) and report the shape and integer tables.

@@ -272,20 +272,33 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
   uint32_t kmax = 0;
   for (int t = 0; t < q->T; ++t) kmax = std::max(kmax, q->atom_k[t]);
   h.kmax = kmax;
-  // Lookup points u_i = (v - a'_i) mod 2^n span W = a'_{m-1} - a'_1 + 1
-  // consecutive values; with 2^K >= W they meet at most two aligned blocks of
-  // 2^K values, whose first levels are shared.  The lookup DCF walks
-  // rL = r ceil(n / r) bits, r per level, so K is raised to a multiple of r
-  // and the shared levels are (rL - K) / r; they need K < n (at least two
-  // blocks).  Worth it when m >= 4.
+  // Lookup points u_i = (v - a'_i) mod 2^n span a cyclic window of
+  // W = a'_{m-1} - a'_1 + 1 consecutive values, which meets at most
+  // B = ceil((W - 1) / 2^K) + 1 aligned blocks of 2^K values.  The lookup DCF
+  // walks rL = r ceil(n / r) bits, r per level; with K a multiple of r the
+  // first D = L - K / r levels of every point in a block are that block's, so
+  // they are walked once per block (B walks) instead of once per point.  K is
+  // chosen to minimise the AES blocks of the walks, B <= kMaxTopBlocks,
+  // K < n; no sharing (D = 0) when m < 4 or nothing is saved.
   h.lookup_r = (uint32_t)r;
   {
     const uint64_t W = (m >= 2) ? (q->aprime[m - 1] - q->aprime[1] + 1) : 1;
     const int L = (n + r - 1) / r;
-    int K = 0;
-    while (K < n && ((uint64_t)1 << K) < W) ++K;
-    K = (K + r - 1) / r * r;
-    h.top_depth = (m >= 4 && K < n) ? (uint32_t)(L - K / r) : 0u;
+    const double lvl = 1 + (q->p + 1) / 2, points = m - 1;
+    double best = points * L * lvl;  // D = 0
+    h.top_depth = 0;
+    h.top_blocks = 0;
+    for (int K = r; m >= 4 && K < n; K += r) {
+      const uint64_t B = (W <= 1 ? 0 : (W - 2) >> K) + 1 + (W > 1 ? 1 : 0);  // ceil((W-1)/2^K) + 1
+      if (B > (uint64_t)kMaxTopBlocks || B > ((uint64_t)1 << (n - K))) continue;
+      const int D = L - K / r;
+      const double cost = (double)B * D * lvl + points * (L - D) * lvl;
+      if (cost < best) {
+        best = cost;
+        h.top_depth = (uint32_t)D;
+        h.top_blocks = (uint32_t)B;
+      }
+    }
   }
   h.tile_bytes = q->layout.tile_bytes;
   h.spec_hash = S->hash;
@@ -463,6 +476,7 @@ int fss_spec_query(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, fss_
     info->out_frac_bits = q->F_out; info->T = q->T; info->ell = q->ell;
     info->lookup_r = (int32_t)q->hdr.lookup_r;
     info->top_depth = (int32_t)q->hdr.top_depth;
+    info->top_blocks = (int32_t)q->hdr.top_blocks;
     for (int t = 0; t < q->T; ++t) {
       info->atom_k[t] = (int32_t)q->atom_k[t];
       info->atom_c[t] = (int64_t)q->atom_c[t];
@@ -693,8 +707,8 @@ ElemCost elem_cost(const KeyHeader& h) {
   const double L = (double)((h.n + h.lookup_r - 1) / h.lookup_r), D = h.top_depth;
   c.aes_base = L * lvl + nb;
   c.lk_base = L * shared(lvl) + shared(nb);
-  c.aes_tops = 2 * D * lvl;
-  c.lk_tops = 2 * D * shared(lvl);
+  c.aes_tops = h.top_blocks * D * lvl;
+  c.lk_tops = h.top_blocks * D * shared(lvl);
   c.aes_point = (L - D) * lvl + nb;
   c.lk_point = (L - D) * shared(lvl) + shared(nb);
   c.points = (int)h.m - 1;
@@ -791,7 +805,8 @@ int read_header(const void* keys, KeyHeader* h) {
   HIP_TRY(hipMemcpyAsync(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(header)");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(header)");
   if (h->magic != kMagic || h->version != kVersion) return fail(FSS_E_SHAPE, "not a key buffer");
-  if (h->lookup_r < 2 || h->lookup_r > 4 || h->rec_bytes != 16 + 8 * (uint64_t)h->p)
+  if (h->lookup_r < 2 || h->lookup_r > 4 || h->rec_bytes != 16 + 8 * (uint64_t)h->p ||
+      (h->top_depth > 0 && (h->top_blocks < 2 || h->top_blocks > (uint32_t)kMaxTopBlocks)))
     return fail(FSS_E_SHAPE, "key buffer with an unknown lookup layout");
   return FSS_OK;
 }

@@ -92,19 +92,21 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
 constexpr int kMaxP = 4;
 constexpr int kDefaultLookupR = 3;  // input bits per lookup-DCF level unless a spec sets it
+constexpr int kMaxTopBlocks = 4;    // top walks shared by the lookup points
 constexpr uint64_t kHeaderBytes = 16384;
 
 struct KeyHeader {
   uint32_t magic, version, party, layout;
   uint32_t n, f, m, d, p, T, ell, F_out;
   uint32_t n_prim, n_views, kmax, top_depth;  // top_depth: shared lookup-DCF levels of the lookup points
-  uint32_t lookup_r, reserved0;            // lookup_r: input bits per lookup-DCF level (2, 3 or 4)
+  uint32_t lookup_r;                       // input bits per lookup-DCF level (2, 3 or 4)
+  uint32_t top_blocks;                     // aligned blocks of lookup points walked through the shared levels (2..4)
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];

@@ -407,17 +407,6 @@ __device__ __forceinline__ VState<P> vroot(GHdr h, const uint8_t* tile, int lane
   return st;
 }
 
-template <int P>
-__device__ __forceinline__ VState<P> vselect(bool c, const VState<P>& a, const VState<P>& b) {
-  VState<P> r;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) r.s[k] = c ? a.s[k] : b.s[k];
-  r.t = c ? a.t : b.t;
-#pragma unroll
-  for (int q = 0; q < P; ++q) r.V[q] = c ? a.V[q] : b.V[q];
-  return r;
-}
-
 // Advance `st` through levels [i0, i1) of the lookup DCF along the base-2^R
 // digits of the input x: the DCF has L = ceil(n / R) levels of 2^R children
 // and level i consumes digit L - 1 - i (R L - n leading zero bits).
@@ -487,11 +476,15 @@ __device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* t
 // Then y = sum_j q_j xhat^j.  (Ring arithmetic mod 2^64: any order is exact.)
 //
 // Shared prefixes: the points u_1 > ... > u_{m-1} (cyclically) lie in a window
-// of W = a'_{m-1} - a'_1 + 1 consecutive values, which meets at most two
-// aligned blocks of 2^K >= W values.  With K = 2L - 2D the first D levels of
-// the lookup DCF are walked once per block (A, the block of u_{m-1}, and its
-// successor B, modulo the 2^(n-K) blocks of the n-bit domain) and each point
-// resumes from its block's state: same outputs, (m - 3) * D fewer levels.
+// of W = a'_{m-1} - a'_1 + 1 consecutive values, which meets at most
+// B = top_blocks aligned blocks of 2^K values (K = R (L - D)): block A (that
+// of u_{m-1}) and its B - 1 successors, modulo the 2^(n-K) blocks of the
+// n-bit domain.  The first D levels of the lookup DCF are walked once per
+// block and each point resumes from its block's seed and control bit.  The
+// partial sum V of a block's walk is the same for all its points, so it
+// enters q right after that walk (q += tab_i V for each point i of the
+// block) and only the seeds stay live: same outputs, (m - 1 - B) D fewer
+// levels than walking every point from the root.
 //
 // Every term of q, and so of y = sum_j q_j xhat^j, is linear: a tile's work can
 // be split into parts that each return their share of y (mod 2^64).  This call
@@ -509,21 +502,57 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   const uint32_t v = ((uint32_t)xhat + half) & Nmask;
   const uint8_t* rhop = tile + h->off_crho + lane * 8;
   const int K = D > 0 ? R * (L - D) : 0;  // input bits below the shared levels (D > 0: R <= K < n)
+  const int NT = D > 0 ? (int)h->top_blocks : 0;
   const uint32_t blk_mask = D > 0 ? (1u << (n - K)) - 1u : 0u;
   const uint32_t blkA = D > 0 ? (((v - (uint32_t)h->aprime[m - 1]) & Nmask) >> K) : 0u;
-  const uint32_t blkB = (blkA + 1u) & blk_mask;
   uint64_t q[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) q[k] = 0;
-  VState<P> sa = vroot<P>(h, tile, lane, b), sb = sa;
-  if (D > 0 && iend > i0) {
-    vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkA << K), 0, D, sa);
-    vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)blkB << K), 0, D, sb);
+  const VState<P> root = vroot<P>(h, tile, lane, b);
+  // seed (words 0..3) and control bit (word 4) of each block after the shared levels
+  uint32_t ts[kMaxTopBlocks][5];
+#pragma unroll
+  for (int c = 0; c < kMaxTopBlocks; ++c) {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) ts[c][w] = root.s[w];
+    ts[c][4] = root.t;
+  }
+  if (iend > i0) {
+#pragma unroll 1
+    for (int bk = 0; bk < NT; ++bk) {
+      VState<P> st = root;
+      vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)((blkA + (uint32_t)bk) & blk_mask) << K), 0, D, st);
+#pragma unroll
+      for (int c = 0; c < kMaxTopBlocks; ++c)
+        if (c == bk) {
+#pragma unroll
+          for (int w = 0; w < 4; ++w) ts[c][w] = st.s[w];
+          ts[c][4] = st.t;
+        }
+      for (int i = i0; i < iend; ++i) {
+        const uint32_t u = (v - (uint32_t)h->aprime[i]) & Nmask;
+        const uint64_t in = ((((u >> K) - blkA) & blk_mask) == (uint32_t)bk) ? ~0ull : 0ull;
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+#pragma unroll
+          for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * (st.V[k] & in);
+      }
+    }
   }
   for (int i = i0; i < iend; ++i) {
     const uint32_t ap = (uint32_t)h->aprime[i];
     const uint32_t u = (v - ap) & Nmask;
-    VState<P> st = vselect<P>((u >> K) == blkA, sa, sb);  // D = 0: both are the root
+    const uint32_t off = ((u >> K) - blkA) & blk_mask;  // D = 0: every block holds the root
+    VState<P> st;
+#pragma unroll
+    for (int w = 0; w < 5; ++w) {
+      uint32_t x = ts[0][w];
+#pragma unroll
+      for (int c = 1; c < kMaxTopBlocks; ++c) x = off == (uint32_t)c ? ts[c][w] : x;
+      if (w < 4) st.s[w] = x; else st.t = x;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) st.V[k] = 0;
     vec_walk<P, R>(tb, h, tile, lane, b, u, D, L, st);
     uint64_t g[P];
     vec_final<P, R>(tb, h, tile, lane, b, st, g);

@@ -58,7 +58,7 @@ class SpecInfo(C.Structure):
                 ("degree", C.c_int32), ("p", C.c_int32), ("out_frac_bits", C.c_int32),
                 ("T", C.c_int32), ("ell", C.c_int32), ("atom_k", C.c_int32 * MAX_ATOMS),
                 ("atom_c", C.c_int64 * MAX_ATOMS), ("atom_is_mask", C.c_int32 * MAX_ATOMS),
-                ("lookup_r", C.c_int32), ("top_depth", C.c_int32)]
+                ("lookup_r", C.c_int32), ("top_depth", C.c_int32), ("top_blocks", C.c_int32)]
 
 
 class WorkItem(C.Structure):
@@ -196,7 +196,7 @@ class Spec:
                 "F_out": info.out_frac_bits, "T": info.T, "ell": info.ell,
                 "atom_k": list(info.atom_k[:info.T]), "atom_c": list(info.atom_c[:info.T]),
                 "atom_is_mask": list(info.atom_is_mask[:info.T]),
-                "lookup_r": info.lookup_r, "top_depth": info.top_depth,
+                "lookup_r": info.lookup_r, "top_depth": info.top_depth, "top_blocks": info.top_blocks,
                 "aprime": list(ap), "coef": [[co[i * p + l] for l in range(p)] for i in range(m)]}
 
     def key_bytes(self, n_bits: int, frac_bits: int, n_elems: int) -> int:

@@ -126,16 +126,21 @@ def test_key_bytes_shape(r):
 
 
 def test_lookup_radix_setting():
-    """The radix is per spec; shared levels of the lookup points follow it: GELU at
-    n = 24 has its lookup window in 2^16 values, so K = 16 (r = 2, 4) or 18 (r = 3)
-    input bits lie below the shared levels."""
+    """The radix is per spec; the shared levels of the lookup points follow it.
+    GELU at n = 24, f = 12: the 17 lookup points span W = 16 * 3072 + 1 values.
+    Cost of the walks in levels, K bits below the shared levels (a multiple of
+    r), B = ceil((W - 1) / 2^K) + 1 blocks, D = 24 / r - K / r shared levels:
+    B D + 17 (24 / r - D).  r = 2: K = 14 gives B = 4, D = 5 (20 + 119 = 139
+    against K = 16: 8 + 136); r = 3: K = 15 gives B = 3, D = 3 (9 + 85 against
+    K = 18: 4 + 102); r = 4: K = 16 gives B = 2, D = 2 (K = 12 would need 13
+    blocks)."""
     s = F.Spec(W.gelu_spec())
     default = s.lookup_r
     assert default in (2, 3, 4)
-    for r, depth in ((2, 4), (3, 2), (4, 2)):
+    for r, depth, blocks in ((2, 5, 4), (3, 3, 3), (4, 2, 2)):
         s2 = F.Spec(W.gelu_spec(), lookup_r=r)
         q = s2.query(24, 12)
-        assert (q["lookup_r"], q["top_depth"]) == (r, depth)
+        assert (q["lookup_r"], q["top_depth"], q["top_blocks"]) == (r, depth, blocks)
     assert s.query(24, 12)["lookup_r"] == default
     for bad in (0, 1, 5, -2):
         with pytest.raises(F.FssError) as e:
