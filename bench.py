@@ -52,13 +52,14 @@ def pct(xs, q):
 def keygen_aes_per_elem(inst) -> int:
     """Dealer AES blocks per element: both parties' children of every Z_2 DCF
     level (2 each), of every lookup-DCF level (2^r children of 1 + ceil(p/2)
-    blocks each, L = ceil(n/r) levels) and the leaf conversions, plus the
-    counter-mode randomness (1 + ceil(p/2) blocks per lookup level)."""
+    blocks each, L = ceil(n/r) levels, the last level's children without
+    their seed block), plus the counter-mode randomness (1 + ceil(p/2) blocks
+    per lookup level above the last)."""
     nb = (inst.p + 1) // 2
     r = inst.lookup_r
     L = -(-inst.n_bits // r)
-    prg = sum(4 * k for k in inst.atom_k) + 2 * L * (1 << r) * (1 + nb) + 2 * nb
-    rand = 2 * inst.T + 7 + L * (1 + nb)
+    prg = sum(4 * k for k in inst.atom_k) + 2 * (1 << r) * ((L - 1) * (1 + nb) + nb)
+    rand = 2 * inst.T + 7 + (L - 1) * (1 + nb)
     return prg + rand
 
 

@@ -50,7 +50,7 @@ MAXC = 16                # children per level at r = 4
 class DcfRKey(C.Structure):
     _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("r", C.c_int32), ("root", Blk),
                 ("scw", (Blk * MAXC) * MAXLR), ("tcw", (C.c_uint8 * MAXC) * MAXLR),
-                ("vcw", ((C.c_uint64 * MAXP) * MAXC) * MAXLR), ("fin", C.c_uint64 * MAXP)]
+                ("vcw", ((C.c_uint64 * MAXP) * MAXC) * MAXLR)]
 
 
 class ElemKey(C.Structure):
@@ -189,7 +189,7 @@ def dcf_eval(b: int, key: DcfKey, x: int):
 
 def dcfr_gen(n: int, r: int, p: int, alpha: int, beta, root0, root1, keep_rand):
     """2^r children per level.  keep_rand: (ceil(n/r) * (1 + ceil(p/2))) (lo, hi)
-    blocks, the on-path child's corrections level by level."""
+    blocks, the on-path child's corrections level by level (the last level's unused)."""
     b = (C.c_uint64 * MAXP)(*([int(v) & (2**64 - 1) for v in (beta if p else [beta])]))
     kr = (Blk * max(1, len(keep_rand)))(*[Blk(lo, hi) for lo, hi in keep_rand])
     k0, k1 = DcfRKey(), DcfRKey()

@@ -356,18 +356,6 @@ static void expand_r(int r, int p, orc_blk s, int c, orc_blk* s_out, int* t_out,
   }
 }
 
-static void convert_r(int r, int p, orc_blk s, uint64_t* out) {
-  if (p == 0) {
-    out[0] = (s.lo >> 2) & 1;
-  } else {
-    uint64_t w[4];
-    orc_blk a = orc_prg(s, 3 * (1 << r));
-    w[0] = a.lo; w[1] = a.hi;
-    if (p > 2) { orc_blk b = orc_prg(s, 3 * (1 << r) + 1); w[2] = b.lo; w[3] = b.hi; }
-    for (int k = 0; k < p; k++) out[k] = w[k];
-  }
-}
-
 /* Base-2^r digit i (most significant first) of x over `levels` digits. */
 static int digit_r(int r, uint64_t x, int levels, int i) {
   return (int)((x >> (r * (levels - 1 - i))) & (((uint64_t)1 << r) - 1));
@@ -396,10 +384,16 @@ void orc_dcfr_gen(int n, int r, int p, uint64_t alpha, const uint64_t* beta, orc
     for (int b = 0; b < 2; b++)
       for (int c = 0; c < C; c++) expand_r(r, p, s[b], c, &sc[b][c], &tc[b][c], vc[b][c]);
     const orc_blk* kr = keep_rand + (size_t)i * nr;
+    const int last = (i == levels - 1);
     for (int c = 0; c < C; c++) {
       orc_blk scw;
       uint64_t vcw[ORC_MAXP];
-      if (c != a) {
+      /* Below the last level nothing is walked: there every child, alpha's
+       * included, takes the equalising value correction (alpha's without
+       * beta), which brings the reconstructed sum at x = alpha to zero, so no
+       * leaf conversion or final correction is needed; the last level's seed
+       * and control-bit corrections would never be used and are zero. */
+      if (c != a || last) {
         /* the parties' children become equal: seeds, control bits and, for
          * the value, V_CW = (-1)^{t1} (v1^c - v0^c - V_alpha [+ beta if c < a]) */
         scw.lo = sc[0][c].lo ^ sc[1][c].lo;
@@ -421,7 +415,8 @@ void orc_dcfr_gen(int n, int r, int p, uint64_t alpha, const uint64_t* beta, orc
           for (int k = 0; k < p; k++) vcw[k] = w[k];
         }
       }
-      const int tcw = tc[0][c] ^ tc[1][c] ^ (c == a);
+      const int tcw = last ? 0 : tc[0][c] ^ tc[1][c] ^ (c == a);
+      if (last) scw.lo = scw.hi = 0;
       k0->scw[i][c] = k1->scw[i][c] = scw;
       k0->tcw[i][c] = k1->tcw[i][c] = (uint8_t)tcw;
       for (int k = 0; k < glen(p); k++) k0->vcw[i][c][k] = k1->vcw[i][c][k] = vcw[k];
@@ -441,14 +436,6 @@ void orc_dcfr_gen(int n, int r, int p, uint64_t alpha, const uint64_t* beta, orc
       t[b] = nt;
     }
   }
-  /* CW_final = (-1)^{t1} (Convert(s1) - Convert(s0) - V_alpha) */
-  uint64_t c0[ORC_MAXP], c1[ORC_MAXP];
-  convert_r(r, p, s[0], c0);
-  convert_r(r, p, s[1], c1);
-  g_sub(p, c1, c0);
-  g_sub(p, c1, Va);
-  g_sign(p, t[1], c1);
-  for (int k = 0; k < glen(p); k++) k0->fin[k] = k1->fin[k] = c1[k];
 }
 
 void orc_dcfr_eval(int b, const orc_dcfr_key* k, uint64_t x, uint64_t* out) {
@@ -475,10 +462,6 @@ void orc_dcfr_eval(int b, const orc_dcfr_key* k, uint64_t x, uint64_t* out) {
     s = ns;
     t = nt;
   }
-  convert_r(r, p, s, tmp);
-  if (t) g_add(p, tmp, k->fin);
-  g_sign(p, b, tmp);
-  g_add(p, V, tmp);
   for (int q = 0; q < glen(p); q++) out[q] = V[q];
 }
 
@@ -667,10 +650,11 @@ void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
   for (int k = 1; k < S->p; k++) rho[k] = rho[k - 1] * ((uint64_t)0 - r_in);
   orc_blk c0 = orc_rand(kseed, e, 64, 0);
   orc_blk c1 = orc_rand(kseed, e, 65, 0);
-  /* the on-path child's corrections at level i: R(e, 69 + k, i) */
+  /* the on-path child's corrections at level i < L - 1: R(e, 69 + k, i) */
   orc_blk kr[ORC_MAXLR * 3];
+  memset(kr, 0, sizeof kr);
   const int levels = (S->n + S->lookup_r - 1) / S->lookup_r, nr = 1 + (S->p + 1) / 2;
-  for (int i = 0; i < levels; i++)
+  for (int i = 0; i + 1 < levels; i++)
     for (int k = 0; k < nr; k++) kr[i * nr + k] = orc_rand(kseed, e, 69 + k, i);
   orc_dcfr_gen(S->n, S->lookup_r, S->p, r_in & lowmask(S->n), rho, c0, c1, kr, &k0->coeff, &k1->coeff);
   orc_blk ra = orc_rand(kseed, e, 67, 0), rb = orc_rand(kseed, e, 68, 0);

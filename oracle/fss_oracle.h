@@ -71,11 +71,15 @@ void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out);
  * control-bit and value correction for each child.  For a child off alpha's
  * path they are the corrections above (with beta entering when that child's
  * digit is below alpha's); for the child on the path they are fresh dealer
- * randomness (`keep_rand`, 1 + ceil(p/2) blocks per level), so the key does
- * not show which child alpha takes.  The input is walked as r * ceil(n / r)
- * bits with leading zeros.  Child c of seed s is H(s, c) (seed and control
- * bit), its value the first p words of H(s, 2^r + 2c + k), and Convert(s)
- * the first p words of H(s, 3 * 2^r + k). */
+ * randomness (`keep_rand`, 1 + ceil(p/2) blocks per level, the last level's
+ * unused), so the key does not show which child alpha takes.  At the last
+ * level alpha's child gets the equalising value correction as well (without
+ * beta): it cancels the sum along alpha's path, so there is no leaf
+ * conversion and no final correction; the last level's seed and control-bit
+ * corrections are never used and are zero.  The input is walked as
+ * r * ceil(n / r) bits with leading zeros.  Child c of seed s is H(s, c)
+ * (seed and control bit) and its value the first p words of
+ * H(s, 2^r + 2c + k). */
 #define ORC_MAXLR ((ORC_MAXN + 1) / 2) /* levels at r = 2 */
 #define ORC_MAXC 16                    /* children at r = 4 */
 typedef struct {
@@ -84,7 +88,6 @@ typedef struct {
   orc_blk scw[ORC_MAXLR][ORC_MAXC];            /* seed corrections (bits 0..1 zero) */
   uint8_t tcw[ORC_MAXLR][ORC_MAXC];            /* control-bit corrections */
   uint64_t vcw[ORC_MAXLR][ORC_MAXC][ORC_MAXP]; /* value corrections */
-  uint64_t fin[ORC_MAXP];
 } orc_dcfr_key;
 
 void orc_dcfr_gen(int n, int r, int p, uint64_t alpha, const uint64_t* beta, orc_blk root0, orc_blk root1,

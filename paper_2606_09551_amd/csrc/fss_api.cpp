@@ -314,7 +314,6 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
   h.off_croot = q->layout.off_croot;
   h.off_crec = q->layout.off_crec;
   h.rec_bytes = q->layout.rec_bytes;
-  h.off_cfin = q->layout.off_cfin;
   h.off_crho = q->layout.off_crho;
   h.off_crout = q->layout.off_crout;
   for (int i = 0; i <= m; ++i) h.aprime[i] = q->aprime[i];
@@ -705,12 +704,12 @@ ElemCost elem_cost(const KeyHeader& h) {
   // the lookup DCF has L = ceil(n / r) levels of 2^r children; D of them shared
   const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb;
   const double L = (double)((h.n + h.lookup_r - 1) / h.lookup_r), D = h.top_depth;
-  c.aes_base = L * lvl + nb;
-  c.lk_base = L * shared(lvl) + shared(nb);
+  c.aes_base = L * lvl;
+  c.lk_base = L * shared(lvl);
   c.aes_tops = h.top_blocks * D * lvl;
   c.lk_tops = h.top_blocks * D * shared(lvl);
-  c.aes_point = (L - D) * lvl + nb;
-  c.lk_point = (L - D) * shared(lvl) + shared(nb);
+  c.aes_point = (L - D) * lvl;
+  c.lk_point = (L - D) * shared(lvl);
   c.points = (int)h.m - 1;
   return c;
 }

@@ -81,7 +81,7 @@ constexpr AesConst kAes = make_aes_const();
 //   atom t : root[64] (16 B) | cw[k_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
 //            | vbits[64] (u64: bit i = value corr. of level i, bit 32 = final)
 //   wshare[64] (u64: bit j = this party's share of the carry of output j)
-//   coeff  : root[64] | rec[L][2^r][64] | fin[p][64]
+//   coeff  : root[64] | rec[L][2^r][64]
 //            | rho[p][64] (share of rho) | rout[64] (share of r_out)
 //   The lookup's vector DCF takes r input bits per level (2^r children), so
 //   it has L = ceil(n / r) levels with corrections for each child.  A record
@@ -92,7 +92,7 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 4;
+constexpr uint32_t kVersion = 5;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -114,7 +114,7 @@ struct KeyHeader {
   uint32_t atom_rview[kMaxAtoms];          // theta atoms: index of their view's mask atom
   uint64_t atom_c[kMaxAtoms];              // view shift
   uint64_t atom_off[kMaxAtoms];            // byte offset of the atom section in a tile
-  uint64_t off_w, off_croot, off_crec, rec_bytes, off_cfin, off_crho, off_crout;  // rec_bytes = 16 + 8 p
+  uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;  // rec_bytes = 16 + 8 p
   uint64_t aprime[kMaxM + 1];              // offset-binary boundaries
   // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
   // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
@@ -125,7 +125,7 @@ static_assert(sizeof(KeyHeader) <= kHeaderBytes, "header too large");
 
 struct Layout {
   uint64_t atom_off[kMaxAtoms];
-  uint64_t off_w, off_croot, off_crec, rec_bytes, off_cfin, off_crho, off_crout;
+  uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;
   uint64_t tile_bytes;
 };
 
@@ -141,7 +141,6 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p, in
   const uint64_t levels = (uint64_t)(n + r - 1) / r;  // 2^r children per level
   L.rec_bytes = 16 + 8 * (uint64_t)p;       // seed correction, then p value corrections
   L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
-  L.off_cfin = o;  o += (uint64_t)p * kTile * 8;
   L.off_crho = o;  o += (uint64_t)p * kTile * 8;
   L.off_crout = o; o += kTile * 8;
   L.tile_bytes = (o + 255) & ~(uint64_t)255;

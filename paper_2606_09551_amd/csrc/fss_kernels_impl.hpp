@@ -411,6 +411,8 @@ __device__ __forceinline__ VState<P> vroot(GHdr h, const uint8_t* tile, int lane
 // digits of the input x: the DCF has L = ceil(n / R) levels of 2^R children
 // and level i consumes digit L - 1 - i (R L - n leading zero bits).
 // Child d of seed s is H(s, d), its value the first P words of H(s, 2^R + 2d + k).
+// The last level adds the child's value only: nothing is walked below it, so
+// its seed and control bit (the block H(s, d)) are not computed.
 template <int P, int R, class TB>
 __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
                                          uint32_t x, int i0, int i1, VState<P>& st) {
@@ -419,7 +421,8 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
   const int L = ((int)h->n + R - 1) / R;
   constexpr uint64_t REC = 16 + 8 * P;
   const uint8_t* recp = tile + h->off_crec + lane * REC;
-  for (int i = i0; i < i1; ++i) {
+  const int imid = i1 < L - 1 ? i1 : L - 1;
+  for (int i = i0; i < imid; ++i) {
     const uint32_t d = (x >> (R * (L - 1 - i))) & (C - 1u);
     uint32_t jj[1 + NB], o[1 + NB][4];
     jj[0] = d;
@@ -444,24 +447,20 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
       st.V[q] += b ? (0ull - v) : v;
     }
   }
-}
-
-// Leaf value: V + (-1)^b (Convert(s) + t * CW_fin), Convert(s) = the first
-// P words of H(s, 3 * 2^R) || H(s, 3 * 2^R + 1).
-template <int P, int R, class TB>
-__device__ __forceinline__ void vec_final(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
-                                          const VState<P>& st, uint64_t (&out)[P]) {
-  constexpr int NB = (P + 1) / 2;
-  uint32_t jj[NB], o[NB][4];
+  if (i1 == L && i0 < L) {  // the last level: the child's value corrections only
+    const uint32_t d = x & (C - 1u);
+    uint32_t jj[NB], o[NB][4];
 #pragma unroll
-  for (int q = 0; q < NB; ++q) jj[q] = 3u * (1u << R) + q;
-  prg_shared<TB, NB>(tb, st.s, jj, o);
-  const uint64_t msk64 = 0ull - (uint64_t)st.t;
+    for (int k = 0; k < NB; ++k) jj[k] = C + 2u * d + k;
+    prg_shared<TB, NB>(tb, st.s, jj, o);
+    const uint8_t* rp = recp + ((uint64_t)(L - 1) * C + d) * kTile * REC;
+    const uint64_t msk64 = 0ull - (uint64_t)st.t;
 #pragma unroll
-  for (int q = 0; q < P; ++q) {
-    uint64_t c = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
-    c += ld8(tile + h->off_cfin + ((uint64_t)q * kTile + lane) * 8) & msk64;
-    out[q] = st.V[q] + (b ? (0ull - c) : c);
+    for (int q = 0; q < P; ++q) {
+      uint64_t v = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
+      v += ld8(rp + 16 + 8 * q) & msk64;
+      st.V[q] += b ? (0ull - v) : v;
+    }
   }
 }
 
@@ -554,11 +553,10 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
 #pragma unroll
     for (int k = 0; k < P; ++k) st.V[k] = 0;
     vec_walk<P, R>(tb, h, tile, lane, b, u, D, L, st);
-    uint64_t g[P];
-    vec_final<P, R>(tb, h, tile, lane, b, st, g);
     const uint64_t lt = v < ap ? ~0ull : 0ull;
+    uint64_t g[P];
 #pragma unroll
-    for (int k = 0; k < P; ++k) g[k] += ld8(rhop + (uint64_t)k * kTile * 8) & lt;
+    for (int k = 0; k < P; ++k) g[k] = st.V[k] + (ld8(rhop + (uint64_t)k * kTile * 8) & lt);
 #pragma unroll
     for (int j = 0; j < P; ++j)
 #pragma unroll
@@ -567,12 +565,10 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   if (base) {
     VState<P> st = vroot<P>(h, tile, lane, b);
     vec_walk<P, R>(tb, h, tile, lane, b, v, 0, L, st);
-    uint64_t Dv[P];
-    vec_final<P, R>(tb, h, tile, lane, b, st, Dv);
 #pragma unroll
     for (int j = 0; j < P; ++j)
 #pragma unroll
-      for (int k = 0; j + k < P; ++k) q[j] -= h->tabv[j][k] * Dv[k];
+      for (int k = 0; j + k < P; ++k) q[j] -= h->tabv[j][k] * st.V[k];
 #pragma unroll
     for (int j = 0; j < P; ++j)
 #pragma unroll
@@ -808,12 +804,13 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
 }
 
 // Vector DCF Gen for f(x) = beta * 1[x < alpha] over n bits, beta in Z^P,
-// with four children per level (L = ceil(n / 2) levels, base-4 digits of
-// alpha).  At every level both parties expand all four children; for the
+// with 2^R children per level (L = ceil(n / R) levels, base-2^R digits of
+// alpha).  At every level both parties expand all 2^R children; for a
 // child off alpha's path the corrections make the parties' children equal:
 // seed XOR, control bits t0 ^ t1, V_CW = (-1)^{t_1} (v_1 - v_0 - V_alpha
-// [+ beta below alpha's digit]).  Alpha's child gets random corrections
-// R(e, 69 + k, level), carries the parties on, and updates V_alpha.
+// [+ beta below alpha's digit]).  Above the last level alpha's child gets
+// random corrections R(e, 69 + k, level), carries the parties on, and
+// updates V_alpha; at the last level it is corrected like the others.
 template <int P, int R, class TB>
 __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t alpha,
                                         const uint64_t (&beta)[P], const uint32_t (&r0)[4],
@@ -825,7 +822,6 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
   // would wait for the store to complete.
   constexpr uint64_t REC = 16 + 8 * P;
   const uint64_t off_croot = h->off_croot, off_crec = h->off_crec;
-  const uint64_t off_cfin = h->off_cfin;
   constexpr uint32_t C = 1u << R;
   const int L = (n + R - 1) / R;
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
@@ -844,6 +840,38 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
     uint64_t dk[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) dk[q] = 0;
+    if (i + 1 == L) {
+      // The last level: value corrections only.  Alpha's child is corrected
+      // like the others (without beta), which zeroes the sum along alpha's
+      // path, so there is no leaf conversion or final correction; nothing is
+      // walked below this level, so its seed and control-bit corrections are
+      // zero and the children's seeds are not computed.
+#pragma unroll 1
+      for (uint32_t c = 0; c < C; ++c) {
+        uint32_t o0[NB][4], o1[NB][4], jj[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) jj[k] = C + 2u * c + k;
+        prg_shared<TB, NB>(tb, s[0], jj, o0);
+        prg_shared<TB, NB>(tb, s[1], jj, o1);
+        const uint64_t ro = off_crec + (((uint64_t)i * C + c) * kTile + lane) * REC;
+        st8(k0 + ro, 0ull);
+        st8(k0 + ro + 8, 0ull);
+        if (k1) {
+          st8(k1 + ro, 0ull);
+          st8(k1 + ro + 8, 0ull);
+        }
+        const uint64_t below = c < a ? ~0ull : 0ull;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+          const uint64_t v0 = mk64(o0[q / 2][2 * (q & 1)], o0[q / 2][2 * (q & 1) + 1]);
+          const uint64_t v1 = mk64(o1[q / 2][2 * (q & 1)], o1[q / 2][2 * (q & 1) + 1]);
+          const uint64_t w = v1 - v0 - Va[q] + (beta[q] & below);
+          st8(k0 + ro + 16 + 8 * q, (w ^ neg) - neg);
+          if (k1) st8(k1 + ro + 16 + 8 * q, (w ^ neg) - neg);
+        }
+      }
+      break;
+    }
 #pragma unroll 1
     for (uint32_t c = 0; c < C; ++c) {
       uint32_t o0[1 + NB][4], o1[1 + NB][4], jj[1 + NB];
@@ -920,26 +948,6 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
       for (int w = 0; w < 4; ++w) s[b][w] = ks[b][w] ^ (scw_a[w] & m);
       t[b] = kt[b] ^ (t[b] & tcw_a);
     }
-  }
-  // CW_fin = (-1)^{t_1} (Convert(s_1) - Convert(s_0) - V_alpha), Convert = H(s, 3 * 2^R + k)
-  uint64_t cv[2][P];
-#pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    uint32_t o[NB][4], jj[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) jj[q] = 3u * C + q;
-    prg_shared<TB, NB>(tb, s[b], jj, o);
-#pragma unroll
-    for (int q = 0; q < P; ++q) cv[b][q] = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
-  }
-  const uint64_t neg = 0ull - (uint64_t)t[1];
-#pragma unroll
-  for (int q = 0; q < P; ++q) {
-    const uint64_t w = cv[1][q] - cv[0][q] - Va[q];
-    const uint64_t f = (w ^ neg) - neg;
-    const uint64_t fo = off_cfin + ((uint64_t)q * kTile + lane) * 8;
-    st8(k0 + fo, f);
-    if (k1) st8(k1 + fo, f);
   }
 }
 

@@ -15,7 +15,7 @@ HDR = np.dtype([
     ("spec_hash", "<u8"), ("negate", "<u8"), ("atom_k", "<u4", MAXA), ("atom_out", "<u4", MAXA),
     ("atom_rview", "<u4", MAXA), ("atom_c", "<u8", MAXA), ("atom_off", "<u8", MAXA),
     ("off_w", "<u8"), ("off_croot", "<u8"), ("off_crec", "<u8"), ("rec_bytes", "<u8"),
-    ("off_cfin", "<u8"), ("off_crho", "<u8"), ("off_crout", "<u8"),
+    ("off_crho", "<u8"), ("off_crout", "<u8"),
     ("aprime", "<u8", MAXM + 1), ("tab", "<u8", (MAXM, MAXP, MAXP)), ("tabv", "<u8", (MAXP, MAXP)),
 ])
 
@@ -62,13 +62,12 @@ class KeyView:
         recs = [[tb + int(h["off_crec"]) + ((i * C + c) * TILE + lane) * rec for c in range(C)] for i in range(L)]
         cws = [[self._blk(r) for r in lv] for lv in recs]
         vcw = [[[self._u64(r + 16 + 8 * q) for q in range(p)] for r in lv] for lv in recs]
-        fin = [self._u64(tb + int(h["off_cfin"]) + (q * TILE + lane) * 8) for q in range(p)]
         rho = [self._u64(tb + int(h["off_crho"]) + (q * TILE + lane) * 8) for q in range(p)]
         rout = self._u64(tb + int(h["off_crout"]) + lane * 8)
         w = self._u64(tb + int(h["off_w"]) + lane * 8)
         return {"root": root, "scw": [[(lo & ~3, hi) for lo, hi in lv] for lv in cws],
                 "tcw": [[lo & 1 for lo, _ in lv] for lv in cws],
-                "vcw": vcw, "fin": fin, "rho": rho, "rout": rout, "wshare": w}
+                "vcw": vcw, "rho": rho, "rout": rout, "wshare": w}
 
 
 def oracle_atom(K, t: int) -> dict:
@@ -86,5 +85,5 @@ def oracle_coeff(K) -> dict:
             "scw": [[(c.scw[i][ch].lo, c.scw[i][ch].hi) for ch in range(C)] for i in range(L)],
             "tcw": [[c.tcw[i][ch] for ch in range(C)] for i in range(L)],
             "vcw": [[[int(c.vcw[i][ch][q]) for q in range(p)] for ch in range(C)] for i in range(L)],
-            "fin": [int(c.fin[q]) for q in range(p)], "rho": [int(K.rho[q]) for q in range(p)],
+            "rho": [int(K.rho[q]) for q in range(p)],
             "rout": int(K.rout), "wshare": int(K.wshare)}
