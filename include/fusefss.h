@@ -210,9 +210,10 @@ int fss_plan_launch(fss_plan* plan, void* stream);
 int fss_plan_free(fss_plan* plan);
 /* AES-128 blocks one launch of `plan` evaluates, as the kernels compute them
  * (per element and party, with B = 1 + ceil(p/2) blocks per level of the
- * lookup DCF, L = ceil(n/2) such levels of four children, and D shared top
- * levels: sum_t k_t + (L + 2D + (m-1)(L-D)) B + m ceil(p/2); the m-1 lookup
- * points share their first D levels, walked once for each of the two aligned
+ * lookup DCF and ceil(p/2) at its last level, L = ceil(n/r) levels of 2^r
+ * children, D shared top levels and T of the spec's top blocks:
+ * sum_t k_t + (L - 1 + T D + (m-1)(L-D-1)) B + m ceil(p/2); the m-1 lookup
+ * points share their first D levels, walked once for each of the T aligned
  * blocks they fall in; a tile run in parts walks them once per part).  Used
  * for throughput reporting. */
 double fss_plan_aes_blocks(const fss_plan* plan);

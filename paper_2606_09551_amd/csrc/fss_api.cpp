@@ -701,15 +701,17 @@ ElemCost elem_cost(const KeyHeader& h) {
   ElemCost c;
   for (uint32_t t = 0; t < h.T; ++t) c.aes_pred += h.atom_k[t];
   c.lk_pred = 160.0 * c.aes_pred;
-  // the lookup DCF has L = ceil(n / r) levels of 2^r children; D of them shared
+  // the lookup DCF has L = ceil(n / r) levels of 2^r children; D of them
+  // shared.  A level expands the child's seed and value blocks (1 + nb); the
+  // last level only its nb value blocks.
   const double nb = (double)((h.p + 1) / 2), lvl = 1 + nb;
   const double L = (double)((h.n + h.lookup_r - 1) / h.lookup_r), D = h.top_depth;
-  c.aes_base = L * lvl;
-  c.lk_base = L * shared(lvl);
+  c.aes_base = (L - 1) * lvl + nb;
+  c.lk_base = (L - 1) * shared(lvl) + shared(nb);
   c.aes_tops = h.top_blocks * D * lvl;
   c.lk_tops = h.top_blocks * D * shared(lvl);
-  c.aes_point = (L - D) * lvl;
-  c.lk_point = (L - D) * shared(lvl);
+  c.aes_point = (L - D - 1) * lvl + nb;
+  c.lk_point = (L - D - 1) * shared(lvl) + shared(nb);
   c.points = (int)h.m - 1;
   return c;
 }

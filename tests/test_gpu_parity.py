@@ -366,3 +366,36 @@ def test_c4_layer_worklist_autotuned_graph(tmp_path):
         out["keys0"] = inst.keys[0].cpu().numpy()
         out["keys1"] = inst.keys[1].cpu().numpy()
         compare(out, o, elems, N)
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_plan_work_counts(r):
+    """The plan's AES-block and table-lookup counts (the roofline's work
+    figure) equal the walks written out one by one: every Z_2 atom level is one
+    block; the lookup DCF's walk at v has L - 1 levels of 1 + nb blocks and a
+    last level of nb (value blocks only); each of the T top blocks walks D
+    levels; each of the m - 1 points walks L - D - 1 full levels and the last.
+    Blocks expanding one seed under K tweaks share 24 of their lookups."""
+    spec = F.Spec(W.gelu_spec(), lookup_r=r)
+    q = spec.query(W.N_BITS, W.F_BITS)
+    p, m, D, T = q["p"], q["m"], q["top_depth"], q["top_blocks"]
+    L = -(-W.N_BITS // r)
+    nb = (p + 1) // 2
+
+    def lk(k):
+        return 160 * k - 24 * (k - 1)
+
+    walks = [(L - 1, 1)] + [(D, 0)] * T + [(L - D - 1, 1)] * (m - 1)  # (full levels, last level)
+    aes = sum(q["atom_k"]) + sum(f * (1 + nb) + e * nb for f, e in walks)
+    lookups = 160 * sum(q["atom_k"]) + sum(f * lk(1 + nb) + e * lk(nb) for f, e in walks)
+    N = 64 * 6144  # the GELU 128 x 3072 launch: 12,288 tiles on 3,072 waves, no tile split
+    op = R.OpInstanceGPU(spec, W.N_BITS, W.F_BITS, N)
+    op.set_input(np.zeros(N, dtype=np.int64))
+    op.keygen(5)
+    plan = F.Plan([op.item(0), op.item(1)])
+    assert plan.parts() == 1
+    assert plan.aes_blocks() == 2 * N * aes
+    assert plan.table_lookups() == 2 * N * lookups
+    if r == 3:
+        assert (aes, lookups) == (360, 53136)
+    plan.free()
