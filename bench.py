@@ -240,10 +240,13 @@ def main() -> None:
                 inst.eval_plain(1)
         ev[2].record(stream)
 
-    def run(fused: bool):
+    def warm(fused: bool):
         for k in range(args.warmup):
             step(k, fused, [torch.cuda.Event(enable_timing=True) for _ in range(3)])
         torch.cuda.synchronize()
+
+    def run(fused: bool):
+        warm(fused)
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -260,6 +263,10 @@ def main() -> None:
         return {"wall_s": wall, "keygen_ms": statistics.mean(kg), "eval_ms": statistics.mean(ev),
                 "lat": lat}
 
+    # Both paths are warmed up before either is timed, so neither run carries
+    # the first launches' start-up (clock ramp, first-touch of the buffers).
+    if not args.no_plain:
+        warm(False)
     fused = run(True)
     plain = None if args.no_plain else run(False)
 
