@@ -19,6 +19,7 @@ struct KgArgs {
   uint64_t bprime[kMaxAtoms];
   int64_t n_elems;
   uint64_t n_tiles;
+  int32_t jobs;  // waves per tile: 1 (one wave does all) or 2 (masks + call 1 | call 2)
 };
 
 // One work-list entry as the persistent kernel sees it.

@@ -993,8 +993,14 @@ __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHead
   TB::fill(lds, threadIdx.x, blockDim.x);
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  // With two jobs per tile (small batches: latency), wave 2j + 0 of a tile
+  // makes the masks and call 1's keys, wave 2j + 1 call 2's key; both draw
+  // r_in from the same counter-mode block, so the keys are those of one wave.
+  const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint64_t tile = ga.jobs == 2 ? wave >> 1 : wave;
   if (tile >= ga.n_tiles) return;
+  const bool do_call1 = ga.jobs != 2 || (wave & 1) == 0;
+  const bool do_call2 = ga.jobs != 2 || (wave & 1) == 1;
   TB tb(lds, lane);
   const GHdr h = ghdr(hdr);
   const uint64_t e = tile * kTile + lane;
@@ -1003,7 +1009,12 @@ __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHead
   uint8_t* t1 = key1 ? key1 + kHeaderBytes + tile * tb_bytes : nullptr;
 
   uint32_t r[4];
-  rand_blk(tb, ga.rk, e, 0, 0, r);
+  if (do_call2) {
+    rand_blk(tb, ga.rk, e, 0, 0, r);
+    keygen_coeff<P, R>(tb, h, ga, e, mk64(r[0], r[1]), t0, t1, lane);
+  }
+  if (!do_call1) return;
+  rand_blk(tb, ga.rk, e, 0, 0, r);  // drawn again rather than held across call 2's keygen
   const uint64_t rin = mk64(r[0], r[1]), rout = mk64(r[2], r[3]);
   if (e < (uint64_t)ga.n_elems) {
     if (r_in) stg64(r_in + e, rin);
@@ -1038,8 +1049,6 @@ __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHead
   const uint64_t W = mk64(r[0], r[1]) & ellmask;
   st8(t0 + h->off_w + lane * 8, W);
   if (t1) st8(t1 + h->off_w + lane * 8, W ^ wout);
-
-  keygen_coeff<P, R>(tb, h, ga, e, rin, t0, t1, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1061,11 +1070,20 @@ inline uint64_t waves_per_block(uint64_t tiles, int cus, int block) {
   return w < 1 ? 1 : (w > full ? full : w);
 }
 
+// A batch whose tiles, two waves each, still fit the resident waves of the
+// grid runs two jobs per tile (call 1's keys beside call 2's): its latency is
+// one tile's keygen, and halving it halves the batch's.  Larger batches keep
+// one wave per tile: a block's waves would otherwise finish at different
+// times and leave its CU part-idle.
 template <int V, int P, int R>
-hipError_t launch_keygen(const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1, uint64_t* ri,
+hipError_t launch_keygen(const KeyHeader* h, const KgArgs& ga_in, uint8_t* k0, uint8_t* k1, uint64_t* ri,
                          uint64_t* ro, int cus, hipStream_t st) {
-  const uint64_t per = waves_per_block(ga.n_tiles, cus, keygen_block<V, P>());
-  const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
+  KgArgs ga = ga_in;
+  const uint64_t slots = (uint64_t)(cus > 0 ? cus : 1) * (keygen_block<V, P>() / 64);
+  ga.jobs = 2 * ga.n_tiles <= slots ? 2 : 1;
+  const uint64_t waves = ga.n_tiles * (uint64_t)ga.jobs;
+  const uint64_t per = waves_per_block(waves, cus, keygen_block<V, P>());
+  const unsigned grid = (unsigned)((waves + per - 1) / per);
   hipLaunchKernelGGL((k_keygen<V, P, R>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, h, ga, k0, k1, ri, ro);
   return hipGetLastError();
 }
