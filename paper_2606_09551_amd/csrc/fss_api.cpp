@@ -288,8 +288,9 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
     double best = points * L * lvl;  // D = 0
     h.top_depth = 0;
     h.top_blocks = 0;
+    // m >= 4 boundaries are distinct, so W >= 3 and ceil((W - 1) / 2^K) = ((W - 2) >> K) + 1
     for (int K = r; m >= 4 && K < n; K += r) {
-      const uint64_t B = (W <= 1 ? 0 : (W - 2) >> K) + 1 + (W > 1 ? 1 : 0);  // ceil((W-1)/2^K) + 1
+      const uint64_t B = ((W - 2) >> K) + 2;
       if (B > (uint64_t)kMaxTopBlocks || B > ((uint64_t)1 << (n - K))) continue;
       const int D = L - K / r;
       const double cost = (double)B * D * lvl + points * (L - D) * lvl;
