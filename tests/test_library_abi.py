@@ -148,6 +148,24 @@ def test_lookup_radix_setting():
         assert e.value.code == -8
     # clip-ReLU has m = 3: no shared levels at any radix
     assert F.Spec(W.clip_relu_spec(), lookup_r=3).query(16, 8)["top_depth"] == 0
+    # exp on [-16, 0) (33 points, W = 16 * 4096 + 1): K = 15 gives B = 3, D = 3 at r = 3
+    # (3 * 3 + 33 * 5 = 174 levels against K = 18: 2 * 2 + 33 * 6 = 202; K = 12 needs 17 blocks)
+    q = F.Spec(W.exp_spec(), lookup_r=3).query(24, 12)
+    assert (q["m"], q["top_depth"], q["top_blocks"]) == (34, 3, 3)
+    # reciprocal on [1, 128) (25 points over geometric intervals, W = 520,193 < 2^19): the
+    # choice recomputed from the boundaries, K = 18 with B = 3, D = 2
+    q = F.Spec(W.recip_spec(7), lookup_r=3).query(24, 12)
+    W_ = q["aprime"][q["m"] - 1] - q["aprime"][1] + 1
+    assert W_ == 520193
+    best = ((q["m"] - 1) * 8, 0, 0)  # no shared levels
+    for K in range(3, 24, 3):
+        B = ((W_ - 2) >> K) + 2
+        if B <= 4 and B <= 2 ** (24 - K):
+            D = 8 - K // 3
+            cost = B * D + (q["m"] - 1) * (8 - D)
+            if cost < best[0]:
+                best = (cost, D, B)
+    assert (q["top_depth"], q["top_blocks"]) == best[1:] == (2, 3)
 
 
 def test_argument_errors():
