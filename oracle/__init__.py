@@ -86,7 +86,8 @@ class Spec(C.Structure):
                 ("prim_out", C.c_int32 * MAXPRED), ("prim_bprime", C.c_uint64 * MAXPRED),
                 ("n_views", C.c_int32), ("view_k", C.c_int32 * MAXPRED),
                 ("view_c", C.c_uint64 * MAXPRED), ("T", C.c_int32),
-                ("negate", C.c_uint8 * MAXL), ("lookup_r", C.c_int32)]
+                ("negate", C.c_uint8 * MAXL), ("lookup_r", C.c_int32), ("is_int", C.c_int32),
+                ("lookup_c", C.c_uint64)]
 
 
 _lib = None
@@ -103,7 +104,7 @@ def lib():
         L.orc_sbox.argtypes = [u8p]
         L.orc_prg.argtypes = [Blk, C.c_int]
         L.orc_prg.restype = Blk
-        L.orc_seed_sched.argtypes = [C.c_uint64, C.c_void_p]
+        L.orc_seed_sched.argtypes = [u8p, C.c_void_p]
         L.orc_rand.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int]
         L.orc_rand.restype = Blk
         L.orc_dcf_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk,
@@ -115,12 +116,14 @@ def lib():
         L.orc_spec_compile.argtypes = [C.POINTER(Interval), C.c_int32, C.POINTER(Piece),
                                        C.POINTER(Pred), C.c_int32, C.c_int32, C.c_int32,
                                        C.c_int32, C.POINTER(Spec)]
-        L.orc_keygen_batch.argtypes = [C.POINTER(Spec), C.c_uint64, i64p, C.c_int64,
+        L.orc_spec_compile_int.argtypes = [C.c_int32, C.c_int32, u64p, C.c_int32, u64p,
+                                           C.POINTER(Pred), C.c_int32, C.POINTER(Spec)]
+        L.orc_keygen_batch.argtypes = [C.POINTER(Spec), u8p, i64p, C.c_int64,
                                        C.POINTER(ElemKey), C.POINTER(ElemKey), u64p, u64p, C.c_int]
         L.orc_eval_batch.argtypes = [C.c_int, C.POINTER(Spec), C.POINTER(ElemKey), u64p,
                                      C.c_int64, u64p, u64p, C.c_int]
-        L.orc_full_batch.argtypes = [C.POINTER(Spec), C.c_uint64, i64p, C.c_int64, i64p,
-                                     u64p, u64p, u64p, u64p, C.c_int]
+        L.orc_full_batch.argtypes = [C.POINTER(Spec), u8p, i64p, C.c_int64, i64p,
+                                     u64p, u64p, u64p, u64p, u64p, u64p, C.c_int]
         L.orc_plain_eval.argtypes = [C.POINTER(Spec), C.c_int64, u64p, u64p]
         L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
                                     C.POINTER(C.c_int32)]
@@ -141,6 +144,11 @@ def _u64p(a: np.ndarray):
 def _i64p(a: np.ndarray):
     assert a.dtype == np.int64 and a.flags.c_contiguous
     return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def seed_bytes(seed: int):
+    """The dealer's 128-bit seed as the 16 little-endian bytes of its AES key."""
+    return (C.c_uint8 * 16).from_buffer_copy(int(seed & (2**128 - 1)).to_bytes(16, "little"))
 
 
 # ---- AES / PRG / randomness ------------------------------------------------
@@ -166,7 +174,7 @@ def prg(lo: int, hi: int, j: int) -> tuple[int, int]:
 
 def rand(seed: int, e: int, purpose: int, ctr: int = 0) -> tuple[int, int]:
     ks = (C.c_uint8 * 176)()
-    lib().orc_seed_sched(seed, ks)
+    lib().orc_seed_sched(seed_bytes(seed), ks)
     r = lib().orc_rand(ks, e, purpose, ctr)
     return r.lo, r.hi
 
@@ -234,6 +242,29 @@ def compile_spec(desc, n_bits: int, frac_bits: int, lookup_r: int = 3) -> Spec:
     return S
 
 
+def compile_spec_int(n_bits: int, alpha, coef, preds=(), lookup_r: int = 3) -> Spec:
+    """Integer spec of Definition "Operator specification": boundaries
+    0 = alpha_0 < ... < alpha_m = 2^n over canonical representatives, coef[i] the
+    ring coefficients of piece i (lowest first, all of one length d + 1), preds
+    PredDesc with integer thresholds."""
+    m = len(alpha) - 1
+    d = len(coef[0]) - 1
+    a = np.ascontiguousarray([int(v) for v in alpha], dtype=np.uint64)
+    c = np.ascontiguousarray([int(v) & (2**64 - 1) for row in coef for v in row], dtype=np.uint64)
+    np_ = len(preds)
+    prs = (Pred * max(np_, 1))()
+    for j, q in enumerate(preds):
+        prs[j] = Pred(q.kind, int(q.negate), q.out, q.f_bits, q.thr, q.gamma, q.c)
+    S = Spec()
+    rc = lib().orc_spec_compile_int(n_bits, m, _u64p(a), d, _u64p(c), prs, np_, C.byref(S))
+    if rc != 0:
+        raise SpecError(f"oracle rejected integer spec: rc={rc}")
+    if lookup_r not in (2, 3, 4):
+        raise SpecError(f"lookup_r must be 2, 3 or 4, got {lookup_r}")
+    S.lookup_r = lookup_r
+    return S
+
+
 def spec_tables(S: Spec) -> dict:
     """Integer tables of a compiled spec, for comparison with the library."""
     m, p = S.m, S.p
@@ -257,7 +288,7 @@ def keygen(S: Spec, seed: int, elems, threads: int = 0):
     K1 = (ElemKey * max(cnt, 1))()
     r_in = np.zeros(cnt, np.uint64)
     r_out = np.zeros(cnt, np.uint64)
-    lib().orc_keygen_batch(C.byref(S), seed, _i64p(elems), cnt, K0, K1, _u64p(r_in),
+    lib().orc_keygen_batch(C.byref(S), seed_bytes(seed), _i64p(elems), cnt, K0, K1, _u64p(r_in),
                            _u64p(r_out), threads)
     return K0, K1, r_in, r_out
 
@@ -271,16 +302,20 @@ def evaluate(b: int, S: Spec, K, xhat, threads: int = 0):
     return y, z
 
 
-def full(S: Spec, seed: int, elems, x, threads: int = 0):
-    """Dealer keygen + both parties' evaluation for the given element indices.
+def full(S: Spec, seed: int, elems, x, threads: int = 0, masks: bool = False):
+    """Dealer keygen + both parties' evaluation for the given element indices
+    (no keys are stored, so any number of elements fits in memory).
 
-    Returns (y0, y1, z0, z1, threads_used)."""
+    Returns (y0, y1, z0, z1, threads_used), or with masks=True
+    (y0, y1, z0, z1, r_in, r_out, threads_used)."""
     elems = np.ascontiguousarray(elems, dtype=np.int64)
     x = np.ascontiguousarray(x, dtype=np.int64)
     cnt = len(elems)
-    y0, y1, z0, z1 = (np.zeros(cnt, np.uint64) for _ in range(4))
-    used = lib().orc_full_batch(C.byref(S), seed, _i64p(elems), cnt, _i64p(x), _u64p(y0),
-                                _u64p(y1), _u64p(z0), _u64p(z1), threads)
+    y0, y1, z0, z1, r_in, r_out = (np.zeros(cnt, np.uint64) for _ in range(6))
+    used = lib().orc_full_batch(C.byref(S), seed_bytes(seed), _i64p(elems), cnt, _i64p(x), _u64p(y0),
+                                _u64p(y1), _u64p(z0), _u64p(z1), _u64p(r_in), _u64p(r_out), threads)
+    if masks:
+        return y0, y1, z0, z1, r_in, r_out, used
     return y0, y1, z0, z1, used
 
 

@@ -11,7 +11,8 @@
  *   * PRG: H(s, j) = AES_K(s ^ J_j) ^ s ^ J_j, K = 00 01 .. 0f, J_j is the
  *     block whose byte 15 is j (j < 8) and every other byte 0.
  *   * Randomness: R(e, pi, c) = AES_{K_seed}(e u64 | pi u16 | c u16 | 0 u32),
- *     K_seed = seed u64 little-endian followed by eight zero bytes.
+ *     K_seed = the dealer's 16-byte seed (a 128-bit AES key, so the masks
+ *     carry the security level of the threat model's Gen(1^lambda)).
  *   * DCF: Boyle et al. EUROCRYPT'21 comparison function f(x) = beta*[x < alpha],
  *     MSB-first over n bits, seeds with bits 0..1 of byte 0 cleared.
  */
@@ -165,11 +166,7 @@ orc_blk orc_prg(orc_blk s, int j) {
   return y;
 }
 
-void orc_seed_sched(uint64_t seed, orc_aes_sched* ks) {
-  uint8_t k[16] = {0};
-  for (int i = 0; i < 8; i++) k[i] = (uint8_t)(seed >> (8 * i));
-  orc_aes128_expand(k, ks);
-}
+void orc_seed_sched(const uint8_t seed[16], orc_aes_sched* ks) { orc_aes128_expand(seed, ks); }
 
 orc_blk orc_rand(const orc_aes_sched* kseed, uint64_t e, int purpose, int ctr) {
   orc_blk x;
@@ -485,57 +482,13 @@ static int find_or_add_view(orc_spec* S, int k, uint64_t c) {
   return S->n_views++;
 }
 
-int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
-                     const orc_pred* pr, int32_t n_pred, int32_t n_bits,
-                     int32_t frac_bits, int32_t out_frac_bits, orc_spec* S) {
-  memset(S, 0, sizeof *S);
-  if (n_bits < 2 || n_bits > ORC_MAXN) return -2;
-  if (frac_bits < 0 || frac_bits >= n_bits) return -2;
-  if (m < 1 || m > ORC_MAXM) return -1;
-  if (n_pred < 0 || n_pred > ORC_MAXPRED) return -2;
-  const int n = n_bits, f = frac_bits;
+/* Predicates (Definition "Operator specification", item 3): quantise at f
+ * fractional bits, map each to a view and a threshold in view space (the
+ * masked rewrites of the comparison, low-bit and MSB lemmas), fold the
+ * sentinels into constants, and list the atoms in descriptor order. */
+static int compile_preds(orc_spec* S, const orc_pred* pr, int32_t n_pred, int f) {
+  const int n = S->n;
   const int64_t N = (int64_t)1 << n, s = N / 2;
-  S->n = n; S->f = f; S->m = m;
-  S->lookup_r = 3;
-
-  /* Partition: contiguous half-open real intervals, tails at -inf / +inf. */
-  if (!(isinf(iv[0].lo) && iv[0].lo < 0)) return -1;
-  if (!(isinf(iv[m - 1].hi) && iv[m - 1].hi > 0)) return -1;
-  for (int i = 0; i < m; i++)
-    if (!(iv[i].lo < iv[i].hi)) return -1;
-  for (int i = 0; i + 1 < m; i++)
-    if (iv[i].hi != iv[i + 1].lo) return -1;
-  S->alpha[0] = -s;
-  S->alpha[m] = s;
-  /* Real boundary a maps to ceil(a 2^f): the integers whose real value is >= a. */
-  for (int i = 1; i < m; i++) S->alpha[i] = clamp_ceil(ldexp(iv[i].lo, f), -s, s);
-  for (int i = 1; i <= m; i++)
-    if (!(S->alpha[i - 1] < S->alpha[i])) return -1;
-  for (int i = 0; i <= m; i++) S->aprime[i] = (uint64_t)(S->alpha[i] + s);
-
-  /* Pieces: coefficient a_l scaled by 2^(F_out - l f), ties to even. */
-  int d = 0;
-  for (int i = 0; i < m; i++) {
-    if (pc[i].degree < 0 || pc[i].degree > 3) return -1;
-    if (pc[i].degree > d) d = pc[i].degree;
-  }
-  S->d = d;
-  S->p = d + 1;
-  S->F_out = out_frac_bits >= 0 ? out_frac_bits : (d <= 1 ? 2 * f : 4 * f);
-  for (int i = 0; i < m; i++) {
-    double X = fmax(fabs((double)S->alpha[i]), fabs((double)(S->alpha[i + 1] - 1)));
-    double bound = 0;
-    for (int l = 0; l <= d; l++) {
-      double a = (l <= pc[i].degree) ? pc[i].coef[l] : 0.0;
-      double q = nearbyint(ldexp(a, S->F_out - l * f));
-      if (!(fabs(q) < 9223372036854775808.0)) return -1; /* also rejects NaN */
-      S->coef[i][l] = (uint64_t)(int64_t)q;
-      bound += fabs(q) * pow(X, l);
-    }
-    if (!(bound < 4611686018427387904.0)) return -1; /* |P_i(x)| < 2^62 on I_i */
-  }
-
-  /* Predicates: quantise, map to a view and a threshold in view space. */
   S->n_user = n_pred;
   S->ell = 0;
   for (int j = 0; j < n_pred; j++) {
@@ -600,6 +553,92 @@ int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
   S->T = S->n_prim + S->n_views;
   if (S->T > ORC_MAXT) return -2;
   return 0;
+}
+
+int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
+                     const orc_pred* pr, int32_t n_pred, int32_t n_bits,
+                     int32_t frac_bits, int32_t out_frac_bits, orc_spec* S) {
+  memset(S, 0, sizeof *S);
+  if (n_bits < 2 || n_bits > ORC_MAXN) return -2;
+  if (frac_bits < 0 || frac_bits >= n_bits) return -2;
+  if (m < 1 || m > ORC_MAXM) return -1;
+  if (n_pred < 0 || n_pred > ORC_MAXPRED) return -2;
+  const int n = n_bits, f = frac_bits;
+  const int64_t N = (int64_t)1 << n, s = N / 2;
+  S->n = n; S->f = f; S->m = m;
+  S->lookup_r = 3;
+  S->lookup_c = (uint64_t)s; /* signed order: offset-binary view of the lookup */
+
+  /* Partition: contiguous half-open real intervals, tails at -inf / +inf. */
+  if (!(isinf(iv[0].lo) && iv[0].lo < 0)) return -1;
+  if (!(isinf(iv[m - 1].hi) && iv[m - 1].hi > 0)) return -1;
+  for (int i = 0; i < m; i++)
+    if (!(iv[i].lo < iv[i].hi)) return -1;
+  for (int i = 0; i + 1 < m; i++)
+    if (iv[i].hi != iv[i + 1].lo) return -1;
+  S->alpha[0] = -s;
+  S->alpha[m] = s;
+  /* Real boundary a maps to ceil(a 2^f): the integers whose real value is >= a. */
+  for (int i = 1; i < m; i++) S->alpha[i] = clamp_ceil(ldexp(iv[i].lo, f), -s, s);
+  for (int i = 1; i <= m; i++)
+    if (!(S->alpha[i - 1] < S->alpha[i])) return -1;
+  for (int i = 0; i <= m; i++) S->aprime[i] = (uint64_t)(S->alpha[i] + s);
+
+  /* Pieces: coefficient a_l scaled by 2^(F_out - l f), ties to even. */
+  int d = 0;
+  for (int i = 0; i < m; i++) {
+    if (pc[i].degree < 0 || pc[i].degree > 3) return -1;
+    if (pc[i].degree > d) d = pc[i].degree;
+  }
+  S->d = d;
+  S->p = d + 1;
+  S->F_out = out_frac_bits >= 0 ? out_frac_bits : (d <= 1 ? 2 * f : 4 * f);
+  for (int i = 0; i < m; i++) {
+    double X = fmax(fabs((double)S->alpha[i]), fabs((double)(S->alpha[i + 1] - 1)));
+    double bound = 0;
+    for (int l = 0; l <= d; l++) {
+      double a = (l <= pc[i].degree) ? pc[i].coef[l] : 0.0;
+      double q = nearbyint(ldexp(a, S->F_out - l * f));
+      if (!(fabs(q) < 9223372036854775808.0)) return -1; /* also rejects NaN */
+      S->coef[i][l] = (uint64_t)(int64_t)q;
+      bound += fabs(q) * pow(X, l);
+    }
+    if (!(bound < 4611686018427387904.0)) return -1; /* |P_i(x)| < 2^62 on I_i */
+  }
+
+  return compile_preds(S, pr, n_pred, f);
+}
+
+/* The Definition's own form: integer boundaries 0 = alpha_0 < ... < alpha_m = 2^n
+ * over canonical representatives {0, .., 2^n - 1} and ring coefficients (the
+ * polynomials are evaluated in Z_{2^64}, at the input's 64-bit value).  The
+ * lookup therefore uses the unshifted view xhat mod 2^n; predicate thresholds
+ * are integers (fractional bits 0). */
+int orc_spec_compile_int(int32_t n_bits, int32_t m, const uint64_t* alpha, int32_t degree,
+                         const uint64_t* coef, const orc_pred* pr, int32_t n_pred, orc_spec* S) {
+  memset(S, 0, sizeof *S);
+  if (n_bits < 2 || n_bits > ORC_MAXN) return -2;
+  if (m < 1 || m > ORC_MAXM) return -1;
+  if (degree < 0 || degree > 3) return -1;
+  if (n_pred < 0 || n_pred > ORC_MAXPRED) return -2;
+  const uint64_t N = (uint64_t)1 << n_bits;
+  if (alpha[0] != 0 || alpha[m] != N) return -1;
+  for (int i = 1; i <= m; i++)
+    if (!(alpha[i - 1] < alpha[i])) return -1;
+  for (int j = 0; j < n_pred; j++)
+    if ((pr[j].kind == ORC_LT_SIGNED || pr[j].kind == ORC_LT_UNSIGNED) && pr[j].thr != floor(pr[j].thr))
+      return -1;
+  S->n = n_bits; S->f = 0; S->m = m; S->d = degree; S->p = degree + 1; S->F_out = 0;
+  S->lookup_r = 3;
+  S->is_int = 1;
+  S->lookup_c = 0;
+  for (int i = 0; i <= m; i++) {
+    S->alpha[i] = (int64_t)alpha[i];
+    S->aprime[i] = alpha[i];
+  }
+  for (int i = 0; i < m; i++)
+    for (int l = 0; l <= degree; l++) S->coef[i][l] = coef[i * (degree + 1) + l];
+  return compile_preds(S, pr, n_pred, 0);
 }
 
 /* ========================================================================= */
@@ -697,13 +736,14 @@ void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xha
     z ^= (uint64_t)bit << S->prim_out[t];
   }
 
-  /* Call 2: interval lookup.  With v = view_{n,s}(xhat) and the offset-binary
-   * x' = (v - r_n) mod N, for each interior boundary a'_i:
+  /* Call 2: interval lookup.  With v = view_{n,c}(xhat) (c = 2^(n-1) for the
+   * signed order of real specs, 0 for the canonical order of integer specs)
+   * and x' = (v - r_n) mod N, for each interior boundary a'_i:
    *   1[x' < a'_i] = 1[(v - a'_i) mod N < r_n] - 1[v < r_n] + 1[v < a'_i],
    * so g_i = D(u_i) - D(v) + 1[v < a'_i] rho_b shares 1[x' < a'_i] rho. */
   const int n = S->n, m = S->m, p = S->p, d = S->d;
-  const uint64_t N = (uint64_t)1 << n, s = N / 2;
-  uint64_t v = ((xhat & (N - 1)) + s) & (N - 1);
+  const uint64_t N = (uint64_t)1 << n;
+  uint64_t v = ((xhat & (N - 1)) + S->lookup_c) & (N - 1);
   uint64_t Dv[ORC_MAXP];
   orc_dcfr_eval(b, &K->coeff, v, Dv);
   uint64_t g[ORC_MAXM + 1][ORC_MAXP];
@@ -745,7 +785,12 @@ void orc_plain_eval(const orc_spec* S, int64_t x, uint64_t* y_out, uint64_t* z_o
   const int n = S->n;
   const uint64_t N = (uint64_t)1 << n, s = N / 2;
   int is = 0;
-  while (is + 1 < S->m && x >= S->alpha[is + 1]) is++;
+  if (S->is_int) {
+    const uint64_t rep = (uint64_t)x & (N - 1);
+    while (is + 1 < S->m && rep >= S->aprime[is + 1]) is++;
+  } else {
+    while (is + 1 < S->m && x >= S->alpha[is + 1]) is++;
+  }
   uint64_t y = 0, xp = 1;
   for (int l = 0; l <= S->d; l++) {
     y += S->coef[is][l] * xp;
@@ -770,42 +815,48 @@ void orc_plain_eval(const orc_spec* S, int64_t x, uint64_t* y_out, uint64_t* z_o
 /* Protocol "Compile a scalar gate instance", lookup part                    */
 /* ========================================================================= */
 
+/* The translated lookup partition of Definition "Interval lookup with vector
+ * payload" as the compilation protocol builds it (step 1): in xhat space,
+ * xhat = x + r mod N, interval I_i = [alpha_i, alpha_{i+1}) becomes the cyclic
+ * range starting at (alpha_i + r) mod N.  Reading xhat upward from 0 meets the
+ * intervals in cyclic order, beginning with the one that holds x = -r mod N;
+ * that interval comes back at the top of the range, cut by the wrap point,
+ * unless its translated start is 0.  A partition that was not cut is padded
+ * to M = min(m + 1, N) intervals so that the shape does not depend on r: here
+ * the last interval of length >= 2 loses its top value to a new interval
+ * with the same payload index. */
 int orc_protocol3(int n, const uint64_t* alpha, int m, uint64_t r, uint64_t* B, int32_t* ord) {
   const uint64_t N = (uint64_t)1 << n;
-  int M = (uint64_t)(m + 1) < N ? m + 1 : (int)N;
-  uint64_t st[ORC_MAXM + 2];
-  int32_t pi[ORC_MAXM + 2];
-  for (int i = 0; i < m; i++) { st[i] = (alpha[i] + r) % N; pi[i] = i; }
-  /* sort translated starts (insertion sort, plain) */
-  for (int i = 1; i < m; i++)
-    for (int j = i; j > 0 && st[pi[j - 1]] > st[pi[j]]; j--) {
-      int32_t t = pi[j]; pi[j] = pi[j - 1]; pi[j - 1] = t;
-    }
-  int nb = 0, no = 0;
-  if (st[pi[0]] == 0) {
-    for (int j = 0; j < m; j++) B[nb++] = st[pi[j]];
-    B[nb++] = N;
-    for (int j = 0; j < m; j++) ord[no++] = pi[j];
-    if ((uint64_t)m < N) {
-      int js = 0;
-      while (B[js + 1] - B[js] < 2) js++;
-      uint64_t delta = B[js] + 1;
-      for (int q = nb; q > js + 1; q--) B[q] = B[q - 1];
-      B[js + 1] = delta;
-      nb++;
-      for (int q = no; q > js + 1; q--) ord[q] = ord[q - 1];
-      ord[js + 1] = ord[js];
-      no++;
-    }
-  } else {
-    B[nb++] = 0;
-    for (int j = 0; j < m; j++) B[nb++] = st[pi[j]];
-    B[nb++] = N;
-    ord[no++] = pi[m - 1];
-    for (int j = 0; j < m; j++) ord[no++] = pi[j];
+  const int M = (uint64_t)(m + 1) < N ? m + 1 : (int)N;
+  r &= N - 1;
+  const uint64_t x0 = (N - r) & (N - 1); /* the preimage of xhat = 0 */
+  int first = 0;
+  while (first + 1 < m && alpha[first + 1] <= x0) first++;
+  int cnt = 0;
+  B[0] = 0;
+  ord[cnt++] = first;
+  for (int k = 1; k < m; k++) { /* the other intervals, in cyclic order */
+    const int i = (first + k) % m;
+    B[cnt] = (alpha[i] + r) & (N - 1);
+    ord[cnt++] = i;
   }
-  (void)nb;
-  return no == M ? M : -1;
+  const uint64_t top = (alpha[first] + r) & (N - 1);
+  if (top != 0) { /* the first interval's upper part */
+    B[cnt] = top;
+    ord[cnt++] = first;
+  }
+  B[cnt] = N;
+  if (cnt < M) { /* pad: split the last interval of length >= 2 below its end */
+    int j = cnt - 1;
+    while (j >= 0 && B[j + 1] - B[j] < 2) j--;
+    if (j < 0) return -1;
+    for (int q = cnt; q > j; q--) B[q + 1] = B[q];
+    for (int q = cnt - 1; q > j; q--) ord[q + 1] = ord[q];
+    B[j + 1] = B[j + 2] - 1;
+    ord[j + 1] = ord[j];
+    cnt++;
+  }
+  return cnt == M ? M : -1;
 }
 
 /* ========================================================================= */
@@ -824,7 +875,7 @@ int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
 typedef struct {
   int kind;  /* 0 keygen, 1 eval, 2 full */
   const orc_spec* S;
-  uint64_t seed;
+  uint8_t seed[16];
   const int64_t* elems;
   int64_t lo, hi;
   orc_elem_key *k0, *k1;
@@ -849,6 +900,8 @@ static void* run_job(void* arg) {
       orc_elem_key a, b;
       uint64_t rin, rout;
       orc_keygen_elem(J->S, &ks, (uint64_t)J->elems[i], &a, &b, &rin, &rout);
+      if (J->r_in) J->r_in[i] = rin;
+      if (J->r_out) J->r_out[i] = rout;
       uint64_t xh = (uint64_t)J->x[i] + rin;
       orc_eval_elem(0, J->S, &a, xh, &J->y0[i], &J->z0[i]);
       orc_eval_elem(1, J->S, &b, xh, &J->y1[i], &J->z1[i]);
@@ -873,13 +926,13 @@ static int run_jobs(job_t proto, int64_t count, int threads) {
   return threads;
 }
 
-int orc_keygen_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+int orc_keygen_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
                      orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in, uint64_t* r_out,
                      int threads) {
   if (S->lookup_r < 2 || S->lookup_r > 4) return -3;
   job_t J;
   memset(&J, 0, sizeof J);
-  J.kind = 0; J.S = S; J.seed = seed; J.elems = elems;
+  J.kind = 0; J.S = S; memcpy(J.seed, seed, 16); J.elems = elems;
   J.k0 = k0; J.k1 = k1; J.r_in = r_in; J.r_out = r_out;
   return run_jobs(J, count, threads);
 }
@@ -892,13 +945,13 @@ int orc_eval_batch(int b, const orc_spec* S, const orc_elem_key* K, const uint64
   return run_jobs(J, count, threads);
 }
 
-int orc_full_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+int orc_full_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
                    const int64_t* x, uint64_t* y0, uint64_t* y1, uint64_t* z0, uint64_t* z1,
-                   int threads) {
+                   uint64_t* r_in, uint64_t* r_out, int threads) {
   if (S->lookup_r < 2 || S->lookup_r > 4) return -3;
   job_t J;
   memset(&J, 0, sizeof J);
-  J.kind = 2; J.S = S; J.seed = seed; J.elems = elems; J.x = x;
-  J.y0 = y0; J.y1 = y1; J.z0 = z0; J.z1 = z1;
+  J.kind = 2; J.S = S; memcpy(J.seed, seed, 16); J.elems = elems; J.x = x;
+  J.y0 = y0; J.y1 = y1; J.z0 = z0; J.z1 = z1; J.r_in = r_in; J.r_out = r_out;
   return run_jobs(J, count, threads);
 }

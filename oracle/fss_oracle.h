@@ -46,7 +46,8 @@ void orc_aes128_encrypt_key(const uint8_t key[16], const uint8_t in[16], uint8_t
 void orc_sbox(uint8_t out[256]);
 /* H(s, j) = AES_K(s ^ J_j) ^ s ^ J_j with the fixed PRG key. */
 orc_blk orc_prg(orc_blk s, int j);
-void orc_seed_sched(uint64_t seed, orc_aes_sched* ks);
+/* K_seed: the AES-128 key schedule of the dealer's 16-byte seed. */
+void orc_seed_sched(const uint8_t seed[16], orc_aes_sched* ks);
 /* R(e, purpose, ctr) = AES_{K_seed}(e || purpose || ctr || 0). */
 orc_blk orc_rand(const orc_aes_sched* kseed, uint64_t e, int purpose, int ctr);
 
@@ -125,6 +126,8 @@ typedef struct {
   int32_t T;                            /* atoms: n_prim thresholds, then n_views mask atoms */
   uint8_t negate[ORC_MAXL];             /* public constant flip per output bit */
   int32_t lookup_r;                     /* input bits per level of call 2's DCF (2, 3 or 4) */
+  int32_t is_int;                       /* 1: integer spec over canonical representatives */
+  uint64_t lookup_c;                    /* public shift of the lookup's view: 2^(n-1) or 0 */
 } orc_spec;
 
 /* Returns 0 on success, negative on an invalid or unsupported spec.  Sets
@@ -132,6 +135,13 @@ typedef struct {
 int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
                      const orc_pred* pr, int32_t n_pred, int32_t n_bits,
                      int32_t frac_bits, int32_t out_frac_bits, orc_spec* S);
+
+/* Integer form of the Definition: boundaries alpha[0..m] with 0 = alpha_0 <
+ * ... < alpha_m = 2^n over canonical representatives, ring coefficients
+ * coef[i * (degree + 1) + l] (lowest degree first), predicate thresholds
+ * given as integers.  Returns 0 or a negative code like orc_spec_compile. */
+int orc_spec_compile_int(int32_t n_bits, int32_t m, const uint64_t* alpha, int32_t degree,
+                         const uint64_t* coef, const orc_pred* pr, int32_t n_pred, orc_spec* S);
 
 /* ---- per-element keys ------------------------------------------------------- */
 typedef struct {
@@ -150,15 +160,16 @@ void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xha
 void orc_plain_eval(const orc_spec* S, int64_t x, uint64_t* y, uint64_t* zbits);
 
 /* Batched drivers over a list of element indices (threads: 0 = all cores). */
-int orc_keygen_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+int orc_keygen_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
                      orc_elem_key* k0, orc_elem_key* k1, uint64_t* r_in, uint64_t* r_out,
                      int threads);
 int orc_eval_batch(int b, const orc_spec* S, const orc_elem_key* K, const uint64_t* xhat,
                    int64_t count, uint64_t* y, uint64_t* zbits, int threads);
-/* keygen + both parties' evaluation without storing keys (CPU baseline). */
-int orc_full_batch(const orc_spec* S, uint64_t seed, const int64_t* elems, int64_t count,
+/* keygen + both parties' evaluation without storing keys (CPU baseline and
+ * full-size parity checks); r_in / r_out may be NULL. */
+int orc_full_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
                    const int64_t* x, uint64_t* y0, uint64_t* y1, uint64_t* z0, uint64_t* z1,
-                   int threads);
+                   uint64_t* r_in, uint64_t* r_out, int threads);
 int orc_hw_threads(void);
 int orc_sizeof_elem_key(void);
 int orc_sizeof_dcf_key(void);
@@ -167,7 +178,7 @@ int orc_sizeof_spec(void);
 
 /* ---- Protocol "Compile a scalar gate instance", lookup part ---------------- */
 /* alpha: boundaries 0=a_0<...<a_m=N of the partition being translated; r: mask.
- * Writes B[0..M] and ord[0..M-1]; returns M. */
+ * Writes B[0..M] and ord[0..M-1] (B needs room for m + 2 entries); returns M. */
 int orc_protocol3(int n, const uint64_t* alpha, int m, uint64_t r, uint64_t* B, int32_t* ord);
 
 #endif
