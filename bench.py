@@ -49,41 +49,45 @@ def pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def keygen_aes_per_elem(inst) -> int:
-    """Dealer AES blocks per element: both parties' children of every Z_2 DCF
-    level (2 each), of every lookup-DCF level (2^r children of 1 + ceil(p/2)
-    blocks each, L = ceil(n/r) levels, the last level's children without
-    their seed block), plus the counter-mode randomness (1 + ceil(p/2) blocks
-    per lookup level above the last)."""
-    nb = (inst.p + 1) // 2
-    r = inst.lookup_r
-    L = -(-inst.n_bits // r)
-    prg = sum(4 * k for k in inst.atom_k) + 2 * (1 << r) * ((L - 1) * (1 + nb) + nb)
-    rand = 2 * inst.T + 7 + (L - 1) * (1 + nb)
-    return prg + rand
-
-
-def cpu_baseline(op, n_bits, f_bits, seconds: float) -> dict:
-    """The oracle (keygen + both parties' evaluation) on a bounded sample."""
+def cpu_baseline(op, n_bits, f_bits, lookup_r, gpu_shares) -> dict:
+    """The oracle (dealer keygen + both parties' evaluation) on fixed samples of
+    the workload: the first 131,072 elements (2,048 tiles) on every host thread
+    and the first 4,096 on one.  The all-thread sample's shares and masks are
+    compared with the GPU's for the same seed (`gpu_shares(count)` runs the
+    fused path once at the operator's seed and returns its first `count`
+    elements)."""
     import numpy as np
 
     import oracle as O
 
-    S = O.compile_spec(op.spec, n_bits, f_bits)
-    threads = O.hw_threads()
-    cal = max(2 * threads, 16)
-    t0 = time.perf_counter()
-    O.full(S, op.seed, np.arange(cal, dtype=np.int64), op.x[:cal])
-    per = (time.perf_counter() - t0) / cal
-    count = int(min(len(op.x), max(cal, seconds / max(per, 1e-9))))
-    elems = np.arange(count, dtype=np.int64)
-    t0 = time.perf_counter()
-    *_, used = O.full(S, op.seed, elems, op.x[:count])
-    dt = time.perf_counter() - t0
-    return {"value": round(2 * count / dt, 3), "unit": "element-evals/s", "cores": int(used),
-            "kind": "oracle",
-            "sample": f"first {count} of {len(op.x)} elements: dealer keygen + both parties' "
-                      f"evaluation, {dt:.1f} s wall on {used} threads"}
+    S = O.compile_spec(op.spec, n_bits, f_bits, lookup_r=lookup_r)
+    out = {"unit": "element-evals/s", "kind": "oracle"}
+    rates = {}
+    for label, count, threads in (("single_core", 4096, 1), ("all_cores", 131072, 0)):
+        count = min(count, len(op.x))
+        elems = np.arange(count, dtype=np.int64)
+        a0 = O.aes_blocks()
+        t0 = time.perf_counter()
+        y0, y1, z0, z1, r_in, r_out, used = O.full(S, op.seed, elems, op.x[:count], threads=threads, masks=True)
+        dt = time.perf_counter() - t0
+        aes = O.aes_blocks() - a0
+        rates[label] = {"element_evals_per_s": round(2 * count / dt, 1), "aes_blocks_per_s": round(aes / dt, 1),
+                        "threads": int(used), "elements": count, "wall_s": round(dt, 3)}
+        if label == "all_cores":
+            g = gpu_shares(count)
+            ok = all(np.array_equal(a, b) for a, b in ((g["y0"], y0), (g["y1"], y1), (g["z0"], z0),
+                                                         (g["z1"], z1), (g["r_in"], r_in), (g["r_out"], r_out)))
+            out["verified_elements"] = count if ok else 0
+            out["verified"] = bool(ok)
+    allc = rates["all_cores"]
+    out.update({"value": allc["element_evals_per_s"], "cores": allc["threads"],
+                "aes_blocks_per_s": allc["aes_blocks_per_s"],
+                "single_core": rates["single_core"],
+                "sample": (f"first {allc['elements']} of {len(op.x)} elements on {allc['threads']} threads "
+                           f"({allc['wall_s']} s) and first {rates['single_core']['elements']} on one thread "
+                           f"({rates['single_core']['wall_s']} s): dealer keygen + both parties' evaluation; "
+                           "the all-thread sample's shares and masks compared with the GPU's at the same seed")})
+    return out
 
 
 KERNEL_SOURCES = ["paper_2606_09551_amd/csrc/fss_kernels_impl.hpp", "paper_2606_09551_amd/csrc/fss_common.hpp",
@@ -142,6 +146,8 @@ def layer_groups(ops) -> list:
 
 
 def main() -> None:
+    import tempfile
+
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -149,10 +155,12 @@ def main() -> None:
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=64, help="c5: requests in the Poisson stream")
     ap.add_argument("--rate", type=float, default=50.0, help="c5: mean arrival rate (req/s)")
-    ap.add_argument("--graphs", action="store_true", help="replay each layer's launch from a HIP graph")
-    ap.add_argument("--autotune", default=None, metavar="CACHE",
-                    help="autotune the fused launch on the first layer (cache file path)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-graphs", action="store_true", help="launch each layer's plan directly (no HIP graph)")
+    ap.add_argument("--autotune", default=os.path.join(tempfile.gettempdir(), "fusefss_tune_cache.txt"),
+                    metavar="CACHE", help="autotuner cache file (the fused launch is tuned on the first layer)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the planner's default launch")
+    ap.add_argument("--latency-reps", type=int, default=60,
+                    help="fused/plain step pairs, alternating, for the latency percentiles and ratios")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--lookup-r", type=int, default=None, choices=[2, 3, 4],
@@ -168,6 +176,7 @@ def main() -> None:
               "(the path shards by element range across GPUs, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_2606_09551_amd import fss as F
@@ -193,30 +202,33 @@ def main() -> None:
     torch.cuda.synchronize()
     groups = layer_groups(ops)
     tune = None
-    if args.autotune:
+    if not args.no_autotune:
         tune = F.fss_autotune([insts[i].item(b) for i in groups[0] for b in (0, 1)], args.autotune)
     plans = [F.Plan([insts[i].item(b) for i in g for b in (0, 1)], tune) for g in groups]
-    graphs = [F.Graph([p]) for p in plans] if args.graphs else None
+    graphs = None if args.no_graphs else [F.Graph([p]) for p in plans]
     cfg = plans[0].config()
     cfg["parts"] = max(p.parts() for p in plans)
     eval_aes = sum(p.aes_blocks() for p in plans)
     eval_lookups = sum(p.table_lookups() for p in plans)
-    kg_aes = sum(keygen_aes_per_elem(i) * i.n for i in insts)
+    kg_work = [i.spec.keygen_work(n_bits, f_bits, i.n) for i in insts]
+    kg_aes = sum(w[0] for w in kg_work)
+    kg_lookups = sum(w[1] for w in kg_work)
 
     # Dealer work of different operators is independent: with several operators
     # it is spread over side streams (joined before evaluation), so the
     # keygen of a small operator overlaps that of a large one.
     dealers = [torch.cuda.Stream() for _ in range(min(4, len(insts)))] if len(insts) > 1 else []
 
-    def step(k: int, fused: bool, ev):
+    def step(k: int, fused: bool, ev, seeds=None):
         base = 0xB3C4 + 7919 * k
         ev[0].record(stream)
+        seed_of = (lambda j, op: op.seed) if seeds == "op" else (lambda j, op: (op.seed ^ base) + j)
         if dealers:
             for d in dealers:
                 d.wait_event(ev[0])
             for j, (inst, op) in enumerate(zip(insts, ops)):
                 with torch.cuda.stream(dealers[j % len(dealers)]):
-                    inst.keygen((op.seed ^ base) + j)
+                    inst.keygen(seed_of(j, op))
                     inst.mask()
             for d in dealers:
                 done = torch.cuda.Event()
@@ -224,7 +236,7 @@ def main() -> None:
                 stream.wait_event(done)
         else:
             for j, (inst, op) in enumerate(zip(insts, ops)):
-                inst.keygen((op.seed ^ base) + j)
+                inst.keygen(seed_of(j, op))
                 inst.mask()
         ev[1].record(stream)
         if fused:
@@ -240,35 +252,64 @@ def main() -> None:
                 inst.eval_plain(1)
         ev[2].record(stream)
 
-    def warm(fused: bool):
-        for k in range(args.warmup):
-            step(k, fused, [torch.cuda.Event(enable_timing=True) for _ in range(3)])
-        torch.cuda.synchronize()
+    def events():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(3)]
 
-    def run(fused: bool):
-        warm(fused)
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            step(args.warmup + k, fused, evs[k])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
+    def check_status():
         code = F.fss_status()
         if code != 0:
             raise SystemExit(f"device status {code}")
-        kg = [e[0].elapsed_time(e[1]) for e in evs]
-        ev = [e[1].elapsed_time(e[2]) for e in evs]
-        lat = [e[0].elapsed_time(e[2]) for e in evs]
-        return {"wall_s": wall, "keygen_ms": statistics.mean(kg), "eval_ms": statistics.mean(ev),
-                "lat": lat}
 
     # Both paths are warmed up before either is timed, so neither run carries
     # the first launches' start-up (clock ramp, first-touch of the buffers).
+    for k in range(args.warmup):
+        step(k, True, events())
+        if not args.no_plain:
+            step(k, False, events())
+    torch.cuda.synchronize()
+
+    # The timed steps: K fused steps back to back between two synchronisations.
+    evs = [events() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k, True, evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    check_status()
+    fused = {"wall_s": wall, "keygen_ms": statistics.mean(e[0].elapsed_time(e[1]) for e in evs),
+             "eval_ms": statistics.mean(e[1].elapsed_time(e[2]) for e in evs),
+             "lat": [e[0].elapsed_time(e[2]) for e in evs]}
+
+    # Fused against plain: pairs of steps with the same seeds, the order
+    # alternating from pair to pair so that neither path always follows the
+    # other (the part carries its clock from one kernel to the next); every
+    # step is bracketed by synchronisations.  Latency percentiles come from
+    # these repetitions.
+    cmp = None
     if not args.no_plain:
-        warm(False)
-    fused = run(True)
-    plain = None if args.no_plain else run(False)
+        reps = max(args.latency_reps, 50)
+        rec = {True: [], False: []}
+        for k in range(reps):
+            for fz in ((True, False) if k % 2 == 0 else (False, True)):
+                ev = events()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                step(1000 + k, fz, ev)
+                torch.cuda.synchronize()
+                rec[fz].append((time.perf_counter() - t1, ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]),
+                                ev[0].elapsed_time(ev[2])))
+        check_status()
+
+        def summary(rows):
+            lat = [r[3] for r in rows]
+            ev_ = [r[2] for r in rows]
+            return {"step_wall_ms": round(1e3 * statistics.mean(r[0] for r in rows), 4),
+                    "keygen_ms": round(statistics.mean(r[1] for r in rows), 4),
+                    "eval_ms": round(statistics.mean(ev_), 4),
+                    "latency_ms": {"p50": round(pct(lat, 0.5), 4), "p99": round(pct(lat, 0.99), 4)},
+                    "eval_latency_ms": {"p50": round(pct(ev_, 0.5), 4), "p99": round(pct(ev_, 0.99), 4)}}
+        cmp = {"reps": reps, "fused": summary(rec[True]), "plain": summary(rec[False])}
 
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
@@ -282,6 +323,8 @@ def main() -> None:
     eval_s = fused["eval_ms"] / 1e3
     achieved = eval_lookups / eval_s / 1e12
     valu_achieved = eval_aes * OPS_PER_AES / eval_s / 1e12
+    kg_s = fused["keygen_ms"] / 1e3
+    kg_achieved = kg_lookups / kg_s / 1e12
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -300,10 +343,9 @@ def main() -> None:
                    "path": "fused persistent work-list" + (", HIP graph per layer" if graphs else ""),
                    "launches_per_step": len(plans),
                    "step": "keygen (both parties) + masked opening + eval (both parties)",
-                   "launch": cfg, "autotuned": bool(args.autotune),
+                   "launch": cfg, "autotuned": tune is not None,
                    "lookup_r": insts[0].lookup_r,
                    "key_bytes_per_party": sum(i.key_bytes for i in insts)},
-        "latency_ms": {"p50": round(pct(fused["lat"], 0.5), 4), "p99": round(pct(fused["lat"], 0.99), 4)},
         "breakdown_ms": {"keygen": round(fused["keygen_ms"], 4), "eval": round(fused["eval_ms"], 4)},
         "aes_blocks_per_s": round((eval_aes + kg_aes) * args.steps / fused["wall_s"], 1),
         "eval_only_element_evals_per_s": round(evals / eval_s, 1),
@@ -315,17 +357,44 @@ def main() -> None:
                      "aes_blocks_per_launch": eval_aes / len(plans),
                      "valu": {"achieved": round(valu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
                               "unit": "Tops/s", "frac": round(valu_achieved / VALU_PEAK_TOPS, 4),
-                              "ops_per_aes_block": OPS_PER_AES}},
+                              "ops_per_aes_block": OPS_PER_AES},
+                     "keygen": {"kernel": "k_keygen", "achieved": round(kg_achieved, 3),
+                                "peak": round(LOOKUP_PEAK_T, 3), "unit": "T table-lookups/s",
+                                "frac": round(kg_achieved / LOOKUP_PEAK_T, 4),
+                                "lookups_per_step": kg_lookups, "aes_blocks_per_step": kg_aes,
+                                "ms": round(fused["keygen_ms"], 4)}},
     }
-    if plain is not None:
-        out["plain"] = {"value": round(evals * args.steps / plain["wall_s"], 1),
-                        "ms_per_step": round(plain["wall_s"] * 1e3 / args.steps, 4),
-                        "latency_ms": {"p50": round(pct(plain["lat"], 0.5), 4),
-                                       "p99": round(pct(plain["lat"], 0.99), 4)},
-                        "eval_ms": round(plain["eval_ms"], 4)}
-        out["fused_over_plain"] = round(out["value"] / out["plain"]["value"], 4)
+    if cmp is None:
+        out["latency_ms"] = {"p50": round(pct(fused["lat"], 0.5), 4), "p99": round(pct(fused["lat"], 0.99), 4),
+                             "samples": args.steps, "of": "the timed steps (keygen + opening + eval), HIP events"}
+    else:
+        f_, p_ = cmp["fused"], cmp["plain"]
+        out["latency_ms"] = dict(f_["latency_ms"], samples=cmp["reps"],
+                                 of="step (keygen + opening + eval), HIP events, over the fused/plain pairs "
+                                    "run after the timed steps")
+        out["eval_latency_ms"] = dict(f_["eval_latency_ms"], samples=cmp["reps"])
+        out["plain"] = {"value": round(evals / (p_["step_wall_ms"] / 1e3), 1), "step_wall_ms": p_["step_wall_ms"],
+                        "keygen_ms": p_["keygen_ms"], "eval_ms": p_["eval_ms"],
+                        "latency_ms": p_["latency_ms"], "eval_latency_ms": p_["eval_latency_ms"]}
+        out["fused_paired"] = {"value": round(evals / (f_["step_wall_ms"] / 1e3), 1),
+                               "step_wall_ms": f_["step_wall_ms"], "keygen_ms": f_["keygen_ms"],
+                               "eval_ms": f_["eval_ms"]}
+        out["fused_over_plain"] = round(p_["step_wall_ms"] / f_["step_wall_ms"], 4)
+        out["eval_fused_over_plain"] = round(p_["eval_ms"] / f_["eval_ms"], 4)
+        out["comparison"] = (f"{cmp['reps']} pairs of one fused and one plain step with the same seeds, "
+                             "order alternating, each step between synchronisations")
+
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ops[0], n_bits, f_bits, args.cpu_seconds)
+        def gpu_shares(count):
+            # one fused step at the operator's own seed, first `count` elements
+            step(0, True, events(), seeds="op")
+            torch.cuda.synchronize()
+            check_status()
+            h = insts[0].host()
+            return {"y0": h["y0"][:count], "y1": h["y1"][:count], "r_in": h["r_in"][:count],
+                    "r_out": h["r_out"][:count], "z0": R.unpack_bits(h["z0"], insts[0].n)[:count],
+                    "z1": R.unpack_bits(h["z1"], insts[0].n)[:count]}
+        out["cpu_baseline"] = cpu_baseline(ops[0], n_bits, f_bits, insts[0].lookup_r, gpu_shares)
     print(json.dumps(out), flush=True)
 
 

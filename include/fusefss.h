@@ -101,6 +101,26 @@ int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces,
                      fss_spec** out);
 void fss_spec_free(fss_spec* spec);
 
+/* The Definition "Operator specification" in its integer form, as the paper
+ * states it over Z_{2^n}: boundaries 0 = alpha_0 < alpha_1 < ... < alpha_m =
+ * 2^n_bits over the canonical representatives {0, ..., 2^n_bits - 1}, piece i
+ * applying to the inputs whose representative lies in [alpha_i, alpha_{i+1}),
+ * and ring coefficients in Z_{2^64} (the polynomial is evaluated at the
+ * input's 64-bit value, mod 2^64).  This is the form of the appendix's worked
+ * example (ReLU with alpha_1 = 2^(n-1)).
+ *   alpha: host, m + 1 u64.  coef: host, m * (degree + 1) u64, row-major,
+ *     lowest degree first.  preds: host (NULL when n_preds == 0); comparison
+ *     thresholds `thr` must be integers (there are no fractional bits).
+ *   The spec is used at (n_bits, frac_bits = 0) only; other sizes return
+ *   FSS_E_SHAPE.  Call 2 then reads the unshifted view xhat mod 2^n_bits
+ *   (real-valued specs read the offset-binary view of the signed order).
+ *   Errors: FSS_E_INVALID_SPEC for boundaries that do not run increasing from
+ *   0 to 2^n_bits, a degree outside [0, 3] or a non-integer threshold;
+ *   FSS_E_UNSUPPORTED for n_bits outside [2, 32]; FSS_E_NEEDS_PHI for AND/OR.
+ *   *out receives a handle owned by the caller (free with fss_spec_free). */
+int fss_compile_spec_int(int32_t n_bits, int32_t m, const uint64_t* alpha, int32_t degree,
+                         const uint64_t* coef, const fss_pred* preds, int32_t n_preds, fss_spec** out);
+
 /* Input bits per level of call 2's vector DCF (the interval lookup of
  * Definition "Interval lookup with vector payload", realised as one DCF
  * evaluated at m points): 2, 3 or 4, i.e. 4, 8 or 16 children per level and
@@ -144,14 +164,27 @@ int fss_key_bytes(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64
                   size_t* per_party);
 
 /* Generate both parties' keys for n_elems fresh gate instances.
+ *   seed: host, 16 bytes: the AES-128 key of the dealer's randomness (a
+ *     128-bit integer in little-endian byte order), so the masks have the
+ *     security parameter of Gen(1^lambda) (Sec. "Threat Model and
+ *     Preprocessing").  Read before the call returns.
  *   key0, key1: device, fss_key_bytes each (key1 may be NULL to skip party 1).
  *   r_in, r_out: device, n_elems u64 each (the dealer's masks; may be NULL).
  * Each element e draws all of its randomness from AES keyed by `seed`
  * (counter mode over e), so the output is a pure function of the arguments.
  * Keys are one-time material: evaluate each buffer on one input only. */
-int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t seed,
+int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, const uint8_t* seed,
                int64_t n_elems, void* key0, void* key1, uint64_t* r_in, uint64_t* r_out,
                void* stream);
+
+/* Work of one fss_keygen call over n_elems elements, as the kernel computes
+ * it (host out-params): AES-128 blocks, and T-table lookups (16 per round,
+ * less the 24 lookups of rounds 1-2 shared by the blocks that expand one seed
+ * under several tweaks).  Per element: both parties' two children of every
+ * comparison-DCF level, both parties' 2^r children of every lookup-DCF level,
+ * and the counter-mode randomness blocks.  Used for throughput reporting. */
+int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems,
+                    double* aes_blocks, double* table_lookups);
 
 /* Protocol "Shares -> masked opening" collapsed to one process that holds
  * the plaintext: xhat[e] = x[e] + r_in[e] mod 2^64 (all device, n each). */
@@ -188,26 +221,46 @@ typedef struct {
 
 /* Launch configuration of the persistent kernel (0 = library default). */
 typedef struct {
-  int32_t block_threads;  /* 64 .. 1024, multiple of 64 */
+  int32_t block_threads;  /* set by the library from the table layout */
   int32_t blocks_per_cu;  /* resident blocks per compute unit */
   int32_t aes_variant;    /* AES table layout, 0 .. fss_aes_variants()-1 */
   int32_t order;          /* 0: costliest tiles first, 1: work-list order */
+  int32_t parts;          /* units call 2 of a tile is split into: 0 = planner's choice, 1 .. 4 */
+  int32_t pred_unit;      /* call 1 of a tile: 0 = planner's choice, 1 = in the unit that runs
+                             call 2's first part (one pass over the elements), 2 = its own unit */
 } fss_tune;
 
 typedef struct fss_plan fss_plan;
 
-/* Build a work-list plan: reads each item's key header (synchronously, once),
- * uploads the tile list, and records the launch configuration (`tune` may be
- * NULL for defaults).  Items may mix parties, specs and sizes. */
+/* Build a work-list plan: reads each item's key header (synchronously, once;
+ * the keys must have been generated), uploads the unit list, and records the
+ * launch configuration (`tune` may be NULL for defaults).  Items may mix
+ * parties, specs and sizes.  A unit is normally one tile's call 1 and call 2
+ * in one pass over its elements; when whole tiles would leave waves idle the
+ * planner splits call 2 into parts and may run call 1 as a unit of its own
+ * (fss_plan_config reports the choice). */
 int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune* tune,
                     fss_plan** out);
-/* One persistent launch evaluating both calls of every element of every item
- * in a single pass.  Enqueue-only and safe to capture into a HIP graph. */
+/* One persistent launch evaluating both calls of every element of every item.
+ * Enqueue-only and safe to capture into a HIP graph. */
 int fss_plan_launch(fss_plan* plan, void* stream);
-/* Waits for the plan's last launch (direct or through a graph), then returns
- * its device buffers to the library's pool.  Free graphs that captured a plan
- * before the plan itself. */
+/* Releases the plan without waiting: its device buffers return to the
+ * library's pool once its last launch (direct or through a graph) has
+ * completed.  Free graphs that captured a plan before the plan itself. */
 int fss_plan_free(fss_plan* plan);
+
+/* Fused, batched evaluation of a work-list in one call (Sec. 5.3 "Online
+ * Evaluation" for many gate instances at once): plan, one persistent launch
+ * on `stream`, release.  `party` is 0 or 1, and then every item must be that
+ * party's, or FSS_PARTY_ANY to let the items mix parties (both parties
+ * simulated on one device).  The planner reads the items' key headers on the
+ * host, so the call first waits for the work already enqueued on `stream`
+ * (for example the keygen that wrote them); it returns once the launch is
+ * enqueued.  Errors: FSS_E_PARTY (an item of the other party, or a bad
+ * `party`), FSS_E_SHAPE (not a key buffer, n_elems beyond the keys),
+ * FSS_E_ARG (NULL buffers), FSS_E_HIP. */
+#define FSS_PARTY_ANY (-1)
+int fss_eval_batch(int32_t party, const fss_work_item* items, int32_t n_items, void* stream);
 /* AES-128 blocks one launch of `plan` evaluates, as the kernels compute them
  * (per element and party, with B = 1 + ceil(p/2) blocks per level of the
  * lookup DCF and ceil(p/2) at its last level, L = ceil(n/r) levels of 2^r
@@ -228,7 +281,8 @@ double fss_plan_table_lookups(const fss_plan* plan);
  * adds its share of y (mod 2^64, exact) into y, which the launch zeroes first.
  * Returns 0 for a NULL plan. */
 int fss_plan_parts(const fss_plan* plan);
-/* Resolved launch configuration of a plan (host out-params). */
+/* Resolved launch configuration of a plan (host out-params): the tune with
+ * `parts` and `pred_unit` set to the planner's choice. */
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid);
 
 /* Capture the launches of n_plans plans, in order, into one HIP graph. */

@@ -346,3 +346,10 @@ def protocol3(n: int, alpha, r: int):
 
 def hw_threads() -> int:
     return lib().orc_hw_threads()
+
+
+def aes_blocks() -> int:
+    """AES-128 blocks the batched drivers have encrypted so far in this process."""
+    L = lib()
+    L.orc_aes_blocks.restype = C.c_uint64
+    return int(L.orc_aes_blocks())

@@ -171,6 +171,8 @@ int orc_full_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* ele
                    const int64_t* x, uint64_t* y0, uint64_t* y1, uint64_t* z0, uint64_t* z1,
                    uint64_t* r_in, uint64_t* r_out, int threads);
 int orc_hw_threads(void);
+/* AES-128 blocks the batched drivers have encrypted so far (all threads). */
+uint64_t orc_aes_blocks(void);
 int orc_sizeof_elem_key(void);
 int orc_sizeof_dcf_key(void);
 int orc_sizeof_dcfr_key(void);

@@ -135,6 +135,11 @@ struct fss_spec {
   std::vector<fss_piece> pc;
   std::vector<fss_pred> pr;
   int32_t out_frac_bits = -1;
+  // Integer form (fss_compile_spec_int): boundaries over canonical
+  // representatives of Z_{2^n} and ring coefficients, fixed n, no fraction.
+  bool is_int = false;
+  int32_t int_n = 0, int_degree = 0;
+  std::vector<uint64_t> ialpha, icoef;
   int32_t lookup_r = kDefaultLookupR;  // input bits per level of call 2's DCF
   uint64_t hash = 0;
   std::mutex mu;
@@ -155,12 +160,29 @@ uint64_t fnv1a(const void* data, size_t len, uint64_t h = 0xcbf29ce484222325ull)
 int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out) {
   if (n < 2 || n > 32) return fail(FSS_E_UNSUPPORTED, "n_bits=%d outside [2,32]", n);
   if (f < 0 || f >= n) return fail(FSS_E_UNSUPPORTED, "frac_bits=%d must be in [0,n_bits)", f);
+  if (S->is_int && (n != S->int_n || f != 0))
+    return fail(FSS_E_SHAPE, "integer spec over n_bits=%d used at n_bits=%d frac_bits=%d", S->int_n, n, f);
   auto q = std::make_shared<QSpec>();
-  const int m = (int)S->iv.size();
+  const int m = S->is_int ? (int)S->ialpha.size() - 1 : (int)S->iv.size();
   const int64_t N = (int64_t)1 << n, s = N / 2;
   q->n = n;
   q->f = f;
   q->m = m;
+  int d = 0;
+  if (S->is_int) {
+    // Integer form: the boundaries are canonical representatives already and
+    // the coefficients ring elements; the lookup reads the unshifted view.
+    for (int i = 0; i <= m; ++i) {
+      q->alpha[i] = (int64_t)S->ialpha[i];
+      q->aprime[i] = S->ialpha[i];
+    }
+    d = S->int_degree;
+    q->d = d;
+    q->p = d + 1;
+    q->F_out = 0;
+    for (int i = 0; i < m; ++i)
+      for (int l = 0; l <= d; ++l) q->coef[i][l] = S->icoef[(size_t)i * (d + 1) + l];
+  } else {
   // Partition: real boundary a -> ceil(a 2^f), the first grid point >= a.
   q->alpha[0] = -s;
   q->alpha[m] = s;
@@ -170,7 +192,6 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
       return fail(FSS_E_INVALID_SPEC, "boundaries %d and %d coincide at n=%d f=%d", i, i + 1, n, f);
   for (int i = 0; i <= m; ++i) q->aprime[i] = (uint64_t)(q->alpha[i] + s);
   // Pieces.
-  int d = 0;
   for (const auto& pc : S->pc) d = std::max(d, (int)pc.degree);
   q->d = d;
   q->p = d + 1;
@@ -189,6 +210,7 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
     }
     if (!(bound < 4611686018427387904.0))
       return fail(FSS_E_INVALID_SPEC, "piece %d may reach |P| >= 2^62 on its interval", i);
+  }
   }
   // Predicates -> (view, threshold) atoms, sentinels folded into constants.
   struct View { int k; uint64_t c; };
@@ -281,6 +303,8 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
   // chosen to minimise the AES blocks of the walks, B <= kMaxTopBlocks,
   // K < n; no sharing (D = 0) when m < 4 or nothing is saved.
   h.lookup_r = (uint32_t)r;
+  h.lookup_c = S->is_int ? 0u : (uint32_t)s;
+  h.is_int = S->is_int ? 1u : 0u;
   {
     const uint64_t W = (m >= 2) ? (q->aprime[m - 1] - q->aprime[1] + 1) : 1;
     const int L = (n + r - 1) / r;
@@ -374,10 +398,25 @@ int device_header(const fss_spec* Sc, QSpec* q, uint8_t** out) {
   return FSS_OK;
 }
 
-void seed_round_keys(uint64_t seed, uint32_t rk[44]) {
-  uint8_t key[16] = {};
-  for (int i = 0; i < 8; ++i) key[i] = (uint8_t)(seed >> (8 * i));
-  expand_key(kAes.sbox, key, rk);
+// The dealer's randomness R(e, purpose, ctr) is AES-128 keyed by the whole
+// 16-byte seed, so the masks carry the full security parameter.
+void seed_round_keys(const uint8_t seed[16], uint32_t rk[44]) { expand_key(kAes.sbox, seed, rk); }
+
+// Predicate list checks shared by both spec forms.  Integer specs take
+// integer comparison thresholds (they have no fractional bits).
+int check_preds(const fss_pred* preds, int32_t n_preds, bool integer) {
+  for (int j = 0; j < n_preds; ++j) {
+    if (preds[j].combine == FSS_COMBINE_AND || preds[j].combine == FSS_COMBINE_OR)
+      return fail(FSS_E_NEEDS_PHI, "predicate %d combines with AND/OR: needs post-processing", j);
+    if (preds[j].combine != FSS_COMBINE_XOR) return fail(FSS_E_UNSUPPORTED, "predicate %d combine", j);
+    if (preds[j].out < 0 || preds[j].out >= 64) return fail(FSS_E_UNSUPPORTED, "predicate %d out", j);
+    if (preds[j].kind < FSS_PRED_LT_SIGNED || preds[j].kind > FSS_PRED_MSB_SHIFT)
+      return fail(FSS_E_UNSUPPORTED, "predicate %d kind %d", j, preds[j].kind);
+    if (integer && (preds[j].kind == FSS_PRED_LT_SIGNED || preds[j].kind == FSS_PRED_LT_UNSIGNED) &&
+        preds[j].thr != std::floor(preds[j].thr))
+      return fail(FSS_E_INVALID_SPEC, "predicate %d: integer specs take integer thresholds", j);
+  }
+  return FSS_OK;
 }
 
 int check_party(int32_t party) {
@@ -413,14 +452,8 @@ int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces,
     for (int l = 0; l <= pieces[i].degree; ++l)
       if (!std::isfinite(pieces[i].coef[l])) return fail(FSS_E_INVALID_SPEC, "piece %d coef %d not finite", i, l);
   }
-  for (int j = 0; j < n_preds; ++j) {
-    if (preds[j].combine == FSS_COMBINE_AND || preds[j].combine == FSS_COMBINE_OR)
-      return fail(FSS_E_NEEDS_PHI, "predicate %d combines with AND/OR: needs post-processing", j);
-    if (preds[j].combine != FSS_COMBINE_XOR) return fail(FSS_E_UNSUPPORTED, "predicate %d combine", j);
-    if (preds[j].out < 0 || preds[j].out >= 64) return fail(FSS_E_UNSUPPORTED, "predicate %d out", j);
-    if (preds[j].kind < FSS_PRED_LT_SIGNED || preds[j].kind > FSS_PRED_MSB_SHIFT)
-      return fail(FSS_E_UNSUPPORTED, "predicate %d kind %d", j, preds[j].kind);
-  }
+  int rc = check_preds(preds, n_preds, false);
+  if (rc) return rc;
   fss_spec* S = new (std::nothrow) fss_spec();
   if (!S) return fail(FSS_E_OOM, "out of host memory");
   S->iv.assign(iv, iv + m);
@@ -431,6 +464,42 @@ int fss_compile_spec(const fss_interval* iv, int32_t m, const fss_piece* pieces,
   h = fnv1a(pieces, sizeof(fss_piece) * m, h);
   if (n_preds) h = fnv1a(preds, sizeof(fss_pred) * n_preds, h);
   h = fnv1a(&out_frac_bits, sizeof out_frac_bits, h);
+  S->hash = h;
+  *out = S;
+  return FSS_OK;
+}
+
+int fss_compile_spec_int(int32_t n_bits, int32_t m, const uint64_t* alpha, int32_t degree, const uint64_t* coef,
+                         const fss_pred* preds, int32_t n_preds, fss_spec** out) {
+  if (!out) return fail(FSS_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!alpha || !coef) return fail(FSS_E_ARG, "alpha/coef NULL");
+  if (n_bits < 2 || n_bits > 32) return fail(FSS_E_UNSUPPORTED, "n_bits=%d outside [2,32]", n_bits);
+  if (m < 1 || m > FSS_MAX_INTERVALS) return fail(FSS_E_INVALID_SPEC, "m=%d outside [1,%d]", m, FSS_MAX_INTERVALS);
+  if (degree < 0 || degree > FSS_MAX_DEGREE) return fail(FSS_E_INVALID_SPEC, "degree %d outside [0,3]", degree);
+  if (n_preds < 0 || n_preds > FSS_MAX_PREDS) return fail(FSS_E_UNSUPPORTED, "n_preds=%d", n_preds);
+  if (n_preds > 0 && !preds) return fail(FSS_E_ARG, "preds NULL");
+  const uint64_t N = 1ull << n_bits;
+  if (alpha[0] != 0 || alpha[m] != N) return fail(FSS_E_INVALID_SPEC, "boundaries must run from 0 to 2^n");
+  for (int i = 1; i <= m; ++i)
+    if (!(alpha[i - 1] < alpha[i])) return fail(FSS_E_INVALID_SPEC, "boundaries %d and %d not increasing", i - 1, i);
+  int rc = check_preds(preds, n_preds, true);
+  if (rc) return rc;
+  fss_spec* S = new (std::nothrow) fss_spec();
+  if (!S) return fail(FSS_E_OOM, "out of host memory");
+  S->is_int = true;
+  S->int_n = n_bits;
+  S->int_degree = degree;
+  S->ialpha.assign(alpha, alpha + m + 1);
+  S->icoef.assign(coef, coef + (size_t)m * (degree + 1));
+  if (n_preds) S->pr.assign(preds, preds + n_preds);
+  S->out_frac_bits = 0;
+  uint64_t h = fnv1a("int", 3);
+  h = fnv1a(&n_bits, sizeof n_bits, h);
+  h = fnv1a(alpha, sizeof(uint64_t) * (m + 1), h);
+  h = fnv1a(&degree, sizeof degree, h);
+  h = fnv1a(coef, sizeof(uint64_t) * m * (degree + 1), h);
+  if (n_preds) h = fnv1a(preds, sizeof(fss_pred) * n_preds, h);
   S->hash = h;
   *out = S;
   return FSS_OK;
@@ -502,9 +571,9 @@ int fss_key_bytes(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64
   return FSS_OK;
 }
 
-int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t seed, int64_t n_elems,
+int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, const uint8_t* seed, int64_t n_elems,
                void* key0, void* key1, uint64_t* r_in, uint64_t* r_out, void* stream) {
-  if (!spec || !key0) return fail(FSS_E_ARG, "spec/key0 NULL");
+  if (!spec || !key0 || !seed) return fail(FSS_E_ARG, "spec/seed/key0 NULL");
   if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
   std::shared_ptr<QSpec> q;
   int rc = get_qspec(spec, n_bits, frac_bits, &q);
@@ -527,6 +596,32 @@ int fss_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, uint64_t
   HIP_TRY(launch_keygen(keygen_variant(), q->p, (int)q->hdr.lookup_r, reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
                         (uint8_t*)key1, r_in, r_out, cus, st),
           "keygen launch");
+  return FSS_OK;
+}
+
+int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, double* aes_blocks,
+                    double* table_lookups) {
+  if (!spec || !aes_blocks || !table_lookups) return fail(FSS_E_ARG, "NULL argument");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  std::shared_ptr<QSpec> q;
+  int rc = get_qspec(spec, n_bits, frac_bits, &q);
+  if (rc) return rc;
+  const KeyHeader& h = q->hdr;
+  auto shared = [](double K) { return 160.0 * K - 24.0 * (K - 1.0); };
+  const double nb = (double)((h.p + 1) / 2), C = (double)(1u << h.lookup_r);
+  const double L = (double)((h.n + h.lookup_r - 1) / h.lookup_r);
+  double atoms_lv = 0;
+  for (uint32_t t = 0; t < h.T; ++t) atoms_lv += h.atom_k[t];
+  // Both parties' children: two tweaks per Z_2 level, 2^r children of
+  // 1 + nb blocks per lookup level above the last and of nb at the last.
+  const double prg_aes = atoms_lv * 2 * 2 + C * 2 * ((L - 1) * (1 + nb) + nb);
+  const double prg_lk = atoms_lv * 2 * shared(2) + C * 2 * ((L - 1) * shared(1 + nb) + shared(nb));
+  // Counter-mode randomness: masks (drawn by both halves of the work), the
+  // r_out share, two roots per atom, carries, two lookup roots, two rho-share
+  // blocks and 1 + nb on-path corrections per lookup level above the last.
+  const double rnd = 8.0 + 2.0 * h.T + (L - 1) * (1 + nb);
+  *aes_blocks = (prg_aes + rnd) * (double)n_elems;
+  *table_lookups = (prg_lk + 160.0 * rnd) * (double)n_elems;
   return FSS_OK;
 }
 
@@ -609,6 +704,7 @@ struct fss_plan {
   uint32_t n_split = 0;
   uint64_t max_split_elems = 0;
   int parts = 1;                  // parts per tile chosen by the planner
+  bool merged_pred = true;        // call 1 runs in call 2's first unit of a tile
   fss_tune tune{};
   int grid = 0;
   double aes_per_launch = 0;  // algorithmic AES blocks of one launch
@@ -621,16 +717,37 @@ struct fss_plan {
 namespace {
 // Device buffers of freed plans are kept per device and reused, so building a
 // plan per scheduling step does not allocate once the pool is warm.
+// A freed plan whose last launch may still run parks its buffers with that
+// launch's event; they rejoin the pool once the event has completed.
 struct PoolBuf { int dev; size_t bytes; void* p; };
+struct PoolPending { hipEvent_t ev; std::vector<void*> bufs; };
 std::mutex g_pool_mu;
 std::vector<PoolBuf> g_pool_free;
+std::vector<PoolPending> g_pool_pending;
 std::map<void*, PoolBuf> g_pool_all;
+
+// Caller holds g_pool_mu.
+void pool_reclaim_locked() {
+  for (size_t i = 0; i < g_pool_pending.size();) {
+    if (hipEventQuery(g_pool_pending[i].ev) == hipSuccess) {
+      for (void* p : g_pool_pending[i].bufs) {
+        auto it = g_pool_all.find(p);
+        if (it != g_pool_all.end()) g_pool_free.push_back(it->second);
+      }
+      (void)hipEventDestroy(g_pool_pending[i].ev);
+      g_pool_pending.erase(g_pool_pending.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
 
 int pool_get(size_t bytes, void** out) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
   {
     std::lock_guard<std::mutex> lk(g_pool_mu);
+    pool_reclaim_locked();
     int bi = -1;
     for (size_t i = 0; i < g_pool_free.size(); ++i)
       if (g_pool_free[i].dev == dev && g_pool_free[i].bytes >= bytes &&
@@ -655,11 +772,25 @@ void pool_put(void* p) {
   auto it = g_pool_all.find(p);
   if (it != g_pool_all.end()) g_pool_free.push_back(it->second);
 }
+
+// Buffers that may be handed to another plan only after `ev` completes.
+void pool_put_after(hipEvent_t ev, std::vector<void*> bufs) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pool_pending.push_back(PoolPending{ev, std::move(bufs)});
+}
 }  // namespace
 
 fss_plan::~fss_plan() {
-  // Buffers may be handed to another plan only after the last enqueued launch.
-  if (launched) (void)hipEventSynchronize(done);
+  // Buffers may be handed to another plan only after the last enqueued
+  // launch: a launched plan parks them with its completion event instead of
+  // waiting, so freeing never blocks the host.
+  if (launched && done) {
+    std::vector<void*> bufs;
+    for (void* p : {(void*)d_items, (void*)d_tiles, (void*)d_counter, (void*)d_split})
+      if (p) bufs.push_back(p);
+    pool_put_after(done, std::move(bufs));
+    return;
+  }
   if (done) (void)hipEventDestroy(done);
   pool_put(d_items);
   pool_put(d_tiles);
@@ -695,6 +826,7 @@ struct ElemCost {
   double aes_pred = 0, aes_base = 0, aes_tops = 0, aes_point = 0;
   double lk_pred = 0, lk_base = 0, lk_tops = 0, lk_point = 0;
   int points = 0;  // m - 1
+  int ell = 0;     // predicate output bits: call 1 runs (and writes them) whenever ell > 0
 };
 
 ElemCost elem_cost(const KeyHeader& h) {
@@ -714,6 +846,7 @@ ElemCost elem_cost(const KeyHeader& h) {
   c.aes_point = (L - D - 1) * lvl + nb;
   c.lk_point = (L - D - 1) * shared(lvl) + shared(nb);
   c.points = (int)h.m - 1;
+  c.ell = (int)h.ell;
   return c;
 }
 
@@ -723,13 +856,16 @@ struct Unit {
   double aes, lookups;
 };
 
-// The units of one tile: call 1 on its own (when the spec has atoms), and
-// call 2 whole or split into `parts` (at most one per lookup point), with
-// flags, point range and per-element cost.  Call 2's part 0 carries the base
-// (the walk at v) and so takes fewer points.  Every tile of an item splits the
-// same way.  Call 1 as a unit of its own lets the costlier call-2 units run
-// first and the short call-1 units fill the end of the schedule.
-std::vector<Unit> tile_parts(const ElemCost& c, int parts) {
+// The units of one tile: call 2 whole or split into `parts` (at most one per
+// lookup point), with flags, point range and per-element cost, and call 1
+// (whenever the spec has predicate bits, even if every predicate folded to a
+// constant: the unit still writes them).  Call 2's part 0 carries the base
+// (the walk at v) and so takes fewer points.  With `merge_pred`, call 1 runs
+// in part 0's unit: one pass over the tile's elements (x-hat loaded once);
+// otherwise it is a unit of its own, which lets the costlier call-2 units run
+// first and the short call-1 units fill the end of the schedule.  Every tile
+// of an item splits the same way.
+std::vector<Unit> tile_parts(const ElemCost& c, int parts, bool merge_pred) {
   std::vector<Unit> out;
   const int S = std::max(1, std::min(parts, c.points));
   if (S == 1) {
@@ -738,8 +874,9 @@ std::vector<Unit> tile_parts(const ElemCost& c, int parts) {
                    c.aes_base + tops * c.aes_tops + c.points * c.aes_point,
                    c.lk_base + tops * c.lk_tops + c.points * c.lk_point});
   } else {
-    const double total = c.aes_base + c.points * c.aes_point;
-    int k0 = (int)std::lround((total / S - c.aes_base) / c.aes_point);
+    const double total = c.aes_base + c.points * c.aes_point + (merge_pred ? c.aes_pred : 0.0);
+    const double base = c.aes_base + (merge_pred ? c.aes_pred : 0.0);
+    int k0 = (int)std::lround((total / S - base) / c.aes_point);
     k0 = std::max(0, std::min(k0, c.points - (S - 1)));
     const int rest = c.points - k0;
     int i = 1;
@@ -757,7 +894,15 @@ std::vector<Unit> tile_parts(const ElemCost& c, int parts) {
       i += k;
     }
   }
-  if (c.aes_pred > 0) out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred, c.lk_pred});
+  if (c.ell > 0) {
+    if (merge_pred) {
+      out[0].flags |= kUnitPred;
+      out[0].aes += c.aes_pred;
+      out[0].lookups += c.lk_pred;
+    } else {
+      out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred, c.lk_pred});
+    }
+  }
   return out;
 }
 
@@ -819,6 +964,8 @@ fss_tune default_tune() {
   t.block_threads = variant_block(t.aes_variant);
   t.blocks_per_cu = 0;
   t.order = 0;
+  t.parts = 0;
+  t.pred_unit = 0;
   return t;
 }
 
@@ -840,6 +987,10 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   if (n_items < 0 || (n_items > 0 && !items)) return fail(FSS_E_ARG, "bad items");
   fss_tune tn = tune ? *tune : default_tune();
   if (tn.aes_variant < 0 || tn.aes_variant >= kNumAesVariants) return fail(FSS_E_ARG, "aes_variant");
+  if (tn.parts < 0 || tn.parts > 4) return fail(FSS_E_ARG, "tune.parts=%d outside [0,4]", tn.parts);
+  if (tn.pred_unit < 0 || tn.pred_unit > 2) return fail(FSS_E_ARG, "tune.pred_unit=%d outside [0,2]", tn.pred_unit);
+  if (tn.order < 0 || tn.order > 1) return fail(FSS_E_ARG, "tune.order=%d outside [0,1]", tn.order);
+  if (tn.blocks_per_cu < 0 || tn.blocks_per_cu > 32) return fail(FSS_E_ARG, "tune.blocks_per_cu=%d", tn.blocks_per_cu);
   tn.block_threads = variant_block(tn.aes_variant);
   if (tn.blocks_per_cu <= 0) tn.blocks_per_cu = blocks_per_cu_default(tn.aes_variant);
   int cus = 0;
@@ -870,49 +1021,61 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   // tiles do not divide evenly over the resident waves, whole tiles leave some
   // waves a tile behind the others, and parts even that out at the price of
   // repeating the shared top walks.  Candidates: 1..4 parts for every tile,
-  // compared by the simulated schedule (all tiles of an item cost the same).
+  // call 1 in the first part's unit (one pass over the elements) or in a unit
+  // of its own, compared by the simulated schedule (all tiles of an item cost
+  // the same).  A tune's `parts` / `pred_unit` fix either choice.
   struct Group { double cost; uint32_t item, part; uint64_t count; };
-  auto groups_for = [&](int parts, std::vector<std::vector<Unit>>& tp, std::vector<Group>& g) {
+  auto groups_for = [&](int parts, bool merge, std::vector<std::vector<Unit>>& tp, std::vector<Group>& g) {
     tp.assign(n_items, {});
     g.clear();
     for (int i = 0; i < n_items; ++i) {
       if (dev[i].words == 0) continue;
-      tp[i] = tile_parts(cost[i], parts);
+      tp[i] = tile_parts(cost[i], parts, merge);
       for (uint32_t q = 0; q < tp[i].size(); ++q) g.push_back({tp[i][q].aes, (uint32_t)i, q, (uint64_t)dev[i].words});
     }
     if (tn.order == 0)
       std::stable_sort(g.begin(), g.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
   };
-  int best_parts = 1;
+  int best_parts = 0;
+  bool best_merge = true;
   double best_span = 0;
   uint64_t best_units = 0;
   std::vector<std::vector<Unit>> tp;
   std::vector<Group> groups;
-  for (int parts = 1; parts <= 4; ++parts) {
-    groups_for(parts, tp, groups);
-    uint64_t n_units = 0;
-    for (const Group& g : groups) n_units += g.count;
-    if (parts > 1 && n_units == best_units) break;  // nothing left to split
-    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * tn.blocks_per_cu,
-                                                                  (n_units + waves_per_block - 1) / waves_per_block));
-    ScheduleSim sim((uint64_t)grid * waves_per_block);
-    if (tn.order == 0) {
-      for (const Group& g : groups) sim.run(g.cost, g.count);
-    } else {  // natural order: tile by tile, parts in turn
-      for (int i = 0; i < n_items; ++i)
-        for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t)
-          for (const Unit& u : tp[i]) sim.run(u.aes, 1);
-    }
-    const double span = sim.makespan();
-    // a split has to win clearly: the simulation does not see that the last
-    // waves run faster once the others have finished
-    if (parts == 1 || span < best_span * 0.97) {
-      best_span = span;
-      best_parts = parts;
-      best_units = n_units;
+  int max_points = 1;  // a tile splits into at most one part per lookup point
+  for (int i = 0; i < n_items; ++i) max_points = std::max(max_points, cost[i].points);
+  const int p_lo = tn.parts > 0 ? tn.parts : 1, p_hi = tn.parts > 0 ? tn.parts : std::min(4, max_points);
+  for (int parts = p_lo; parts <= p_hi; ++parts) {
+    for (int mi = 0; mi < 2; ++mi) {
+      const bool merge = mi == 0;
+      if ((tn.pred_unit == 1 && !merge) || (tn.pred_unit == 2 && merge)) continue;
+      groups_for(parts, merge, tp, groups);
+      uint64_t n_units = 0;
+      for (const Group& g : groups) n_units += g.count;
+      const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)cus * tn.blocks_per_cu,
+                                                                    (n_units + waves_per_block - 1) / waves_per_block));
+      ScheduleSim sim((uint64_t)grid * waves_per_block);
+      if (tn.order == 0) {
+        for (const Group& g : groups) sim.run(g.cost, g.count);
+      } else {  // natural order: tile by tile, parts in turn
+        for (int i = 0; i < n_items; ++i)
+          for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t)
+            for (const Unit& u : tp[i]) sim.run(u.aes, 1);
+      }
+      const double span = sim.makespan();
+      // A candidate with more units has to win clearly: the simulation does
+      // not see that the last waves run faster once the others have finished,
+      // nor the second pass over x-hat of a separate call-1 unit.
+      if (best_parts == 0 || span < best_span * 0.97) {
+        best_span = span;
+        best_parts = parts;
+        best_merge = merge;
+        best_units = n_units;
+      }
     }
   }
-  groups_for(best_parts, tp, groups);
+  if (best_parts == 0) return fail(FSS_E_ARG, "tune: no work-list shape allowed (pred_unit=%d)", tn.pred_unit);
+  groups_for(best_parts, best_merge, tp, groups);
   std::vector<Unit> best;
   best.reserve(best_units);
   if (tn.order == 0) {
@@ -982,6 +1145,7 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   P->n_split = (uint32_t)split.size();
   P->max_split_elems = max_split_elems;
   P->parts = best_parts;
+  P->merged_pred = best_merge;
   P->tune = tn;
   P->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
                                       (int)((best.size() + waves_per_block - 1) / waves_per_block)));
@@ -1084,8 +1248,9 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
       std::istringstream ls(line);
       std::string kk;
       fss_tune t{};
-      if (ls >> kk >> t.aes_variant >> t.block_threads >> t.blocks_per_cu >> t.order && kk == k &&
-          t.aes_variant >= 0 && t.aes_variant < kNumAesVariants) {
+      if (ls >> kk >> t.aes_variant >> t.block_threads >> t.blocks_per_cu >> t.order >> t.parts >> t.pred_unit &&
+          kk == k && t.aes_variant >= 0 && t.aes_variant < kNumAesVariants && t.parts >= 0 && t.parts <= 4 &&
+          t.pred_unit >= 0 && t.pred_unit <= 2) {
         *best = t;
         return FSS_OK;
       }
@@ -1096,39 +1261,61 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
   HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  // One candidate: plan it, launch it three times, keep the faster of the
+  // last two (the first pays for the plan's first touch).
+  auto time_tune = [&](fss_tune t, double* ms, fss_tune* resolved) -> int {
+    fss_plan* P = nullptr;
+    int r = fss_plan_create(items, n_items, &t, &P);
+    if (r) return r;
+    *ms = 1e30;
+    for (int rep = 0; rep < 3 && r == FSS_OK; ++rep) {
+      (void)hipEventRecord(e0, s);
+      r = fss_plan_launch(P, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float m = 0;
+      (void)hipEventElapsedTime(&m, e0, e1);
+      if (rep > 0) *ms = std::min(*ms, (double)m);
+    }
+    *resolved = P->tune;
+    fss_plan_free(P);
+    return r;
+  };
   double best_ms = 1e30;
   fss_tune bt = default_tune();
-  for (int v = 0; v < kNumAesVariants; ++v) {
+  // Stage 1: table layout x resident blocks x unit order, units as planned.
+  for (int v = 0; v < kNumAesVariants && rc == FSS_OK; ++v) {
     const int dflt = blocks_per_cu_default(v);
     for (int bpc : {dflt, std::max(1, dflt / 2), dflt * 2}) {
       for (int order : {0, 1}) {
-        fss_tune t{};
+        fss_tune t{}, res{};
         t.aes_variant = v;
         t.blocks_per_cu = bpc;
         t.order = order;
-        fss_plan* P = nullptr;
-        if ((rc = fss_plan_create(items, n_items, &t, &P))) break;
-        double ms = 1e30;
-        for (int rep = 0; rep < 3 && rc == FSS_OK; ++rep) {
-          (void)hipEventRecord(e0, s);
-          rc = fss_plan_launch(P, s);
-          (void)hipEventRecord(e1, s);
-          (void)hipEventSynchronize(e1);
-          float m = 0;
-          (void)hipEventElapsedTime(&m, e0, e1);
-          if (rep > 0) ms = std::min(ms, (double)m);
-        }
-        t = P->tune;
-        fss_plan_free(P);
-        if (rc) break;
+        double ms = 0;
+        if ((rc = time_tune(t, &ms, &res))) break;
         if (ms < best_ms) {
           best_ms = ms;
-          bt = t;
+          bt = res;
         }
       }
       if (rc) break;
     }
-    if (rc) break;
+  }
+  // Stage 2: on the best launch shape, the work-list's units: call 2 of a
+  // tile in 1..4 parts, call 1 in the first part's pass or a unit of its own.
+  for (int parts = 1; parts <= 4 && rc == FSS_OK; ++parts) {
+    for (int pu : {1, 2}) {
+      fss_tune t = bt, res{};
+      t.parts = parts;
+      t.pred_unit = pu;
+      double ms = 0;
+      if ((rc = time_tune(t, &ms, &res))) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        bt = res;
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1137,7 +1324,8 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
   *best = bt;
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
-    o << k << " " << bt.aes_variant << " " << bt.block_threads << " " << bt.blocks_per_cu << " " << bt.order << "\n";
+    o << k << " " << bt.aes_variant << " " << bt.block_threads << " " << bt.blocks_per_cu << " " << bt.order << " "
+      << bt.parts << " " << bt.pred_unit << "\n";
   }
   return FSS_OK;
 }
@@ -1150,8 +1338,30 @@ int fss_plan_parts(const fss_plan* plan) { return plan ? plan->parts : 0; }
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid) {
   if (!plan || !tune || !grid) return fail(FSS_E_ARG, "NULL argument");
   *tune = plan->tune;
+  tune->parts = plan->parts;
+  tune->pred_unit = plan->merged_pred ? 1 : 2;
   *grid = plan->grid;
   return FSS_OK;
+}
+
+int fss_eval_batch(int32_t party, const fss_work_item* items, int32_t n_items, void* stream) {
+  if (party != FSS_PARTY_ANY) {
+    int rc = check_party(party);
+    if (rc) return rc;
+  }
+  if (n_items < 0 || (n_items > 0 && !items)) return fail(FSS_E_ARG, "bad items");
+  if (n_items == 0) return FSS_OK;
+  for (int i = 0; i < n_items; ++i)
+    if (party != FSS_PARTY_ANY && items[i].party != party)
+      return fail(FSS_E_PARTY, "item %d is party %d's, the batch party %d's", i, items[i].party, party);
+  // The planner reads the key headers on the host: they must be in memory.
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize(eval_batch)");
+  fss_plan* P = nullptr;
+  int rc = fss_plan_create(items, n_items, nullptr, &P);
+  if (rc) return rc;
+  rc = fss_plan_launch(P, stream);
+  fss_plan_free(P);  // buffers return to the pool after the launch completes
+  return rc;
 }
 
 }  // extern "C"

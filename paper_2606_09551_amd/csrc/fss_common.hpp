@@ -92,7 +92,7 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 5;
+constexpr uint32_t kVersion = 6;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -107,6 +107,8 @@ struct KeyHeader {
   uint32_t n_prim, n_views, kmax, top_depth;  // top_depth: shared lookup-DCF levels of the lookup points
   uint32_t lookup_r;                       // input bits per lookup-DCF level (2, 3 or 4)
   uint32_t top_blocks;                     // aligned blocks of lookup points walked through the shared levels (2..4)
+  uint32_t lookup_c;                       // view shift of call 2: v = (xhat + lookup_c) mod 2^n
+  uint32_t is_int;                         // 1: integer spec over canonical representatives
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];

@@ -464,7 +464,9 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
   }
 }
 
-// With v = view_{n,s}(xhat) and u_i = (v - a'_i) mod N, the share of
+// With v = view_{n,c}(xhat) (c = 2^(n-1), the offset-binary view of the signed
+// order, for real specs; c = 0 for integer specs over canonical
+// representatives) and u_i = (v - a'_i) mod N, the share of
 // 1[x' < a'_i] rho is g_i = D(u_i) - D(v) + 1[v < a'_i] rho_b, and the
 // active piece's coefficients at xhat are
 //   q = tab_0 rho_b + sum_{i=1}^{m-1} tab_i g_i  (+ r_out share in q_0),
@@ -497,8 +499,7 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
   const int L = (n + R - 1) / R;
   const int iend = i1 < m ? i1 : m;
   const uint32_t Nmask = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
-  const uint32_t half = 1u << (n - 1);
-  const uint32_t v = ((uint32_t)xhat + half) & Nmask;
+  const uint32_t v = ((uint32_t)xhat + h->lookup_c) & Nmask;  // 2^(n-1): signed order; 0: canonical
   const uint8_t* rhop = tile + h->off_crho + lane * 8;
   const int K = D > 0 ? R * (L - D) : 0;  // input bits below the shared levels (D > 0: R <= K < n)
   const int NT = D > 0 ? (int)h->top_blocks : 0;
@@ -657,9 +658,11 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* 
 }
 
 // ---------------------------------------------------------------------------
-// Fused persistent kernel: waves pull (item, tile) pairs from a work-list in
-// cost order and run both calls plus the combination in one pass per element
-// (xhat loaded once, AES tables staged once per resident block).
+// Fused persistent kernel: waves pull units from a work-list in cost order.
+// A unit is a tile's call 1 and call 2 with the combination in one pass over
+// its elements (x-hat loaded once), or a part of that work (call 1 alone, or
+// a range of lookup points) when the planner splits tiles to balance the
+// waves; the AES tables are staged once per resident block.
 // ---------------------------------------------------------------------------
 template <int V>
 __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items, const uint32_t* tiles,
@@ -700,7 +703,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     const bool valid = e < (uint64_t)it.n_elems;
     const uint64_t xh = valid ? ldg64(it.xhat + e) : 0;
     const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
-    if ((flags & kUnitPred) && h->T > 0)
+    if (flags & kUnitPred)  // also with T = 0: the bits are then the public constants and carry shares
       pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
     if (!(flags & kUnitBase) && (range & 0xffffu) >= (range >> 16)) continue;  // a call-1 unit
     const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),

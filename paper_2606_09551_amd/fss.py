@@ -30,6 +30,7 @@ ERRORS = {-1: "FSS_E_INVALID_SPEC", -2: "FSS_E_UNSUPPORTED", -3: "FSS_E_NEEDS_PH
 MAX_ATOMS = 16
 
 PRED_LT_SIGNED, PRED_LT_UNSIGNED, PRED_LOWBITS_LT, PRED_MSB_SHIFT = 0, 1, 2, 3
+PARTY_ANY = -1
 COMBINE_XOR, COMBINE_AND, COMBINE_OR = 0, 1, 2
 
 
@@ -69,7 +70,8 @@ class WorkItem(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("aes_variant", C.c_int32), ("order", C.c_int32)]
+                ("aes_variant", C.c_int32), ("order", C.c_int32), ("parts", C.c_int32),
+                ("pred_unit", C.c_int32)]
 
 
 def _load():
@@ -81,13 +83,16 @@ def _load():
     sig = {
         "fss_compile_spec": [C.POINTER(Interval), i32, C.POINTER(Piece), C.POINTER(Pred), i32, i32,
                              C.POINTER(vp)],
+        "fss_compile_spec_int": [i32, i32, C.POINTER(u64), i32, C.POINTER(u64), C.POINTER(Pred), i32,
+                                 C.POINTER(vp)],
         "fss_spec_free": [vp],
         "fss_spec_set_lookup_radix": [vp, i32],
         "fss_spec_get_lookup_radix": [vp],
         "fss_spec_query": [vp, i32, i32, C.POINTER(SpecInfo), vp, vp],
         "fss_key_bytes": [vp, i32, i32, i64, C.POINTER(C.c_size_t)],
-        "fss_keygen": [vp, i32, i32, u64, i64, vp, vp, vp, vp, vp],
+        "fss_keygen": [vp, i32, i32, C.POINTER(C.c_uint8), i64, vp, vp, vp, vp, vp],
         "fss_mask_input": [vp, vp, i64, vp, vp],
+        "fss_keygen_work": [vp, i32, i32, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "fss_eval": [i32, vp, vp, i64, vp, vp, vp],
         "fss_eval_pred": [i32, vp, vp, i64, vp, vp],
         "fss_eval_coeff": [i32, vp, vp, i64, vp, vp],
@@ -98,6 +103,7 @@ def _load():
         "fss_plan_table_lookups": [vp],
         "fss_plan_parts": [vp],
         "fss_plan_config": [vp, C.POINTER(Tune), C.POINTER(i32)],
+        "fss_eval_batch": [i32, C.POINTER(WorkItem), i32, vp],
         "fss_graph_capture": [C.POINTER(vp), i32, C.POINTER(vp)],
         "fss_graph_launch": [vp, vp],
         "fss_graph_free": [vp],
@@ -148,8 +154,36 @@ def _stream(stream) -> int | None:
 
 # ---------------------------------------------------------------------------
 
+def _preds(preds):
+    np_ = len(preds)
+    prs = (Pred * max(np_, 1))()
+    for j, q in enumerate(preds):
+        prs[j] = Pred(q.kind, int(q.negate), q.out, getattr(q, "combine", 0), q.f_bits, 0,
+                      q.thr, q.gamma, q.c)
+    return prs, np_
+
+
 class Spec:
-    """An operator specification compiled by the library (fss_compile_spec)."""
+    """An operator specification compiled by the library (fss_compile_spec),
+    or in the integer form (fss_compile_spec_int) via ``Spec.integer``."""
+
+    @classmethod
+    def integer(cls, n_bits: int, alpha, coef, preds=(), lookup_r: int | None = None, name: str = "int"):
+        """alpha: m + 1 boundaries 0 = alpha_0 < ... < alpha_m = 2^n_bits; coef: m rows
+        of degree + 1 ring coefficients (lowest first)."""
+        m = len(alpha) - 1
+        deg = len(coef[0]) - 1
+        a = (C.c_uint64 * (m + 1))(*[int(v) for v in alpha])
+        c = (C.c_uint64 * (m * (deg + 1)))(*[int(v) & (2**64 - 1) for row in coef for v in row])
+        prs, np_ = _preds(list(preds))
+        h = C.c_void_p()
+        _check(lib.fss_compile_spec_int(n_bits, m, a, deg, c, prs if np_ else None, np_, C.byref(h)))
+        self = cls.__new__(cls)
+        self.handle = h
+        self.name = name
+        if lookup_r is not None:
+            _check(lib.fss_spec_set_lookup_radix(h, lookup_r))
+        return self
 
     def __init__(self, desc, lookup_r: int | None = None):
         m = len(desc.intervals)
@@ -159,11 +193,7 @@ class Spec:
             pcs[i].degree = len(coefs) - 1
             for l, c in enumerate(coefs[:4]):
                 pcs[i].coef[l] = c
-        np_ = len(desc.preds)
-        prs = (Pred * max(np_, 1))()
-        for j, q in enumerate(desc.preds):
-            prs[j] = Pred(q.kind, int(q.negate), q.out, getattr(q, "combine", 0), q.f_bits, 0,
-                          q.thr, q.gamma, q.c)
+        prs, np_ = _preds(desc.preds)
         h = C.c_void_p()
         _check(lib.fss_compile_spec(iv, m, pcs, prs if np_ else None, np_, desc.out_frac_bits,
                                     C.byref(h)))
@@ -199,14 +229,27 @@ class Spec:
                 "lookup_r": info.lookup_r, "top_depth": info.top_depth, "top_blocks": info.top_blocks,
                 "aprime": list(ap), "coef": [[co[i * p + l] for l in range(p)] for i in range(m)]}
 
+    def keygen_work(self, n_bits: int, frac_bits: int, n_elems: int) -> tuple:
+        """(AES blocks, T-table lookups) of one fss_keygen over n_elems elements."""
+        a, l = C.c_double(), C.c_double()
+        _check(lib.fss_keygen_work(self.handle, n_bits, frac_bits, n_elems, C.byref(a), C.byref(l)))
+        return a.value, l.value
+
     def key_bytes(self, n_bits: int, frac_bits: int, n_elems: int) -> int:
         out = C.c_size_t()
         _check(lib.fss_key_bytes(self.handle, n_bits, frac_bits, n_elems, C.byref(out)))
         return out.value
 
 
+def seed_bytes(seed: int):
+    """A 128-bit dealer seed as the 16 little-endian bytes fss_keygen takes."""
+    if not 0 <= int(seed) < 2**128:
+        raise ValueError("the dealer seed is a 128-bit unsigned integer")
+    return (C.c_uint8 * 16).from_buffer_copy(int(seed).to_bytes(16, "little"))
+
+
 def fss_keygen(spec: Spec, n_bits, frac_bits, seed, n_elems, key0, key1, r_in, r_out, stream=None):
-    _check(lib.fss_keygen(spec.handle, n_bits, frac_bits, seed & (2**64 - 1), n_elems, _p(key0),
+    _check(lib.fss_keygen(spec.handle, n_bits, frac_bits, seed_bytes(seed), n_elems, _p(key0),
                           _p(key1), _p(r_in), _p(r_out), _stream(stream)))
 
 
@@ -241,6 +284,12 @@ def work_items(items) -> C.Array:
     return arr, len(items)
 
 
+def fss_eval_batch(party, items, stream=None):
+    """items: iterable of (party, keys, xhat, y, zbits, n_elems); party 0, 1 or PARTY_ANY."""
+    arr, n = work_items(items)
+    _check(lib.fss_eval_batch(party, arr, n, _stream(stream)))
+
+
 class Plan:
     """fss_plan: a work-list evaluated by one persistent fused launch."""
 
@@ -266,7 +315,8 @@ class Plan:
         t, g = Tune(), C.c_int32()
         _check(lib.fss_plan_config(self.handle, C.byref(t), C.byref(g)))
         return {"aes_variant": t.aes_variant, "block_threads": t.block_threads,
-                "blocks_per_cu": t.blocks_per_cu, "order": t.order, "grid": g.value}
+                "blocks_per_cu": t.blocks_per_cu, "order": t.order, "grid": g.value,
+                "parts": t.parts, "pred_unit": t.pred_unit}
 
     def free(self, _free=lib.fss_plan_free):
         if self.handle is not None and self.handle.value:

@@ -49,26 +49,50 @@ def test_served_equals_alone_and_oracle():
             for k in a:
                 for u, v in zip(a[k], b[k]):
                     assert np.array_equal(u, v), (rid, path, k)
-    # oracle: party-0 shares of sampled elements of every op of request 1, layer 1
-    rid, layer = 1, 1
-    L = 16
+    # oracle: party-0 shares of every element of every op of request 1, all layers
+    check_request_vs_oracle(mix[1], 1, 16, 2)
+
+
+def check_request_vs_oracle(req, rid, L, layers):
+    """Party-0 shares (y and the predicate bits) of every element of every
+    operator of every layer of one served request equal the oracle's."""
     descs = W.request_specs(L)
-    for j, name in enumerate(W.REQUEST_OPS):
-        y, z, x = mix[rid].outputs[(layer, name)]
-        n = len(x)
-        elems = np.unique(np.r_[np.linspace(0, n - 1, 24).astype(np.int64), [n - 1]])
-        Sp = O.compile_spec(descs[name], W.N_BITS, W.F_BITS, lookup_r=F.Spec(descs[name]).lookup_r)
-        K0, _, r_in, _ = O.keygen(Sp, W.request_dealer_seed(rid, layer, j), elems)
-        xhat = x[elems].view(np.uint64) + r_in
-        y0, z0 = O.evaluate(0, Sp, K0, xhat)
-        assert np.array_equal(y[elems], y0), name
-        ell = Sp.ell
-        words = (n + 63) // 64
-        zp = z[: ell * words].reshape(ell, words)
-        got = np.zeros(len(elems), np.uint64)
-        for bit in range(ell):
-            got |= ((zp[bit][elems >> 6] >> (elems & 63).astype(np.uint64)) & np.uint64(1)) << np.uint64(bit)
-        assert np.array_equal(got, z0), name
+    total = 0
+    for layer in range(layers):
+        for j, name in enumerate(W.REQUEST_OPS):
+            y, z, x = req.outputs[(layer, name)]
+            n = len(x)
+            Sp = O.compile_spec(descs[name], W.N_BITS, W.F_BITS, lookup_r=F.Spec(descs[name]).lookup_r)
+            elems = np.arange(n, dtype=np.int64)
+            y0, _, z0, _, _ = O.full(Sp, W.request_dealer_seed(rid, layer, j), elems, x)
+            assert np.array_equal(y[:n], y0), (layer, name)
+            ell = Sp.ell
+            words = (n + 63) // 64
+            zp = z[: ell * words].reshape(ell, words)
+            got = np.zeros(n, np.uint64)
+            for bit in range(ell):
+                got |= ((zp[bit][elems >> 6] >> (elems & 63).astype(np.uint64)) & np.uint64(1)) << np.uint64(bit)
+            assert np.array_equal(got, z0), (layer, name)
+            total += n
+        print(f"request {rid} layer {layer}: every element equals the oracle", flush=True)
+    return total
+
+
+def test_c5_request_every_layer():
+    """A BERT-base request of the serving workload (L = 16, all 12 layers of
+    GELU, exp, reciprocal and two rsqrt per token) served beside a second
+    request: every element of every layer equals the oracle."""
+    stream = [(1, 16, 0.0), (2, 20, 0.0)]
+    probe = S.Server(arena_bytes=1, layers=12, path="fused")
+    need = sum(probe.plan_request(rid, L, 0.0).footprint for rid, L, _ in stream)
+    del probe
+    srv = S.Server(arena_bytes=need + 2**20, layers=12, path="fused")
+    print("serving two requests over 12 layers (fused)", flush=True)
+    stats = srv.run(stream, keep={1})
+    req = {r.rid: r for r in stats["_requests"]}[1]
+    assert len(req.outputs) == 12 * len(W.REQUEST_OPS)
+    total = check_request_vs_oracle(req, 1, 16, 12)
+    assert total == 12 * sum(W.request_op_sizes(16).values())
 
 
 def test_arena_first_fit_and_coalescing():

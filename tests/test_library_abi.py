@@ -37,6 +37,74 @@ def test_library_exports_every_declared_symbol():
     assert "gfx950" in F.version()
 
 
+# The calls of the boundary: the spec in both forms, keygen, the plain and
+# the fused evaluators, the autotuner.
+BOUNDARY = ["fss_compile_spec", "fss_compile_spec_int", "fss_key_bytes", "fss_keygen", "fss_eval",
+            "fss_eval_batch", "fss_autotune", "fss_spec_free"]
+
+
+def test_boundary_calls_declared_and_exported():
+    names = declared_functions()
+    for n in BOUNDARY:
+        assert n in names, n
+        assert hasattr(F.lib, n), n
+
+
+def test_integer_spec_tables_match_oracle():
+    """The worked ReLU (alpha = 0, N/2, N) and random integer specs: the
+    library's quantised tables equal the oracle's, with the unshifted lookup view."""
+    import random
+    P = W.PredDesc
+    rnd = random.Random(41)
+    cases = [(10, [0, 512, 1024], [[0, 1], [0, 0]], [P(W.MSB_SHIFT, 0, c=0)])]
+    for _ in range(6):
+        n = rnd.randint(4, 24)
+        N = 1 << n
+        m = rnd.randint(1, 12)
+        alpha = [0] + sorted(rnd.sample(range(1, N), m - 1)) + [N]
+        d = rnd.randint(0, 3)
+        coef = [[rnd.getrandbits(64) for _ in range(d + 1)] for _ in range(m)]
+        preds = [P(W.LT_SIGNED, 0, thr=float(rnd.randint(-N // 2, N // 2))),
+                 P(W.LT_UNSIGNED, 1, thr=float(rnd.randint(1, N - 1))),
+                 P(W.LOWBITS_LT, 1, f_bits=min(n, 3), gamma=2), P(W.MSB_SHIFT, 2, c=rnd.randint(0, N - 1))]
+        cases.append((n, alpha, coef, preds))
+    for n, alpha, coef, preds in cases:
+        lib_t = F.Spec.integer(n, alpha, coef, preds).query(n, 0)
+        orc = O.spec_tables(O.compile_spec_int(n, alpha, coef, preds))
+        for k in ("m", "d", "p", "F_out", "T", "ell", "aprime", "coef"):
+            assert lib_t[k] == orc[k], (n, k)
+        atoms = [(k, c % 2**64, msk) for k, c, msk in zip(lib_t["atom_k"], lib_t["atom_c"], lib_t["atom_is_mask"])]
+        assert atoms == [(a[0], a[1], a[2]) for a in orc["atoms"]]
+
+
+def test_integer_spec_rejections():
+    P = W.PredDesc
+    N = 64
+    F.Spec.integer(6, [0, 32, N], [[1], [2]])
+    for alpha in ([1, 32, N], [0, 32, N - 1], [0, 32, 32, N], [0, 40, 32, N]):
+        with pytest.raises(F.FssError) as e:
+            F.Spec.integer(6, alpha, [[0]] * (len(alpha) - 1))
+        assert e.value.code == -1
+    with pytest.raises(F.FssError) as e:
+        F.Spec.integer(6, [0, 32, N], [[1], [2]], [P(W.LT_SIGNED, 0, thr=2.5)])
+    assert e.value.code == -1
+    with pytest.raises(F.FssError) as e:
+        F.Spec.integer(40, [0, 2**40], [[1]])
+    assert e.value.code == -2
+    s = F.Spec.integer(6, [0, 32, N], [[1], [2]])
+    for n, f in ((7, 0), (6, 2)):
+        with pytest.raises(F.FssError) as e:
+            s.query(n, f)
+        assert e.value.code == -4
+
+
+def test_seed_is_128_bits_at_the_boundary():
+    for bad in (-1, 2**128):
+        with pytest.raises(ValueError):
+            F.seed_bytes(bad)
+    assert bytes(F.seed_bytes(2**64 + 5)) == (2**64 + 5).to_bytes(16, "little")
+
+
 SPECS = [(W.clip_relu_spec(), 16, 8), (W.gelu_spec(), 24, 12), (W.exp_spec(), 24, 12),
          (W.recip_spec(7), 24, 12), (W.recip_spec(9), 24, 12), (W.rsqrt_spec(), 24, 12),
          (W.relu_worked_example_spec(), 10, 0), (W.gelu_spec(f=5), 10, 5)]
