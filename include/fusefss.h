@@ -281,6 +281,22 @@ double fss_plan_table_lookups(const fss_plan* plan);
  * adds its share of y (mod 2^64, exact) into y, which the launch zeroes first.
  * Returns 0 for a NULL plan. */
 int fss_plan_parts(const fss_plan* plan);
+/* fss_eval_batch for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, outputs and errors as fss_eval_batch, but the work-list
+ * lives in a fixed device array of 8 MiB that the library holds on each
+ * device it runs on until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call (the key headers are read on `stream`).
+ * Limits: at most FSS_NOALLOC_MAX_ITEMS items and FSS_NOALLOC_MAX_UNITS
+ * work-list units (a unit is a 64-element tile of one item, or one of up to
+ * five parts of it); larger work-lists return FSS_E_ARG before anything is
+ * enqueued.  Every call on a device uses that device's one array: calls that
+ * overlap on one device race (order them, e.g. on one stream).  Kernel-side
+ * validation failures are reported by fss_status like the others. */
+#define FSS_NOALLOC_MAX_ITEMS 1024
+#define FSS_NOALLOC_MAX_UNITS 491520
+int fss_eval_batch_noalloc(int32_t party, const fss_work_item* items, int32_t n_items, void* stream);
+
 /* Resolved launch configuration of a plan (host out-params): the tune with
  * `parts` and `pred_unit` set to the planner's choice. */
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid);

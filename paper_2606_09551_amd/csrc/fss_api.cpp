@@ -19,6 +19,7 @@
 
 #include "../../include/fusefss.h"
 #include "fss_kernels.hpp"
+#include "fss_plan.hpp"
 
 using namespace fss;
 
@@ -679,9 +680,15 @@ int fss_status(void* stream, int32_t* device_code) {
   int* st = nullptr;
   int rc = device_status_ptr(&st);
   if (rc) return rc;
+  // the library's status word, then that of the no-alloc path (if it ran here)
   int v = 0;
-  HIP_TRY(hipMemcpy(&v, st, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(status)");
-  if (v) HIP_TRY(hipMemset(st, 0, sizeof(int)), "hipMemset(status)");
+  for (int* w : {st, noalloc_status_word()}) {
+    if (!w) continue;
+    int c = 0;
+    HIP_TRY(hipMemcpy(&c, w, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy(status)");
+    if (c) HIP_TRY(hipMemset(w, 0, sizeof(int)), "hipMemset(status)");
+    if (!v) v = c;
+  }
   HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
   *device_code = v;
   return FSS_OK;
@@ -945,10 +952,16 @@ int aux_stream(hipStream_t* out) {
   return FSS_OK;
 }
 
-int read_header(const void* keys, KeyHeader* h) {
-  hipStream_t s;
-  int rc = aux_stream(&s);
-  if (rc) return rc;
+// Reads a key header to the host on `*on` (which may be the null stream), or
+// on the library's own stream when `on` is null.
+int read_header(const void* keys, KeyHeader* h, const hipStream_t* on = nullptr) {
+  hipStream_t s = nullptr;
+  if (on) {
+    s = *on;
+  } else {
+    int rc = aux_stream(&s);
+    if (rc) return rc;
+  }
   HIP_TRY(hipMemcpyAsync(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(header)");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(header)");
   if (h->magic != kMagic || h->version != kVersion) return fail(FSS_E_SHAPE, "not a key buffer");
@@ -981,9 +994,24 @@ int blocks_per_cu_default(int variant) {
 
 extern "C" {
 
-int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune* tune, fss_plan** out) {
-  if (!out) return fail(FSS_E_ARG, "out NULL");
-  *out = nullptr;
+}  // extern "C"
+
+namespace fss {
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int set_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune* tune,
+                    const hipStream_t* header_stream, HostPlan* hp) {
   if (n_items < 0 || (n_items > 0 && !items)) return fail(FSS_E_ARG, "bad items");
   fss_tune tn = tune ? *tune : default_tune();
   if (tn.aes_variant < 0 || tn.aes_variant >= kNumAesVariants) return fail(FSS_E_ARG, "aes_variant");
@@ -1006,7 +1034,7 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
     if (!it.keys || it.n_elems < 0 || (it.n_elems > 0 && (!it.xhat || !it.y)))
       return fail(FSS_E_ARG, "item %d: bad buffers", i);
     KeyHeader h;
-    if ((rc = read_header(it.keys, &h))) return rc;
+    if ((rc = read_header(it.keys, &h, header_stream))) return rc;
     if ((int)h.party != it.party) return fail(FSS_E_PARTY, "item %d: key buffer of party %u", i, h.party);
     if ((uint64_t)it.n_elems > h.n_elems) return fail(FSS_E_SHAPE, "item %d: n_elems exceeds keys", i);
     if (h.ell > 0 && it.n_elems > 0 && !it.zbits) return fail(FSS_E_ARG, "item %d: zbits NULL", i);
@@ -1116,41 +1144,67 @@ int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune*
   }
   uint64_t max_split_elems = 0;
   for (uint32_t i : split) max_split_elems = std::max<uint64_t>(max_split_elems, (uint64_t)dev[i].n_elems);
+  hp->items = std::move(dev);
+  hp->units = std::move(flat);
+  hp->split = std::move(split);
+  hp->max_split_elems = max_split_elems;
+  hp->parts = best_parts;
+  hp->merged_pred = best_merge;
+  hp->tune = tn;
+  hp->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
+                                       (int)((best.size() + waves_per_block - 1) / waves_per_block)));
+  hp->aes = aes_total;
+  hp->lookups = lookups_total;
+  return FSS_OK;
+}
+
+}  // namespace fss
+
+extern "C" {
+
+int fss_plan_create(const fss_work_item* items, int32_t n_items, const fss_tune* tune, fss_plan** out) {
+  if (!out) return fail(FSS_E_ARG, "out NULL");
+  *out = nullptr;
+  HostPlan hp;
+  int rc = build_host_plan(items, n_items, tune, nullptr, &hp);
+  if (rc) return rc;
   std::unique_ptr<fss_plan> P(new (std::nothrow) fss_plan());
   if (!P) return fail(FSS_E_OOM, "out of host memory");
   HIP_TRY(hipGetDevice(&P->device), "hipGetDevice");
   void *pi = nullptr, *pt = nullptr, *pc = nullptr, *ps = nullptr;
-  if ((rc = pool_get(sizeof(DevItem) * std::max<size_t>(1, dev.size()), &pi))) return rc;
+  if ((rc = pool_get(sizeof(DevItem) * std::max<size_t>(1, hp.items.size()), &pi))) return rc;
   P->d_items = (DevItem*)pi;
-  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(kUnitWords, flat.size()), &pt))) return rc;
+  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(kUnitWords, hp.units.size()), &pt))) return rc;
   P->d_tiles = (uint32_t*)pt;
   if ((rc = pool_get(sizeof(uint32_t), &pc))) return rc;
   P->d_counter = (uint32_t*)pc;
-  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(1, split.size()), &ps))) return rc;
+  if ((rc = pool_get(sizeof(uint32_t) * std::max<size_t>(1, hp.split.size()), &ps))) return rc;
   P->d_split = (uint32_t*)ps;
   hipStream_t up;
   if ((rc = aux_stream(&up))) return rc;
-  if (!dev.empty())
-    HIP_TRY(hipMemcpyAsync(P->d_items, dev.data(), sizeof(DevItem) * dev.size(), hipMemcpyHostToDevice, up),
+  if (!hp.items.empty())
+    HIP_TRY(hipMemcpyAsync(P->d_items, hp.items.data(), sizeof(DevItem) * hp.items.size(), hipMemcpyHostToDevice,
+                           up),
             "upload items");
-  if (!flat.empty())
-    HIP_TRY(hipMemcpyAsync(P->d_tiles, flat.data(), sizeof(uint32_t) * flat.size(), hipMemcpyHostToDevice, up),
+  if (!hp.units.empty())
+    HIP_TRY(hipMemcpyAsync(P->d_tiles, hp.units.data(), sizeof(uint32_t) * hp.units.size(), hipMemcpyHostToDevice,
+                           up),
             "upload work-list");
-  if (!split.empty())
-    HIP_TRY(hipMemcpyAsync(P->d_split, split.data(), sizeof(uint32_t) * split.size(), hipMemcpyHostToDevice, up),
+  if (!hp.split.empty())
+    HIP_TRY(hipMemcpyAsync(P->d_split, hp.split.data(), sizeof(uint32_t) * hp.split.size(), hipMemcpyHostToDevice,
+                           up),
             "upload split items");
   HIP_TRY(hipStreamSynchronize(up), "hipStreamSynchronize(upload)");
   HIP_TRY(hipEventCreateWithFlags(&P->done, hipEventDisableTiming), "hipEventCreate(plan)");
-  P->n_tiles = (uint32_t)best.size();
-  P->n_split = (uint32_t)split.size();
-  P->max_split_elems = max_split_elems;
-  P->parts = best_parts;
-  P->merged_pred = best_merge;
-  P->tune = tn;
-  P->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
-                                      (int)((best.size() + waves_per_block - 1) / waves_per_block)));
-  P->aes_per_launch = aes_total;
-  P->lookups_per_launch = lookups_total;
+  P->n_tiles = (uint32_t)(hp.units.size() / kUnitWords);
+  P->n_split = (uint32_t)hp.split.size();
+  P->max_split_elems = hp.max_split_elems;
+  P->parts = hp.parts;
+  P->merged_pred = hp.merged_pred;
+  P->tune = hp.tune;
+  P->grid = hp.grid;
+  P->aes_per_launch = hp.aes;
+  P->lookups_per_launch = hp.lookups;
   *out = P.release();
   return FSS_OK;
 }

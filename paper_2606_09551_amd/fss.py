@@ -104,6 +104,7 @@ def _load():
         "fss_plan_parts": [vp],
         "fss_plan_config": [vp, C.POINTER(Tune), C.POINTER(i32)],
         "fss_eval_batch": [i32, C.POINTER(WorkItem), i32, vp],
+        "fss_eval_batch_noalloc": [i32, C.POINTER(WorkItem), i32, vp],
         "fss_graph_capture": [C.POINTER(vp), i32, C.POINTER(vp)],
         "fss_graph_launch": [vp, vp],
         "fss_graph_free": [vp],
@@ -288,6 +289,15 @@ def fss_eval_batch(party, items, stream=None):
     """items: iterable of (party, keys, xhat, y, zbits, n_elems); party 0, 1 or PARTY_ANY."""
     arr, n = work_items(items)
     _check(lib.fss_eval_batch(party, arr, n, _stream(stream)))
+
+
+def fss_eval_batch_noalloc(party, items, stream=None):
+    """fss_eval_batch without device allocation (fixed work-list array)."""
+    arr, n = work_items(items)
+    _check(lib.fss_eval_batch_noalloc(party, arr, n, _stream(stream)))
+
+
+NOALLOC_MAX_ITEMS, NOALLOC_MAX_UNITS = 1024, 491520
 
 
 class Plan:
