@@ -43,6 +43,12 @@ class DcfKey(C.Structure):
                 ("vcw", (C.c_uint64 * MAXP) * MAXN), ("fin", C.c_uint64 * MAXP)]
 
 
+class DcfZKey(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nu", C.c_int32), ("root", Blk), ("scw", Blk * MAXN),
+                ("tl", C.c_uint8 * MAXN), ("tr", C.c_uint8 * MAXN), ("vcw", C.c_uint8 * MAXN),
+                ("leaf", Blk)]
+
+
 MAXLR = (MAXN + 1) // 2  # lookup-DCF levels at r = 2
 MAXC = 16                # children per level at r = 4
 
@@ -54,7 +60,7 @@ class DcfRKey(C.Structure):
 
 
 class ElemKey(C.Structure):
-    _fields_ = [("atom", DcfKey * MAXT), ("wshare", C.c_uint64), ("coeff", DcfRKey),
+    _fields_ = [("atom", DcfZKey * MAXT), ("wshare", C.c_uint64), ("coeff", DcfRKey),
                 ("rho", C.c_uint64 * MAXP), ("rout", C.c_uint64)]
 
 
@@ -110,6 +116,8 @@ def lib():
         L.orc_dcf_gen.argtypes = [C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk,
                                   C.POINTER(DcfKey), C.POINTER(DcfKey)]
         L.orc_dcf_eval.argtypes = [C.c_int, C.POINTER(DcfKey), C.c_uint64, u64p]
+        L.orc_dcfz_gen.argtypes = [C.c_int, C.c_uint64, Blk, Blk, C.POINTER(DcfZKey), C.POINTER(DcfZKey)]
+        L.orc_dcfz_eval.argtypes = [C.c_int, C.POINTER(DcfZKey), C.c_uint64]
         L.orc_dcfr_gen.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, u64p, Blk, Blk, C.POINTER(Blk),
                                    C.POINTER(DcfRKey), C.POINTER(DcfRKey)]
         L.orc_dcfr_eval.argtypes = [C.c_int, C.POINTER(DcfRKey), C.c_uint64, u64p]
@@ -128,6 +136,7 @@ def lib():
         L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
                                     C.POINTER(C.c_int32)]
         for name, cls in (("orc_sizeof_elem_key", ElemKey), ("orc_sizeof_dcf_key", DcfKey),
+                          ("orc_sizeof_dcfz_key", DcfZKey),
                           ("orc_sizeof_dcfr_key", DcfRKey), ("orc_sizeof_spec", Spec)):
             got = getattr(L, name)()
             if got != C.sizeof(cls):
@@ -193,6 +202,22 @@ def dcf_eval(b: int, key: DcfKey, x: int):
     out = (C.c_uint64 * MAXP)()
     lib().orc_dcf_eval(b, C.byref(key), x, out)
     return out[0] if key.p == 0 else list(out[: key.p])
+
+
+def dcfz_nu(n: int) -> int:
+    """Low input bits the early-terminated Z_2 DCF resolves at its leaves."""
+    return lib().orc_dcfz_nu(n)
+
+
+def dcfz_gen(n: int, alpha: int, root0, root1):
+    """Z_2 DCF for 1[x < alpha] with a 2^nu-bit leaf (early termination)."""
+    k0, k1 = DcfZKey(), DcfZKey()
+    lib().orc_dcfz_gen(n, alpha, Blk(*root0), Blk(*root1), C.byref(k0), C.byref(k1))
+    return k0, k1
+
+
+def dcfz_eval(b: int, key: DcfZKey, x: int) -> int:
+    return lib().orc_dcfz_eval(b, C.byref(key), x)
 
 
 def dcfr_gen(n: int, r: int, p: int, alpha: int, beta, root0, root1, keep_rand):

@@ -339,6 +339,109 @@ void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out) {
 }
 
 /* ========================================================================= */
+/* Z_2 DCF with early termination: the tree stops nu = min(7, n) levels      */
+/* above the leaves and each leaf seed is converted into a 128-bit vector    */
+/* whose bit j is that leaf's output at the low input bits j (the            */
+/* early-termination idea of Boyle, Gilboa and Ishai's DPF, applied to the   */
+/* comparison).                                                              */
+/* ========================================================================= */
+
+static int leaf_bit(orc_blk b, unsigned j) { return (int)((j < 64 ? b.lo >> j : b.hi >> (j - 64)) & 1); }
+
+/* The leaf conversion: the seed's expansion under tweak 2 (children use 0, 1). */
+static orc_blk convert_leaf(orc_blk s) { return orc_prg(s, 2); }
+
+int orc_dcfz_nu(int n) { return n < 7 ? n : 7; }
+
+void orc_dcfz_gen(int n, uint64_t alpha, orc_blk root0, orc_blk root1, orc_dcfz_key* k0, orc_dcfz_key* k1) {
+  memset(k0, 0, sizeof *k0);
+  memset(k1, 0, sizeof *k1);
+  const int nu = orc_dcfz_nu(n), h = n - nu;
+  k0->n = k1->n = n;
+  k0->nu = k1->nu = nu;
+  /* The top h levels are the textbook construction (Z_2, beta = 1) over the
+   * high bits alpha >> nu: the same steps as orc_dcf_gen with p = 0. */
+  const uint64_t ah = alpha >> nu, al = alpha & (((uint64_t)1 << nu) - 1);
+  orc_blk s[2] = {clear2(root0), clear2(root1)};
+  int t[2] = {0, 1};
+  k0->root = s[0];
+  k1->root = s[1];
+  int Va = 0;
+  for (int i = 0; i < h; i++) {
+    int ai = (int)((ah >> (h - 1 - i)) & 1);
+    orc_blk sc[2][2];
+    int tc[2][2];
+    uint64_t vc[2][2][ORC_MAXP];
+    for (int b = 0; b < 2; b++)
+      for (int c = 0; c < 2; c++) expand(0, s[b], c, &sc[b][c], &tc[b][c], vc[b][c]);
+    int keep = ai, lose = 1 - ai;
+    orc_blk scw;
+    scw.lo = sc[0][lose].lo ^ sc[1][lose].lo;
+    scw.hi = sc[0][lose].hi ^ sc[1][lose].hi;
+    int vcw = (int)(vc[1][lose][0] ^ vc[0][lose][0]) ^ Va ^ (lose == 0 ? 1 : 0);
+    Va ^= (int)(vc[1][keep][0] ^ vc[0][keep][0]) ^ vcw;
+    int tlcw = tc[0][0] ^ tc[1][0] ^ ai ^ 1;
+    int trcw = tc[0][1] ^ tc[1][1] ^ ai;
+    int tkeep = keep ? trcw : tlcw;
+    k0->scw[i] = k1->scw[i] = scw;
+    k0->tl[i] = k1->tl[i] = (uint8_t)tlcw;
+    k0->tr[i] = k1->tr[i] = (uint8_t)trcw;
+    k0->vcw[i] = k1->vcw[i] = (uint8_t)vcw;
+    for (int b = 0; b < 2; b++) {
+      orc_blk ns = sc[b][keep];
+      if (t[b]) { ns.lo ^= scw.lo; ns.hi ^= scw.hi; }
+      t[b] = tc[b][keep] ^ (t[b] & tkeep);
+      s[b] = ns;
+    }
+  }
+  /* At alpha's leaf exactly one party adds the correction (t_0 ^ t_1 = 1), so
+   * the two leaves XOR to Conv(s_0) ^ Conv(s_1) ^ CW.  Choose CW so that this
+   * is the vector (1[j < alpha_low])_j, with V_alpha (the parties' path sums,
+   * which differ by V_alpha) cancelled in every bit. */
+  orc_blk c0 = convert_leaf(s[0]), c1 = convert_leaf(s[1]), cw;
+  cw.lo = c0.lo ^ c1.lo;
+  cw.hi = c0.hi ^ c1.hi;
+  for (unsigned j = 0; j < 128; j++) {
+    int m = (j < al) ^ Va;
+    if (!m) continue;
+    if (j < 64) cw.lo ^= (uint64_t)1 << j;
+    else cw.hi ^= (uint64_t)1 << (j - 64);
+  }
+  k0->leaf = k1->leaf = cw;
+}
+
+int orc_dcfz_eval(int b, const orc_dcfz_key* k, uint64_t x) {
+  const int nu = k->nu, h = k->n - nu;
+  const uint64_t xh = x >> nu;
+  const unsigned xl = (unsigned)(x & (((uint64_t)1 << nu) - 1));
+  orc_blk s = k->root;
+  int t = b, V = 0;
+  for (int i = 0; i < h; i++) {
+    int xi = (int)((xh >> (h - 1 - i)) & 1);
+    orc_blk ns;
+    int nt;
+    uint64_t v[ORC_MAXP];
+    expand(0, s, xi, &ns, &nt, v);
+    int vb = (int)v[0];
+    if (t) {
+      ns.lo ^= k->scw[i].lo;
+      ns.hi ^= k->scw[i].hi;
+      nt ^= xi ? k->tr[i] : k->tl[i];
+      vb ^= k->vcw[i];
+    }
+    V ^= vb;
+    s = ns;
+    t = nt;
+  }
+  orc_blk leaf = convert_leaf(s);
+  if (t) {
+    leaf.lo ^= k->leaf.lo;
+    leaf.hi ^= k->leaf.hi;
+  }
+  return V ^ leaf_bit(leaf, xl);
+}
+
+/* ========================================================================= */
 /* DCF with 2^r children per level: r input bits (one base-2^r digit) per    */
 /* level, the per-child form of the corrections above.                       */
 /* ========================================================================= */
@@ -679,10 +782,9 @@ void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
       k = S->view_k[t - S->n_prim];
       alpha = r_in & lowmask(k);
     }
-    uint64_t beta = 1;
     orc_blk a = orc_rand(kseed, e, 2 + 2 * t, 0);
     orc_blk b = orc_rand(kseed, e, 3 + 2 * t, 0);
-    orc_dcf_gen(k, 0, alpha, &beta, a, b, &k0->atom[t], &k1->atom[t]);
+    orc_dcfz_gen(k, alpha, a, b, &k0->atom[t], &k1->atom[t]);
   }
   uint64_t W = orc_rand(kseed, e, 66, 0).lo & lowmask(S->ell);
   k0->wshare = W;
@@ -730,9 +832,7 @@ void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xha
     int vi = (t < S->n_prim) ? S->prim_view[t] : t - S->n_prim;
     int k = S->view_k[vi];
     uint64_t u = ((xhat & lowmask(k)) + S->view_c[vi]) & lowmask(k);
-    uint64_t bit;
-    orc_dcf_eval(b, &K->atom[t], u, &bit);
-    A[t] = (int)bit;
+    A[t] = orc_dcfz_eval(b, &K->atom[t], u);
   }
   uint64_t z = K->wshare;
   if (b == 0)
@@ -875,6 +975,7 @@ int orc_hw_threads(void) {
 }
 int orc_sizeof_elem_key(void) { return (int)sizeof(orc_elem_key); }
 int orc_sizeof_dcf_key(void) { return (int)sizeof(orc_dcf_key); }
+int orc_sizeof_dcfz_key(void) { return (int)sizeof(orc_dcfz_key); }
 int orc_sizeof_dcfr_key(void) { return (int)sizeof(orc_dcfr_key); }
 int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
 

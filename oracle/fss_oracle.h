@@ -66,6 +66,27 @@ void orc_dcf_gen(int n, int p, uint64_t alpha, const uint64_t* beta,
                  orc_blk root0, orc_blk root1, orc_dcf_key* k0, orc_dcf_key* k1);
 void orc_dcf_eval(int b, const orc_dcf_key* k, uint64_t x, uint64_t* out);
 
+/* ---- Z_2 DCF with early termination -------------------------------------- */
+/* f(x) = 1[x < alpha] over n bits, the construction above (p = 0, beta = 1)
+ * on the high n - nu bits, nu = min(7, n), with each leaf seed s converted
+ * into the 128-bit vector H(s, 2): the output at x is the XOR of the path's
+ * values and bit (x mod 2^nu) of the leaf vector (plus the leaf correction
+ * when the control bit is set).  At alpha's leaf the correction makes the two
+ * parties' vectors XOR to (1[j < alpha mod 2^nu])_j; at every other leaf the
+ * parties' seeds agree and their vectors cancel.  Evaluation walks n - nu
+ * levels and one conversion block. */
+typedef struct {
+  int32_t n, nu;
+  orc_blk root;                     /* this party's root seed (bits 0..1 zero) */
+  orc_blk scw[ORC_MAXN];            /* levels 0 .. n - nu - 1 */
+  uint8_t tl[ORC_MAXN], tr[ORC_MAXN], vcw[ORC_MAXN];
+  orc_blk leaf;                     /* the leaf correction (bit j: low input bits j) */
+} orc_dcfz_key;
+
+int orc_dcfz_nu(int n);
+void orc_dcfz_gen(int n, uint64_t alpha, orc_blk root0, orc_blk root1, orc_dcfz_key* k0, orc_dcfz_key* k1);
+int orc_dcfz_eval(int b, const orc_dcfz_key* k, uint64_t x);
+
 /* ---- DCF with 2^r children per level --------------------------------------- */
 /* The same construction with r input bits (one base-2^r digit) per level, r in
  * {2, 3, 4}: each level has 2^r children, and the key carries a seed,
@@ -145,7 +166,7 @@ int orc_spec_compile_int(int32_t n_bits, int32_t m, const uint64_t* alpha, int32
 
 /* ---- per-element keys ------------------------------------------------------- */
 typedef struct {
-  orc_dcf_key atom[ORC_MAXT];
+  orc_dcfz_key atom[ORC_MAXT];
   uint64_t wshare;                      /* bit j: this party's share of the carry of output j */
   orc_dcfr_key coeff;                   /* call 2's vector DCF, 2^r children per level */
   uint64_t rho[ORC_MAXP];               /* additive share of rho = ((-r_in)^k)_k */
@@ -175,6 +196,7 @@ int orc_hw_threads(void);
 uint64_t orc_aes_blocks(void);
 int orc_sizeof_elem_key(void);
 int orc_sizeof_dcf_key(void);
+int orc_sizeof_dcfz_key(void);
 int orc_sizeof_dcfr_key(void);
 int orc_sizeof_spec(void);
 

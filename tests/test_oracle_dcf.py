@@ -191,3 +191,63 @@ def test_dcfr_corrections_do_not_single_out_alpha_child(r):
     # at least 1200 and 3600 Bernoulli(1/2) samples: 5 sigma is about 0.072 and 0.042
     assert abs(frac_on - 0.5) < 0.072, frac_on
     assert abs(frac_off - 0.5) < 0.042, frac_off
+
+
+# ---- the Z_2 DCF with early termination (a 2^nu-bit leaf, nu = min(7, n)) ----
+
+@pytest.mark.parametrize("n", [1, 3, 6, 7, 8, 9, 10])
+def test_dcfz_bruteforce(n):
+    """Every alpha and x: Eval_0(x) ^ Eval_1(x) = 1[x < alpha].  n <= 7 is a
+    single leaf (no tree level), n = 8..10 one to three levels above the leaves."""
+    rnd = random.Random(700 + n)
+    assert O.dcfz_nu(n) == min(7, n)
+    alphas = range(2**n) if n <= 8 else sorted({0, 1, 127, 128, 129, 2**n - 1} | {rnd.getrandbits(n) for _ in range(40)})
+    for alpha in alphas:
+        k0, k1 = O.dcfz_gen(n, alpha, *_roots(rnd))
+        for x in range(2**n):
+            assert O.dcfz_eval(0, k0, x) ^ O.dcfz_eval(1, k1, x) == int(x < alpha), (n, alpha, x)
+
+
+def test_dcfz_wide_domain_sampled():
+    rnd = random.Random(77)
+    for n in (16, 24, 31, 32):
+        for _ in range(8):
+            alpha = rnd.getrandbits(n)
+            k0, k1 = O.dcfz_gen(n, alpha, *_roots(rnd))
+            pts = {0, 2**n - 1, alpha, (alpha - 1) % 2**n, (alpha + 1) % 2**n, alpha ^ 64, alpha ^ 128}
+            pts |= {rnd.getrandbits(n) for _ in range(30)}
+            for x in pts:
+                assert O.dcfz_eval(0, k0, x) ^ O.dcfz_eval(1, k1, x) == int(x < alpha), (n, alpha, x)
+
+
+@pytest.mark.parametrize("n", [8, 12, 24])
+def test_dcfz_tree_is_the_textbook_dcf_on_the_high_bits(n):
+    """The levels above the leaves are the textbook construction over the high
+    n - nu bits: same roots give the same seed, control-bit and value
+    corrections as orc_dcf_gen(n - nu, Z_2, alpha >> nu, beta = 1)."""
+    rnd = random.Random(n)
+    nu = O.dcfz_nu(n)
+    for _ in range(5):
+        alpha = rnd.getrandbits(n)
+        roots = _roots(rnd)
+        z0, z1 = O.dcfz_gen(n, alpha, *roots)
+        t0, t1 = O.dcf_gen(n - nu, 0, alpha >> nu, 1, *roots)
+        assert (z0.root.lo, z0.root.hi) == (t0.root.lo, t0.root.hi)
+        for i in range(n - nu):
+            assert (z0.scw[i].lo, z0.scw[i].hi) == (t0.scw[i].lo, t0.scw[i].hi)
+            assert (z0.tl[i], z0.tr[i], z0.vcw[i]) == (t0.tl[i], t0.tr[i], t0.vcw[i][0])
+            assert (z1.scw[i].lo, z1.scw[i].hi) == (z0.scw[i].lo, z0.scw[i].hi)
+        assert (z0.leaf.lo, z0.leaf.hi) == (z1.leaf.lo, z1.leaf.hi)
+
+
+def test_dcfz_leaf_outputs_agree_off_alpha_leaf():
+    """At every leaf other than alpha's the parties' 128-bit leaf vectors are
+    equal (their seeds and control bits agree), so only the path decides."""
+    rnd = random.Random(3)
+    n, alpha = 10, 0b1011001101
+    k0, k1 = O.dcfz_gen(n, alpha, *_roots(rnd))
+    for hi in range(2**(n - 7)):
+        if hi == alpha >> 7:
+            continue
+        f = [O.dcfz_eval(0, k0, (hi << 7) | j) ^ O.dcfz_eval(1, k1, (hi << 7) | j) for j in range(128)]
+        assert f == [int(hi < alpha >> 7)] * 128

@@ -116,7 +116,7 @@ def test_worked_example_relu(n):
         r = int(r_in[i]) % N
         thr = []
         for a in range(2):
-            f = [O.dcf_eval(0, K0[i].atom[a], u) ^ O.dcf_eval(1, K1[i].atom[a], u) for u in range(N)]
+            f = [O.dcfz_eval(0, K0[i].atom[a], u) ^ O.dcfz_eval(1, K1[i].atom[a], u) for u in range(N)]
             # reconstructs a threshold function 1[u < theta]
             theta = sum(f)
             assert f == [1] * theta + [0] * (N - theta)
@@ -137,7 +137,7 @@ def test_key_shape_is_mask_independent():
         K0, K1, _, _ = O.keygen(S, seed, np.arange(2, dtype=np.int64))
         for K in (K0[0], K1[1]):
             shapes.add((tuple(K.atom[t].n for t in range(S.T)),
-                        tuple(K.atom[t].p for t in range(S.T)), K.coeff.n, K.coeff.p))
+                        tuple(K.atom[t].nu for t in range(S.T)), K.coeff.n, K.coeff.p))
     assert len(shapes) == 1
 
 
