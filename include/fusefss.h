@@ -265,7 +265,9 @@ int fss_eval_batch(int32_t party, const fss_work_item* items, int32_t n_items, v
  * (per element and party, with B = 1 + ceil(p/2) blocks per level of the
  * lookup DCF and ceil(p/2) at its last level, L = ceil(n/r) levels of 2^r
  * children, D shared top levels and T of the spec's top blocks:
- * sum_t k_t + (L - 1 + T D + (m-1)(L-D-1)) B + m ceil(p/2); the m-1 lookup
+ * sum_t (k_t - min(7, k_t) + 1) + (L - 1 + T D + (m-1)(L-D-1)) B + m ceil(p/2),
+ * each comparison atom walking its tree above the 128-bit leaves and one
+ * leaf conversion; the m-1 lookup
  * points share their first D levels, walked once for each of the T aligned
  * blocks they fall in; a tile run in parts walks them once per part).  Used
  * for throughput reporting. */

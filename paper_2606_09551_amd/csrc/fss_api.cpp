@@ -612,11 +612,12 @@ int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int
   const double nb = (double)((h.p + 1) / 2), C = (double)(1u << h.lookup_r);
   const double L = (double)((h.n + h.lookup_r - 1) / h.lookup_r);
   double atoms_lv = 0;
-  for (uint32_t t = 0; t < h.T; ++t) atoms_lv += h.atom_k[t];
-  // Both parties' children: two tweaks per Z_2 level, 2^r children of
-  // 1 + nb blocks per lookup level above the last and of nb at the last.
-  const double prg_aes = atoms_lv * 2 * 2 + C * 2 * ((L - 1) * (1 + nb) + nb);
-  const double prg_lk = atoms_lv * 2 * shared(2) + C * 2 * ((L - 1) * shared(1 + nb) + shared(nb));
+  for (uint32_t t = 0; t < h.T; ++t) atoms_lv += h.atom_k[t] - atom_leaf_bits((int)h.atom_k[t]);
+  // Both parties' children: two tweaks per Z_2 level above the leaves and
+  // one leaf conversion per atom, 2^r children of 1 + nb blocks per lookup
+  // level above the last and of nb at the last.
+  const double prg_aes = atoms_lv * 2 * 2 + 2.0 * h.T + C * 2 * ((L - 1) * (1 + nb) + nb);
+  const double prg_lk = atoms_lv * 2 * shared(2) + 2.0 * 160 * h.T + C * 2 * ((L - 1) * shared(1 + nb) + shared(nb));
   // Counter-mode randomness: masks (drawn by both halves of the work), the
   // r_out share, two roots per atom, carries, two lookup roots, two rho-share
   // blocks and 1 + nb on-path corrections per lookup level above the last.
@@ -839,7 +840,8 @@ struct ElemCost {
 ElemCost elem_cost(const KeyHeader& h) {
   auto shared = [](double K) { return 160.0 * K - 24.0 * (K - 1.0); };
   ElemCost c;
-  for (uint32_t t = 0; t < h.T; ++t) c.aes_pred += h.atom_k[t];
+  // each atom: its tree levels above the leaves, then one leaf conversion
+  for (uint32_t t = 0; t < h.T; ++t) c.aes_pred += h.atom_k[t] - atom_leaf_bits((int)h.atom_k[t]) + 1;
   c.lk_pred = 160.0 * c.aes_pred;
   // the lookup DCF has L = ceil(n / r) levels of 2^r children; D of them
   // shared.  A level expands the child's seed and value blocks (1 + nb); the

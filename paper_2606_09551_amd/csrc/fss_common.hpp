@@ -78,8 +78,11 @@ constexpr AesConst kAes = make_aes_const();
 // Key buffer: a header, then n_tiles tiles of 64 elements.  Inside a tile
 // the fields are stored over the 64 lanes, so a wave that owns a tile reads
 // each field with one coalesced access per level.
-//   atom t : root[64] (16 B) | cw[k_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
-//            | vbits[64] (u64: bit i = value corr. of level i, bit 32 = final)
+//   atom t : root[64] (16 B) | cw[k_t - nu_t][64] (16 B: seed corr., bit0 tL, bit1 tR)
+//            | vbits[64] (u64: bit i = value corr. of level i)
+//            | leaf[64] (16 B: the leaf correction, bit j for low input bits j)
+//            The comparison tree stops nu = min(7, k) levels above the
+//            leaves; a leaf seed s becomes the 128-bit vector H(s, 2).
 //   wshare[64] (u64: bit j = this party's share of the carry of output j)
 //   coeff  : root[64] | rec[L][2^r][64]
 //            | rho[p][64] (share of rho) | rout[64] (share of r_out)
@@ -92,7 +95,7 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 6;
+constexpr uint32_t kVersion = 7;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -125,6 +128,10 @@ struct KeyHeader {
 };
 static_assert(sizeof(KeyHeader) <= kHeaderBytes, "header too large");
 
+// Low input bits a comparison atom of width k resolves at its leaves.
+constexpr int kLeafBits = 7;
+FSS_HD constexpr int atom_leaf_bits(int k) { return k < kLeafBits ? k : kLeafBits; }
+
 struct Layout {
   uint64_t atom_off[kMaxAtoms];
   uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;
@@ -136,7 +143,8 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p, in
   uint64_t o = 0;
   for (int t = 0; t < T; ++t) {
     L.atom_off[t] = o;
-    o += (uint64_t)kTile * 16 * (1 + atom_k[t]) + (uint64_t)kTile * 8;
+    const int levels = (int)atom_k[t] - atom_leaf_bits((int)atom_k[t]);
+    o += (uint64_t)kTile * 16 * (1 + levels) + (uint64_t)kTile * 8 + (uint64_t)kTile * 16;
   }
   L.off_w = o;     o += kTile * 8;
   L.off_croot = o; o += kTile * 16;

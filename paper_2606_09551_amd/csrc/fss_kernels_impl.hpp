@@ -305,6 +305,10 @@ __device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
 
 // ---------------------------------------------------------------------------
 // Call 1: packed comparison.  Up to three Z_2 DCF atoms walk in lockstep.
+// Each atom's tree has k - nu levels over the high bits of its view (nu =
+// min(7, k)); the leaf seed s is converted into the 128-bit vector H(s, 2)
+// (plus the leaf correction when the control bit is set), whose bit
+// (view mod 2^nu) completes the share.
 // ---------------------------------------------------------------------------
 template <class TB>
 __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8_t* tile,
@@ -313,33 +317,37 @@ __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8
   uint32_t bits = 0;
   for (int g = 0; g < T; g += 3) {
     const int cnt = T - g < 3 ? T - g : 3;
-    uint32_t s[3][4], t[3], V[3], xv[3];
-    int k[3];
+    uint32_t s[3][4], t[3], V[3], xh[3], xl[3];
+    int lev[3];
     uint64_t vb[3];
     const uint8_t* base[3];
-    int kmax = 0;
+    int lmax = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int at = g + (a < cnt ? a : 0);
-      k[a] = a < cnt ? (int)h->atom_k[at] : 0;
-      kmax = k[a] > kmax ? k[a] : kmax;
+      const int k = (int)h->atom_k[at];
+      const int nu = atom_leaf_bits(k);
+      lev[a] = a < cnt ? k - nu : 0;
+      lmax = lev[a] > lmax ? lev[a] : lmax;
       base[a] = tile + h->atom_off[at];
       const uint4 r = ld16(base[a] + lane * 16);
       s[a][0] = r.x; s[a][1] = r.y; s[a][2] = r.z; s[a][3] = r.w;
       t[a] = (uint32_t)b;
       V[a] = 0;
-      const uint64_t msk = (k[a] >= 64) ? ~0ull : ((1ull << k[a]) - 1);
-      xv[a] = (uint32_t)(((xhat & msk) + h->atom_c[at]) & msk);
-      vb[a] = ld8(base[a] + (uint64_t)kTile * 16 * (1 + k[a]) + lane * 8);
+      const uint64_t msk = (k >= 64) ? ~0ull : ((1ull << k) - 1);
+      const uint32_t xv = (uint32_t)(((xhat & msk) + h->atom_c[at]) & msk);
+      xh[a] = xv >> nu;
+      xl[a] = xv & ((1u << nu) - 1u);
+      vb[a] = ld8(base[a] + (uint64_t)kTile * 16 * (1 + k - nu) + lane * 8);
     }
-    for (int i = 0; i < kmax; ++i) {
+    for (int i = 0; i < lmax; ++i) {
       uint32_t j[3], o[3][4];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) j[a] = (i < k[a]) ? ((xv[a] >> (k[a] - 1 - i)) & 1u) : 0u;
+      for (int a = 0; a < 3; ++a) j[a] = (i < lev[a]) ? ((xh[a] >> (lev[a] - 1 - i)) & 1u) : 0u;
       prg<TB, 3>(tb, s, j, o);
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        if (i < k[a]) {
+        if (i < lev[a]) {
           const uint4 cw = ld16(base[a] + kTile * 16 + ((uint64_t)i * kTile + lane) * 16);
           const uint32_t msk = 0u - t[a];
           const uint32_t nt = (o[a][0] & 1u) ^ ((cw.x >> j[a]) & t[a] & 1u);
@@ -353,11 +361,22 @@ __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8
         }
       }
     }
+    {  // the leaves
+      uint32_t j[3] = {2u, 2u, 2u}, o[3][4];
+      prg<TB, 3>(tb, s, j, o);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (a < cnt) {
-        V[a] ^= ((s[a][0] >> 2) & 1u) ^ ((uint32_t)(vb[a] >> 32) & t[a] & 1u);
-        bits |= (V[a] & 1u) << (g + a);
+      for (int a = 0; a < 3; ++a) {
+        if (a < cnt) {
+          const uint4 lc = ld16(base[a] + (uint64_t)kTile * 16 * (1 + lev[a]) + kTile * 8 + lane * 16);
+          const uint32_t msk = 0u - t[a];
+          const uint32_t w = xl[a] >> 5;
+          uint32_t word = (o[a][0] ^ (lc.x & msk));
+          word = w == 1 ? (o[a][1] ^ (lc.y & msk)) : word;
+          word = w == 2 ? (o[a][2] ^ (lc.z & msk)) : word;
+          word = w == 3 ? (o[a][3] ^ (lc.w & msk)) : word;
+          V[a] ^= (word >> (xl[a] & 31u)) & 1u;
+          bits |= (V[a] & 1u) << (g + a);
+        }
       }
     }
   }
@@ -746,20 +765,25 @@ __device__ __forceinline__ void rand_blks(const TB& tb, const RoundKeys& rk, uin
   aes_encrypt(RtKey{rk}, tb, o);
 }
 
-// Z_2 DCF Gen for f(x) = 1[x < alpha] over k bits; writes root, cw, vbits.
-// The PRG tweaks are chosen so block 0/1 of each party is the child on /
-// off alpha's path ("keep" / "lose"); no register array is indexed at run time.
+// Z_2 DCF Gen for f(x) = 1[x < alpha] over k bits, the tree stopping nu =
+// min(7, k) levels above the leaves; writes root, cw, vbits and the leaf
+// correction.  The PRG tweaks are chosen so block 0/1 of each party is the
+// child on / off alpha's path ("keep" / "lose"); no register array is indexed
+// at run time.
 template <class TB>
 __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, const uint32_t (&r0)[4],
                                        const uint32_t (&r1)[4], uint8_t* a0, uint8_t* a1, int lane) {
+  const int nu = atom_leaf_bits(k), lev = k - nu;
+  const uint64_t ah = alpha >> nu;
+  const uint32_t al = (uint32_t)(alpha & ((1ull << nu) - 1));
   uint32_t s0[4] = {r0[0] & ~3u, r0[1], r0[2], r0[3]};
   uint32_t s1[4] = {r1[0] & ~3u, r1[1], r1[2], r1[3]};
   uint32_t t0 = 0, t1 = 1, Va = 0;
   uint64_t vbits = 0;
   st16(a0 + lane * 16, make_uint4(s0[0], s0[1], s0[2], s0[3]));
   if (a1) st16(a1 + lane * 16, make_uint4(s1[0], s1[1], s1[2], s1[3]));
-  for (int i = 0; i < k; ++i) {
-    const uint32_t ai = (uint32_t)(alpha >> (k - 1 - i)) & 1u;
+  for (int i = 0; i < lev; ++i) {
+    const uint32_t ai = (uint32_t)(ah >> (lev - 1 - i)) & 1u;
     uint32_t o[4][4];  // p0 keep, p0 lose, p1 keep, p1 lose
     {
       const uint32_t jj[2] = {ai, ai ^ 1u};
@@ -799,11 +823,30 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
     t0 = tk0 ^ (t0 & tk);
     t1 = tk1 ^ (t1 & tk);
   }
-  const uint32_t fin = ((s0[0] >> 2) & 1u) ^ ((s1[0] >> 2) & 1u) ^ Va;
-  vbits |= (uint64_t)fin << 32;
-  uint8_t* vbo = a0 + (uint64_t)kTile * 16 * (1 + k) + lane * 8;
+  uint8_t* vbo = a0 + (uint64_t)kTile * 16 * (1 + lev) + lane * 8;
   st8(vbo, vbits);
   if (a1) st8(a1 + (vbo - a0), vbits);
+  // The leaf correction: the parties' vectors H(s_b, 2) at alpha's leaf XOR to
+  // (1[j < alpha mod 2^nu])_j once it is added, with V_alpha cancelled.
+  uint32_t in[2][4], o[2][4];
+  const uint32_t jj[2] = {2u, 2u};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    in[0][c] = s0[c];
+    in[1][c] = s1[c];
+  }
+  prg<TB, 2>(tb, in, jj, o);
+  const uint32_t flip = 0u - Va;
+  uint32_t lw[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t lo = 32u * (uint32_t)w;
+    const uint32_t below = al >= lo + 32u ? 0xffffffffu : (al <= lo ? 0u : ((1u << (al - lo)) - 1u));
+    lw[w] = o[0][w] ^ o[1][w] ^ below ^ flip;
+  }
+  const uint64_t leaf_off = (uint64_t)kTile * 16 * (1 + lev) + kTile * 8 + lane * 16;
+  st16(a0 + leaf_off, make_uint4(lw[0], lw[1], lw[2], lw[3]));
+  if (a1) st16(a1 + leaf_off, make_uint4(lw[0], lw[1], lw[2], lw[3]));
 }
 
 // Vector DCF Gen for f(x) = beta * 1[x < alpha] over n bits, beta in Z^P,

@@ -40,14 +40,18 @@ class KeyView:
         return HEADER_BYTES + (e // TILE) * int(self.h["tile_bytes"])
 
     def atom(self, e: int, t: int) -> dict:
+        """A comparison atom of width k: its tree has k - min(7, k) levels,
+        then the 16-byte leaf correction (after the value-correction bits)."""
         lane, k = e % TILE, int(self.h["atom_k"][t])
+        lev = k - min(7, k)
         base = self.tile_base(e) + int(self.h["atom_off"][t])
         root = self._blk(base + lane * 16)
-        cws = [self._blk(base + TILE * 16 + (i * TILE + lane) * 16) for i in range(k)]
-        vb = self._u64(base + TILE * 16 * (1 + k) + lane * 8)
+        cws = [self._blk(base + TILE * 16 + (i * TILE + lane) * 16) for i in range(lev)]
+        vb = self._u64(base + TILE * 16 * (1 + lev) + lane * 8)
+        leaf = self._blk(base + TILE * 16 * (1 + lev) + TILE * 8 + lane * 16)
         return {"root": root, "scw": [(lo & ~3, hi) for lo, hi in cws],
                 "tl": [lo & 1 for lo, _ in cws], "tr": [(lo >> 1) & 1 for lo, _ in cws],
-                "vcw": [(vb >> i) & 1 for i in range(k)], "fin": (vb >> 32) & 1}
+                "vcw": [(vb >> i) & 1 for i in range(lev)], "leaf": leaf}
 
     def coeff(self, e: int) -> dict:
         """The lookup DCF: L = ceil(n / r) levels of 2^r children; child c of
@@ -73,10 +77,10 @@ class KeyView:
 
 def oracle_atom(K, t: int) -> dict:
     a = K.atom[t]
-    k = a.n
-    return {"root": (a.root.lo, a.root.hi), "scw": [(a.scw[i].lo, a.scw[i].hi) for i in range(k)],
-            "tl": [a.tl[i] for i in range(k)], "tr": [a.tr[i] for i in range(k)],
-            "vcw": [int(a.vcw[i][0]) for i in range(k)], "fin": int(a.fin[0])}
+    lev = a.n - a.nu
+    return {"root": (a.root.lo, a.root.hi), "scw": [(a.scw[i].lo, a.scw[i].hi) for i in range(lev)],
+            "tl": [a.tl[i] for i in range(lev)], "tr": [a.tr[i] for i in range(lev)],
+            "vcw": [int(a.vcw[i]) for i in range(lev)], "leaf": (a.leaf.lo, a.leaf.hi)}
 
 
 def oracle_coeff(K) -> dict:
