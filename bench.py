@@ -159,6 +159,9 @@ def main() -> None:
     ap.add_argument("--autotune", default=os.path.join(tempfile.gettempdir(), "fusefss_tune_cache.txt"),
                     metavar="CACHE", help="autotuner cache file (the fused launch is tuned on the first layer)")
     ap.add_argument("--no-autotune", action="store_true", help="use the planner's default launch")
+    ap.add_argument("--tune", default=None, metavar="V,BPC,ORDER,PARTS,PRED",
+                    help="fix the fused launch: AES variant, blocks per CU, unit order, parts per tile, "
+                         "call-1 unit (as fss_tune; replaces the autotuner)")
     ap.add_argument("--latency-reps", type=int, default=60,
                     help="fused/plain step pairs, alternating, for the latency percentiles and ratios")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -202,7 +205,10 @@ def main() -> None:
     torch.cuda.synchronize()
     groups = layer_groups(ops)
     tune = None
-    if not args.no_autotune:
+    if args.tune:
+        v, bpc, order, parts, pred = (int(t) for t in args.tune.split(","))
+        tune = F.Tune(0, bpc, v, order, parts, pred)
+    elif not args.no_autotune:
         tune = F.fss_autotune([insts[i].item(b) for i in groups[0] for b in (0, 1)], args.autotune)
     plans = [F.Plan([insts[i].item(b) for i in g for b in (0, 1)], tune) for g in groups]
     graphs = None if args.no_graphs else [F.Graph([p]) for p in plans]
@@ -288,23 +294,33 @@ def main() -> None:
     # these repetitions.
     cmp = None
     if not args.no_plain:
+        import gc
+
         reps = max(args.latency_reps, 50)
         rec = {True: [], False: []}
-        for k in range(reps):
-            for fz in ((True, False) if k % 2 == 0 else (False, True)):
-                ev = events()
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                step(1000 + k, fz, ev)
-                torch.cuda.synchronize()
-                rec[fz].append((time.perf_counter() - t1, ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]),
-                                ev[0].elapsed_time(ev[2])))
+        pair_events = [[events(), events()] for _ in range(reps)]
+        gc.collect()
+        gc.disable()  # no collector pause inside a timed step
+        try:
+            for k in range(reps):
+                for i, fz in enumerate((True, False) if k % 2 == 0 else (False, True)):
+                    ev = pair_events[k][i]
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    step(1000 + k, fz, ev)
+                    torch.cuda.synchronize()
+                    rec[fz].append((time.perf_counter() - t1, ev))
+        finally:
+            gc.enable()
+        rec = {fz: [(w, ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[0].elapsed_time(ev[2]))
+                    for w, ev in rows] for fz, rows in rec.items()}
         check_status()
 
         def summary(rows):
             lat = [r[3] for r in rows]
             ev_ = [r[2] for r in rows]
             return {"step_wall_ms": round(1e3 * statistics.mean(r[0] for r in rows), 4),
+                    "step_wall_p50_ms": round(1e3 * pct([r[0] for r in rows], 0.5), 4),
                     "keygen_ms": round(statistics.mean(r[1] for r in rows), 4),
                     "eval_ms": round(statistics.mean(ev_), 4),
                     "latency_ms": {"p50": round(pct(lat, 0.5), 4), "p99": round(pct(lat, 0.99), 4)},
@@ -343,7 +359,7 @@ def main() -> None:
                    "path": "fused persistent work-list" + (", HIP graph per layer" if graphs else ""),
                    "launches_per_step": len(plans),
                    "step": "keygen (both parties) + masked opening + eval (both parties)",
-                   "launch": cfg, "autotuned": tune is not None,
+                   "launch": cfg, "autotuned": tune is not None and not args.tune,
                    "lookup_r": insts[0].lookup_r,
                    "key_bytes_per_party": sum(i.key_bytes for i in insts)},
         "breakdown_ms": {"keygen": round(fused["keygen_ms"], 4), "eval": round(fused["eval_ms"], 4)},
@@ -380,6 +396,7 @@ def main() -> None:
                                "step_wall_ms": f_["step_wall_ms"], "keygen_ms": f_["keygen_ms"],
                                "eval_ms": f_["eval_ms"]}
         out["fused_over_plain"] = round(p_["step_wall_ms"] / f_["step_wall_ms"], 4)
+        out["fused_over_plain_p50"] = round(p_["step_wall_p50_ms"] / f_["step_wall_p50_ms"], 4)
         out["eval_fused_over_plain"] = round(p_["eval_ms"] / f_["eval_ms"], 4)
         out["comparison"] = (f"{cmp['reps']} pairs of one fused and one plain step with the same seeds, "
                              "order alternating, each step between synchronisations")

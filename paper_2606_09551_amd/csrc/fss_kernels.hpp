@@ -8,7 +8,7 @@
 
 namespace fss {
 
-constexpr int kNumAesVariants = 4;
+constexpr int kNumAesVariants = 5;  // 0-3: T-table layouts in LDS, 4: bitsliced PRG
 
 struct RoundKeys { uint32_t w[44]; };
 
@@ -61,6 +61,7 @@ extern template struct VariantOps<0>;
 extern template struct VariantOps<1>;
 extern template struct VariantOps<2>;
 extern template struct VariantOps<3>;
+extern template struct VariantOps<4>;
 
 hipError_t launch_header_init(uint8_t* dst, const uint8_t* src, int64_t n_elems, uint64_t n_tiles,
                               uint32_t party, hipStream_t st);

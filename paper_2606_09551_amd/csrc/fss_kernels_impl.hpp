@@ -11,6 +11,7 @@
 
 #include <utility>
 
+#include "fss_aes_bs.hpp"
 #include "fss_kernels.hpp"
 
 namespace fss {
@@ -68,6 +69,7 @@ __device__ __forceinline__ uint32_t lane_addr(uint32_t w, uint32_t base) {
 
 // Variant 0: the four 1 KB tables, one copy each.
 struct Tab0 {
+  static constexpr bool kBitsliced = false;
   static constexpr int kWords = 1024;
   const uint32_t* lds;
   __device__ Tab0(const uint32_t* l, int) : lds(l) {}
@@ -83,6 +85,7 @@ struct Tab0 {
 // Variant 1: four tables, 32 lane-private copies, 256-byte entry rows:
 // entry x of table t at byte (t>>1)*65536 + x*256 + (t&1)*128 + (lane&31)*4.
 struct Tab1 {
+  static constexpr bool kBitsliced = false;
   static constexpr int kWords = 32768;
   const uint8_t* lds;
   uint32_t base01, base23;
@@ -106,6 +109,7 @@ struct Tab1 {
 
 // Variant 2: Te0 and Te2 with 32 copies (64 KB); T1, T3 by an 8-bit rotate.
 struct Tab2 {
+  static constexpr bool kBitsliced = false;
   static constexpr int kWords = 16384;
   const uint8_t* lds;
   uint32_t base;
@@ -127,6 +131,7 @@ struct Tab2 {
 
 // Variant 3: Te0 only, 64 lane-private copies (64 KB); T1..T3 by rotates.
 struct Tab3 {
+  static constexpr bool kBitsliced = false;
   static constexpr int kWords = 16384;
   const uint8_t* lds;
   uint32_t base;
@@ -145,11 +150,22 @@ struct Tab3 {
   }
 };
 
+// Variant 4: the fixed-key PRG is bitsliced in registers (fss_aes_bs.hpp: two
+// blocks as eight bit planes, SubBytes by composite-field inversion), with no
+// table lookups; AES under a key known only at launch (the dealer's
+// counter-mode randomness) keeps layout 1's tables.
+struct TabBS : Tab1 {
+  static constexpr bool kBitsliced = true;
+  __device__ TabBS(const uint32_t* l, int lane) : Tab1(l, lane) {}
+};
+static __constant__ bs::PrgPlanes c_prg_planes = bs::make_prg_planes(kAes.prg_rk);
+
 template <int V> struct TabOf;
 template <> struct TabOf<0> { using T = Tab0; static constexpr int kBlock = 256; };
 template <> struct TabOf<1> { using T = Tab1; static constexpr int kBlock = 768; };
 template <> struct TabOf<2> { using T = Tab2; static constexpr int kBlock = 512; };
 template <> struct TabOf<3> { using T = Tab3; static constexpr int kBlock = 512; };
+template <> struct TabOf<4> { using T = TabBS; static constexpr int kBlock = 768; };
 
 // ---------------------------------------------------------------------------
 // AES-128 encryption of K independent blocks, round-interleaved for ILP.
@@ -236,10 +252,46 @@ __device__ __forceinline__ void aes_encrypt(const Key& key, const TB& tb, uint32
   aes_final(key, tb, s);
 }
 
+// AES_K of K blocks under the fixed PRG key, bitsliced two at a time (an odd
+// last block is encrypted beside a copy of itself).
+template <int K>
+__device__ __forceinline__ void prg_aes_bitsliced(const uint32_t (&x)[K][4], uint32_t (&o)[K][4]) {
+#pragma unroll
+  for (int k = 0; k < K; k += 2) {
+    const int k2 = k + 1 < K ? k + 1 : k;
+    uint32_t a[4] = {x[k][0], x[k][1], x[k][2], x[k][3]}, b[4] = {x[k2][0], x[k2][1], x[k2][2], x[k2][3]};
+    uint32_t pl[8];
+    bs::pack(a, b, pl);
+    bs::encrypt_pair(c_prg_planes, pl);
+    bs::unpack(pl, a, b);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      o[k][c] = a[c];
+      if (k + 1 < K) o[k2][c] = b[c];
+    }
+  }
+}
+
 // H(s, j) = AES_K(s ^ J_j) ^ s ^ J_j with J_j = byte 15 set to j.
 template <class TB, int K>
 __device__ __forceinline__ void prg(const TB& tb, const uint32_t (&s)[K][4], const uint32_t (&j)[K],
                                     uint32_t (&o)[K][4]) {
+  if constexpr (TB::kBitsliced) {
+    uint32_t x[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      x[k][0] = s[k][0];
+      x[k][1] = s[k][1];
+      x[k][2] = s[k][2];
+      x[k][3] = s[k][3] ^ (j[k] << 24);
+    }
+    prg_aes_bitsliced<K>(x, o);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) o[k][c] ^= x[k][c];
+    return;
+  }
   uint32_t x[K][4];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -262,6 +314,15 @@ __device__ __forceinline__ void prg(const TB& tb, const uint32_t (&s)[K][4], con
 template <class TB, int K>
 __device__ __forceinline__ void prg_shared(const TB& tb, const uint32_t (&s)[4], const uint32_t (&j)[K],
                                            uint32_t (&o)[K][4]) {
+  if constexpr (TB::kBitsliced) {  // no table lookups to share: K blocks, two per bitsliced pair
+    uint32_t ss[K][4];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ss[k][c] = s[c];
+    prg<TB, K>(tb, ss, j, o);
+    return;
+  }
   constexpr PrgKey key{};
   const uint32_t a0 = s[0] ^ key.template w<0>(), a1 = s[1] ^ key.template w<1>();
   const uint32_t a2 = s[2] ^ key.template w<2>(), a3 = s[3] ^ key.template w<3>();

@@ -57,6 +57,7 @@ hipError_t launch_keygen(int v, int p, int r, const KeyHeader* h, const KgArgs& 
     case 1: return VariantOps<1>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
     case 2: return VariantOps<2>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
     case 3: return VariantOps<3>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
+    case 4: return VariantOps<4>::keygen(h, p, r, ga, k0, k1, ri, ro, cus, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -68,6 +69,7 @@ hipError_t launch_eval_pred(int v, int party, const uint8_t* keys, const uint64_
     case 1: return VariantOps<1>::pred(party, keys, xhat, n, z, status, cus, st);
     case 2: return VariantOps<2>::pred(party, keys, xhat, n, z, status, cus, st);
     case 3: return VariantOps<3>::pred(party, keys, xhat, n, z, status, cus, st);
+    case 4: return VariantOps<4>::pred(party, keys, xhat, n, z, status, cus, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -79,6 +81,7 @@ hipError_t launch_eval_coeff(int v, int party, const uint8_t* keys, const uint64
     case 1: return VariantOps<1>::coeff(party, keys, xhat, n, y, status, cus, st);
     case 2: return VariantOps<2>::coeff(party, keys, xhat, n, y, status, cus, st);
     case 3: return VariantOps<3>::coeff(party, keys, xhat, n, y, status, cus, st);
+    case 4: return VariantOps<4>::coeff(party, keys, xhat, n, y, status, cus, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -111,6 +114,7 @@ hipError_t launch_fused(int v, const DevItem* items, const uint32_t* tiles, uint
     case 1: return VariantOps<1>::fused(items, tiles, n_tiles, counter, status, grid, st);
     case 2: return VariantOps<2>::fused(items, tiles, n_tiles, counter, status, grid, st);
     case 3: return VariantOps<3>::fused(items, tiles, n_tiles, counter, status, grid, st);
+    case 4: return VariantOps<4>::fused(items, tiles, n_tiles, counter, status, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -120,7 +124,8 @@ int variant_block(int v) {
     case 0: return VariantOps<0>::block();
     case 1: return VariantOps<1>::block();
     case 2: return VariantOps<2>::block();
-    default: return VariantOps<3>::block();
+    case 3: return VariantOps<3>::block();
+    default: return VariantOps<4>::block();
   }
 }
 
@@ -129,7 +134,8 @@ int variant_lds_bytes(int v) {
     case 0: return VariantOps<0>::lds_bytes();
     case 1: return VariantOps<1>::lds_bytes();
     case 2: return VariantOps<2>::lds_bytes();
-    default: return VariantOps<3>::lds_bytes();
+    case 3: return VariantOps<3>::lds_bytes();
+    default: return VariantOps<4>::lds_bytes();
   }
 }
 
