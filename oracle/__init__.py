@@ -132,6 +132,8 @@ def lib():
                                      C.c_int64, u64p, u64p, C.c_int]
         L.orc_full_batch.argtypes = [C.POINTER(Spec), u8p, i64p, C.c_int64, i64p,
                                      u64p, u64p, u64p, u64p, u64p, u64p, C.c_int]
+        L.orc_trunc_batch.argtypes = [C.c_int, C.c_int, u8p, i64p, C.c_int64, u64p, u64p, u64p, u64p, u64p,
+                                      C.c_int]
         L.orc_plain_eval.argtypes = [C.POINTER(Spec), C.c_int64, u64p, u64p]
         L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
                                     C.POINTER(C.c_int32)]
@@ -378,3 +380,20 @@ def aes_blocks() -> int:
     L = lib()
     L.orc_aes_blocks.restype = C.c_uint64
     return int(L.orc_aes_blocks())
+
+
+# ---- rescaling gate ------------------------------------------------------------
+
+def trunc(shift: int, seed: int, elems, r_in, yhat, lookup_r: int = 3, threads: int = 0):
+    """ARS gate: keygen at the given input masks r_in and both parties'
+    evaluation at the openings yhat.  Returns (z0, z1, r_out)."""
+    elems = np.ascontiguousarray(elems, dtype=np.int64)
+    r_in = np.ascontiguousarray(r_in, dtype=np.uint64)
+    yhat = np.ascontiguousarray(yhat, dtype=np.uint64)
+    cnt = len(elems)
+    z0, z1, r_out = (np.zeros(cnt, np.uint64) for _ in range(3))
+    rc = lib().orc_trunc_batch(shift, lookup_r, seed_bytes(seed), _i64p(elems), cnt, _u64p(r_in), _u64p(yhat),
+                               _u64p(z0), _u64p(z1), _u64p(r_out), threads)
+    if rc < 0:
+        raise ValueError(f"oracle rejected the rescaling gate (shift={shift}, r={lookup_r})")
+    return z0, z1, r_out

@@ -918,6 +918,57 @@ void orc_plain_eval(const orc_spec* S, int64_t x, uint64_t* y_out, uint64_t* z_o
 }
 
 /* ========================================================================= */
+/* Rescaling gate: arithmetic right shift of a masked 64-bit value           */
+/* ========================================================================= */
+/* Fixed-point rescaling by ARS (Sec. 3.2 encoding; the paper lists truncation
+ * and ARS among the specification-compatible gates).  The input is the
+ * opening yhat = y + r_in of a signed y with |y| < 2^62 (the bound every
+ * compiled piece satisfies), masked by the previous gate's output mask r_in;
+ * the output is shares of floor(y / 2^s) + r_out.  With u = y + 2^62 in
+ * [0, 2^63) and uhat = yhat + 2^62 = u + r_in (mod 2^64):
+ *   u >> s = (uhat >> s) - (r_in >> s) - c + 2^(64-s) w,
+ *   c = 1[uhat mod 2^s < r_in mod 2^s]   (the borrow of the low s bits),
+ *   w = 1[u + r_in >= 2^64] = MSB(r_in) (1 - MSB(uhat))   (as u < 2^63),
+ * and floor(y / 2^s) = (u >> s) - 2^(62-s).  The borrow is a comparison of
+ * the public uhat with the secret r_in over s bits: one DCF with payload -1 in
+ * Z_{2^64} (the 2^r-children DCF above, p = 1) gives additive shares of -c
+ * directly.  The dealer also shares k0 = r_out - (r_in >> s) and
+ * k1 = 2^(64-s) MSB(r_in). */
+
+uint64_t orc_ars(int64_t y, int s) { return (uint64_t)(y >> s); }
+
+void orc_trunc_keygen_elem(int s, int r, const orc_aes_sched* kseed, uint64_t e, uint64_t r_in,
+                           orc_trunc_key* k0, orc_trunc_key* k1, uint64_t* r_out_out) {
+  const uint64_t r_out = orc_rand(kseed, e, 0, 0).lo;
+  const uint64_t v0 = r_out - (r_in >> s);
+  const uint64_t v1 = (r_in >> 63) ? (uint64_t)1 << (64 - s) : 0;
+  const orc_blk sh = orc_rand(kseed, e, 1, 0);
+  k0->k0 = sh.lo;
+  k1->k0 = v0 - sh.lo;
+  k0->k1 = sh.hi;
+  k1->k1 = v1 - sh.hi;
+  orc_blk c0 = orc_rand(kseed, e, 64, 0);
+  orc_blk c1 = orc_rand(kseed, e, 65, 0);
+  orc_blk kr[ORC_MAXLR * 3];
+  memset(kr, 0, sizeof kr);
+  const int levels = (s + r - 1) / r;
+  for (int i = 0; i + 1 < levels; i++)
+    for (int k = 0; k < 2; k++) kr[i * 2 + k] = orc_rand(kseed, e, 69 + k, i);
+  const uint64_t beta = (uint64_t)0 - 1;
+  orc_dcfr_gen(s, r, 1, r_in & lowmask(s), &beta, c0, c1, kr, &k0->dcf, &k1->dcf);
+  *r_out_out = r_out;
+}
+
+uint64_t orc_trunc_eval_elem(int b, int s, const orc_trunc_key* K, uint64_t yhat) {
+  const uint64_t uhat = yhat + ((uint64_t)1 << 62);
+  uint64_t negc;
+  orc_dcfr_eval(b, &K->dcf, uhat & lowmask(s), &negc);
+  uint64_t z = K->k0 + (1 - (uhat >> 63)) * K->k1 + negc;
+  if (b == 0) z += (uhat >> s) - ((uint64_t)1 << (62 - s));
+  return z;
+}
+
+/* ========================================================================= */
 /* Protocol "Compile a scalar gate instance", lookup part                    */
 /* ========================================================================= */
 
@@ -980,7 +1031,8 @@ int orc_sizeof_dcfr_key(void) { return (int)sizeof(orc_dcfr_key); }
 int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
 
 typedef struct {
-  int kind;  /* 0 keygen, 1 eval, 2 full */
+  int kind;  /* 0 keygen, 1 eval, 2 full, 3 rescaling gate (keygen + both parties' evaluation) */
+  int shift, radix;
   const orc_spec* S;
   uint8_t seed[16];
   const int64_t* elems;
@@ -1006,6 +1058,13 @@ static void* run_job(void* arg) {
       orc_keygen_elem(J->S, &ks, (uint64_t)J->elems[i], &J->k0[i], &J->k1[i], &J->r_in[i], &J->r_out[i]);
     } else if (J->kind == 1) {
       orc_eval_elem(J->b, J->S, &J->K[i], J->xhat[i], &J->y0[i], &J->z0[i]);
+    } else if (J->kind == 3) {
+      orc_trunc_key a, b;
+      uint64_t rout;
+      orc_trunc_keygen_elem(J->shift, J->radix, &ks, (uint64_t)J->elems[i], J->r_in[i], &a, &b, &rout);
+      J->r_out[i] = rout;
+      J->y0[i] = orc_trunc_eval_elem(0, J->shift, &a, J->xhat[i]);
+      J->y1[i] = orc_trunc_eval_elem(1, J->shift, &b, J->xhat[i]);
     } else {
       orc_elem_key a, b;
       uint64_t rin, rout;
@@ -1064,5 +1123,16 @@ int orc_full_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* ele
   memset(&J, 0, sizeof J);
   J.kind = 2; J.S = S; memcpy(J.seed, seed, 16); J.elems = elems; J.x = x;
   J.y0 = y0; J.y1 = y1; J.z0 = z0; J.z1 = z1; J.r_in = r_in; J.r_out = r_out;
+  return run_jobs(J, count, threads);
+}
+
+int orc_trunc_batch(int s, int r, const uint8_t seed[16], const int64_t* elems, int64_t count,
+                    const uint64_t* r_in, const uint64_t* yhat, uint64_t* z0, uint64_t* z1, uint64_t* r_out,
+                    int threads) {
+  if (s < 1 || s > ORC_MAXN || r < 2 || r > 4) return -3;
+  job_t J;
+  memset(&J, 0, sizeof J);
+  J.kind = 3; J.shift = s; J.radix = r; memcpy(J.seed, seed, 16); J.elems = elems;
+  J.r_in = (uint64_t*)r_in; J.xhat = yhat; J.y0 = z0; J.y1 = z1; J.r_out = r_out;
   return run_jobs(J, count, threads);
 }

@@ -200,6 +200,28 @@ int orc_sizeof_dcfz_key(void);
 int orc_sizeof_dcfr_key(void);
 int orc_sizeof_spec(void);
 
+/* ---- rescaling gate: ARS of a masked 64-bit value ------------------------- */
+/* Input: the opening yhat = y + r_in of a signed y, |y| < 2^62, masked by the
+ * previous gate's output mask r_in.  Output: additive shares of
+ * floor(y / 2^s) + r_out, 1 <= s <= 32.  Key: a DCF with payload -1 over the
+ * s low bits (2^r children per level, r in {2, 3, 4}) at alpha = r_in mod 2^s,
+ * and additive shares of k0 = r_out - (r_in >> s) and k1 = 2^(64-s) MSB(r_in).
+ * Randomness R(e, .): purpose 0 -> r_out (lo), 1 -> party-0 shares of k0 (lo)
+ * and k1 (hi), 64 / 65 -> DCF roots, 69 + k -> on-path corrections. */
+typedef struct {
+  orc_dcfr_key dcf;
+  uint64_t k0, k1;
+} orc_trunc_key;
+
+uint64_t orc_ars(int64_t y, int s);
+void orc_trunc_keygen_elem(int s, int r, const orc_aes_sched* kseed, uint64_t e, uint64_t r_in,
+                           orc_trunc_key* k0, orc_trunc_key* k1, uint64_t* r_out);
+uint64_t orc_trunc_eval_elem(int b, int s, const orc_trunc_key* K, uint64_t yhat);
+/* Keygen at the given r_in and both parties' evaluation at yhat, per element. */
+int orc_trunc_batch(int s, int r, const uint8_t seed[16], const int64_t* elems, int64_t count,
+                    const uint64_t* r_in, const uint64_t* yhat, uint64_t* z0, uint64_t* z1, uint64_t* r_out,
+                    int threads);
+
 /* ---- Protocol "Compile a scalar gate instance", lookup part ---------------- */
 /* alpha: boundaries 0=a_0<...<a_m=N of the partition being translated; r: mask.
  * Writes B[0..M] and ord[0..M-1] (B needs room for m + 2 entries); returns M. */
