@@ -91,7 +91,7 @@ def cpu_baseline(op, n_bits, f_bits, lookup_r, gpu_shares) -> dict:
 
 
 KERNEL_SOURCES = ["paper_2606_09551_amd/csrc/fss_kernels_impl.hpp", "paper_2606_09551_amd/csrc/fss_common.hpp",
-                  "paper_2606_09551_amd/csrc/fss_kernels.hpp"]
+                  "paper_2606_09551_amd/csrc/fss_kernels.hpp", "paper_2606_09551_amd/csrc/fss_aes_bs.hpp"]
 
 
 def measured_traffic(workload: str, lookup_r: int):
@@ -194,8 +194,16 @@ def main() -> None:
         return
     ops, n_bits, f_bits, wname = build_ops(args.workload)
     insts = []
+    tuned_r = {}
     for op in ops:
-        inst = R.OpInstanceGPU(F.Spec(op.spec, args.lookup_r), n_bits, f_bits, len(op.x))
+        spec = F.Spec(op.spec, args.lookup_r)
+        if args.lookup_r is None and not (args.no_autotune or args.tune):
+            # the key-layout knob: lookup radix per spec and size, timed once and cached
+            key = (op.spec.name, len(op.x))
+            if key not in tuned_r:
+                tuned_r[key] = spec.autotune_radix(n_bits, f_bits, len(op.x), args.autotune)
+            F.lib.fss_spec_set_lookup_radix(spec.handle, tuned_r[key])
+        inst = R.OpInstanceGPU(spec, n_bits, f_bits, len(op.x))
         inst.set_input(op.x)
         insts.append(inst)
     n_elems = sum(i.n for i in insts)
@@ -361,6 +369,7 @@ def main() -> None:
                    "step": "keygen (both parties) + masked opening + eval (both parties)",
                    "launch": cfg, "autotuned": tune is not None and not args.tune,
                    "lookup_r": insts[0].lookup_r,
+                   "lookup_r_autotuned": bool(tuned_r),
                    "key_bytes_per_party": sum(i.key_bytes for i in insts)},
         "breakdown_ms": {"keygen": round(fused["keygen_ms"], 4), "eval": round(fused["eval_ms"], 4)},
         "aes_blocks_per_s": round((eval_aes + kg_aes) * args.steps / fused["wall_s"], 1),

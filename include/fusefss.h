@@ -191,6 +191,38 @@ int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int
 int fss_mask_input(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat,
                    void* stream);
 
+/* ---- rescaling gate: ARS of a masked value ---------------------------------
+ * Fixed-point rescaling by arithmetic right shift (Sec. 3.2 encoding; the
+ * paper counts truncation and ARS among the specification-compatible gates
+ * of Definition "Specification-compatible scalar gate").  The gate composes
+ * with an operator gate the way FSS gates compose: the operator's output
+ * mask r_out is the rescaling gate's input mask, the parties open
+ * yhat = y_0 + y_1 = y + r_out (fss_open), and each evaluates its key on
+ * yhat.  For a signed y with |y| < 2^62 (every compiled piece satisfies the
+ * bound) the outputs are shares of floor(y / 2^shift_bits) + r_out', with a
+ * fresh output mask r_out'.  shift_bits in [1, 32]; lookup_bits (2, 3 or 4)
+ * is the input bits per level of the gate's comparison DCF. */
+
+/* Bytes of one party's rescaling-gate key buffer (mask-independent). */
+int fss_rescale_key_bytes(int32_t shift_bits, int32_t lookup_bits, int64_t n_elems, size_t* per_party);
+/* Dealer keygen of n_elems rescaling gates.
+ *   seed: host, 16 bytes (the gate's own dealer seed, as in fss_keygen).
+ *   r_in: device, n_elems u64: the input masks (the previous gate's r_out).
+ *   key0, key1: device, fss_rescale_key_bytes each (key1 may be NULL).
+ *   r_out: device, n_elems u64 output masks (may be NULL).
+ * Errors: FSS_E_UNSUPPORTED (shift_bits), FSS_E_ARG. */
+int fss_rescale_keygen(int32_t shift_bits, int32_t lookup_bits, const uint8_t* seed, int64_t n_elems,
+                       const uint64_t* r_in, void* key0, void* key1, uint64_t* r_out, void* stream);
+/* Party `party`'s evaluation at the openings yhat (device, n_elems u64);
+ * z: device, n_elems u64 output shares.  Key-buffer mismatches are recorded
+ * in the device status word (fss_status). */
+int fss_rescale_eval(int32_t party, const void* keys, const uint64_t* yhat, int64_t n_elems, uint64_t* z,
+                     void* stream);
+/* The opening of additive shares held on one device (both parties simulated
+ * in one process; across two devices each party would send its share):
+ * yhat[e] = y0[e] + y1[e] mod 2^64, all device, n each. */
+int fss_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat, void* stream);
+
 /* ---- online evaluation (Sec. 5.3 "Online Evaluation", steps 2-3) ------- */
 
 /* Plain evaluator: call 1 then call 2 as two kernel launches.
@@ -315,6 +347,17 @@ int fss_graph_free(fss_graph* graph);
 int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_path,
                  fss_tune* best);
 int fss_aes_variants(void);
+
+/* The key-layout knob: pick the input bits per level of call 2's DCF (2, 3
+ * or 4, fss_spec_set_lookup_radix) for `spec` at (n_bits, frac_bits) over
+ * n_elems elements by timing one step per candidate -- both parties' keygen
+ * and one fused launch of both parties' evaluation -- on scratch buffers this
+ * call allocates and frees.  A larger radix (larger keys) must be faster by
+ * 2 % to be chosen.  Sets the spec's radix to the winner and returns it in
+ * *best_bits; results are cached in `cache_path` (may be NULL) keyed by the
+ * spec, sizes and device.  Keys generated afterwards use the chosen radix. */
+int fss_autotune_radix(fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, const char* cache_path,
+                       int32_t* best_bits);
 
 /* ---- status ------------------------------------------------------------ */
 

@@ -627,6 +627,130 @@ int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int
   return FSS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Header templates of rescaling gates, per (shift, lookup bits), uploaded
+// once per device.
+struct RescaleTemplate {
+  KeyHeader h;
+  std::map<int, uint8_t*> dev;
+};
+std::mutex g_rs_mu;
+std::map<std::pair<int, int>, std::unique_ptr<RescaleTemplate>> g_rs;
+
+int rescale_template(int shift, int r, RescaleTemplate** out) {
+  if (shift < 1 || shift > 32) return fail(FSS_E_UNSUPPORTED, "shift_bits=%d outside [1,32]", shift);
+  if (r < 2 || r > 4) return fail(FSS_E_ARG, "lookup radix bits=%d not in {2, 3, 4}", r);
+  std::lock_guard<std::mutex> lk(g_rs_mu);
+  auto& slot = g_rs[std::make_pair(shift, r)];
+  if (!slot) {
+    slot.reset(new RescaleTemplate());
+    KeyHeader& h = slot->h;
+    memset(&h, 0, sizeof h);
+    const Layout L = make_rescale_layout(shift, r);
+    h.magic = kMagic;
+    h.version = kVersion;
+    h.kind = kGateRescale;
+    h.shift = (uint32_t)shift;
+    h.n = (uint32_t)shift;
+    h.p = 1;
+    h.lookup_r = (uint32_t)r;
+    h.tile_bytes = L.tile_bytes;
+    h.off_croot = L.off_croot;
+    h.off_crec = L.off_crec;
+    h.rec_bytes = L.rec_bytes;
+    h.off_tk0 = L.off_crho;
+    h.off_tk1 = L.off_crout;
+  }
+  *out = slot.get();
+  return FSS_OK;
+}
+
+int rescale_device_header(RescaleTemplate* t, uint8_t** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_rs_mu);
+  auto it = t->dev.find(dev);
+  if (it != t->dev.end()) {
+    *out = it->second;
+    return FSS_OK;
+  }
+  hipStream_t up;
+  int rc = aux_stream(&up);
+  if (rc) return rc;
+  uint8_t* p = nullptr;
+  HIP_TRY(hipMalloc(&p, sizeof(KeyHeader)), "hipMalloc(header)");
+  HIP_TRY(hipMemcpyAsync(p, &t->h, sizeof(KeyHeader), hipMemcpyHostToDevice, up), "hipMemcpyAsync(header)");
+  HIP_TRY(hipStreamSynchronize(up), "hipStreamSynchronize(header)");
+  t->dev[dev] = p;
+  *out = p;
+  return FSS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int fss_rescale_key_bytes(int32_t shift_bits, int32_t lookup_bits, int64_t n_elems, size_t* per_party) {
+  if (!per_party) return fail(FSS_E_ARG, "per_party NULL");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  RescaleTemplate* t = nullptr;
+  int rc = rescale_template(shift_bits, lookup_bits, &t);
+  if (rc) return rc;
+  *per_party = (size_t)(kHeaderBytes + (((uint64_t)n_elems + kTile - 1) / kTile) * t->h.tile_bytes);
+  return FSS_OK;
+}
+
+int fss_rescale_keygen(int32_t shift_bits, int32_t lookup_bits, const uint8_t* seed, int64_t n_elems,
+                       const uint64_t* r_in, void* key0, void* key1, uint64_t* r_out, void* stream) {
+  if (!seed || !key0) return fail(FSS_E_ARG, "seed/key0 NULL");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  if (n_elems > 0 && !r_in) return fail(FSS_E_ARG, "r_in NULL");
+  RescaleTemplate* t = nullptr;
+  int rc = rescale_template(shift_bits, lookup_bits, &t);
+  if (rc) return rc;
+  uint8_t* dh = nullptr;
+  if ((rc = rescale_device_header(t, &dh))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t tiles = ((uint64_t)n_elems + kTile - 1) / kTile;
+  HIP_TRY(launch_header_init((uint8_t*)key0, dh, n_elems, tiles, 0, st), "header_init");
+  if (key1) HIP_TRY(launch_header_init((uint8_t*)key1, dh, n_elems, tiles, 1, st), "header_init");
+  if (tiles == 0) return FSS_OK;
+  KgArgs ga{};
+  seed_round_keys(seed, ga.rk.w);
+  ga.n_elems = n_elems;
+  ga.n_tiles = tiles;
+  ga.jobs = 1;
+  int cus = 0;
+  if ((rc = current_cus(&cus))) return rc;
+  HIP_TRY(launch_rescale_keygen(keygen_variant(), lookup_bits, reinterpret_cast<const KeyHeader*>(dh), ga, r_in,
+                                (uint8_t*)key0, (uint8_t*)key1, r_out, cus, st),
+          "rescale keygen launch");
+  return FSS_OK;
+}
+
+int fss_rescale_eval(int32_t party, const void* keys, const uint64_t* yhat, int64_t n_elems, uint64_t* z,
+                     void* stream) {
+  int rc = check_party(party);
+  if (rc) return rc;
+  if (!keys || n_elems < 0 || (n_elems > 0 && (!yhat || !z))) return fail(FSS_E_ARG, "bad arguments");
+  int* st = nullptr;
+  if ((rc = device_status_ptr(&st))) return rc;
+  int cus = 0;
+  if ((rc = current_cus(&cus))) return rc;
+  HIP_TRY(launch_rescale_eval(eval_variant(), party, (const uint8_t*)keys, yhat, n_elems, z, st, cus,
+                              (hipStream_t)stream),
+          "rescale eval launch");
+  return FSS_OK;
+}
+
+int fss_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat, void* stream) {
+  if (n < 0) return fail(FSS_E_ARG, "n < 0");
+  if (n > 0 && (!y0 || !y1 || !yhat)) return fail(FSS_E_ARG, "NULL buffer");
+  HIP_TRY(launch_open(y0, y1, n, yhat, (hipStream_t)stream), "open launch");
+  return FSS_OK;
+}
+
 int fss_mask_input(const int64_t* x, const uint64_t* r_in, int64_t n, uint64_t* xhat, void* stream) {
   if (n < 0) return fail(FSS_E_ARG, "n < 0");
   if (n > 0 && (!x || !r_in || !xhat)) return fail(FSS_E_ARG, "NULL buffer");
@@ -967,6 +1091,7 @@ int read_header(const void* keys, KeyHeader* h, const hipStream_t* on = nullptr)
   HIP_TRY(hipMemcpyAsync(h, keys, sizeof(KeyHeader), hipMemcpyDeviceToHost, s), "hipMemcpyAsync(header)");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(header)");
   if (h->magic != kMagic || h->version != kVersion) return fail(FSS_E_SHAPE, "not a key buffer");
+  if (h->kind != kGateOperator) return fail(FSS_E_SHAPE, "not an operator gate's key buffer");
   if (h->lookup_r < 2 || h->lookup_r > 4 || h->rec_bytes != 16 + 8 * (uint64_t)h->p ||
       (h->top_depth > 0 && (h->top_blocks < 2 || h->top_blocks > (uint32_t)kMaxTopBlocks)))
     return fail(FSS_E_SHAPE, "key buffer with an unknown lookup layout");
@@ -1384,6 +1509,109 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
       << bt.parts << " " << bt.pred_unit << "\n";
   }
   return FSS_OK;
+}
+
+int fss_autotune_radix(fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, const char* cache_path,
+                       int32_t* best_bits) {
+  if (!spec || !best_bits) return fail(FSS_E_ARG, "NULL argument");
+  if (n_elems < 1) return fail(FSS_E_ARG, "n_elems must be positive");
+  int cus = 0;
+  std::string arch;
+  int rc = device_cus(&cus, &arch);
+  if (rc) return rc;
+  std::ostringstream key;
+  key << "radix|" << arch << ":" << cus << "|" << std::hex << spec->hash << std::dec << "," << n_bits << ","
+      << frac_bits << "," << n_elems;
+  const std::string k = std::to_string(fnv1a(key.str().data(), key.str().size()));
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      std::istringstream ls(line);
+      std::string kk;
+      int r = 0;
+      if (ls >> kk >> r && kk == k && r >= 2 && r <= 4) {
+        *best_bits = r;
+        return fss_spec_set_lookup_radix(spec, r);
+      }
+    }
+  }
+  const int r0 = fss_spec_get_lookup_radix(spec);
+  std::shared_ptr<QSpec> q;
+  if ((rc = get_qspec(spec, n_bits, frac_bits, &q))) return rc;
+  const int ell = q->ell;
+  hipStream_t s;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+  HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+  const size_t words = (size_t)(n_elems + 63) / 64;
+  uint64_t *xh = nullptr, *y = nullptr, *z = nullptr;
+  double best_ms = 1e30;
+  int best = r0;
+  double ms_of[5] = {0, 0, 0, 0, 0};
+  const uint8_t seed[16] = {0x5a};
+  if (hipMalloc(&xh, 8 * (size_t)n_elems) != hipSuccess || hipMalloc(&y, 16 * (size_t)n_elems) != hipSuccess ||
+      hipMalloc(&z, 16 * std::max<size_t>(1, (size_t)ell * words)) != hipSuccess)
+    rc = fail(FSS_E_HIP, "hipMalloc(radix autotune buffers)");
+  if (rc == FSS_OK) (void)hipMemsetAsync(xh, 0, 8 * (size_t)n_elems, s);
+  for (int r = 2; r <= 4 && rc == FSS_OK; ++r) {
+    if ((rc = fss_spec_set_lookup_radix(spec, r))) break;
+    size_t kb = 0;
+    if ((rc = fss_key_bytes(spec, n_bits, frac_bits, n_elems, &kb))) break;
+    void *k0 = nullptr, *k1 = nullptr;
+    if (hipMalloc(&k0, kb) != hipSuccess || hipMalloc(&k1, kb) != hipSuccess) {
+      rc = fail(FSS_E_HIP, "hipMalloc(radix autotune keys)");
+      (void)hipFree(k0);
+      break;
+    }
+    // one step as the benchmark times it: both parties' keys, then one fused
+    // launch of both parties' evaluation; the faster of two after a warm-up
+    double ms = 1e30;
+    fss_plan* P = nullptr;
+    for (int rep = 0; rep < 3 && rc == FSS_OK; ++rep) {
+      (void)hipEventRecord(e0, s);
+      rc = fss_keygen(spec, n_bits, frac_bits, seed, n_elems, k0, k1, nullptr, nullptr, s);
+      if (rc == FSS_OK && !P) {
+        HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize(radix)");
+        fss_work_item it[2] = {{0, 0, k0, xh, y, z, n_elems}, {1, 0, k1, xh, y + n_elems, z + ell * words, n_elems}};
+        rc = fss_plan_create(it, 2, nullptr, &P);
+      }
+      if (rc == FSS_OK) rc = fss_plan_launch(P, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float m = 0;
+      (void)hipEventElapsedTime(&m, e0, e1);
+      if (rep > 0) ms = std::min(ms, (double)m);
+    }
+    if (P) fss_plan_free(P);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(k0);
+    (void)hipFree(k1);
+    if (rc) break;
+    ms_of[r] = ms;
+    // keys grow with the radix: a larger one has to win clearly
+    if (ms < best_ms * (r > best ? 0.98 : 1.0)) {
+      best_ms = ms;
+      best = r;
+    }
+  }
+  (void)hipFree(xh);
+  (void)hipFree(y);
+  (void)hipFree(z);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamDestroy(s);
+  if (rc) {
+    (void)fss_spec_set_lookup_radix(spec, r0);
+    return rc;
+  }
+  *best_bits = best;
+  if (cache_path) {
+    std::ofstream o(cache_path, std::ios::app);
+    o << k << " " << best << " " << ms_of[2] << " " << ms_of[3] << " " << ms_of[4] << "\n";
+  }
+  return fss_spec_set_lookup_radix(spec, best);
 }
 
 // Extra introspection used by the benchmark: algorithmic AES blocks of one

@@ -95,7 +95,8 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 7;
+constexpr uint32_t kVersion = 8;
+constexpr uint32_t kGateOperator = 0, kGateRescale = 1;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -112,6 +113,8 @@ struct KeyHeader {
   uint32_t top_blocks;                     // aligned blocks of lookup points walked through the shared levels (2..4)
   uint32_t lookup_c;                       // view shift of call 2: v = (xhat + lookup_c) mod 2^n
   uint32_t is_int;                         // 1: integer spec over canonical representatives
+  uint32_t kind;                           // kGateOperator or kGateRescale
+  uint32_t shift;                          // rescaling gate: bits shifted out (its DCF's domain, = n)
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];
@@ -120,6 +123,7 @@ struct KeyHeader {
   uint64_t atom_c[kMaxAtoms];              // view shift
   uint64_t atom_off[kMaxAtoms];            // byte offset of the atom section in a tile
   uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;  // rec_bytes = 16 + 8 p
+  uint64_t off_tk0, off_tk1;               // rescaling gate: shares of its two constants
   uint64_t aprime[kMaxM + 1];              // offset-binary boundaries
   // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
   // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
@@ -153,6 +157,23 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p, in
   L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
   L.off_crho = o;  o += (uint64_t)p * kTile * 8;
   L.off_crout = o; o += kTile * 8;
+  L.tile_bytes = (o + 255) & ~(uint64_t)255;
+  return L;
+}
+
+// A rescaling gate's tile: its DCF (p = 1) over `shift` bits with 2^r children
+// per level -- root[64] | rec[L][2^r][64] (24 B: seed correction, value
+// correction) -- then the shares of k0 = r_out - (r_in >> s) and
+// k1 = 2^(64-s) MSB(r_in), 8 B per lane each.
+FSS_HD inline Layout make_rescale_layout(int shift, int r) {
+  Layout L{};
+  uint64_t o = 0;
+  L.off_croot = o; o += kTile * 16;
+  const uint64_t levels = (uint64_t)(shift + r - 1) / r;
+  L.rec_bytes = 24;
+  L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
+  L.off_crho = o;  o += kTile * 8;   // k0 shares
+  L.off_crout = o; o += kTile * 8;   // k1 shares
   L.tile_bytes = (o + 255) & ~(uint64_t)255;
   return L;
 }

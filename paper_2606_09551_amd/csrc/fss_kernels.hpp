@@ -56,6 +56,11 @@ struct VariantOps {
                           int* status, int cus, hipStream_t st);
   static hipError_t fused(const DevItem* items, const uint32_t* units, uint32_t n_units, uint32_t* counter,
                           int* status, int grid, hipStream_t st);
+  // the rescaling gate (ARS of a masked value)
+  static hipError_t rescale_keygen(const KeyHeader* h, int r, const KgArgs& ga, const uint64_t* r_in, uint8_t* k0,
+                                   uint8_t* k1, uint64_t* r_out, int cus, hipStream_t st);
+  static hipError_t rescale_eval(int party, const uint8_t* keys, const uint64_t* yhat, int64_t n, uint64_t* z,
+                                 int* status, int cus, hipStream_t st);
 };
 extern template struct VariantOps<0>;
 extern template struct VariantOps<1>;
@@ -79,6 +84,12 @@ hipError_t launch_eval_coeff(int variant, int party, const uint8_t* keys, const 
 hipError_t launch_fused(int variant, const DevItem* items, const uint32_t* units, uint32_t n_units,
                         uint32_t* counter, int* status, int grid, const uint32_t* split_items,
                         uint32_t n_split, uint64_t max_split_elems, hipStream_t st);
+hipError_t launch_rescale_keygen(int variant, int r, const KeyHeader* dev_hdr, const KgArgs& ga, const uint64_t* r_in,
+                                 uint8_t* key0, uint8_t* key1, uint64_t* r_out, int cus, hipStream_t st);
+hipError_t launch_rescale_eval(int variant, int party, const uint8_t* keys, const uint64_t* yhat, int64_t n,
+                               uint64_t* z, int* status, int cus, hipStream_t st);
+// yhat = y0 + y1 (the opening of two additive shares, both on this device).
+hipError_t launch_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat, hipStream_t st);
 int variant_block(int variant);
 int variant_lds_bytes(int variant);
 

@@ -356,7 +356,7 @@ __device__ __forceinline__ void prg_shared(const TB& tb, const uint32_t (&s)[4],
 // Header validation (uniform across the launch)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
-  if (h->magic != kMagic || h->version != kVersion) return kStatusShape;
+  if (h->magic != kMagic || h->version != kVersion || h->kind != kGateOperator) return kStatusShape;
   if (h->rec_bytes != 16 + 8 * (uint64_t)h->p) return kStatusShape;
   if (h->lookup_r < 2 || h->lookup_r > 4) return kStatusShape;
   if ((int)h->party != party) return kStatusParty;
@@ -1159,6 +1159,90 @@ __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHead
 }
 
 // ---------------------------------------------------------------------------
+// Rescaling gate: shares of floor(y / 2^s) + r_out from the opening
+// yhat = y + r_in (|y| < 2^62).  With uhat = yhat + 2^62 the borrow of the low
+// s bits, 1[uhat mod 2^s < r_in mod 2^s], comes from one DCF with payload -1
+// (additive shares of -borrow); the overflow of the top bit is
+// MSB(r_in) (1 - MSB(uhat)), a public factor times a dealer-shared constant.
+// ---------------------------------------------------------------------------
+template <int V, int R>
+__global__ __launch_bounds__(TabOf<V>::kBlock) void k_rescale_keygen(const KeyHeader* hdr, KgArgs ga,
+                                                                      const uint64_t* r_in, uint8_t* key0,
+                                                                      uint8_t* key1, uint64_t* r_out) {
+  using TB = typename TabOf<V>::T;
+  __shared__ __align__(16) uint32_t lds[TB::kWords];
+  TB::fill(lds, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (tile >= ga.n_tiles) return;
+  TB tb(lds, lane);
+  const GHdr h = ghdr(hdr);
+  const int s = (int)h->shift;
+  const uint64_t e = tile * kTile + lane;
+  const bool valid = e < (uint64_t)ga.n_elems;
+  const uint64_t tbb = h->tile_bytes, off_k0 = h->off_tk0, off_k1 = h->off_tk1;
+  uint8_t* t0 = key0 + kHeaderBytes + tile * tbb;
+  uint8_t* t1 = key1 ? key1 + kHeaderBytes + tile * tbb : nullptr;
+  const uint64_t rin = valid ? ldg64(r_in + e) : 0;
+  uint32_t r[4];
+  rand_blk(tb, ga.rk, e, 0, 0, r);
+  const uint64_t rout = mk64(r[0], r[1]);
+  if (valid && r_out) stg64(r_out + e, rout);
+  const uint64_t v0 = rout - (rin >> s);
+  const uint64_t v1 = (rin >> 63) ? (1ull << (64 - s)) : 0ull;
+  rand_blk(tb, ga.rk, e, 1, 0, r);
+  const uint64_t sh0 = mk64(r[0], r[1]), sh1 = mk64(r[2], r[3]);
+  st8(t0 + off_k0 + lane * 8, sh0);
+  st8(t0 + off_k1 + lane * 8, sh1);
+  if (t1) {
+    st8(t1 + off_k0 + lane * 8, v0 - sh0);
+    st8(t1 + off_k1 + lane * 8, v1 - sh1);
+  }
+  uint32_t c0[4], c1[4];
+  rand_blk(tb, ga.rk, e, 64, 0, c0);
+  rand_blk(tb, ga.rk, e, 65, 0, c1);
+  const uint64_t beta[1] = {~0ull};  // -1
+  gen_vec<1, R>(tb, h, s, rin & ((1ull << s) - 1), beta, c0, c1, ga.rk, e, t0, t1, lane);
+}
+
+template <int V>
+__global__ __launch_bounds__(TabOf<V>::kBlock) void k_rescale_eval(const uint8_t* keys, const uint64_t* yhat,
+                                                                    int64_t n, uint64_t* z, int party,
+                                                                    int* status) {
+  using TB = typename TabOf<V>::T;
+  __shared__ __align__(16) uint32_t lds[TB::kWords];
+  TB::fill(lds, threadIdx.x, blockDim.x);
+  __syncthreads();
+  const GHdr h = ghdr(keys);
+  if (h->magic != kMagic || h->version != kVersion || h->kind != kGateRescale || h->rec_bytes != 24 ||
+      h->lookup_r < 2 || h->lookup_r > 4 || h->shift < 1 || h->shift > 32 || n < 0 || (uint64_t)n > h->n_elems ||
+      (int)h->party != party) {
+    if (threadIdx.x == 0) set_status(status, (int)h->party != party ? kStatusParty : kStatusShape);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const uint64_t tile = (uint64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (tile * kTile >= (uint64_t)n) return;
+  const uint64_t e = tile * kTile + lane;
+  const bool valid = e < (uint64_t)n;
+  TB tb(lds, lane);
+  const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
+  const int s = (int)h->shift;
+  const uint64_t uhat = (valid ? ldg64(yhat + e) : 0) + (1ull << 62);
+  const uint32_t x = (uint32_t)(uhat & ((1ull << s) - 1));
+  VState<1> st = vroot<1>(h, tp, lane, party);
+  switch (h->lookup_r) {
+    case 2: vec_walk<1, 2>(tb, h, tp, lane, party, x, 0, (s + 1) / 2, st); break;
+    case 3: vec_walk<1, 3>(tb, h, tp, lane, party, x, 0, (s + 2) / 3, st); break;
+    default: vec_walk<1, 4>(tb, h, tp, lane, party, x, 0, (s + 3) / 4, st); break;
+  }
+  uint64_t out = ld8(tp + h->off_tk0 + lane * 8) + (1ull - (uhat >> 63)) * ld8(tp + h->off_tk1 + lane * 8) + st.V[0];
+  if (party == 0) out += (uhat >> s) - (1ull << (62 - s));
+  if (valid) stg64(z + e, out);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers of one table layout (explicitly instantiated per translation unit)
 // ---------------------------------------------------------------------------
 template <int V>
@@ -1239,6 +1323,34 @@ hipError_t VariantOps<V>::coeff(int party, const uint8_t* keys, const uint64_t* 
   const uint64_t per = waves_per_block(tiles, cus, TabOf<V>::kBlock);
   const unsigned grid = (unsigned)((tiles + per - 1) / per);
   hipLaunchKernelGGL((k_eval_coeff<V>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, keys, xhat, n, y, party,
+                     status);
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t VariantOps<V>::rescale_keygen(const KeyHeader* h, int r, const KgArgs& ga, const uint64_t* r_in,
+                                         uint8_t* k0, uint8_t* k1, uint64_t* ro, int cus, hipStream_t st) {
+  if (ga.n_tiles == 0) return hipSuccess;
+  const uint64_t per = waves_per_block(ga.n_tiles, cus, TabOf<V>::kBlock);
+  const unsigned grid = (unsigned)((ga.n_tiles + per - 1) / per);
+  const dim3 g(grid), b((unsigned)(per * 64));
+  switch (r) {
+    case 2: hipLaunchKernelGGL((k_rescale_keygen<V, 2>), g, b, 0, st, h, ga, r_in, k0, k1, ro); break;
+    case 3: hipLaunchKernelGGL((k_rescale_keygen<V, 3>), g, b, 0, st, h, ga, r_in, k0, k1, ro); break;
+    case 4: hipLaunchKernelGGL((k_rescale_keygen<V, 4>), g, b, 0, st, h, ga, r_in, k0, k1, ro); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t VariantOps<V>::rescale_eval(int party, const uint8_t* keys, const uint64_t* yhat, int64_t n, uint64_t* z,
+                                       int* status, int cus, hipStream_t st) {
+  const uint64_t tiles = ((uint64_t)n + 63) / 64;
+  if (tiles == 0) return hipSuccess;
+  const uint64_t per = waves_per_block(tiles, cus, TabOf<V>::kBlock);
+  const unsigned grid = (unsigned)((tiles + per - 1) / per);
+  hipLaunchKernelGGL((k_rescale_eval<V>), dim3(grid), dim3((unsigned)(per * 64)), 0, st, keys, yhat, n, z, party,
                      status);
   return hipGetLastError();
 }

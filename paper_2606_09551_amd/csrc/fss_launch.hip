@@ -31,6 +31,12 @@ __global__ void k_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64
   if (i < n) xhat[i] = (uint64_t)x[i] + r_in[i];
 }
 
+// The opening of two additive shares held on one device: yhat = y0 + y1.
+__global__ void k_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) yhat[i] = y0[i] + y1[i];
+}
+
 // Work counters are cleared by a kernel rather than a memset node so a
 // captured graph replays correctly.
 __global__ void k_reset_counter(uint32_t* counter) {
@@ -48,6 +54,37 @@ hipError_t launch_mask(const int64_t* x, const uint64_t* r_in, int64_t n, uint64
   const unsigned grid = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(k_mask, dim3(grid), dim3(256), 0, st, x, r_in, n, xhat);
   return hipGetLastError();
+}
+
+hipError_t launch_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_open, dim3(grid), dim3(256), 0, st, y0, y1, n, yhat);
+  return hipGetLastError();
+}
+
+hipError_t launch_rescale_keygen(int v, int r, const KeyHeader* h, const KgArgs& ga, const uint64_t* r_in,
+                                 uint8_t* k0, uint8_t* k1, uint64_t* ro, int cus, hipStream_t st) {
+  switch (v) {
+    case 0: return VariantOps<0>::rescale_keygen(h, r, ga, r_in, k0, k1, ro, cus, st);
+    case 1: return VariantOps<1>::rescale_keygen(h, r, ga, r_in, k0, k1, ro, cus, st);
+    case 2: return VariantOps<2>::rescale_keygen(h, r, ga, r_in, k0, k1, ro, cus, st);
+    case 3: return VariantOps<3>::rescale_keygen(h, r, ga, r_in, k0, k1, ro, cus, st);
+    case 4: return VariantOps<4>::rescale_keygen(h, r, ga, r_in, k0, k1, ro, cus, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rescale_eval(int v, int party, const uint8_t* keys, const uint64_t* yhat, int64_t n, uint64_t* z,
+                               int* status, int cus, hipStream_t st) {
+  switch (v) {
+    case 0: return VariantOps<0>::rescale_eval(party, keys, yhat, n, z, status, cus, st);
+    case 1: return VariantOps<1>::rescale_eval(party, keys, yhat, n, z, status, cus, st);
+    case 2: return VariantOps<2>::rescale_eval(party, keys, yhat, n, z, status, cus, st);
+    case 3: return VariantOps<3>::rescale_eval(party, keys, yhat, n, z, status, cus, st);
+    case 4: return VariantOps<4>::rescale_eval(party, keys, yhat, n, z, status, cus, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_keygen(int v, int p, int r, const KeyHeader* h, const KgArgs& ga, uint8_t* k0, uint8_t* k1,

@@ -93,6 +93,10 @@ def _load():
         "fss_keygen": [vp, i32, i32, C.POINTER(C.c_uint8), i64, vp, vp, vp, vp, vp],
         "fss_mask_input": [vp, vp, i64, vp, vp],
         "fss_keygen_work": [vp, i32, i32, i64, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "fss_rescale_key_bytes": [i32, i32, i64, C.POINTER(C.c_size_t)],
+        "fss_rescale_keygen": [i32, i32, C.POINTER(C.c_uint8), i64, vp, vp, vp, vp, vp],
+        "fss_rescale_eval": [i32, vp, vp, i64, vp, vp],
+        "fss_open": [vp, vp, i64, vp, vp],
         "fss_eval": [i32, vp, vp, i64, vp, vp, vp],
         "fss_eval_pred": [i32, vp, vp, i64, vp, vp],
         "fss_eval_coeff": [i32, vp, vp, i64, vp, vp],
@@ -110,6 +114,7 @@ def _load():
         "fss_graph_free": [vp],
         "fss_autotune": [C.POINTER(WorkItem), i32, C.c_char_p, C.POINTER(Tune)],
         "fss_aes_variants": [],
+        "fss_autotune_radix": [vp, i32, i32, i64, C.c_char_p, C.POINTER(i32)],
         "fss_status": [vp, C.POINTER(i32)],
         "fss_last_error": [],
         "fss_version": [],
@@ -230,6 +235,14 @@ class Spec:
                 "lookup_r": info.lookup_r, "top_depth": info.top_depth, "top_blocks": info.top_blocks,
                 "aprime": list(ap), "coef": [[co[i * p + l] for l in range(p)] for i in range(m)]}
 
+    def autotune_radix(self, n_bits: int, frac_bits: int, n_elems: int, cache_path: str | None = None) -> int:
+        """Time keygen + fused evaluation at lookup radix 2, 3 and 4 and keep the fastest
+        (fss_autotune_radix); returns the chosen input bits per level."""
+        best = C.c_int32()
+        _check(lib.fss_autotune_radix(self.handle, n_bits, frac_bits, n_elems,
+                                      cache_path.encode() if cache_path else None, C.byref(best)))
+        return best.value
+
     def keygen_work(self, n_bits: int, frac_bits: int, n_elems: int) -> tuple:
         """(AES blocks, T-table lookups) of one fss_keygen over n_elems elements."""
         a, l = C.c_double(), C.c_double()
@@ -252,6 +265,25 @@ def seed_bytes(seed: int):
 def fss_keygen(spec: Spec, n_bits, frac_bits, seed, n_elems, key0, key1, r_in, r_out, stream=None):
     _check(lib.fss_keygen(spec.handle, n_bits, frac_bits, seed_bytes(seed), n_elems, _p(key0),
                           _p(key1), _p(r_in), _p(r_out), _stream(stream)))
+
+
+def fss_rescale_key_bytes(shift_bits: int, lookup_bits: int, n_elems: int) -> int:
+    out = C.c_size_t()
+    _check(lib.fss_rescale_key_bytes(shift_bits, lookup_bits, n_elems, C.byref(out)))
+    return out.value
+
+
+def fss_rescale_keygen(shift_bits, lookup_bits, seed, n_elems, r_in, key0, key1, r_out, stream=None):
+    _check(lib.fss_rescale_keygen(shift_bits, lookup_bits, seed_bytes(seed), n_elems, _p(r_in), _p(key0),
+                                  _p(key1), _p(r_out), _stream(stream)))
+
+
+def fss_rescale_eval(party, keys, yhat, n, z, stream=None):
+    _check(lib.fss_rescale_eval(party, _p(keys), _p(yhat), n, _p(z), _stream(stream)))
+
+
+def fss_open(y0, y1, n, yhat, stream=None):
+    _check(lib.fss_open(_p(y0), _p(y1), n, _p(yhat), _stream(stream)))
 
 
 def fss_mask_input(x, r_in, n, xhat, stream=None):

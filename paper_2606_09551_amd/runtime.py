@@ -69,6 +69,36 @@ class OpInstanceGPU:
         return out
 
 
+class RescaleGPU:
+    """A rescaling gate (ARS by `shift` bits) over n elements whose input mask
+    is a previous gate's output mask: keys for both parties, the opening
+    yhat = y0 + y1 of that gate's shares, and both parties' output shares."""
+
+    def __init__(self, shift: int, n: int, lookup_bits: int = 3, device: str = "cuda"):
+        self.shift, self.n, self.lookup_bits = shift, n, lookup_bits
+        self.key_bytes = F.fss_rescale_key_bytes(shift, lookup_bits, n)
+        dev = torch.device(device)
+        self.keys = {b: torch.empty(self.key_bytes, dtype=torch.uint8, device=dev) for b in (0, 1)}
+        mk = lambda: torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        self.yhat, self.r_out = mk(), mk()
+        self.z = {b: mk() for b in (0, 1)}
+
+    def keygen(self, seed: int, r_in, stream=None):
+        F.fss_rescale_keygen(self.shift, self.lookup_bits, seed, self.n, r_in, self.keys[0], self.keys[1],
+                             self.r_out, stream)
+
+    def open(self, y0, y1, stream=None):
+        F.fss_open(y0, y1, self.n, self.yhat, stream)
+
+    def eval(self, party: int, stream=None):
+        F.fss_rescale_eval(party, self.keys[party], self.yhat, self.n, self.z[party], stream)
+
+    def host(self) -> dict:
+        n = self.n
+        return {"yhat": to_u64(self.yhat)[:n], "r_out": to_u64(self.r_out)[:n],
+                "z0": to_u64(self.z[0])[:n], "z1": to_u64(self.z[1])[:n]}
+
+
 def unpack_bits(planes: np.ndarray, n: int) -> np.ndarray:
     """(ell, words) u64 bit-planes -> per-element u64 with bit j = predicate j."""
     ell = planes.shape[0]

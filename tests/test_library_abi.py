@@ -242,3 +242,21 @@ def test_argument_errors():
     with pytest.raises(F.FssError) as e:
         s.key_bytes(16, 8, -1)
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_rescale_key_bytes(r):
+    """Rescaling gate: root, ceil(s / r) levels x 2^r children of 24-byte records
+    (seed and value correction), then the two 8-byte constant shares; 64-lane tiles."""
+    for s in (1, 8, 24, 32):
+        per_tile = F.fss_rescale_key_bytes(s, r, 64) - F.fss_rescale_key_bytes(s, r, 0)
+        expect = 64 * 16 + (-(-s // r)) * 2**r * 64 * 24 + 2 * 64 * 8
+        assert per_tile == (expect + 255) // 256 * 256
+        assert F.fss_rescale_key_bytes(s, r, 1000) == 16384 + 16 * per_tile
+    for bad_s, code in ((0, -2), (33, -2)):
+        with pytest.raises(F.FssError) as e:
+            F.fss_rescale_key_bytes(bad_s, r, 10)
+        assert e.value.code == code
+    with pytest.raises(F.FssError) as e:
+        F.fss_rescale_key_bytes(8, 5, 10)
+    assert e.value.code == -8
