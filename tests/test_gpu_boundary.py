@@ -196,3 +196,22 @@ def test_eval_batch_checks_party():
     assert e.value.code == -5
     F.fss_eval_batch(F.PARTY_ANY, [])
     assert F.fss_status() == 0
+
+
+def test_radix_autotune_sets_and_caches(tmp_path):
+    """The key-layout knob: the autotuner times keygen + fused evaluation at
+    every lookup radix, sets the fastest on the spec and caches it; keys then
+    generated at that radix equal the oracle's."""
+    desc = W.gelu_spec(f=7)
+    n, f = 12, 7
+    spec = F.Spec(desc)
+    cache = str(tmp_path / "radix.txt")
+    r = spec.autotune_radix(n, f, 20000, cache)
+    assert r in (2, 3, 4) and spec.lookup_r == r
+    other = F.Spec(desc)
+    assert other.autotune_radix(n, f, 20000, cache) == r  # from the cache
+    g = np.random.Generator(np.random.PCG64(8))
+    x = g.integers(-(1 << (n - 1)), 1 << (n - 1), size=500).astype(np.int64)
+    S = O.compile_spec(desc, n, f, lookup_r=r)
+    o = _oracle(S, x, 0x77)
+    _check(_run(spec, n, f, x, 0x77, "plan"), o, len(x), ("radix", r))

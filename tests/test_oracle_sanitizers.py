@@ -1,0 +1,30 @@
+"""The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (gcc,
+CPU only) and driven at its size limits (n = 32 at radix 2, m = 64 intervals of
+degree 3, eight predicates, Protocol 3 at m = 64, integer specs, the rescaling
+gate at s = 32): no out-of-bounds access, no undefined behaviour, every
+reconstruction holds."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+
+
+def test_oracle_under_asan_and_ubsan(tmp_path):
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    exe = str(tmp_path / "orc_san")
+    r = subprocess.run(["gcc", "-O1", "-g", "-std=c11", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        "-fno-omit-frame-pointer", "-pthread", "-o", exe, os.path.join(HERE, "host", "oracle_sanitize.c"),
+                        os.path.join(ROOT, "oracle", "fss_oracle.c"), "-lm"],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0 and "sanitize" in r.stdout and ("cannot find" in r.stdout or "unrecognized" in r.stdout):
+        pytest.skip("sanitizer runtime not available: " + r.stdout[-200:])
+    assert r.returncode == 0, r.stdout[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("LD_PRELOAD", None)
+    run = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=600)
+    assert run.returncode == 0 and run.stdout.strip().endswith("ok"), run.stdout[-3000:]
