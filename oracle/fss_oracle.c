@@ -446,19 +446,23 @@ int orc_dcfz_eval(int b, const orc_dcfz_key* k, uint64_t x) {
 /* level, the per-child form of the corrections above.                       */
 /* ========================================================================= */
 
-/* Child c (0..2^r-1) of seed s: next seed, control bit t, and group value v. */
+/* Child c (0..2^r-1) of seed s: next seed and control bit from H(s, c); its
+ * value (Z_2: bit 1 of that block; Z_{2^64}^p: words c p .. c p + p - 1 of the
+ * stream H(s, 2^r),
+ * H(s, 2^r + 1), ..., two words per block, lo first), so the 2^r children
+ * of one seed use ceil(2^r p / 2) value blocks between them. */
 static void expand_r(int r, int p, orc_blk s, int c, orc_blk* s_out, int* t_out, uint64_t* v_out) {
   orc_blk n = orc_prg(s, c);
   *t_out = (int)(n.lo & 1);
   *s_out = clear2(n);
-  if (p == 0) {
+  if (p == 0) {  /* Z_2 payload: bit 1 of the seed block */
     v_out[0] = (n.lo >> 1) & 1;
-  } else {
-    uint64_t w[4];
-    orc_blk a = orc_prg(s, (1 << r) + 2 * c);
-    w[0] = a.lo; w[1] = a.hi;
-    if (p > 2) { orc_blk b = orc_prg(s, (1 << r) + 2 * c + 1); w[2] = b.lo; w[3] = b.hi; }
-    for (int k = 0; k < p; k++) v_out[k] = w[k];
+    return;
+  }
+  for (int k = 0; k < p; k++) {
+    const int w = c * p + k;
+    const orc_blk b = orc_prg(s, (1 << r) + (w >> 1));
+    v_out[k] = (w & 1) ? b.hi : b.lo;
   }
 }
 

@@ -100,8 +100,8 @@ int orc_dcfz_eval(int b, const orc_dcfz_key* k, uint64_t x);
  * conversion and no final correction; the last level's seed and control-bit
  * corrections are never used and are zero.  The input is walked as
  * r * ceil(n / r) bits with leading zeros.  Child c of seed s is H(s, c)
- * (seed and control bit) and its value the first p words of
- * H(s, 2^r + 2c + k). */
+ * (seed and control bit); its value is words c p .. c p + p - 1 of the
+ * stream H(s, 2^r), H(s, 2^r + 1), ... (two 64-bit words per block). */
 #define ORC_MAXLR ((ORC_MAXN + 1) / 2) /* levels at r = 2 */
 #define ORC_MAXC 16                    /* children at r = 4 */
 typedef struct {

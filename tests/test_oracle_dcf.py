@@ -127,7 +127,7 @@ def test_dcfr_corrections(r):
     randomness at every level but the last, every other child corrects the
     parties' children to equal seeds and values (checked on the first level,
     where both parties expand their roots: child c is H(root, c), its value
-    H(root, 2^r + 2c)).  At the last level alpha's child's value is corrected
+    H(root, 2^r + j), child c taking words c p .. c p + p - 1).  At the last level alpha's child's value is corrected
     like the others (the brute-force tests check that this zeroes x = alpha)
     and all seed and control-bit corrections are zero (never used)."""
     rnd = random.Random(21 + r)
@@ -159,8 +159,10 @@ def test_dcfr_corrections(r):
         c0, c1 = O.prg(k0.root.lo, k0.root.hi, c), O.prg(k1.root.lo, k1.root.hi, c)
         assert k0.scw[0][c].lo == (c0[0] ^ c1[0]) & ~3 and k0.scw[0][c].hi == c0[1] ^ c1[1]
         assert k0.tcw[0][c] == (c0[0] ^ c1[0]) & 1
-        v0 = O.prg(k0.root.lo, k0.root.hi, C + 2 * c) + O.prg(k0.root.lo, k0.root.hi, C + 2 * c + 1)
-        v1 = O.prg(k1.root.lo, k1.root.hi, C + 2 * c) + O.prg(k1.root.lo, k1.root.hi, C + 2 * c + 1)
+        # child c's values: words c p .. c p + p - 1 of H(s, C), H(s, C + 1), ...
+        stream0 = [w for j in range(((c + 1) * p + 1) // 2) for w in O.prg(k0.root.lo, k0.root.hi, C + j)]
+        stream1 = [w for j in range(((c + 1) * p + 1) // 2) for w in O.prg(k1.root.lo, k1.root.hi, C + j)]
+        v0, v1 = stream0[c * p:(c + 1) * p], stream1[c * p:(c + 1) * p]
         for q in range(p):
             w = (v1[q] - v0[q] + (beta[q] if c < a0 else 0)) & M64
             assert k0.vcw[0][c][q] == (-w) & M64, (r, c, q)   # (-1)^{t_1}, t_1 = 1 at the root
