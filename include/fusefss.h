@@ -48,6 +48,7 @@ extern "C" {
 #define FSS_E_HIP (-6)          /* a HIP runtime call failed (message has the hipError_t) */
 #define FSS_E_OOM (-7)          /* host allocation failed */
 #define FSS_E_ARG (-8)          /* NULL pointer, negative size, bad tuning value */
+#define FSS_E_CONSUMED (-9)     /* (device status) a key evaluated again at another masked input */
 
 #define FSS_MAX_INTERVALS 64
 #define FSS_MAX_PREDS 16
@@ -224,6 +225,19 @@ int fss_rescale_eval(int32_t party, const void* keys, const uint64_t* yhat, int6
 int fss_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat, void* stream);
 
 /* ---- online evaluation (Sec. 5.3 "Online Evaluation", steps 2-3) ------- */
+
+/* One-time keys (Sec. "Threat Model and Preprocessing": all preprocessing
+ * material is one-time; two openings under one mask would reveal x - x').
+ * Every evaluator below records, in the key buffer itself, the masked input
+ * each element is first evaluated at (8 bytes per element, set by one atomic
+ * compare-and-swap against a random per-tile sentinel that keygen writes).
+ * Evaluating an element again at the same masked input is a replay and
+ * allowed (it reveals nothing new: graphs, retries, the two calls of the
+ * plain path); at a different one the element is refused: its output shares
+ * are zero and fss_status reports FSS_E_CONSUMED.  Key buffers are therefore
+ * written by evaluation; launches that overlap on one key buffer are checked
+ * against each other too.  This guards against accidental reuse by the
+ * caller, not against a party that copies its key bytes. */
 
 /* Plain evaluator: call 1 then call 2 as two kernel launches.
  *   keys: device key buffer of `party` (self-describing header).

@@ -342,6 +342,8 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
   h.rec_bytes = q->layout.rec_bytes;
   h.off_crho = q->layout.off_crho;
   h.off_crout = q->layout.off_crout;
+  h.off_seen = q->layout.off_seen;
+  h.off_sentinel = q->layout.off_sentinel;
   for (int i = 0; i <= m; ++i) h.aprime[i] = q->aprime[i];
   // A_i maps a share of 1[x in I_i] rho to the xhat-coefficients of piece i:
   // A_i[j][k] = a_{i,j+k} C(j+k, j).  tab_0 = A_{m-1}, tab_i = A_{i-1} - A_i.
@@ -614,10 +616,24 @@ int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int
   double atoms_lv = 0;
   for (uint32_t t = 0; t < h.T; ++t) atoms_lv += h.atom_k[t] - atom_leaf_bits((int)h.atom_k[t]);
   // Both parties' children: two tweaks per Z_2 level above the leaves and
-  // one leaf conversion per atom, 2^r children of 1 + nb blocks per lookup
-  // level above the last and of nb at the last.
-  const double prg_aes = atoms_lv * 2 * 2 + 2.0 * h.T + C * 2 * ((L - 1) * (1 + nb) + nb);
-  const double prg_lk = atoms_lv * 2 * shared(2) + 2.0 * 160 * h.T + C * 2 * ((L - 1) * shared(1 + nb) + shared(nb));
+  // one leaf conversion per atom; per lookup level the 2^r children, two at a
+  // time: a pair's seed blocks and the value blocks of the seed's value
+  // stream it uses (odd p: the pair shares one of them), the last level
+  // values only.
+  double pair_aes, pair_lk, last_aes, last_lk;
+  if (h.p == 3) {
+    pair_aes = 5; pair_lk = shared(3) + shared(2);
+    last_aes = 3; last_lk = shared(2) + shared(1);
+  } else if (h.p == 1) {
+    pair_aes = 3; pair_lk = shared(2) + shared(1);
+    last_aes = 1; last_lk = shared(1);
+  } else {
+    pair_aes = 2 * (1 + nb); pair_lk = 2 * shared(1 + nb);
+    last_aes = 2 * nb; last_lk = 2 * shared(nb);
+  }
+  const double pairs = C / 2;
+  const double prg_aes = atoms_lv * 2 * 2 + 2.0 * h.T + 2 * pairs * ((L - 1) * pair_aes + last_aes);
+  const double prg_lk = atoms_lv * 2 * shared(2) + 2.0 * 160 * h.T + 2 * pairs * ((L - 1) * pair_lk + last_lk);
   // Counter-mode randomness: masks (drawn by both halves of the work), the
   // r_out share, two roots per atom, carries, two lookup roots, two rho-share
   // blocks and 1 + nb on-path corrections per lookup level above the last.
@@ -662,6 +678,8 @@ int rescale_template(int shift, int r, RescaleTemplate** out) {
     h.rec_bytes = L.rec_bytes;
     h.off_tk0 = L.off_crho;
     h.off_tk1 = L.off_crout;
+    h.off_seen = L.off_seen;
+    h.off_sentinel = L.off_sentinel;
   }
   *out = slot.get();
   return FSS_OK;

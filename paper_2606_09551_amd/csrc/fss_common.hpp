@@ -86,6 +86,8 @@ constexpr AesConst kAes = make_aes_const();
 //   wshare[64] (u64: bit j = this party's share of the carry of output j)
 //   coeff  : root[64] | rec[L][2^r][64]
 //            | rho[p][64] (share of rho) | rout[64] (share of r_out)
+//   seen[64] (u64: the x-hat an element was first evaluated at) | used (u64:
+//   bit lane set once that element has been evaluated; zeroed by keygen)
 //   The lookup's vector DCF takes r input bits per level (2^r children), so
 //   it has L = ceil(n / r) levels with corrections for each child.  A record
 //   rec[i][c][lane] (16 + 8p bytes) holds child c's seed correction (bit 0 =
@@ -95,7 +97,7 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 8;
+constexpr uint32_t kVersion = 9;
 constexpr uint32_t kGateOperator = 0, kGateRescale = 1;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
@@ -124,6 +126,8 @@ struct KeyHeader {
   uint64_t atom_off[kMaxAtoms];            // byte offset of the atom section in a tile
   uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;  // rec_bytes = 16 + 8 p
   uint64_t off_tk0, off_tk1;               // rescaling gate: shares of its two constants
+  uint64_t off_seen, off_sentinel;         // one-time use: x-hat each element was first evaluated at
+                                           // (the tile's sentinel until then), the sentinel
   uint64_t aprime[kMaxM + 1];              // offset-binary boundaries
   // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
   // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
@@ -139,6 +143,7 @@ FSS_HD constexpr int atom_leaf_bits(int k) { return k < kLeafBits ? k : kLeafBit
 struct Layout {
   uint64_t atom_off[kMaxAtoms];
   uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;
+  uint64_t off_seen, off_sentinel;
   uint64_t tile_bytes;
 };
 
@@ -157,6 +162,8 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p, in
   L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
   L.off_crho = o;  o += (uint64_t)p * kTile * 8;
   L.off_crout = o; o += kTile * 8;
+  L.off_seen = o;  o += kTile * 8;
+  L.off_sentinel = o;  o += 8;
   L.tile_bytes = (o + 255) & ~(uint64_t)255;
   return L;
 }
@@ -164,7 +171,7 @@ FSS_HD inline Layout make_layout(int T, const uint32_t* atom_k, int n, int p, in
 // A rescaling gate's tile: its DCF (p = 1) over `shift` bits with 2^r children
 // per level -- root[64] | rec[L][2^r][64] (24 B: seed correction, value
 // correction) -- then the shares of k0 = r_out - (r_in >> s) and
-// k1 = 2^(64-s) MSB(r_in), 8 B per lane each.
+// k1 = 2^(64-s) MSB(r_in), 8 B per lane each, and the one-time record.
 FSS_HD inline Layout make_rescale_layout(int shift, int r) {
   Layout L{};
   uint64_t o = 0;
@@ -174,6 +181,8 @@ FSS_HD inline Layout make_rescale_layout(int shift, int r) {
   L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
   L.off_crho = o;  o += kTile * 8;   // k0 shares
   L.off_crout = o; o += kTile * 8;   // k1 shares
+  L.off_seen = o;  o += kTile * 8;
+  L.off_sentinel = o;  o += 8;
   L.tile_bytes = (o + 255) & ~(uint64_t)255;
   return L;
 }
@@ -181,5 +190,9 @@ FSS_HD inline Layout make_rescale_layout(int shift, int r) {
 // Device status codes (mirrors of FSS_E_*).
 constexpr int kStatusShape = -4;
 constexpr int kStatusParty = -5;
+constexpr int kStatusConsumed = -9;
+// PRG purpose of a tile's one-time-record sentinel (the method's own purposes
+// stay below 256).
+constexpr uint32_t kPurposeSentinel = 0xffffu;
 
 }  // namespace fss

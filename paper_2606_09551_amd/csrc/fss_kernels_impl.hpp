@@ -365,6 +365,33 @@ __device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// One-time use of key material (Sec. "Threat Model and Preprocessing": all
+// preprocessing material is one-time).  Each element's slot in the tile's
+// record holds the tile's random sentinel until the element is first
+// evaluated, then the x-hat it was evaluated at; one relaxed compare-and-swap
+// per element records or checks it, so concurrent units of one tile (and
+// overlapping launches) need no fence.  Evaluating again at the recorded
+// x-hat (a replay) passes; at another x-hat the lane is refused: its outputs
+// are zero and the status reports kStatusConsumed.  An x-hat equal to the
+// sentinel (probability 2^-64) is not recorded.  Returns whether the lane may
+// output.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool claim_once(GHdr h, const uint8_t* tile, int lane, uint64_t xh, bool valid,
+                                           int* status) {
+  bool ok = true;
+  if (valid) {
+    const unsigned long long none = ld8(tile + h->off_sentinel);
+    unsigned long long seen = none;  // the slot's value when the exchange fails
+    __hip_atomic_compare_exchange_strong(
+        (FSS_GLOBAL unsigned long long*)(const_cast<uint8_t*>(tile) + h->off_seen) + lane, &seen,
+        (unsigned long long)xh, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok = seen == none || seen == xh;
+  }
+  if (__ballot(!ok) && lane == 0) set_status(status, kStatusConsumed);
+  return ok;
+}
+
+// ---------------------------------------------------------------------------
 // Call 1: packed comparison.  Up to three Z_2 DCF atoms walk in lockstep.
 // Each atom's tree has k - nu levels over the high bits of its view (nu =
 // min(7, k)); the leaf seed s is converted into the 128-bit vector H(s, 2)
@@ -446,10 +473,12 @@ __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8
 
 // Combine atom shares into output-bit shares and ballot-pack 64 elements
 // per word: z_j = negate_j (party 0) ^ w_j ^ XOR over atoms of (A_t ^ A_r(t)).
-template <class TB>
+// `claim` is called once, after the bits are computed and before they are
+// stored (the one-time record's check; a refused lane outputs zero bits).
+template <class TB, class Claim>
 __device__ __forceinline__ void pred_tile(const TB& tb, GHdr h, const uint8_t* tile,
                                           int lane, int b, uint64_t xhat, bool valid, uint64_t* z,
-                                          uint64_t tile_idx, uint64_t words) {
+                                          uint64_t tile_idx, uint64_t words, Claim&& claim) {
   const uint32_t A = eval_atoms(tb, h, tile, lane, b, xhat);
   uint64_t bits = ld8(tile + h->off_w + lane * 8);
   if (b == 0) bits ^= h->negate;
@@ -458,9 +487,10 @@ __device__ __forceinline__ void pred_tile(const TB& tb, GHdr h, const uint8_t* t
     const uint32_t bit = ((A >> t) ^ (A >> h->atom_rview[t])) & 1u;
     bits ^= (uint64_t)bit << h->atom_out[t];
   }
+  const bool ok = claim();
   const int ell = (int)h->ell;
   for (int j = 0; j < ell; ++j) {
-    const uint64_t word = __ballot(valid && ((bits >> j) & 1ull));
+    const uint64_t word = __ballot(valid && ok && ((bits >> j) & 1ull));
     if (lane == 0) stg64(z + (uint64_t)j * words + tile_idx, word);
   }
 }
@@ -487,12 +517,32 @@ __device__ __forceinline__ VState<P> vroot(GHdr h, const uint8_t* tile, int lane
   return st;
 }
 
+// The value of child d: words d P .. d P + P - 1 of the stream H(s, 2^R),
+// H(s, 2^R + 1), ... (two words per block), i.e. NB = ceil(P/2) blocks from
+// block (d P) / 2 on; for odd P an odd d starts at the first block's high word.
+template <int P, int R>
+__device__ __forceinline__ uint32_t value_block0(uint32_t d) { return (1u << R) + ((d * (uint32_t)P) >> 1); }
+
+template <int P, int NB, int O>
+__device__ __forceinline__ uint64_t value_word(const uint32_t (&o)[O][4], uint32_t d, int q) {
+  // o[O - NB .. O - 1] are the NB value blocks; word w of them is o[O-NB+w/2][2(w&1)..]
+  const uint64_t even = mk64(o[O - NB + q / 2][2 * (q & 1)], o[O - NB + q / 2][2 * (q & 1) + 1]);
+  if constexpr ((P & 1) == 0) {
+    return even;
+  } else {
+    const int w = q + 1;  // the word index when d P is odd
+    const uint64_t odd = w / 2 < NB ? mk64(o[O - NB + w / 2][2 * (w & 1)], o[O - NB + w / 2][2 * (w & 1) + 1]) : 0ull;
+    return (d & 1u) ? odd : even;
+  }
+}
+
 // Advance `st` through levels [i0, i1) of the lookup DCF along the base-2^R
 // digits of the input x: the DCF has L = ceil(n / R) levels of 2^R children
 // and level i consumes digit L - 1 - i (R L - n leading zero bits).
-// Child d of seed s is H(s, d), its value the first P words of H(s, 2^R + 2d + k).
-// The last level adds the child's value only: nothing is walked below it, so
-// its seed and control bit (the block H(s, d)) are not computed.
+// Child d of seed s is H(s, d); its value comes from the seed's shared value
+// stream (value_word).  The last level adds the child's value only: nothing
+// is walked below it, so its seed and control bit (the block H(s, d)) are not
+// computed.
 template <int P, int R, class TB>
 __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
                                          uint32_t x, int i0, int i1, VState<P>& st) {
@@ -506,8 +556,8 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
     const uint32_t d = (x >> (R * (L - 1 - i))) & (C - 1u);
     uint32_t jj[1 + NB], o[1 + NB][4];
     jj[0] = d;
-    jj[1] = C + 2u * d;
-    if (NB > 1) jj[NB > 1 ? 2 : 0] = C + 1u + 2u * d;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) jj[1 + k] = value_block0<P, R>(d) + (uint32_t)k;
     prg_shared<TB, 1 + NB>(tb, st.s, jj, o);
     const uint8_t* rp = recp + ((uint64_t)i * C + d) * kTile * REC;  // child d's record at level i
     const uint64_t c01 = ld8(rp), c23 = ld8(rp + 8);
@@ -522,7 +572,7 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
     st.s[3] = o[0][3] ^ (cw.w & msk);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      uint64_t v = mk64(o[1 + q / 2][2 * (q & 1)], o[1 + q / 2][2 * (q & 1) + 1]);
+      uint64_t v = value_word<P, NB>(o, d, q);
       v += ld8(rp + 16 + 8 * q) & msk64;
       st.V[q] += b ? (0ull - v) : v;
     }
@@ -531,13 +581,13 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
     const uint32_t d = x & (C - 1u);
     uint32_t jj[NB], o[NB][4];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) jj[k] = C + 2u * d + k;
+    for (int k = 0; k < NB; ++k) jj[k] = value_block0<P, R>(d) + (uint32_t)k;
     prg_shared<TB, NB>(tb, st.s, jj, o);
     const uint8_t* rp = recp + ((uint64_t)(L - 1) * C + d) * kTile * REC;
     const uint64_t msk64 = 0ull - (uint64_t)st.t;
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-      uint64_t v = mk64(o[q / 2][2 * (q & 1)], o[q / 2][2 * (q & 1) + 1]);
+      uint64_t v = value_word<P, NB>(o, d, q);
       v += ld8(rp + 16 + 8 * q) & msk64;
       st.V[q] += b ? (0ull - v) : v;
     }
@@ -709,7 +759,8 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_pred(const uint8_t* k
   const uint64_t xh = valid ? ldg64(xhat + e) : 0;
   TB tb(lds, lane);
   const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
-  pred_tile(tb, h, tp, lane, party, xh, valid, z, tile, words);
+  pred_tile(tb, h, tp, lane, party, xh, valid, z, tile, words,
+            [&] { return claim_once(h, tp, lane, xh, valid, status); });
 }
 
 template <int V>
@@ -734,7 +785,8 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* 
   TB tb(lds, lane);
   const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
   const uint64_t out = coeff_dispatch(tb, h, tp, lane, party, xh);
-  if (valid) stg64(y + e, out);
+  const bool ok = claim_once(h, tp, lane, xh, valid, status);
+  if (valid) stg64(y + e, ok ? out : 0ull);
 }
 
 // ---------------------------------------------------------------------------
@@ -783,17 +835,24 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     const bool valid = e < (uint64_t)it.n_elems;
     const uint64_t xh = valid ? ldg64(it.xhat + e) : 0;
     const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
+    // The one-time check runs after the unit's work and before its first
+    // store: its atomic's latency then holds up no key load.
+    bool ok = true, claimed = false;
     if (flags & kUnitPred)  // also with T = 0: the bits are then the public constants and carry shares
-      pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words);
+      pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words, [&] {
+        claimed = true;
+        return ok = claim_once(h, tp, lane, xh, valid, status);
+      });
     if (!(flags & kUnitBase) && (range & 0xffffu) >= (range >> 16)) continue;  // a call-1 unit
     const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),
                                         (flags & kUnitBase) != 0);
+    if (!claimed) ok = claim_once(h, tp, lane, xh, valid, status);
     if (valid) {
       if (flags & kUnitAccumulate)  // parts of one tile add their shares of y (mod 2^64)
-        __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)out,
+        __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)(ok ? out : 0ull),
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       else
-        stg64(it.y + e, out);
+        stg64(it.y + e, ok ? out : 0ull);
     }
   }
 }
@@ -824,6 +883,26 @@ __device__ __forceinline__ void rand_blks(const TB& tb, const RoundKeys& rk, uin
     o[k][3] = 0u;
   }
   aes_encrypt(RtKey{rk}, tb, o);
+}
+
+// Keygen's side: the record starts with every slot at the tile's sentinel
+// (one PRG block of the tile's first element), the sentinel itself, then
+// zeros over the tile's padding (at most 248 bytes), so that a key buffer is
+// a function of the dealer's seed alone.
+template <class TB>
+__device__ __forceinline__ void init_record(const TB& tb, const RoundKeys& rk, uint64_t tile, uint64_t off_seen,
+                                            uint64_t off_sentinel, uint64_t tile_bytes, uint8_t* t0, uint8_t* t1,
+                                            int lane) {
+  uint32_t r[4];
+  rand_blk(tb, rk, tile * kTile, kPurposeSentinel, 0, r);
+  const uint64_t none = mk64(r[0], r[1]);
+  st8(t0 + off_seen + lane * 8, none);
+  if (t1) st8(t1 + off_seen + lane * 8, none);
+  if ((uint64_t)lane * 8 < tile_bytes - off_sentinel) {
+    const uint64_t v = lane == 0 ? none : 0ull;
+    st8(t0 + off_sentinel + lane * 8, v);
+    if (t1) st8(t1 + off_sentinel + lane * 8, v);
+  }
 }
 
 // Z_2 DCF Gen for f(x) = 1[x < alpha] over k bits, the tree stopping nu =
@@ -947,82 +1026,191 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
     uint64_t dk[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) dk[q] = 0;
-    if (i + 1 == L) {
-      // The last level: value corrections only.  Alpha's child is corrected
-      // like the others (without beta), which zeroes the sum along alpha's
-      // path, so there is no leaf conversion or final correction; nothing is
-      // walked below this level, so its seed and control-bit corrections are
-      // zero and the children's seeds are not computed.
-#pragma unroll 1
-      for (uint32_t c = 0; c < C; ++c) {
-        uint32_t o0[NB][4], o1[NB][4], jj[NB];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) jj[k] = C + 2u * c + k;
-        prg_shared<TB, NB>(tb, s[0], jj, o0);
-        prg_shared<TB, NB>(tb, s[1], jj, o1);
-        const uint64_t ro = off_crec + (((uint64_t)i * C + c) * kTile + lane) * REC;
-        st8(k0 + ro, 0ull);
-        st8(k0 + ro + 8, 0ull);
-        if (k1) {
-          st8(k1 + ro, 0ull);
-          st8(k1 + ro + 8, 0ull);
-        }
-        const uint64_t below = c < a ? ~0ull : 0ull;
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-          const uint64_t v0 = mk64(o0[q / 2][2 * (q & 1)], o0[q / 2][2 * (q & 1) + 1]);
-          const uint64_t v1 = mk64(o1[q / 2][2 * (q & 1)], o1[q / 2][2 * (q & 1) + 1]);
-          const uint64_t w = v1 - v0 - Va[q] + (beta[q] & below);
-          st8(k0 + ro + 16 + 8 * q, (w ^ neg) - neg);
-          if (k1) st8(k1 + ro + 16 + 8 * q, (w ^ neg) - neg);
-        }
-      }
-      break;
-    }
-#pragma unroll 1
-    for (uint32_t c = 0; c < C; ++c) {
-      uint32_t o0[1 + NB][4], o1[1 + NB][4], jj[1 + NB];
-      jj[0] = c;
-#pragma unroll
-      for (int k = 0; k < NB; ++k) jj[1 + k] = C + 2u * c + k;
-      prg_shared<TB, 1 + NB>(tb, s[0], jj, o0);
-      prg_shared<TB, 1 + NB>(tb, s[1], jj, o1);
-      const uint32_t t0c = o0[0][0] & 1u, t1c = o1[0][0] & 1u;
-      if (c == a) {
-        ks[0][0] = o0[0][0] & ~3u;
-        ks[1][0] = o1[0][0] & ~3u;
+    const bool last = i + 1 == L;
+    // The corrections of child c from both parties' expansions: seed blocks
+    // sd0 / sd1 (above the last level) and values v0 / v1.  At the last level
+    // only values: alpha's child is corrected like the others (without beta),
+    // which zeroes the sum along alpha's path, so there is no leaf conversion
+    // or final correction; nothing is walked below it, so its seed and
+    // control-bit corrections are zero and its seed blocks are not computed.
+    auto child = [&](uint32_t c, const uint32_t (&sd0)[4], const uint32_t (&sd1)[4], const uint64_t (&v0)[P],
+                     const uint64_t (&v1)[P]) {
+      const uint64_t ro = off_crec + (((uint64_t)i * C + c) * kTile + lane) * REC;
+      const uint64_t below = c < a ? ~0ull : 0ull;
+      if (!last && c == a) {
+        ks[0][0] = sd0[0] & ~3u;
+        ks[1][0] = sd1[0] & ~3u;
 #pragma unroll
         for (int w = 1; w < 4; ++w) {
-          ks[0][w] = o0[0][w];
-          ks[1][w] = o1[0][w];
+          ks[0][w] = sd0[w];
+          ks[1][w] = sd1[w];
         }
-        kt[0] = t0c;
-        kt[1] = t1c;
+        kt[0] = sd0[0] & 1u;
+        kt[1] = sd1[0] & 1u;
 #pragma unroll
-        for (int q = 0; q < P; ++q)
-          dk[q] = mk64(o0[1 + q / 2][2 * (q & 1)], o0[1 + q / 2][2 * (q & 1) + 1]) -
-                  mk64(o1[1 + q / 2][2 * (q & 1)], o1[1 + q / 2][2 * (q & 1) + 1]);
+        for (int q = 0; q < P; ++q) dk[q] = v0[q] - v1[q];
+        return;
+      }
+      uint64_t c01 = 0, c23 = 0;
+      if (!last) {
+        const uint32_t t0c = sd0[0] & 1u, t1c = sd1[0] & 1u;
+        c01 = mk64(((sd0[0] ^ sd1[0]) & ~3u) | (t0c ^ t1c), sd0[1] ^ sd1[1]);
+        c23 = mk64(sd0[2] ^ sd1[2], sd0[3] ^ sd1[3]);
+      }
+      st8(k0 + ro, c01);
+      st8(k0 + ro + 8, c23);
+      if (k1) {
+        st8(k1 + ro, c01);
+        st8(k1 + ro + 8, c23);
+      }
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const uint64_t w = v1[q] - v0[q] - Va[q] + (beta[q] & below);
+        st8(k0 + ro + 16 + 8 * q, (w ^ neg) - neg);
+        if (k1) st8(k1 + ro + 16 + 8 * q, (w ^ neg) - neg);
+      }
+    };
+    // Both parties' expansions of the children, two at a time: with odd P the
+    // pair's values share a block of the seed's value stream, expanded once.
+#pragma unroll 1
+    for (uint32_t c = 0; c < C; c += 2) {
+      const uint32_t vb0 = value_block0<P, R>(c);
+      if constexpr (P == 3) {
+        // child c: words 0..2 of blocks vb0, vb0 + 1; child c + 1: word 3 of
+        // them and words 0..1 of vb0 + 2
+        uint64_t carry[2];
+        {
+          uint32_t o0[3][4], o1[3][4];
+          if (last) {
+            const uint32_t jj[2] = {vb0, vb0 + 1};
+            uint32_t p0[2][4], p1[2][4];
+            prg_shared<TB, 2>(tb, s[0], jj, p0);
+            prg_shared<TB, 2>(tb, s[1], jj, p1);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              o0[0][w] = o1[0][w] = 0u;
+              o0[1][w] = p0[0][w]; o0[2][w] = p0[1][w];
+              o1[1][w] = p1[0][w]; o1[2][w] = p1[1][w];
+            }
+          } else {
+            const uint32_t jj[3] = {c, vb0, vb0 + 1};
+            prg_shared<TB, 3>(tb, s[0], jj, o0);
+            prg_shared<TB, 3>(tb, s[1], jj, o1);
+          }
+          const uint64_t v0[3] = {mk64(o0[1][0], o0[1][1]), mk64(o0[1][2], o0[1][3]), mk64(o0[2][0], o0[2][1])};
+          const uint64_t v1[3] = {mk64(o1[1][0], o1[1][1]), mk64(o1[1][2], o1[1][3]), mk64(o1[2][0], o1[2][1])};
+          carry[0] = mk64(o0[2][2], o0[2][3]);
+          carry[1] = mk64(o1[2][2], o1[2][3]);
+          const uint32_t sd0[4] = {o0[0][0], o0[0][1], o0[0][2], o0[0][3]};
+          const uint32_t sd1[4] = {o1[0][0], o1[0][1], o1[0][2], o1[0][3]};
+          child(c, sd0, sd1, v0, v1);
+        }
+        {
+          uint32_t o0[2][4], o1[2][4];
+          if (last) {
+            const uint32_t jj[1] = {vb0 + 2};
+            uint32_t p0[1][4], p1[1][4];
+            prg_shared<TB, 1>(tb, s[0], jj, p0);
+            prg_shared<TB, 1>(tb, s[1], jj, p1);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              o0[0][w] = o1[0][w] = 0u;
+              o0[1][w] = p0[0][w];
+              o1[1][w] = p1[0][w];
+            }
+          } else {
+            const uint32_t jj[2] = {c + 1, vb0 + 2};
+            prg_shared<TB, 2>(tb, s[0], jj, o0);
+            prg_shared<TB, 2>(tb, s[1], jj, o1);
+          }
+          const uint64_t v0[3] = {carry[0], mk64(o0[1][0], o0[1][1]), mk64(o0[1][2], o0[1][3])};
+          const uint64_t v1[3] = {carry[1], mk64(o1[1][0], o1[1][1]), mk64(o1[1][2], o1[1][3])};
+          const uint32_t sd0[4] = {o0[0][0], o0[0][1], o0[0][2], o0[0][3]};
+          const uint32_t sd1[4] = {o1[0][0], o1[0][1], o1[0][2], o1[0][3]};
+          child(c + 1, sd0, sd1, v0, v1);
+        }
+      } else if constexpr (P == 1) {
+        // both children's values are the two words of block vb0
+        uint32_t o0[2][4], o1[2][4];
+        if (last) {
+          const uint32_t jj[1] = {vb0};
+          uint32_t p0[1][4], p1[1][4];
+          prg_shared<TB, 1>(tb, s[0], jj, p0);
+          prg_shared<TB, 1>(tb, s[1], jj, p1);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            o0[0][w] = o1[0][w] = 0u;
+            o0[1][w] = p0[0][w];
+            o1[1][w] = p1[0][w];
+          }
+        } else {
+          const uint32_t jj[2] = {c, vb0};
+          prg_shared<TB, 2>(tb, s[0], jj, o0);
+          prg_shared<TB, 2>(tb, s[1], jj, o1);
+        }
+        {
+          const uint64_t v0[1] = {mk64(o0[1][0], o0[1][1])}, v1[1] = {mk64(o1[1][0], o1[1][1])};
+          const uint32_t sd0[4] = {o0[0][0], o0[0][1], o0[0][2], o0[0][3]};
+          const uint32_t sd1[4] = {o1[0][0], o1[0][1], o1[0][2], o1[0][3]};
+          child(c, sd0, sd1, v0, v1);
+        }
+        const uint64_t w0 = mk64(o0[1][2], o0[1][3]), w1 = mk64(o1[1][2], o1[1][3]);
+        uint32_t sd0[4] = {0u, 0u, 0u, 0u}, sd1[4] = {0u, 0u, 0u, 0u};
+        if (!last) {
+          const uint32_t jj[1] = {c + 1};
+          uint32_t p0[1][4], p1[1][4];
+          prg_shared<TB, 1>(tb, s[0], jj, p0);
+          prg_shared<TB, 1>(tb, s[1], jj, p1);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            sd0[w] = p0[0][w];
+            sd1[w] = p1[0][w];
+          }
+        }
+        const uint64_t v0[1] = {w0}, v1[1] = {w1};
+        child(c + 1, sd0, sd1, v0, v1);
       } else {
-        const uint4 cw = make_uint4(((o0[0][0] ^ o1[0][0]) & ~3u) | (t0c ^ t1c), o0[0][1] ^ o1[0][1],
-                                    o0[0][2] ^ o1[0][2], o0[0][3] ^ o1[0][3]);
-        const uint64_t ro = off_crec + (((uint64_t)i * C + c) * kTile + lane) * REC;
-        st8(k0 + ro, mk64(cw.x, cw.y));
-        st8(k0 + ro + 8, mk64(cw.z, cw.w));
-        if (k1) {
-          st8(k1 + ro, mk64(cw.x, cw.y));
-          st8(k1 + ro + 8, mk64(cw.z, cw.w));
-        }
-        const uint64_t below = c < a ? ~0ull : 0ull;
+        // even P: each child's values fill whole blocks of its own
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-          const uint64_t v0 = mk64(o0[1 + q / 2][2 * (q & 1)], o0[1 + q / 2][2 * (q & 1) + 1]);
-          const uint64_t v1 = mk64(o1[1 + q / 2][2 * (q & 1)], o1[1 + q / 2][2 * (q & 1) + 1]);
-          const uint64_t w = v1 - v0 - Va[q] + (beta[q] & below);
-          st8(k0 + ro + 16 + 8 * q, (w ^ neg) - neg);
-          if (k1) st8(k1 + ro + 16 + 8 * q, (w ^ neg) - neg);
+        for (uint32_t cc = c; cc < c + 2; ++cc) {
+          const uint32_t vb = value_block0<P, R>(cc);
+          uint32_t o0[1 + NB][4], o1[1 + NB][4];
+          if (last) {
+            uint32_t jj[NB], p0[NB][4], p1[NB][4];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) jj[k] = vb + (uint32_t)k;
+            prg_shared<TB, NB>(tb, s[0], jj, p0);
+            prg_shared<TB, NB>(tb, s[1], jj, p1);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              o0[0][w] = o1[0][w] = 0u;
+#pragma unroll
+              for (int k = 0; k < NB; ++k) {
+                o0[1 + k][w] = p0[k][w];
+                o1[1 + k][w] = p1[k][w];
+              }
+            }
+          } else {
+            uint32_t jj[1 + NB];
+            jj[0] = cc;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) jj[1 + k] = vb + (uint32_t)k;
+            prg_shared<TB, 1 + NB>(tb, s[0], jj, o0);
+            prg_shared<TB, 1 + NB>(tb, s[1], jj, o1);
+          }
+          uint64_t v0[P], v1[P];
+#pragma unroll
+          for (int q = 0; q < P; ++q) {
+            v0[q] = mk64(o0[1 + q / 2][2 * (q & 1)], o0[1 + q / 2][2 * (q & 1) + 1]);
+            v1[q] = mk64(o1[1 + q / 2][2 * (q & 1)], o1[1 + q / 2][2 * (q & 1) + 1]);
+          }
+          const uint32_t sd0[4] = {o0[0][0], o0[0][1], o0[0][2], o0[0][3]};
+          const uint32_t sd1[4] = {o1[0][0], o1[0][1], o1[0][2], o1[0][3]};
+          child(cc, sd0, sd1, v0, v1);
         }
       }
     }
+    if (last) break;
     // Alpha's child: random seed and value corrections R(e, 69 + k, level);
     // the parties' next seeds and V_alpha.
     uint32_t kr[1 + NB][4];
@@ -1151,6 +1339,7 @@ __global__ __launch_bounds__((keygen_block<V, P>())) void k_keygen(const KeyHead
     rand_blk(tb, ga.rk, e, 3 + 2 * t, 0, rb);
     gen_z2(tb, k, alpha, ra, rb, t0 + h->atom_off[t], t1 ? t1 + h->atom_off[t] : nullptr, lane);
   }
+  init_record(tb, ga.rk, tile, h->off_seen, h->off_sentinel, tb_bytes, t0, t1, lane);
   rand_blk(tb, ga.rk, e, 66, 0, r);
   const uint64_t ellmask = h->ell >= 64 ? ~0ull : ((1ull << h->ell) - 1);
   const uint64_t W = mk64(r[0], r[1]) & ellmask;
@@ -1185,6 +1374,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_rescale_keygen(const KeyHe
   uint8_t* t0 = key0 + kHeaderBytes + tile * tbb;
   uint8_t* t1 = key1 ? key1 + kHeaderBytes + tile * tbb : nullptr;
   const uint64_t rin = valid ? ldg64(r_in + e) : 0;
+  init_record(tb, ga.rk, tile, h->off_seen, h->off_sentinel, tbb, t0, t1, lane);
   uint32_t r[4];
   rand_blk(tb, ga.rk, e, 0, 0, r);
   const uint64_t rout = mk64(r[0], r[1]);
@@ -1229,7 +1419,8 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_rescale_eval(const uint8_t
   TB tb(lds, lane);
   const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
   const int s = (int)h->shift;
-  const uint64_t uhat = (valid ? ldg64(yhat + e) : 0) + (1ull << 62);
+  const uint64_t yh = valid ? ldg64(yhat + e) : 0;
+  const uint64_t uhat = yh + (1ull << 62);
   const uint32_t x = (uint32_t)(uhat & ((1ull << s) - 1));
   VState<1> st = vroot<1>(h, tp, lane, party);
   switch (h->lookup_r) {
@@ -1239,7 +1430,8 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_rescale_eval(const uint8_t
   }
   uint64_t out = ld8(tp + h->off_tk0 + lane * 8) + (1ull - (uhat >> 63)) * ld8(tp + h->off_tk1 + lane * 8) + st.V[0];
   if (party == 0) out += (uhat >> s) - (1ull << (62 - s));
-  if (valid) stg64(z + e, out);
+  const bool ok = claim_once(h, tp, lane, yh, valid, status);
+  if (valid) stg64(z + e, ok ? out : 0ull);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,7 +26,8 @@ LIB_PATH = os.environ.get("FUSEFSS_LIB") or os.path.join(_HERE, "_lib", "libfuse
 
 FSS_OK = 0
 ERRORS = {-1: "FSS_E_INVALID_SPEC", -2: "FSS_E_UNSUPPORTED", -3: "FSS_E_NEEDS_PHI",
-          -4: "FSS_E_SHAPE", -5: "FSS_E_PARTY", -6: "FSS_E_HIP", -7: "FSS_E_OOM", -8: "FSS_E_ARG"}
+          -4: "FSS_E_SHAPE", -5: "FSS_E_PARTY", -6: "FSS_E_HIP", -7: "FSS_E_OOM", -8: "FSS_E_ARG",
+          -9: "FSS_E_CONSUMED"}
 MAX_ATOMS = 16
 
 PRED_LT_SIGNED, PRED_LT_UNSIGNED, PRED_LOWBITS_LT, PRED_MSB_SHIFT = 0, 1, 2, 3

@@ -18,6 +18,7 @@ HDR = np.dtype([
     ("atom_rview", "<u4", MAXA), ("atom_c", "<u8", MAXA), ("atom_off", "<u8", MAXA),
     ("off_w", "<u8"), ("off_croot", "<u8"), ("off_crec", "<u8"), ("rec_bytes", "<u8"),
     ("off_crho", "<u8"), ("off_crout", "<u8"), ("off_tk0", "<u8"), ("off_tk1", "<u8"),
+    ("off_seen", "<u8"), ("off_sentinel", "<u8"),
     ("aprime", "<u8", MAXM + 1), ("tab", "<u8", (MAXM, MAXP, MAXP)), ("tabv", "<u8", (MAXP, MAXP)),
 ])
 

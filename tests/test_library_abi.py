@@ -183,15 +183,15 @@ def test_key_bytes_shape(r):
         assert s.key_bytes(24, 12, N) == 16384 + ((N + 63) // 64) * per_tile
     # 3 Z_2 atoms (root, 24 - 7 tree levels, value bits, 16-byte leaf correction), w shares,
     # then the lookup DCF: root, 24 / r levels x 2^r children of seed (16 B) and p = 3
-    # value corrections, rho and r_out shares
+    # value corrections, rho and r_out shares; the one-time record (x-hat of each element, used mask)
     expect = (3 * (64 * 16 * 18 + 64 * 8 + 64 * 16) + 64 * 8 + 64 * 16 + (24 // r) * 2**r * 64 * (16 + 3 * 8)
-              + 3 * 64 * 8 + 64 * 8)
+              + 3 * 64 * 8 + 64 * 8 + 64 * 8 + 8)
     assert per_tile == (expect + 255) // 256 * 256
     c = F.Spec(W.clip_relu_spec(), lookup_r=r)
     # n = 16, p = 2: atoms 3 * ((1 + 9) * 16 + 8 + 16), w 8, root 16, ceil(16 / r) levels x 2^r
-    # x (16 + 16), rho 16, r_out 8
-    assert (c.key_bytes(16, 8, 4096) - 16384) // 4096 == \
-        3 * (10 * 16 + 8 + 16) + 8 + 16 + (-(-16 // r)) * 2**r * 32 + 16 + 8
+    # x (16 + 16), rho 16, r_out 8 per element; the one-time record; tiles rounded to 256 bytes
+    elem = 3 * (10 * 16 + 8 + 16) + 8 + 16 + (-(-16 // r)) * 2**r * 32 + 16 + 8
+    assert c.key_bytes(16, 8, 4096) - 16384 == 64 * ((64 * elem + 64 * 8 + 8 + 255) // 256 * 256)
 
 
 def test_lookup_radix_setting():
@@ -247,10 +247,11 @@ def test_argument_errors():
 @pytest.mark.parametrize("r", [2, 3, 4])
 def test_rescale_key_bytes(r):
     """Rescaling gate: root, ceil(s / r) levels x 2^r children of 24-byte records
-    (seed and value correction), then the two 8-byte constant shares; 64-lane tiles."""
+    (seed and value correction), then the two 8-byte constant shares and the one-time
+    record (x-hat of each element, used mask); 64-lane tiles."""
     for s in (1, 8, 24, 32):
         per_tile = F.fss_rescale_key_bytes(s, r, 64) - F.fss_rescale_key_bytes(s, r, 0)
-        expect = 64 * 16 + (-(-s // r)) * 2**r * 64 * 24 + 2 * 64 * 8
+        expect = 64 * 16 + (-(-s // r)) * 2**r * 64 * 24 + 2 * 64 * 8 + 64 * 8 + 8
         assert per_tile == (expect + 255) // 256 * 256
         assert F.fss_rescale_key_bytes(s, r, 1000) == 16384 + 16 * per_tile
     for bad_s, code in ((0, -2), (33, -2)):
