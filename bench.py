@@ -159,9 +159,9 @@ def main() -> None:
     ap.add_argument("--autotune", default=os.path.join(tempfile.gettempdir(), "fusefss_tune_cache.txt"),
                     metavar="CACHE", help="autotuner cache file (the fused launch is tuned on the first layer)")
     ap.add_argument("--no-autotune", action="store_true", help="use the planner's default launch")
-    ap.add_argument("--tune", default=None, metavar="V,BPC,ORDER,PARTS,PRED",
+    ap.add_argument("--tune", default=None, metavar="V,BPC,ORDER,PARTS,PRED[,LANES]",
                     help="fix the fused launch: AES variant, blocks per CU, unit order, parts per tile, "
-                         "call-1 unit (as fss_tune; replaces the autotuner)")
+                         "call-1 unit, lanes per element (as fss_tune; replaces the autotuner)")
     ap.add_argument("--latency-reps", type=int, default=60,
                     help="fused/plain step pairs, alternating, for the latency percentiles and ratios")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -214,8 +214,8 @@ def main() -> None:
     groups = layer_groups(ops)
     tune = None
     if args.tune:
-        v, bpc, order, parts, pred = (int(t) for t in args.tune.split(","))
-        tune = F.Tune(0, bpc, v, order, parts, pred)
+        v, bpc, order, parts, pred, *lanes = (int(t) for t in args.tune.split(","))
+        tune = F.Tune(0, bpc, v, order, parts, pred, lanes[0] if lanes else 0)
     elif not args.no_autotune:
         tune = F.fss_autotune([insts[i].item(b) for i in groups[0] for b in (0, 1)], args.autotune)
     plans = [F.Plan([insts[i].item(b) for i in g for b in (0, 1)], tune) for g in groups]

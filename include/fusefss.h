@@ -274,6 +274,11 @@ typedef struct {
   int32_t parts;          /* units call 2 of a tile is split into: 0 = planner's choice, 1 .. 4 */
   int32_t pred_unit;      /* call 1 of a tile: 0 = planner's choice, 1 = in the unit that runs
                              call 2's first part (one pass over the elements), 2 = its own unit */
+  int32_t lanes;          /* lanes per element in call 2, i.e. elements per wave = 64 / lanes:
+                             0 or 1 = one lane per element; 2 or 4 = each element's lookup
+                             points split over that many lanes, whose shares of y are summed
+                             across the wave (then parts <= 1, call 1 in its own unit, and
+                             aes_variant 1 or 2) */
 } fss_tune;
 
 typedef struct fss_plan fss_plan;
@@ -346,7 +351,7 @@ int fss_plan_parts(const fss_plan* plan);
 int fss_eval_batch_noalloc(int32_t party, const fss_work_item* items, int32_t n_items, void* stream);
 
 /* Resolved launch configuration of a plan (host out-params): the tune with
- * `parts` and `pred_unit` set to the planner's choice. */
+ * `parts`, `pred_unit` and `lanes` set to the planner's choice. */
 int fss_plan_config(const fss_plan* plan, fss_tune* tune, int32_t* grid);
 
 /* Capture the launches of n_plans plans, in order, into one HIP graph. */

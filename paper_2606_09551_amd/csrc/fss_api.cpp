@@ -1001,10 +1001,12 @@ ElemCost elem_cost(const KeyHeader& h) {
   return c;
 }
 
-// One work-list unit before upload.
+// One work-list unit before upload: `aes` / `lookups` per element of the
+// unit (the work of all its lanes), `span` the AES blocks of its longest lane
+// (its duration in the schedule).
 struct Unit {
   uint32_t item, tile, range, flags;
-  double aes, lookups;
+  double aes, lookups, span;
 };
 
 // The units of one tile: call 2 whole or split into `parts` (at most one per
@@ -1014,16 +1016,37 @@ struct Unit {
 // (the walk at v) and so takes fewer points.  With `merge_pred`, call 1 runs
 // in part 0's unit: one pass over the tile's elements (x-hat loaded once);
 // otherwise it is a unit of its own, which lets the costlier call-2 units run
-// first and the short call-1 units fill the end of the schedule.  Every tile
-// of an item splits the same way.
-std::vector<Unit> tile_parts(const ElemCost& c, int parts, bool merge_pred) {
+// first and the short call-1 units fill the end of the schedule.  With
+// `lanes` > 1, call 2 of a tile is `lanes` units of 64 / lanes elements whose
+// lanes split each element's points (kUnitLanes; call 1 in a unit of its
+// own): a lane group walks the shared top levels for its own points and group
+// 0 the base, so the tile's work grows by (lanes - 1) x (tops + base), and the
+// base runs after the points in every unit.  Every tile of an item splits the
+// same way.
+std::vector<Unit> tile_parts(const ElemCost& c, int parts, bool merge_pred, int lanes) {
   std::vector<Unit> out;
   const int S = std::max(1, std::min(parts, c.points));
-  if (S == 1) {
+  if (lanes > 1) {
+    const int per = c.points / lanes, extra = c.points % lanes;
+    double aes = c.aes_base, lk = c.lk_base;
+    for (int g = 0; g < lanes; ++g) {
+      const int k = per + (g < extra ? 1 : 0);
+      if (k > 0) {
+        aes += c.aes_tops + k * c.aes_point;
+        lk += c.lk_tops + k * c.lk_point;
+      }
+    }
+    const int kmax = per + (extra > 0 ? 1 : 0);
+    const double span = c.aes_base + (kmax > 0 ? c.aes_tops + kmax * c.aes_point : 0.0);
+    const uint32_t E = (uint32_t)(kTile / lanes);
+    for (int g = 0; g < lanes; ++g)
+      out.push_back({0, 0, 1u | ((uint32_t)(1 + c.points) << 16),
+                     kUnitBase | kUnitLanes | ((uint32_t)g * E << 16), aes, lk, span});
+  } else if (S == 1) {
     const double tops = c.points > 0 ? 1.0 : 0.0;
-    out.push_back({0, 0, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitBase,
-                   c.aes_base + tops * c.aes_tops + c.points * c.aes_point,
-                   c.lk_base + tops * c.lk_tops + c.points * c.lk_point});
+    const double aes = c.aes_base + tops * c.aes_tops + c.points * c.aes_point;
+    out.push_back({0, 0, 1u | ((uint32_t)(kMaxM + 1) << 16), kUnitBase, aes,
+                   c.lk_base + tops * c.lk_tops + c.points * c.lk_point, aes});
   } else {
     const double total = c.aes_base + c.points * c.aes_point + (merge_pred ? c.aes_pred : 0.0);
     const double base = c.aes_base + (merge_pred ? c.aes_pred : 0.0);
@@ -1035,23 +1058,25 @@ std::vector<Unit> tile_parts(const ElemCost& c, int parts, bool merge_pred) {
       const int k = part == 0 ? k0 : rest / (S - 1) + (part - 1 < rest % (S - 1) ? 1 : 0);
       const double tops = k > 0 ? 1.0 : 0.0;
       Unit u{0, 0, (uint32_t)i | ((uint32_t)(i + k) << 16), kUnitAccumulate, tops * c.aes_tops + k * c.aes_point,
-             tops * c.lk_tops + k * c.lk_point};
+             tops * c.lk_tops + k * c.lk_point, 0.0};
       if (part == 0) {
         u.flags |= kUnitBase;
         u.aes += c.aes_base;
         u.lookups += c.lk_base;
       }
+      u.span = u.aes;
       out.push_back(u);
       i += k;
     }
   }
   if (c.ell > 0) {
-    if (merge_pred) {
+    if (merge_pred && lanes <= 1) {
       out[0].flags |= kUnitPred;
       out[0].aes += c.aes_pred;
       out[0].lookups += c.lk_pred;
+      out[0].span += c.aes_pred;
     } else {
-      out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred, c.lk_pred});
+      out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred, c.lk_pred, c.aes_pred});
     }
   }
   return out;
@@ -1124,6 +1149,7 @@ fss_tune default_tune() {
   t.order = 0;
   t.parts = 0;
   t.pred_unit = 0;
+  t.lanes = 0;
   return t;
 }
 
@@ -1163,6 +1189,13 @@ int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune*
   if (tn.parts < 0 || tn.parts > 4) return fail(FSS_E_ARG, "tune.parts=%d outside [0,4]", tn.parts);
   if (tn.pred_unit < 0 || tn.pred_unit > 2) return fail(FSS_E_ARG, "tune.pred_unit=%d outside [0,2]", tn.pred_unit);
   if (tn.order < 0 || tn.order > 1) return fail(FSS_E_ARG, "tune.order=%d outside [0,1]", tn.order);
+  if (tn.lanes != 0 && tn.lanes != 1 && tn.lanes != 2 && tn.lanes != 4)
+    return fail(FSS_E_ARG, "tune.lanes=%d: 0, 1, 2 or 4", tn.lanes);
+  const int lanes = std::max(1, (int)tn.lanes);
+  if (lanes > 1 && (tn.parts > 1 || tn.pred_unit == 1))
+    return fail(FSS_E_ARG, "tune.lanes=%d needs parts <= 1 and call 1 in its own unit", tn.lanes);
+  if (lanes > 1 && !lanes_variant(tn.aes_variant))
+    return fail(FSS_E_UNSUPPORTED, "tune.lanes=%d is built for AES variants 1 and 2 only", tn.lanes);
   if (tn.blocks_per_cu < 0 || tn.blocks_per_cu > 32) return fail(FSS_E_ARG, "tune.blocks_per_cu=%d", tn.blocks_per_cu);
   tn.block_threads = variant_block(tn.aes_variant);
   if (tn.blocks_per_cu <= 0) tn.blocks_per_cu = blocks_per_cu_default(tn.aes_variant);
@@ -1203,8 +1236,8 @@ int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune*
     g.clear();
     for (int i = 0; i < n_items; ++i) {
       if (dev[i].words == 0) continue;
-      tp[i] = tile_parts(cost[i], parts, merge);
-      for (uint32_t q = 0; q < tp[i].size(); ++q) g.push_back({tp[i][q].aes, (uint32_t)i, q, (uint64_t)dev[i].words});
+      tp[i] = tile_parts(cost[i], parts, merge, lanes);
+      for (uint32_t q = 0; q < tp[i].size(); ++q) g.push_back({tp[i][q].span, (uint32_t)i, q, (uint64_t)dev[i].words});
     }
     if (tn.order == 0)
       std::stable_sort(g.begin(), g.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
@@ -1217,11 +1250,12 @@ int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune*
   std::vector<Group> groups;
   int max_points = 1;  // a tile splits into at most one part per lookup point
   for (int i = 0; i < n_items; ++i) max_points = std::max(max_points, cost[i].points);
-  const int p_lo = tn.parts > 0 ? tn.parts : 1, p_hi = tn.parts > 0 ? tn.parts : std::min(4, max_points);
+  const int p_lo = tn.parts > 0 ? tn.parts : 1;
+  const int p_hi = lanes > 1 ? 1 : tn.parts > 0 ? tn.parts : std::min(4, max_points);
   for (int parts = p_lo; parts <= p_hi; ++parts) {
     for (int mi = 0; mi < 2; ++mi) {
       const bool merge = mi == 0;
-      if ((tn.pred_unit == 1 && !merge) || (tn.pred_unit == 2 && merge)) continue;
+      if ((tn.pred_unit == 1 && !merge) || (tn.pred_unit == 2 && merge) || (lanes > 1 && merge)) continue;
       groups_for(parts, merge, tp, groups);
       uint64_t n_units = 0;
       for (const Group& g : groups) n_units += g.count;
@@ -1233,7 +1267,7 @@ int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune*
       } else {  // natural order: tile by tile, parts in turn
         for (int i = 0; i < n_items; ++i)
           for (uint64_t t = 0; t < (uint64_t)dev[i].words; ++t)
-            for (const Unit& u : tp[i]) sim.run(u.aes, 1);
+            for (const Unit& u : tp[i]) sim.run(u.span, 1);
       }
       const double span = sim.makespan();
       // A candidate with more units has to win clearly: the simulation does
@@ -1278,8 +1312,11 @@ int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune*
     flat[kUnitWords * k + 1] = u.tile;
     flat[kUnitWords * k + 2] = u.range;
     flat[kUnitWords * k + 3] = u.flags;
-    const uint64_t e0 = (uint64_t)u.tile * kTile;
-    const double elems = (double)std::min<uint64_t>(kTile, (uint64_t)dev[u.item].n_elems - e0);
+    // elements of the unit: the tile's, or a lane unit's slots from s0 on
+    const uint64_t e0 = (uint64_t)u.tile * kTile + ((u.flags & kUnitLanes) ? (u.flags >> 16) & 63u : 0u);
+    const uint64_t width = (u.flags & kUnitLanes) ? (uint64_t)(kTile / lanes) : (uint64_t)kTile;
+    const uint64_t n_it = (uint64_t)dev[u.item].n_elems;
+    const double elems = e0 < n_it ? (double)std::min<uint64_t>(width, n_it - e0) : 0.0;
     aes_total += u.aes * elems;
     lookups_total += u.lookups * elems;
     if ((u.flags & kUnitAccumulate) && !is_split[u.item]) {
@@ -1295,6 +1332,7 @@ int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune*
   hp->max_split_elems = max_split_elems;
   hp->parts = best_parts;
   hp->merged_pred = best_merge;
+  tn.lanes = lanes;
   hp->tune = tn;
   hp->grid = std::max(1, std::min<int>(cus * tn.blocks_per_cu,
                                        (int)((best.size() + waves_per_block - 1) / waves_per_block)));
@@ -1361,7 +1399,8 @@ int fss_plan_launch(fss_plan* plan, void* stream) {
   int rc = device_status_ptr(&st);
   if (rc) return rc;
   HIP_TRY(launch_fused(plan->tune.aes_variant, plan->d_items, plan->d_tiles, plan->n_tiles, plan->d_counter, st,
-                       plan->grid, plan->d_split, plan->n_split, plan->max_split_elems, (hipStream_t)stream),
+                       plan->grid, lanes_log2(plan->tune.lanes), plan->d_split, plan->n_split,
+                       plan->max_split_elems, (hipStream_t)stream),
           "fused launch");
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   HIP_TRY(hipStreamIsCapturing((hipStream_t)stream, &cs), "hipStreamIsCapturing");
@@ -1447,9 +1486,10 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
       std::istringstream ls(line);
       std::string kk;
       fss_tune t{};
-      if (ls >> kk >> t.aes_variant >> t.block_threads >> t.blocks_per_cu >> t.order >> t.parts >> t.pred_unit &&
+      if (ls >> kk >> t.aes_variant >> t.block_threads >> t.blocks_per_cu >> t.order >> t.parts >> t.pred_unit >>
+              t.lanes &&
           kk == k && t.aes_variant >= 0 && t.aes_variant < kNumAesVariants && t.parts >= 0 && t.parts <= 4 &&
-          t.pred_unit >= 0 && t.pred_unit <= 2) {
+          t.pred_unit >= 0 && t.pred_unit <= 2 && (t.lanes == 1 || t.lanes == 2 || t.lanes == 4)) {
         *best = t;
         return FSS_OK;
       }
@@ -1502,18 +1542,33 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
     }
   }
   // Stage 2: on the best launch shape, the work-list's units: call 2 of a
-  // tile in 1..4 parts, call 1 in the first part's pass or a unit of its own.
+  // tile in 1..4 parts, call 1 in the first part's pass or a unit of its own;
+  // then 2 or 4 lanes per element (32 or 16 elements per wave).
   for (int parts = 1; parts <= 4 && rc == FSS_OK; ++parts) {
     for (int pu : {1, 2}) {
       fss_tune t = bt, res{};
       t.parts = parts;
       t.pred_unit = pu;
+      t.lanes = 1;
       double ms = 0;
       if ((rc = time_tune(t, &ms, &res))) break;
       if (ms < best_ms) {
         best_ms = ms;
         bt = res;
       }
+    }
+  }
+  for (int lanes : {2, 4}) {
+    if (rc || !lanes_variant(bt.aes_variant)) break;
+    fss_tune t = bt, res{};
+    t.parts = 1;
+    t.pred_unit = 2;
+    t.lanes = lanes;
+    double ms = 0;
+    if ((rc = time_tune(t, &ms, &res))) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      bt = res;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1524,7 +1579,7 @@ int fss_autotune(const fss_work_item* items, int32_t n_items, const char* cache_
   if (cache_path) {
     std::ofstream o(cache_path, std::ios::app);
     o << k << " " << bt.aes_variant << " " << bt.block_threads << " " << bt.blocks_per_cu << " " << bt.order << " "
-      << bt.parts << " " << bt.pred_unit << "\n";
+      << bt.parts << " " << bt.pred_unit << " " << bt.lanes << "\n";
   }
   return FSS_OK;
 }

@@ -40,6 +40,15 @@ constexpr int kUnitWords = 4;
 constexpr uint32_t kUnitPred = 1u;        // call 1 (the predicate bits)
 constexpr uint32_t kUnitBase = 2u;        // the walk at v, tab_0 rho and r_out terms of call 2
 constexpr uint32_t kUnitAccumulate = 4u;  // add the part's y to memory zeroed before the launch
+// A call-2 unit over 64 / G elements of a tile (G = lane groups of the launch,
+// 2 or 4): lane l takes element slot s0 + l mod (64 / G) and, with the other
+// lanes of its group l / (64 / G), an even share of the unit's lookup points
+// (group 0 also takes the base); the groups' shares of y are summed across
+// lanes.  Flags bits 16..21: s0.
+constexpr uint32_t kUnitLanes = 8u;
+constexpr int kMaxLaneGroupsLog2 = 2;
+// Table layouts with lane-group kernels (the others would only add build time).
+constexpr bool lanes_variant(int v) { return v == 1 || v == 2; }
 
 // Launchers of one AES table layout V (0 .. kNumAesVariants-1).
 template <int V>
@@ -54,8 +63,9 @@ struct VariantOps {
                          int* status, int cus, hipStream_t st);
   static hipError_t coeff(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* y,
                           int* status, int cus, hipStream_t st);
+  // lanes_log2: log2 of the lane groups of the launch's kUnitLanes units (0: none)
   static hipError_t fused(const DevItem* items, const uint32_t* units, uint32_t n_units, uint32_t* counter,
-                          int* status, int grid, hipStream_t st);
+                          int* status, int grid, int lanes_log2, hipStream_t st);
   // the rescaling gate (ARS of a masked value)
   static hipError_t rescale_keygen(const KeyHeader* h, int r, const KgArgs& ga, const uint64_t* r_in, uint8_t* k0,
                                    uint8_t* k1, uint64_t* r_out, int cus, hipStream_t st);
@@ -82,7 +92,7 @@ hipError_t launch_eval_coeff(int variant, int party, const uint8_t* keys, const 
 // (graph-safe), then launches the persistent kernel with `grid` blocks of the
 // variant's block size over `n_units` work-list units.
 hipError_t launch_fused(int variant, const DevItem* items, const uint32_t* units, uint32_t n_units,
-                        uint32_t* counter, int* status, int grid, const uint32_t* split_items,
+                        uint32_t* counter, int* status, int grid, int lanes_log2, const uint32_t* split_items,
                         uint32_t n_split, uint64_t max_split_elems, hipStream_t st);
 hipError_t launch_rescale_keygen(int variant, int r, const KeyHeader* dev_hdr, const KgArgs& ga, const uint64_t* r_in,
                                  uint8_t* key0, uint8_t* key1, uint64_t* r_out, int cus, hipStream_t st);

@@ -376,18 +376,18 @@ __device__ __forceinline__ int header_check(GHdr h, int party, int64_t n) {
 // sentinel (probability 2^-64) is not recorded.  Returns whether the lane may
 // output.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool claim_once(GHdr h, const uint8_t* tile, int lane, uint64_t xh, bool valid,
+__device__ __forceinline__ bool claim_once(GHdr h, const uint8_t* tile, int slot, uint64_t xh, bool valid,
                                            int* status) {
   bool ok = true;
   if (valid) {
     const unsigned long long none = ld8(tile + h->off_sentinel);
     unsigned long long seen = none;  // the slot's value when the exchange fails
     __hip_atomic_compare_exchange_strong(
-        (FSS_GLOBAL unsigned long long*)(const_cast<uint8_t*>(tile) + h->off_seen) + lane, &seen,
+        (FSS_GLOBAL unsigned long long*)(const_cast<uint8_t*>(tile) + h->off_seen) + slot, &seen,
         (unsigned long long)xh, __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     ok = seen == none || seen == xh;
   }
-  if (__ballot(!ok) && lane == 0) set_status(status, kStatusConsumed);
+  if (__ballot(!ok) && (threadIdx.x & 63) == 0) set_status(status, kStatusConsumed);
   return ok;
 }
 
@@ -790,13 +790,51 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_coeff(const uint8_t* 
 }
 
 // ---------------------------------------------------------------------------
+// A kUnitLanes unit: 64 / 2^LG elements of a tile, each evaluated by 2^LG
+// lanes (one per group) that split the unit's lookup points evenly; group 0
+// also takes the base.  The groups' shares of y are added across lanes (two
+// 32-bit swizzles per step), then group 0 stores them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int mask) {
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, mask);
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), mask);
+  return mk64(lo, hi);
+}
+
+template <int LG, class TB>
+__device__ __forceinline__ void lanes_unit(const TB& tb, GHdr h, const DevItem& it, uint64_t tile, uint32_t range,
+                                           uint32_t flags, int lane, int* status) {
+  constexpr int G = 1 << LG, E = kTile >> LG;
+  const int grp = lane / E;
+  const int slot = (int)((flags >> 16) & 63u) + (lane & (E - 1));
+  const uint64_t e = tile * kTile + (uint64_t)slot;
+  const bool valid = e < (uint64_t)it.n_elems;
+  const uint64_t xh = valid ? ldg64(it.xhat + e) : 0;
+  const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
+  const int lo = (int)(range & 0xffffu), cnt = (int)(range >> 16) - lo;
+  const int q = cnt / G, rr = cnt % G;
+  const int i0 = lo + grp * q + (grp < rr ? grp : rr), i1 = i0 + q + (grp < rr ? 1 : 0);
+  uint64_t out = coeff_dispatch(tb, h, tp, slot, it.party, xh, i0, i1, (flags & kUnitBase) != 0 && grp == 0);
+#pragma unroll
+  for (int d = E; d < kTile; d <<= 1) out += shfl_xor64(out, d);
+  const bool ok = claim_once(h, tp, slot, xh, valid && grp == 0, status);
+  if (valid && grp == 0) {
+    if (flags & kUnitAccumulate)
+      __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)(ok ? out : 0ull),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      stg64(it.y + e, ok ? out : 0ull);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused persistent kernel: waves pull units from a work-list in cost order.
 // A unit is a tile's call 1 and call 2 with the combination in one pass over
 // its elements (x-hat loaded once), or a part of that work (call 1 alone, or
 // a range of lookup points) when the planner splits tiles to balance the
 // waves; the AES tables are staged once per resident block.
 // ---------------------------------------------------------------------------
-template <int V>
+template <int V, int LG>
 __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items, const uint32_t* tiles,
                                                              uint32_t n_tiles, uint32_t* counter,
                                                              int* status) {
@@ -831,6 +869,12 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
       if (lane == 0) set_status(status, bad);
       continue;
     }
+    if constexpr (LG > 0) {
+      if (flags & kUnitLanes) {
+        lanes_unit<LG>(tb, h, it, tile, range, flags, lane, status);
+        continue;
+      }
+    }
     const uint64_t e = tile * kTile + lane;
     const bool valid = e < (uint64_t)it.n_elems;
     const uint64_t xh = valid ? ldg64(it.xhat + e) : 0;
@@ -844,15 +888,20 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
         return ok = claim_once(h, tp, lane, xh, valid, status);
       });
     if (!(flags & kUnitBase) && (range & 0xffffu) >= (range >> 16)) continue;  // a call-1 unit
-    const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),
-                                        (flags & kUnitBase) != 0);
-    if (!claimed) ok = claim_once(h, tp, lane, xh, valid, status);
-    if (valid) {
-      if (flags & kUnitAccumulate)  // parts of one tile add their shares of y (mod 2^64)
-        __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)(ok ? out : 0ull),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      else
-        stg64(it.y + e, ok ? out : 0ull);
+    if constexpr (LG > 0) {
+      // launches with lane groups run call 2 in kUnitLanes units only
+      if (lane == 0) set_status(status, kStatusShape);
+    } else {
+      const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),
+                                          (flags & kUnitBase) != 0);
+      if (!claimed) ok = claim_once(h, tp, lane, xh, valid, status);
+      if (valid) {
+        if (flags & kUnitAccumulate)  // parts of one tile add their shares of y (mod 2^64)
+          __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)(ok ? out : 0ull),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          stg64(it.y + e, ok ? out : 0ull);
+      }
     }
   }
 }
@@ -1549,11 +1598,23 @@ hipError_t VariantOps<V>::rescale_eval(int party, const uint8_t* keys, const uin
 
 template <int V>
 hipError_t VariantOps<V>::fused(const DevItem* items, const uint32_t* tiles, uint32_t n_tiles,
-                                uint32_t* counter, int* status, int grid, hipStream_t st) {
+                                uint32_t* counter, int* status, int grid, int lanes_log2, hipStream_t st) {
   constexpr int B = TabOf<V>::kBlock;
   if (grid <= 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_fused<V>), dim3(grid), dim3(B), 0, st, items, tiles, n_tiles, counter, status);
-  return hipGetLastError();
+  if (lanes_log2 == 0) {
+    hipLaunchKernelGGL((k_fused<V, 0>), dim3(grid), dim3(B), 0, st, items, tiles, n_tiles, counter, status);
+    return hipGetLastError();
+  }
+  if constexpr (lanes_variant(V)) {
+    if (lanes_log2 == 1)
+      hipLaunchKernelGGL((k_fused<V, 1>), dim3(grid), dim3(B), 0, st, items, tiles, n_tiles, counter, status);
+    else if (lanes_log2 == 2)
+      hipLaunchKernelGGL((k_fused<V, 2>), dim3(grid), dim3(B), 0, st, items, tiles, n_tiles, counter, status);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fss

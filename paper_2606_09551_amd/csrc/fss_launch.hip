@@ -135,7 +135,7 @@ __global__ void k_zero_split(const DevItem* items, const uint32_t* split_items, 
 }
 
 hipError_t launch_fused(int v, const DevItem* items, const uint32_t* tiles, uint32_t n_tiles, uint32_t* counter,
-                        int* status, int grid, const uint32_t* split_items, uint32_t n_split,
+                        int* status, int grid, int lanes_log2, const uint32_t* split_items, uint32_t n_split,
                         uint64_t max_split_elems, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
   hipError_t e = hipGetLastError();
@@ -147,11 +147,11 @@ hipError_t launch_fused(int v, const DevItem* items, const uint32_t* tiles, uint
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   switch (v) {
-    case 0: return VariantOps<0>::fused(items, tiles, n_tiles, counter, status, grid, st);
-    case 1: return VariantOps<1>::fused(items, tiles, n_tiles, counter, status, grid, st);
-    case 2: return VariantOps<2>::fused(items, tiles, n_tiles, counter, status, grid, st);
-    case 3: return VariantOps<3>::fused(items, tiles, n_tiles, counter, status, grid, st);
-    case 4: return VariantOps<4>::fused(items, tiles, n_tiles, counter, status, grid, st);
+    case 0: return VariantOps<0>::fused(items, tiles, n_tiles, counter, status, grid, lanes_log2, st);
+    case 1: return VariantOps<1>::fused(items, tiles, n_tiles, counter, status, grid, lanes_log2, st);
+    case 2: return VariantOps<2>::fused(items, tiles, n_tiles, counter, status, grid, lanes_log2, st);
+    case 3: return VariantOps<3>::fused(items, tiles, n_tiles, counter, status, grid, lanes_log2, st);
+    case 4: return VariantOps<4>::fused(items, tiles, n_tiles, counter, status, grid, lanes_log2, st);
     default: return hipErrorInvalidValue;
   }
 }

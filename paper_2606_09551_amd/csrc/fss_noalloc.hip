@@ -108,7 +108,8 @@ extern "C" int fss_eval_batch_noalloc(int32_t party, const fss_work_item* items,
   if (e != hipSuccess) return set_hip_error(e, "hipStreamSynchronize(upload, no-alloc)");
   // launch_fused resets the work counter and zeroes the split items' y with
   // kernels before the persistent launch
-  e = launch_fused(hp.tune.aes_variant, d_items, d_units, (uint32_t)n_units, d_counter, d_status, hp.grid, d_split,
+  e = launch_fused(hp.tune.aes_variant, d_items, d_units, (uint32_t)n_units, d_counter, d_status, hp.grid,
+                   lanes_log2(hp.tune.lanes), d_split,
                    (uint32_t)hp.split.size(), hp.max_split_elems, st);
   if (e != hipSuccess) return set_hip_error(e, "fused launch (no-alloc)");
   return FSS_OK;

@@ -30,6 +30,9 @@ struct HostPlan {
 int build_host_plan(const fss_work_item* items, int32_t n_items, const fss_tune* tune,
                     const hipStream_t* header_stream, HostPlan* out);
 
+// log2 of a resolved tune's lane groups (1, 2 or 4 lanes per element).
+inline int lanes_log2(int lanes) { return lanes >= 4 ? 2 : lanes == 2 ? 1 : 0; }
+
 // Record the thread-local error message of the C ABI and return `code`.
 int set_error(int code, const char* fmt, ...);
 int set_hip_error(hipError_t e, const char* what);

@@ -72,7 +72,7 @@ class WorkItem(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("aes_variant", C.c_int32), ("order", C.c_int32), ("parts", C.c_int32),
-                ("pred_unit", C.c_int32)]
+                ("pred_unit", C.c_int32), ("lanes", C.c_int32)]
 
 
 def _load():
@@ -359,7 +359,7 @@ class Plan:
         _check(lib.fss_plan_config(self.handle, C.byref(t), C.byref(g)))
         return {"aes_variant": t.aes_variant, "block_threads": t.block_threads,
                 "blocks_per_cu": t.blocks_per_cu, "order": t.order, "grid": g.value,
-                "parts": t.parts, "pred_unit": t.pred_unit}
+                "parts": t.parts, "pred_unit": t.pred_unit, "lanes": t.lanes}
 
     def free(self, _free=lib.fss_plan_free):
         if self.handle is not None and self.handle.value:

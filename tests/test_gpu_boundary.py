@@ -76,6 +76,8 @@ def _run(spec, n, f, x, seed, path, tune=None):
             assert cfg["parts"] == min(tune.parts, inst.m - 1 if inst.m > 1 else 1), cfg
         if tune is not None and tune.pred_unit:
             assert cfg["pred_unit"] == tune.pred_unit, cfg
+        if tune is not None and tune.lanes:
+            assert cfg["lanes"] == tune.lanes, cfg
         plan.free()
     assert F.fss_status() == 0
     torch.cuda.synchronize()
@@ -215,3 +217,49 @@ def test_radix_autotune_sets_and_caches(tmp_path):
     S = O.compile_spec(desc, n, f, lookup_r=r)
     o = _oracle(S, x, 0x77)
     _check(_run(spec, n, f, x, 0x77, "plan"), o, len(x), ("radix", r))
+
+
+@pytest.mark.parametrize("lanes", [2, 4])
+@pytest.mark.parametrize("variant", [1, 2])
+def test_lanes_per_element_every_value(lanes, variant):
+    """Elements per wave 32 and 16: each element's lookup points split over 2
+    or 4 lanes whose shares of y are summed across the wave.  Random integer
+    specs (1..24 intervals, degree 0..3, so p = 1..4 and from zero points up)
+    at every radix, 777 elements (a ragged last tile), and GELU, against the
+    oracle."""
+    rnd = random.Random(1300 + 10 * lanes + variant)
+    tune = F.Tune(0, 0, variant, 0, 1, 2, lanes)
+    for r in (2, 3, 4):
+        for n in (12, 32):
+            alpha, coef, preds = _random_int_spec(rnd, n)
+            spec = F.Spec.integer(n, alpha, coef, preds, lookup_r=r)
+            S = O.compile_spec_int(n, alpha, coef, preds, lookup_r=r)
+            N = 777
+            x = np.array([rnd.randint(-(1 << (n - 1)), (1 << (n - 1)) - 1) for _ in range(N)], dtype=np.int64)
+            seed = rnd.getrandbits(128)
+            o = _oracle(S, x, seed)
+            _flush(f"lanes={lanes} variant={variant} n={n} m={len(alpha) - 1} d={len(coef[0]) - 1} r={r}")
+            _check(_run(spec, n, 0, x, seed, "plan", tune), o, N, (lanes, variant, n, r))
+    desc = W.gelu_spec(f=7)
+    spec = F.Spec(desc)
+    S = O.compile_spec(desc, 12, 7)
+    x = np.random.Generator(np.random.PCG64(6)).integers(-2048, 2048, size=1000).astype(np.int64)
+    _flush(f"lanes={lanes} variant={variant} GELU n=12")
+    _check(_run(spec, 12, 7, x, 0xAC, "plan", tune), _oracle(S, x, 0xAC), len(x), (lanes, variant))
+
+
+def test_lanes_rejected_where_not_built():
+    """Lane groups need parts <= 1, call 1 in its own unit and table layout 1
+    or 2; other values are rejected on the host."""
+    spec = F.Spec(W.clip_relu_spec())
+    inst = R.OpInstanceGPU(spec, 16, 8, 200)
+    inst.set_input(W.config1()[0].x[:200])
+    inst.keygen(4)
+    inst.mask()
+    items = [inst.item(0), inst.item(1)]
+    for tune, code in ((F.Tune(0, 0, 1, 0, 2, 2, 2), -8), (F.Tune(0, 0, 1, 0, 1, 1, 2), -8),
+                       (F.Tune(0, 0, 1, 0, 1, 2, 3), -8), (F.Tune(0, 0, 0, 0, 1, 2, 4), -2)):
+        with pytest.raises(F.FssError) as e:
+            F.Plan(items, tune)
+        assert e.value.code == code, (tune.lanes, e.value)
+    assert F.fss_status() == 0

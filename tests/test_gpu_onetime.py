@@ -32,6 +32,10 @@ def _eval(inst, path):
     if path == "plain":
         for b in (0, 1):
             inst.eval_plain(b)
+    elif path == "lanes":  # two lanes per element, call 1 in units of its own
+        plan = F.Plan([inst.item(0), inst.item(1)], F.Tune(0, 0, 1, 0, 1, 2, 2))
+        plan.launch()
+        plan.free()
     else:
         F.fss_eval_batch(F.PARTY_ANY, [inst.item(0), inst.item(1)])
     code = F.fss_status()
@@ -39,7 +43,7 @@ def _eval(inst, path):
     return code, inst.host()
 
 
-@pytest.mark.parametrize("path", ["plain", "fused"])
+@pytest.mark.parametrize("path", ["plain", "fused", "lanes"])
 def test_operator_keys_are_one_time(path):
     op = W.config1()[0]
     N = 1000
