@@ -137,6 +137,16 @@ def lib():
         L.orc_plain_eval.argtypes = [C.POINTER(Spec), C.c_int64, u64p, u64p]
         L.orc_protocol3.argtypes = [C.c_int, u64p, C.c_int, C.c_uint64, u64p,
                                     C.POINTER(C.c_int32)]
+        L.orc_lit_batch.argtypes = [C.POINTER(Spec), u8p, i64p, C.c_int64, i64p, u64p, u64p, u64p, u64p,
+                                    u64p, u64p, C.c_int]
+        for name in ("orc_triple", "orc_and_triple"):
+            getattr(L, name).argtypes = [C.c_void_p, C.c_uint64, C.c_int, u64p, u64p, u64p]
+        L.orc_b2a_rand.argtypes = [C.c_void_p, C.c_uint64, C.c_int, u64p, u64p]
+        for name in ("orc_beaver_mul", "orc_and"):
+            getattr(L, name).argtypes = [C.c_int] + [C.c_uint64] * 5
+            getattr(L, name).restype = C.c_uint64
+        L.orc_b2a.argtypes = [C.c_int, C.c_uint64, C.c_uint64]
+        L.orc_b2a.restype = C.c_uint64
         for name, cls in (("orc_sizeof_elem_key", ElemKey), ("orc_sizeof_dcf_key", DcfKey),
                           ("orc_sizeof_dcfz_key", DcfZKey),
                           ("orc_sizeof_dcfr_key", DcfRKey), ("orc_sizeof_spec", Spec)):
@@ -397,3 +407,66 @@ def trunc(shift: int, seed: int, elems, r_in, yhat, lookup_r: int = 3, threads: 
     if rc < 0:
         raise ValueError(f"oracle rejected the rescaling gate (shift={shift}, r={lookup_r})")
     return z0, z1, r_out
+
+
+# ---- the paper's lookup + post-processing pipeline -----------------------------
+
+def lit(S: Spec, seed: int, elems, x, threads: int = 0):
+    """Literal interval lookup (one vector DCF per inner boundary of the
+    translated partition), both parties' coefficient shares at
+    xhat = x + r_in, then Horner's rule with Beaver multiplications.
+    Returns dict(c0, c1 (count x p), y0, y1, r_in, r_out) with
+    y0 + y1 = P(x) + r_out."""
+    elems = np.ascontiguousarray(elems, dtype=np.int64)
+    x = np.ascontiguousarray(x, dtype=np.int64)
+    cnt, p = len(elems), S.p
+    c0, c1 = np.zeros((cnt, p), np.uint64), np.zeros((cnt, p), np.uint64)
+    y0, y1, r_in, r_out = (np.zeros(cnt, np.uint64) for _ in range(4))
+    rc = lib().orc_lit_batch(C.byref(S), seed_bytes(seed), _i64p(elems), cnt, _i64p(x), _u64p(c0), _u64p(c1),
+                             _u64p(y0), _u64p(y1), _u64p(r_in), _u64p(r_out), threads)
+    if rc < 0:
+        raise ValueError("oracle rejected the literal lookup")
+    return dict(c0=c0, c1=c1, y0=y0, y1=y1, r_in=r_in, r_out=r_out)
+
+
+def _sched(seed: int):
+    ks = C.create_string_buffer(4096)
+    lib().orc_seed_sched(seed_bytes(seed), ks)
+    return ks
+
+
+def _pairs(fn, seed: int, idx, step: int):
+    ks = _sched(seed)
+    a, b, c = (np.zeros(2, np.uint64) for _ in range(3))
+    fn(ks, idx, step, _u64p(a), _u64p(b), _u64p(c))
+    return a.copy(), b.copy(), c.copy()
+
+
+def triple(seed: int, e: int, step: int):
+    """Beaver triple of multiplication `step` of element e: (a, b, c) pairs of shares."""
+    return _pairs(lib().orc_triple, seed, e, step)
+
+
+def and_triple(seed: int, w: int, step: int):
+    """AND triple of bit-word w: (a, b, c) pairs of XOR shares."""
+    return _pairs(lib().orc_and_triple, seed, w, step)
+
+
+def b2a_rand(seed: int, e: int, step: int):
+    """(t bit XOR shares, T additive shares) of element e."""
+    ks = _sched(seed)
+    t, T = np.zeros(2, np.uint64), np.zeros(2, np.uint64)
+    lib().orc_b2a_rand(ks, e, step, _u64p(t), _u64p(T))
+    return t.copy(), T.copy()
+
+
+def beaver_mul(party, d, e, a, b, c) -> int:
+    return int(lib().orc_beaver_mul(party, d, e, a, b, c))
+
+
+def and_gate(party, d, e, a, b, c) -> int:
+    return int(lib().orc_and(party, d, e, a, b, c))
+
+
+def b2a(party, c, T) -> int:
+    return int(lib().orc_b2a(party, c, T))

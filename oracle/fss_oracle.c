@@ -20,6 +20,7 @@
 
 #include <math.h>
 #include <pthread.h>
+#include <stdlib.h>
 #include <string.h>
 #include <unistd.h>
 
@@ -1021,6 +1022,149 @@ int orc_protocol3(int n, const uint64_t* alpha, int m, uint64_t r, uint64_t* B, 
 }
 
 /* ========================================================================= */
+/* Literal interval lookup: one vector DCF per inner boundary of the         */
+/* translated partition (compilation protocol, steps (1) and (5))            */
+/* ========================================================================= */
+
+int orc_lit_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e, orc_lit_key* k0,
+                        orc_lit_key* k1, uint64_t* r_in_out, uint64_t* r_out_out) {
+  const int n = S->n, p = S->p, r = S->lookup_r;
+  const orc_blk m0 = orc_rand(kseed, e, 0, 0);
+  const uint64_t r_in = m0.lo, r_out = m0.hi;
+  k0->rout = orc_rand(kseed, e, 1, 0).lo;
+  k1->rout = r_out - k0->rout;
+  k0->rin = orc_rand(kseed, e, 200, 0).lo;
+  k1->rin = r_in - k0->rin;
+  /* the partition of v-space: v = x' + r_in mod 2^n for x' in offset binary
+   * (canonical for integer specs), whose boundaries are aprime */
+  uint64_t B[ORC_MAXM + 2];
+  int32_t ord[ORC_MAXM + 1];
+  const int M = orc_protocol3(n, S->aprime, S->m, r_in & lowmask(n), B, ord);
+  if (M < 1) return -1;
+  k0->M = k1->M = M;
+  const int levels = (n + r - 1) / r, nr = 1 + (p + 1) / 2;
+  for (int j = 1; j < M; j++) {
+    /* payload step at B_j: the piece below the boundary minus the piece above */
+    uint64_t beta[ORC_MAXP];
+    for (int k = 0; k < p; k++) beta[k] = S->coef[ord[j - 1]][k] - S->coef[ord[j]][k];
+    orc_blk kr[ORC_MAXLR * 3];
+    memset(kr, 0, sizeof kr);
+    for (int i = 0; i + 1 < levels; i++)
+      for (int k = 0; k < nr; k++) kr[i * nr + k] = orc_rand(kseed, e, 203 + k, 64 * j + i);
+    orc_dcfr_gen(n, r, p, B[j], beta, orc_rand(kseed, e, 201, j), orc_rand(kseed, e, 202, j), kr, &k0->dcf[j - 1],
+                 &k1->dcf[j - 1]);
+  }
+  const orc_blk sa = orc_rand(kseed, e, 210, 0), sb = orc_rand(kseed, e, 211, 0);
+  const uint64_t sh[4] = {sa.lo, sa.hi, sb.lo, sb.hi};
+  for (int k = 0; k < p; k++) {
+    k0->base[k] = sh[k];
+    k1->base[k] = S->coef[ord[M - 1]][k] - sh[k];
+  }
+  *r_in_out = r_in;
+  *r_out_out = r_out;
+  return 0;
+}
+
+void orc_lit_eval_elem(int b, const orc_spec* S, const orc_lit_key* K, uint64_t xhat, uint64_t* coef,
+                       uint64_t* x_share) {
+  const uint64_t v = (xhat + S->lookup_c) & lowmask(S->n);
+  for (int k = 0; k < S->p; k++) coef[k] = K->base[k];
+  for (int j = 1; j < K->M; j++) {
+    uint64_t out[ORC_MAXP];
+    orc_dcfr_eval(b, &K->dcf[j - 1], v, out);
+    for (int k = 0; k < S->p; k++) coef[k] += out[k];
+  }
+  *x_share = b == 0 ? xhat - K->rin : (uint64_t)0 - K->rin;
+}
+
+/* ========================================================================= */
+/* Post-processing subprotocols over shares                                  */
+/* ========================================================================= */
+
+void orc_triple(const orc_aes_sched* kseed, uint64_t e, int step, uint64_t a[2], uint64_t b[2], uint64_t c[2]) {
+  const orc_blk ab = orc_rand(kseed, e, 220, step), s0 = orc_rand(kseed, e, 221, step);
+  const uint64_t cc = ab.lo * ab.hi;
+  a[0] = s0.lo;
+  a[1] = ab.lo - s0.lo;
+  b[0] = s0.hi;
+  b[1] = ab.hi - s0.hi;
+  c[0] = orc_rand(kseed, e, 222, step).lo;
+  c[1] = cc - c[0];
+}
+
+/* u v = (d + a)(e + b) = d e + d b + e a + a b */
+uint64_t orc_beaver_mul(int party, uint64_t d, uint64_t e, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t z = c + d * b + e * a;
+  if (party == 0) z += d * e;
+  return z;
+}
+
+void orc_and_triple(const orc_aes_sched* kseed, uint64_t w, int step, uint64_t a[2], uint64_t b[2], uint64_t c[2]) {
+  const orc_blk ab = orc_rand(kseed, w, 230, step), s0 = orc_rand(kseed, w, 231, step);
+  a[0] = s0.lo;
+  a[1] = ab.lo ^ s0.lo;
+  b[0] = s0.hi;
+  b[1] = ab.hi ^ s0.hi;
+  c[0] = orc_rand(kseed, w, 232, step).lo;
+  c[1] = (ab.lo & ab.hi) ^ c[0];
+}
+
+/* x & y = (d ^ a) & (e ^ b) = (d & e) ^ (d & b) ^ (e & a) ^ (a & b) */
+uint64_t orc_and(int party, uint64_t d, uint64_t e, uint64_t a, uint64_t b, uint64_t c) {
+  uint64_t z = c ^ (d & b) ^ (e & a);
+  if (party == 0) z ^= d & e;
+  return z;
+}
+
+void orc_b2a_rand(const orc_aes_sched* kseed, uint64_t e, int step, uint64_t tbit[2], uint64_t T[2]) {
+  const uint64_t t = orc_rand(kseed, e, 240, step).lo & 1;
+  const orc_blk s0 = orc_rand(kseed, e, 241, step);
+  tbit[0] = s0.lo & 1;
+  tbit[1] = t ^ tbit[0];
+  T[0] = s0.hi;
+  T[1] = t - s0.hi;
+}
+
+uint64_t orc_b2a(int party, uint64_t c, uint64_t T) {
+  /* z = c ^ t = c + t - 2 c t */
+  uint64_t z = (1 - 2 * c) * T;
+  if (party == 0) z += c;
+  return z;
+}
+
+/* One element of the pipeline: keys, both parties' shares, Horner's rule
+ * with Beaver multiplications (the openings add the parties' masked shares). */
+static int lit_full_elem(const orc_spec* S, const orc_aes_sched* ks, uint64_t e, int64_t x, orc_lit_key* a,
+                         orc_lit_key* b, uint64_t* c0, uint64_t* c1, uint64_t* y0, uint64_t* y1,
+                         uint64_t* r_in, uint64_t* r_out) {
+  uint64_t rin, rout;
+  if (orc_lit_keygen_elem(S, ks, e, a, b, &rin, &rout)) return -1;
+  const uint64_t xh = (uint64_t)x + rin;
+  uint64_t c[2][ORC_MAXP], xs[2];
+  orc_lit_eval_elem(0, S, a, xh, c[0], &xs[0]);
+  orc_lit_eval_elem(1, S, b, xh, c[1], &xs[1]);
+  const int d = S->p - 1;
+  uint64_t acc[2] = {c[0][d], c[1][d]};
+  for (int t = 0; t < d; t++) {
+    uint64_t ta[2], tb[2], tc[2];
+    orc_triple(ks, e, t, ta, tb, tc);
+    const uint64_t D = (acc[0] - ta[0]) + (acc[1] - ta[1]);
+    const uint64_t E = (xs[0] - tb[0]) + (xs[1] - tb[1]);
+    for (int q = 0; q < 2; q++) acc[q] = orc_beaver_mul(q, D, E, ta[q], tb[q], tc[q]) + c[q][d - 1 - t];
+  }
+  if (c0)
+    for (int k = 0; k < S->p; k++) {
+      c0[k] = c[0][k];
+      c1[k] = c[1][k];
+    }
+  *y0 = acc[0] + a->rout;
+  *y1 = acc[1] + b->rout;
+  if (r_in) *r_in = rin;
+  if (r_out) *r_out = rout;
+  return 0;
+}
+
+/* ========================================================================= */
 /* Batched drivers                                                           */
 /* ========================================================================= */
 
@@ -1035,7 +1179,8 @@ int orc_sizeof_dcfr_key(void) { return (int)sizeof(orc_dcfr_key); }
 int orc_sizeof_spec(void) { return (int)sizeof(orc_spec); }
 
 typedef struct {
-  int kind;  /* 0 keygen, 1 eval, 2 full, 3 rescaling gate (keygen + both parties' evaluation) */
+  int kind;  /* 0 keygen, 1 eval, 2 full, 3 rescaling gate (keygen + both parties' evaluation),
+                4 literal lookup + Horner with Beaver multiplications */
   int shift, radix;
   const orc_spec* S;
   uint8_t seed[16];
@@ -1048,6 +1193,8 @@ typedef struct {
   const uint64_t* xhat;
   const int64_t* x;
   uint64_t *y0, *y1, *z0, *z1;
+  uint64_t *c0, *c1;
+  int status;
 } job_t;
 
 uint64_t orc_aes_blocks(void) { return __atomic_load_n(&g_aes_blocks, __ATOMIC_RELAXED); }
@@ -1057,8 +1204,25 @@ static void* run_job(void* arg) {
   tl_aes_blocks = 0;
   orc_aes_sched ks;
   orc_seed_sched(J->seed, &ks);
+  orc_lit_key *la = 0, *lb = 0;
+  if (J->kind == 4) {
+    la = (orc_lit_key*)malloc(sizeof *la);
+    lb = (orc_lit_key*)malloc(sizeof *lb);
+    if (!la || !lb) {
+      free(la);
+      free(lb);
+      J->status = -1;
+      return 0;
+    }
+  }
   for (int64_t i = J->lo; i < J->hi; i++) {
-    if (J->kind == 0) {
+    if (J->kind == 4) {
+      const int p = J->S->p;
+      if (lit_full_elem(J->S, &ks, (uint64_t)J->elems[i], J->x[i], la, lb, J->c0 ? J->c0 + i * p : 0,
+                        J->c1 ? J->c1 + i * p : 0, &J->y0[i], &J->y1[i], J->r_in ? &J->r_in[i] : 0,
+                        J->r_out ? &J->r_out[i] : 0))
+        J->status = -1;
+    } else if (J->kind == 0) {
       orc_keygen_elem(J->S, &ks, (uint64_t)J->elems[i], &J->k0[i], &J->k1[i], &J->r_in[i], &J->r_out[i]);
     } else if (J->kind == 1) {
       orc_eval_elem(J->b, J->S, &J->K[i], J->xhat[i], &J->y0[i], &J->z0[i]);
@@ -1080,6 +1244,8 @@ static void* run_job(void* arg) {
       orc_eval_elem(1, J->S, &b, xh, &J->y1[i], &J->z1[i]);
     }
   }
+  free(la);
+  free(lb);
   __atomic_fetch_add(&g_aes_blocks, tl_aes_blocks, __ATOMIC_RELAXED);
   return 0;
 }
@@ -1096,8 +1262,12 @@ static int run_jobs(job_t proto, int64_t count, int threads) {
     jobs[t].hi = count * (t + 1) / threads;
     if (pthread_create(&th[t], 0, run_job, &jobs[t]) != 0) return -1;
   }
-  for (int t = 0; t < threads; t++) pthread_join(th[t], 0);
-  return threads;
+  int bad = 0;
+  for (int t = 0; t < threads; t++) {
+    pthread_join(th[t], 0);
+    if (jobs[t].status) bad = 1;
+  }
+  return bad ? -1 : threads;
 }
 
 int orc_keygen_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
@@ -1138,5 +1308,16 @@ int orc_trunc_batch(int s, int r, const uint8_t seed[16], const int64_t* elems, 
   memset(&J, 0, sizeof J);
   J.kind = 3; J.shift = s; J.radix = r; memcpy(J.seed, seed, 16); J.elems = elems;
   J.r_in = (uint64_t*)r_in; J.xhat = yhat; J.y0 = z0; J.y1 = z1; J.r_out = r_out;
+  return run_jobs(J, count, threads);
+}
+
+int orc_lit_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
+                  const int64_t* x, uint64_t* coef0, uint64_t* coef1, uint64_t* y0, uint64_t* y1,
+                  uint64_t* r_in, uint64_t* r_out, int threads) {
+  if (S->lookup_r < 2 || S->lookup_r > 4) return -3;
+  job_t J;
+  memset(&J, 0, sizeof J);
+  J.kind = 4; J.S = S; memcpy(J.seed, seed, 16); J.elems = elems; J.x = x;
+  J.c0 = coef0; J.c1 = coef1; J.y0 = y0; J.y1 = y1; J.r_in = r_in; J.r_out = r_out;
   return run_jobs(J, count, threads);
 }

@@ -227,4 +227,61 @@ int orc_trunc_batch(int s, int r, const uint8_t seed[16], const int64_t* elems, 
  * Writes B[0..M] and ord[0..M-1] (B needs room for m + 2 entries); returns M. */
 int orc_protocol3(int n, const uint64_t* alpha, int m, uint64_t r, uint64_t* B, int32_t* ord);
 
+/* ---- literal interval lookup (Definition "Interval lookup with vector payload",
+ * built as the compilation protocol's steps (1) and (5) state it) ------------- */
+/* For the lookup view v = (xhat + lookup_c) mod 2^n and the element's mask,
+ * the partition (B, ord) of v-space from orc_protocol3 and payload v_j = the
+ * ring coefficients of piece ord_j (x-space, lowest degree first):
+ * LUT(v) = v_{M-1} + sum_{j=1}^{M-1} (v_{j-1} - v_j) 1[v < B_j], one vector
+ * DCF (2^r children per level) per inner boundary.  Randomness R(e, ., .) of
+ * the dealer seed: 0 -> r_in, r_out; 1 -> party 0's r_out share; 200 ->
+ * party 0's r_in share; 201 / 202 (ctr j) -> roots of DCF j; 203 + k
+ * (ctr 64 j + level) -> its on-path corrections; 210, 211 -> party 0's
+ * share of v_{M-1}. */
+typedef struct {
+  int32_t M;                  /* intervals after padding; M - 1 DCFs */
+  orc_dcfr_key dcf[ORC_MAXM]; /* DCF of boundary B_j at index j - 1 */
+  uint64_t base[ORC_MAXP];    /* additive share of v_{M-1} */
+  uint64_t rin, rout;         /* additive shares of r_in and r_out */
+} orc_lit_key;
+
+int orc_lit_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e, orc_lit_key* k0,
+                        orc_lit_key* k1, uint64_t* r_in, uint64_t* r_out);
+/* Party b's additive shares of the active piece's coefficients (p words) and
+ * of x = xhat - r_in. */
+void orc_lit_eval_elem(int b, const orc_spec* S, const orc_lit_key* K, uint64_t xhat, uint64_t* coef,
+                       uint64_t* x_share);
+
+/* ---- post-processing subprotocols (Sec. "Standard Preprocessing Subprotocols",
+ * Sec. "Mixed-Domain Conversions") ------------------------------------------ */
+/* Beaver triple for multiplication `step` of element e: a, b uniform, c = a b
+ * mod 2^64, additively shared.  R(e, 220, step) -> (a, b); R(e, 221, step)
+ * -> party 0's shares of (a, b); R(e, 222, step).lo -> party 0's share of c. */
+void orc_triple(const orc_aes_sched* kseed, uint64_t e, int step, uint64_t a[2], uint64_t b[2], uint64_t c[2]);
+/* Party `party`'s share of u v from the opened d = u - a and e = v - b. */
+uint64_t orc_beaver_mul(int party, uint64_t d, uint64_t e, uint64_t a, uint64_t b, uint64_t c);
+/* AND triple for word w (64 independent bits): a, b uniform, c = a & b,
+ * XOR-shared.  R(w, 230, step) -> (a, b); R(w, 231, step) -> party 0's
+ * shares of (a, b); R(w, 232, step).lo -> party 0's share of c. */
+void orc_and_triple(const orc_aes_sched* kseed, uint64_t w, int step, uint64_t a[2], uint64_t b[2], uint64_t c[2]);
+/* Party `party`'s XOR share of x & y from the opened d = x ^ a, e = y ^ b. */
+uint64_t orc_and(int party, uint64_t d, uint64_t e, uint64_t a, uint64_t b, uint64_t c);
+/* B2A randomness for element e: a uniform bit t, XOR-shared (t_0 from
+ * R(e, 241, step).lo bit 0) and additively shared (T_0 = R(e, 241, step).hi),
+ * t = R(e, 240, step).lo bit 0. */
+void orc_b2a_rand(const orc_aes_sched* kseed, uint64_t e, int step, uint64_t tbit[2], uint64_t T[2]);
+/* Party `party`'s additive share of bit z from the opened c = z ^ t:
+ * z = c + (1 - 2c) t. */
+uint64_t orc_b2a(int party, uint64_t c, uint64_t T);
+
+/* The paper's lookup-plus-post-processing pipeline for `count` elements:
+ * literal lookup keys, both parties' coefficient shares at xhat = x + r_in,
+ * then Horner's rule on the shares with one Beaver multiplication per degree
+ * (triple `step` t of element e for the t-th multiplication, openings between
+ * the parties), plus the r_out shares: y0 + y1 = P(x) + r_out.  coef0 / coef1:
+ * count * p words (element-major), may be NULL. */
+int orc_lit_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
+                  const int64_t* x, uint64_t* coef0, uint64_t* coef1, uint64_t* y0, uint64_t* y1,
+                  uint64_t* r_in, uint64_t* r_out, int threads);
+
 #endif
