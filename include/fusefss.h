@@ -378,6 +378,77 @@ int fss_aes_variants(void);
 int fss_autotune_radix(fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, const char* cache_path,
                        int32_t* best_bits);
 
+/* ---- the literal interval lookup (Definition "Interval lookup with vector
+ * payload"; Appendix "Full Compilation Protocol", Protocol "Compile a scalar
+ * gate instance to two backend primitive instances", steps (1) and (5)) ----
+ *
+ * The lookup as the compilation protocol builds it, for comparison with the
+ * single-key lookup of fss_keygen / fss_eval: per element, the partition of
+ * the lookup view v = (xhat + c) mod 2^n translated by the mask, padded to
+ * M = min(m + 1, 2^n) intervals, one vector DCF (2^r children per level, the
+ * spec's lookup radix) per inner boundary B_j with payload v_{j-1} - v_j,
+ * and shares of v_{M-1}; v_j is the ring coefficient vector (x-space, p
+ * words) of the piece that interval j maps to.  Evaluation returns additive
+ * shares of the active piece's coefficients (the constant term's share
+ * includes the party's share of r_out) and of x = xhat - r_in; the
+ * polynomial is then evaluated on shares by Horner's rule with one Beaver
+ * multiplication per degree (fss_triples, fss_beaver_mask, fss_open,
+ * fss_beaver_mul).  Keys are one-time like the operator gate's.  Built for
+ * AES table layout 1. */
+
+/* Bytes of one party's literal key buffer for n_elems elements. */
+int fss_lit_key_bytes(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, size_t* bytes);
+/* Dealer: both parties' literal keys (key1 may be NULL), with r_in and r_out
+ * (device, n_elems u64 each, may be NULL) drawn exactly as fss_keygen draws
+ * them from the same seed. */
+int fss_lit_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, const uint8_t* seed, int64_t n_elems,
+                   void* key0, void* key1, uint64_t* r_in, uint64_t* r_out, void* stream);
+/* Party `party`'s shares: coef (device, p * n_elems u64; coefficient k of
+ * element e at k * n_elems + e) and x_share (device, n_elems u64). */
+int fss_lit_eval(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems, uint64_t* coef,
+                 uint64_t* x_share, void* stream);
+
+/* ---- post-processing subprotocols (Sec. "Standard Preprocessing
+ * Subprotocols": Beaver multiplication over Z_2^64, AND on XOR shares; Sec.
+ * "Mixed-Domain Conversions": B2A) -------------------------------------------
+ *
+ * All buffers are device arrays.  The dealer's correlations are drawn from
+ * its 16-byte seed, per element (or 64-bit word) index i and `step` in
+ * [0, 65535], so that several gates can use one seed.  A party's local steps
+ * run before and after the opening; fss_open (additive) and fss_xopen (XOR)
+ * are the openings, both parties' shares being on this device. */
+
+/* Beaver triples for n products: a, b uniform, c = a b, additively shared. */
+int fss_triples(const uint8_t* seed, int64_t n, int32_t step, uint64_t* a0, uint64_t* b0, uint64_t* c0,
+                uint64_t* a1, uint64_t* b1, uint64_t* c1, void* stream);
+/* A party's masked shares d = u - a and e = v - b (to be opened). */
+int fss_beaver_mask(const uint64_t* u, const uint64_t* v, const uint64_t* a, const uint64_t* b, int64_t n,
+                    uint64_t* d, uint64_t* e, void* stream);
+/* A party's share of u v from the openings d, e: c + d b + e a (+ d e for
+ * party 0), plus `add` (a share to add, may be NULL). */
+int fss_beaver_mul(int32_t party, const uint64_t* d, const uint64_t* e, const uint64_t* a, const uint64_t* b,
+                   const uint64_t* c, const uint64_t* add, int64_t n, uint64_t* z, void* stream);
+/* AND triples for `words` 64-bit words of independent bits, XOR-shared. */
+int fss_and_triples(const uint8_t* seed, int64_t words, int32_t step, uint64_t* a0, uint64_t* b0, uint64_t* c0,
+                    uint64_t* a1, uint64_t* b1, uint64_t* c1, void* stream);
+/* d = x ^ a and, if y is not NULL, e = y ^ b (a party's masked bit words). */
+int fss_xor_mask(const uint64_t* x, const uint64_t* a, const uint64_t* y, const uint64_t* b, int64_t words,
+                 uint64_t* d, uint64_t* e, void* stream);
+/* The XOR opening: out = s0 ^ s1. */
+int fss_xopen(const uint64_t* s0, const uint64_t* s1, int64_t words, uint64_t* out, void* stream);
+/* A party's XOR share of x & y from the openings d, e: c ^ (d & b) ^ (e & a)
+ * (^ d & e for party 0). */
+int fss_and(int32_t party, const uint64_t* d, const uint64_t* e, const uint64_t* a, const uint64_t* b,
+            const uint64_t* c, int64_t words, uint64_t* z, void* stream);
+/* B2A correlation for n bits: a uniform bit t per element, XOR-shared in
+ * bit words t0 / t1 (ceil(n / 64) words, bit i of word i / 64) and
+ * additively shared in T0 / T1 (n words). */
+int fss_b2a_rand(const uint8_t* seed, int64_t n, int32_t step, uint64_t* t0, uint64_t* t1, uint64_t* T0,
+                 uint64_t* T1, void* stream);
+/* A party's additive share of bit z from the opened c = z ^ t (bit words):
+ * z = c + (1 - 2c) t. */
+int fss_b2a(int32_t party, const uint64_t* c, const uint64_t* T, int64_t n, uint64_t* out, void* stream);
+
 /* ---- status ------------------------------------------------------------ */
 
 /* Synchronise `stream`, then read and clear the device status word.

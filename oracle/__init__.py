@@ -414,9 +414,9 @@ def trunc(shift: int, seed: int, elems, r_in, yhat, lookup_r: int = 3, threads: 
 def lit(S: Spec, seed: int, elems, x, threads: int = 0):
     """Literal interval lookup (one vector DCF per inner boundary of the
     translated partition), both parties' coefficient shares at
-    xhat = x + r_in, then Horner's rule with Beaver multiplications.
-    Returns dict(c0, c1 (count x p), y0, y1, r_in, r_out) with
-    y0 + y1 = P(x) + r_out."""
+    xhat = x + r_in (the constant term's shares carry the r_out shares), then
+    Horner's rule with Beaver multiplications.  Returns dict(c0, c1
+    (count x p), y0, y1, r_in, r_out) with y0 + y1 = P(x) + r_out."""
     elems = np.ascontiguousarray(elems, dtype=np.int64)
     x = np.ascontiguousarray(x, dtype=np.int64)
     cnt, p = len(elems), S.p

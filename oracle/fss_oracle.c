@@ -1074,6 +1074,9 @@ void orc_lit_eval_elem(int b, const orc_spec* S, const orc_lit_key* K, uint64_t 
     orc_dcfr_eval(b, &K->dcf[j - 1], v, out);
     for (int k = 0; k < S->p; k++) coef[k] += out[k];
   }
+  /* the output mask enters through the constant term: Horner's rule on these
+   * shares then opens to P(x) + r_out */
+  coef[0] += K->rout;
   *x_share = b == 0 ? xhat - K->rin : (uint64_t)0 - K->rin;
 }
 
@@ -1157,8 +1160,8 @@ static int lit_full_elem(const orc_spec* S, const orc_aes_sched* ks, uint64_t e,
       c0[k] = c[0][k];
       c1[k] = c[1][k];
     }
-  *y0 = acc[0] + a->rout;
-  *y1 = acc[1] + b->rout;
+  *y0 = acc[0];
+  *y1 = acc[1];
   if (r_in) *r_in = rin;
   if (r_out) *r_out = rout;
   return 0;

@@ -247,8 +247,9 @@ typedef struct {
 
 int orc_lit_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e, orc_lit_key* k0,
                         orc_lit_key* k1, uint64_t* r_in, uint64_t* r_out);
-/* Party b's additive shares of the active piece's coefficients (p words) and
- * of x = xhat - r_in. */
+/* Party b's additive shares of the active piece's coefficients (p words; the
+ * constant term's share includes the party's r_out share) and of
+ * x = xhat - r_in. */
 void orc_lit_eval_elem(int b, const orc_spec* S, const orc_lit_key* K, uint64_t xhat, uint64_t* coef,
                        uint64_t* x_share);
 
@@ -278,8 +279,9 @@ uint64_t orc_b2a(int party, uint64_t c, uint64_t T);
  * literal lookup keys, both parties' coefficient shares at xhat = x + r_in,
  * then Horner's rule on the shares with one Beaver multiplication per degree
  * (triple `step` t of element e for the t-th multiplication, openings between
- * the parties), plus the r_out shares: y0 + y1 = P(x) + r_out.  coef0 / coef1:
- * count * p words (element-major), may be NULL. */
+ * the parties); the r_out shares ride in the constant term, so
+ * y0 + y1 = P(x) + r_out.  coef0 / coef1: count * p words (element-major),
+ * may be NULL. */
 int orc_lit_batch(const orc_spec* S, const uint8_t seed[16], const int64_t* elems, int64_t count,
                   const int64_t* x, uint64_t* coef0, uint64_t* coef1, uint64_t* y0, uint64_t* y1,
                   uint64_t* r_in, uint64_t* r_out, int threads);

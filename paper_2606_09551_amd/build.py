@@ -14,7 +14,7 @@ OBJ_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libfusefss.so")
 
 SOURCES = ["fss_api.cpp", "fss_launch.hip", "fss_noalloc.hip", "fss_kernels_v0.hip", "fss_kernels_v1.hip",
-           "fss_kernels_v2.hip", "fss_kernels_v3.hip", "fss_kernels_v4.hip"]
+           "fss_kernels_v2.hip", "fss_kernels_v3.hip", "fss_kernels_v4.hip", "fss_phi.hip"]
 ARCH = os.environ.get("FSS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          # packed FP32 instructions are disabled for all device code

@@ -115,6 +115,9 @@ struct QSpec {
   Layout layout{};
   KeyHeader hdr{};
   std::map<int, uint8_t*> dev_hdr;  // device -> header template
+  KeyHeader lit_hdr{};              // the literal lookup's header (built on first use)
+  bool lit_ready = false;
+  std::map<int, uint8_t*> dev_lit_hdr;
 };
 
 int64_t ceil_clamped(double v, int64_t lo, int64_t hi) {
@@ -401,6 +404,56 @@ int device_header(const fss_spec* Sc, QSpec* q, uint8_t** out) {
   return FSS_OK;
 }
 
+// Header of the literal lookup of a quantised spec: the operator header's
+// spec fields, kind kGateLiteral, M = min(m + 1, 2^n) intervals, the literal
+// tile layout and the pieces' ring coefficients; uploaded once per device.
+int literal_header(const fss_spec* Sc, QSpec* q, uint8_t** dev_out, KeyHeader* host_out) {
+  fss_spec* S = const_cast<fss_spec*>(Sc);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (!q->lit_ready) {
+    KeyHeader h = q->hdr;
+    const int n = (int)h.n, m = (int)h.m, p = (int)h.p, r = (int)h.lookup_r;
+    const uint64_t N = (uint64_t)1 << n;
+    const int M = (uint64_t)(m + 1) < N ? m + 1 : (int)N;
+    const Layout L = make_literal_layout(n, p, r, M);
+    h.kind = kGateLiteral;
+    h.lit_M = (uint32_t)M;
+    h.off_lrin = L.off_lrin;
+    h.off_crout = L.off_crout;
+    h.off_lbase = L.off_lbase;
+    h.off_croot = L.off_croot;
+    h.off_crec = L.off_crec;
+    h.rec_bytes = L.rec_bytes;
+    h.dcf_bytes = L.dcf_bytes;
+    h.off_seen = L.off_seen;
+    h.off_sentinel = L.off_sentinel;
+    h.tile_bytes = L.tile_bytes;
+    for (int i = 0; i < kMaxM; ++i)
+      for (int k = 0; k < kMaxP; ++k) h.lcoef[i][k] = i < m && k < p ? q->coef[i][k] : 0;
+    q->lit_hdr = h;
+    q->lit_ready = true;
+  }
+  if (host_out) *host_out = q->lit_hdr;
+  if (!dev_out) return FSS_OK;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  auto it = q->dev_lit_hdr.find(dev);
+  if (it != q->dev_lit_hdr.end()) {
+    *dev_out = it->second;
+    return FSS_OK;
+  }
+  uint8_t* d = nullptr;
+  hipStream_t up;
+  int rc = aux_stream(&up);
+  if (rc) return rc;
+  HIP_TRY(hipMalloc(&d, sizeof(KeyHeader)), "hipMalloc(literal header)");
+  HIP_TRY(hipMemcpyAsync(d, &q->lit_hdr, sizeof(KeyHeader), hipMemcpyHostToDevice, up), "hipMemcpyAsync(header)");
+  HIP_TRY(hipStreamSynchronize(up), "hipStreamSynchronize(header)");
+  q->dev_lit_hdr[dev] = d;
+  *dev_out = d;
+  return FSS_OK;
+}
+
 // The dealer's randomness R(e, purpose, ctr) is AES-128 keyed by the whole
 // 16-byte seed, so the masks carry the full security parameter.
 void seed_round_keys(const uint8_t seed[16], uint32_t rk[44]) { expand_key(kAes.sbox, seed, rk); }
@@ -641,6 +694,127 @@ int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int
   *aes_blocks = (prg_aes + rnd) * (double)n_elems;
   *table_lookups = (prg_lk + 160.0 * rnd) * (double)n_elems;
   return FSS_OK;
+}
+
+// ---- literal interval lookup ------------------------------------------------
+
+int fss_lit_key_bytes(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_t n_elems, size_t* bytes) {
+  if (!spec || !bytes) return fail(FSS_E_ARG, "NULL argument");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  std::shared_ptr<QSpec> q;
+  int rc = get_qspec(spec, n_bits, frac_bits, &q);
+  if (rc) return rc;
+  KeyHeader h;
+  if ((rc = literal_header(spec, q.get(), nullptr, &h))) return rc;
+  *bytes = (size_t)(kHeaderBytes + (((uint64_t)n_elems + kTile - 1) / kTile) * h.tile_bytes);
+  return FSS_OK;
+}
+
+int fss_lit_keygen(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, const uint8_t* seed, int64_t n_elems,
+                   void* key0, void* key1, uint64_t* r_in, uint64_t* r_out, void* stream) {
+  if (!spec || !key0 || !seed) return fail(FSS_E_ARG, "spec/seed/key0 NULL");
+  if (n_elems < 0) return fail(FSS_E_ARG, "n_elems < 0");
+  std::shared_ptr<QSpec> q;
+  int rc = get_qspec(spec, n_bits, frac_bits, &q);
+  if (rc) return rc;
+  uint8_t* dh = nullptr;
+  if ((rc = literal_header(spec, q.get(), &dh, nullptr))) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const uint64_t tiles = ((uint64_t)n_elems + kTile - 1) / kTile;
+  HIP_TRY(launch_header_init((uint8_t*)key0, dh, n_elems, tiles, 0, st), "header_init");
+  if (key1) HIP_TRY(launch_header_init((uint8_t*)key1, dh, n_elems, tiles, 1, st), "header_init");
+  if (tiles == 0) return FSS_OK;
+  KgArgs ga{};
+  seed_round_keys(seed, ga.rk.w);
+  ga.n_elems = n_elems;
+  ga.n_tiles = tiles;
+  HIP_TRY(launch_lit_keygen(q->p, (int)q->hdr.lookup_r, reinterpret_cast<const KeyHeader*>(dh), ga, (uint8_t*)key0,
+                            (uint8_t*)key1, r_in, r_out, st),
+          "literal keygen launch");
+  return FSS_OK;
+}
+
+int fss_lit_eval(int32_t party, const void* keys, const uint64_t* xhat, int64_t n_elems, uint64_t* coef,
+                 uint64_t* x_share, void* stream) {
+  int rc = check_party(party);
+  if (rc) return rc;
+  if (!keys || n_elems < 0 || (n_elems > 0 && (!xhat || !coef || !x_share))) return fail(FSS_E_ARG, "bad arguments");
+  int* st = nullptr;
+  if ((rc = device_status_ptr(&st))) return rc;
+  HIP_TRY(launch_lit_eval(party, (const uint8_t*)keys, xhat, n_elems, coef, x_share, st, (hipStream_t)stream),
+          "literal eval launch");
+  return FSS_OK;
+}
+
+// ---- post-processing subprotocols -------------------------------------------
+
+static int correlations(int kind, const uint8_t* seed, int64_t n, int32_t step, uint64_t* a0, uint64_t* b0,
+                        uint64_t* c0, uint64_t* a1, uint64_t* b1, uint64_t* c1, void* stream) {
+  if (!seed || n < 0 || step < 0 || step > 0xffff) return fail(FSS_E_ARG, "bad arguments");
+  if (n > 0 && (!a0 || !c0 || !a1 || !c1 || (kind != 2 && (!b0 || !b1)))) return fail(FSS_E_ARG, "NULL buffer");
+  RoundKeys rk{};
+  seed_round_keys(seed, rk.w);
+  HIP_TRY(launch_correlations(rk, kind, n, (uint32_t)step, a0, b0, c0, a1, b1, c1, (hipStream_t)stream),
+          "correlation launch");
+  return FSS_OK;
+}
+
+static int phi_step(int kind, int party, const uint64_t* u, const uint64_t* v, const uint64_t* a, const uint64_t* b,
+                    const uint64_t* c, const uint64_t* add, int64_t n, uint64_t* d, uint64_t* e, uint64_t* z,
+                    void* stream) {
+  if (n < 0) return fail(FSS_E_ARG, "n < 0");
+  if (party != 0 && party != 1) return fail(FSS_E_PARTY, "party must be 0 or 1");
+  HIP_TRY(launch_phi(kind, party, u, v, a, b, c, add, n, d, e, z, (hipStream_t)stream), "subprotocol launch");
+  return FSS_OK;
+}
+
+int fss_triples(const uint8_t* seed, int64_t n, int32_t step, uint64_t* a0, uint64_t* b0, uint64_t* c0, uint64_t* a1,
+                uint64_t* b1, uint64_t* c1, void* stream) {
+  return correlations(0, seed, n, step, a0, b0, c0, a1, b1, c1, stream);
+}
+
+int fss_beaver_mask(const uint64_t* u, const uint64_t* v, const uint64_t* a, const uint64_t* b, int64_t n,
+                    uint64_t* d, uint64_t* e, void* stream) {
+  if (n > 0 && (!u || !v || !a || !b || !d || !e)) return fail(FSS_E_ARG, "NULL buffer");
+  return phi_step(0, 0, u, v, a, b, nullptr, nullptr, n, d, e, nullptr, stream);
+}
+
+int fss_beaver_mul(int32_t party, const uint64_t* d, const uint64_t* e, const uint64_t* a, const uint64_t* b,
+                   const uint64_t* c, const uint64_t* add, int64_t n, uint64_t* z, void* stream) {
+  if (n > 0 && (!d || !e || !a || !b || !c || !z)) return fail(FSS_E_ARG, "NULL buffer");
+  return phi_step(1, party, d, e, a, b, c, add, n, nullptr, nullptr, z, stream);
+}
+
+int fss_and_triples(const uint8_t* seed, int64_t words, int32_t step, uint64_t* a0, uint64_t* b0, uint64_t* c0,
+                    uint64_t* a1, uint64_t* b1, uint64_t* c1, void* stream) {
+  return correlations(1, seed, words, step, a0, b0, c0, a1, b1, c1, stream);
+}
+
+int fss_xor_mask(const uint64_t* x, const uint64_t* a, const uint64_t* y, const uint64_t* b, int64_t words,
+                 uint64_t* d, uint64_t* e, void* stream) {
+  if (words > 0 && (!x || !a || !d || (y && (!b || !e)))) return fail(FSS_E_ARG, "NULL buffer");
+  return phi_step(2, 0, x, y, a, b, nullptr, nullptr, words, d, e, nullptr, stream);
+}
+
+int fss_xopen(const uint64_t* s0, const uint64_t* s1, int64_t words, uint64_t* out, void* stream) {
+  if (words > 0 && (!s0 || !s1 || !out)) return fail(FSS_E_ARG, "NULL buffer");
+  return phi_step(4, 0, s0, s1, nullptr, nullptr, nullptr, nullptr, words, nullptr, nullptr, out, stream);
+}
+
+int fss_and(int32_t party, const uint64_t* d, const uint64_t* e, const uint64_t* a, const uint64_t* b,
+            const uint64_t* c, int64_t words, uint64_t* z, void* stream) {
+  if (words > 0 && (!d || !e || !a || !b || !c || !z)) return fail(FSS_E_ARG, "NULL buffer");
+  return phi_step(3, party, d, e, a, b, c, nullptr, words, nullptr, nullptr, z, stream);
+}
+
+int fss_b2a_rand(const uint8_t* seed, int64_t n, int32_t step, uint64_t* t0, uint64_t* t1, uint64_t* T0,
+                 uint64_t* T1, void* stream) {
+  return correlations(2, seed, n, step, t0, nullptr, T0, t1, nullptr, T1, stream);
+}
+
+int fss_b2a(int32_t party, const uint64_t* c, const uint64_t* T, int64_t n, uint64_t* out, void* stream) {
+  if (n > 0 && (!c || !T || !out)) return fail(FSS_E_ARG, "NULL buffer");
+  return phi_step(5, party, nullptr, nullptr, T, nullptr, c, nullptr, n, nullptr, nullptr, out, stream);
 }
 
 }  // extern "C"

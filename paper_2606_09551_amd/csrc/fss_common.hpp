@@ -97,8 +97,8 @@ constexpr AesConst kAes = make_aes_const();
 //   value arrays would.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
-constexpr uint32_t kVersion = 9;
-constexpr uint32_t kGateOperator = 0, kGateRescale = 1;
+constexpr uint32_t kVersion = 10;
+constexpr uint32_t kGateOperator = 0, kGateRescale = 1, kGateLiteral = 2;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -115,7 +115,7 @@ struct KeyHeader {
   uint32_t top_blocks;                     // aligned blocks of lookup points walked through the shared levels (2..4)
   uint32_t lookup_c;                       // view shift of call 2: v = (xhat + lookup_c) mod 2^n
   uint32_t is_int;                         // 1: integer spec over canonical representatives
-  uint32_t kind;                           // kGateOperator or kGateRescale
+  uint32_t kind;                           // kGateOperator, kGateRescale or kGateLiteral
   uint32_t shift;                          // rescaling gate: bits shifted out (its DCF's domain, = n)
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
@@ -128,6 +128,12 @@ struct KeyHeader {
   uint64_t off_tk0, off_tk1;               // rescaling gate: shares of its two constants
   uint64_t off_seen, off_sentinel;         // one-time use: x-hat each element was first evaluated at
                                            // (the tile's sentinel until then), the sentinel
+  // literal lookup: intervals after padding, the r_in shares and the shares
+  // of the last interval's payload; DCF j (1 .. lit_M - 1) at off_croot +
+  // (j - 1) dcf_bytes, its records 64 x 16 bytes after its roots
+  uint32_t lit_M, lit_pad;
+  uint64_t off_lrin, off_lbase, dcf_bytes;
+  uint64_t lcoef[kMaxM][kMaxP];            // literal lookup: ring coefficients of each piece
   uint64_t aprime[kMaxM + 1];              // offset-binary boundaries
   // Combination table: q_j = sum_i sum_k tab[i][j][k] * G_i[k] with
   // G_0 = rho share, G_i = g_i (i >= 1); see the lookup kernel.
@@ -144,6 +150,7 @@ struct Layout {
   uint64_t atom_off[kMaxAtoms];
   uint64_t off_w, off_croot, off_crec, rec_bytes, off_crho, off_crout;
   uint64_t off_seen, off_sentinel;
+  uint64_t off_lrin, off_lbase, dcf_bytes;
   uint64_t tile_bytes;
 };
 
@@ -181,6 +188,28 @@ FSS_HD inline Layout make_rescale_layout(int shift, int r) {
   L.off_crec = o;  o += levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
   L.off_crho = o;  o += kTile * 8;   // k0 shares
   L.off_crout = o; o += kTile * 8;   // k1 shares
+  L.off_seen = o;  o += kTile * 8;
+  L.off_sentinel = o;  o += 8;
+  L.tile_bytes = (o + 255) & ~(uint64_t)255;
+  return L;
+}
+
+// A literal lookup's tile (M intervals after padding): r_in shares[64],
+// r_out shares[64], shares of the last interval's payload [p][64], then
+// M - 1 vector DCFs of 2^r children per level, each root[64] |
+// rec[L][2^r][64] (16 + 8p bytes), then the one-time record.
+FSS_HD inline Layout make_literal_layout(int n, int p, int r, int M) {
+  Layout L{};
+  uint64_t o = 0;
+  L.off_lrin = o;  o += kTile * 8;
+  L.off_crout = o; o += kTile * 8;
+  L.off_lbase = o; o += (uint64_t)p * kTile * 8;
+  const uint64_t levels = (uint64_t)(n + r - 1) / r;
+  L.rec_bytes = 16 + 8 * (uint64_t)p;
+  L.dcf_bytes = (uint64_t)kTile * 16 + levels * ((uint64_t)1 << r) * kTile * L.rec_bytes;
+  L.off_croot = o;
+  L.off_crec = o + (uint64_t)kTile * 16;
+  o += (uint64_t)(M - 1) * L.dcf_bytes;
   L.off_seen = o;  o += kTile * 8;
   L.off_sentinel = o;  o += 8;
   L.tile_bytes = (o + 255) & ~(uint64_t)255;

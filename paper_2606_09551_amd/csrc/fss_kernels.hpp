@@ -100,6 +100,20 @@ hipError_t launch_rescale_eval(int variant, int party, const uint8_t* keys, cons
                                uint64_t* z, int* status, int cus, hipStream_t st);
 // yhat = y0 + y1 (the opening of two additive shares, both on this device).
 hipError_t launch_open(const uint64_t* y0, const uint64_t* y1, int64_t n, uint64_t* yhat, hipStream_t st);
+// The literal interval lookup (table layout 1) and the post-processing
+// subprotocols (fss_phi.hip).
+hipError_t launch_lit_keygen(int p, int r, const KeyHeader* dev_hdr, const KgArgs& ga, uint8_t* key0, uint8_t* key1,
+                             uint64_t* r_in, uint64_t* r_out, hipStream_t st);
+hipError_t launch_lit_eval(int party, const uint8_t* keys, const uint64_t* xhat, int64_t n, uint64_t* coef,
+                           uint64_t* x_share, int* status, hipStream_t st);
+// kind 0: Beaver triples, 1: AND triples, 2: B2A bits (a0 / a1: XOR-share
+// words, c0 / c1: additive shares)
+hipError_t launch_correlations(const RoundKeys& rk, int kind, int64_t n, uint32_t step, uint64_t* a0, uint64_t* b0,
+                               uint64_t* c0, uint64_t* a1, uint64_t* b1, uint64_t* c1, hipStream_t st);
+// a party's local step of a subprotocol (see k_phi)
+hipError_t launch_phi(int kind, int party, const uint64_t* u, const uint64_t* v, const uint64_t* a,
+                      const uint64_t* b, const uint64_t* c, const uint64_t* add, int64_t n, uint64_t* d,
+                      uint64_t* e, uint64_t* z, hipStream_t st);
 int variant_block(int variant);
 int variant_lds_bytes(int variant);
 

@@ -506,15 +506,21 @@ struct VState {  // a node of the GGM tree: seed, control bit, partial sum
   uint64_t V[P];
 };
 
+// `rootp`: the DCF's root seeds (16 bytes per lane) in the tile.
 template <int P>
-__device__ __forceinline__ VState<P> vroot(GHdr h, const uint8_t* tile, int lane, int b) {
+__device__ __forceinline__ VState<P> vroot_at(const uint8_t* rootp, int lane, int b) {
   VState<P> st;
-  const uint4 r = ld16(tile + h->off_croot + lane * 16);
+  const uint4 r = ld16(rootp + lane * 16);
   st.s[0] = r.x; st.s[1] = r.y; st.s[2] = r.z; st.s[3] = r.w;
   st.t = (uint32_t)b;
 #pragma unroll
   for (int q = 0; q < P; ++q) st.V[q] = 0;
   return st;
+}
+
+template <int P>
+__device__ __forceinline__ VState<P> vroot(GHdr h, const uint8_t* tile, int lane, int b) {
+  return vroot_at<P>(tile + h->off_croot, lane, b);
 }
 
 // The value of child d: words d P .. d P + P - 1 of the stream H(s, 2^R),
@@ -543,14 +549,15 @@ __device__ __forceinline__ uint64_t value_word(const uint32_t (&o)[O][4], uint32
 // stream (value_word).  The last level adds the child's value only: nothing
 // is walked below it, so its seed and control bit (the block H(s, d)) are not
 // computed.
+// `recbase`: the DCF's records in the tile; n: its input bits.
 template <int P, int R, class TB>
-__device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
-                                         uint32_t x, int i0, int i1, VState<P>& st) {
+__device__ __forceinline__ void vec_walk_at(const TB& tb, int n, const uint8_t* recbase, int lane, int b,
+                                            uint32_t x, int i0, int i1, VState<P>& st) {
   constexpr int NB = (P + 1) / 2;
   constexpr uint32_t C = 1u << R;
-  const int L = ((int)h->n + R - 1) / R;
+  const int L = (n + R - 1) / R;
   constexpr uint64_t REC = 16 + 8 * P;
-  const uint8_t* recp = tile + h->off_crec + lane * REC;
+  const uint8_t* recp = recbase + lane * REC;
   const int imid = i1 < L - 1 ? i1 : L - 1;
   for (int i = i0; i < imid; ++i) {
     const uint32_t d = (x >> (R * (L - 1 - i))) & (C - 1u);
@@ -592,6 +599,12 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
       st.V[q] += b ? (0ull - v) : v;
     }
   }
+}
+
+template <int P, int R, class TB>
+__device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
+                                         uint32_t x, int i0, int i1, VState<P>& st) {
+  vec_walk_at<P, R>(tb, (int)h->n, tile + h->off_crec, lane, b, x, i0, i1, st);
 }
 
 // With v = view_{n,c}(xhat) (c = 2^(n-1), the offset-binary view of the signed
@@ -1046,17 +1059,15 @@ __device__ __forceinline__ void gen_z2(const TB& tb, int k, uint64_t alpha, cons
 // [+ beta below alpha's digit]).  Above the last level alpha's child gets
 // random corrections R(e, 69 + k, level), carries the parties on, and
 // updates V_alpha; at the last level it is corrected like the others.
+// The DCF's root seeds and records sit at off_croot / off_crec of the tile;
+// the on-path child's corrections at level i are R(e, pur0 + k, ctr0 + i).
 template <int P, int R, class TB>
-__device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t alpha,
-                                        const uint64_t (&beta)[P], const uint32_t (&r0)[4],
-                                        const uint32_t (&r1)[4], const RoundKeys& rk, uint64_t e,
-                                        uint8_t* k0, uint8_t* k1, int lane) {
+__device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uint64_t off_crec, uint32_t pur0,
+                                           uint32_t ctr0, int n, uint64_t alpha, const uint64_t (&beta)[P],
+                                           const uint32_t (&r0)[4], const uint32_t (&r1)[4], const RoundKeys& rk,
+                                           uint64_t e, uint8_t* k0, uint8_t* k1, int lane) {
   constexpr int NB = (P + 1) / 2;
-  // Header offsets are read before the first key store: the compiler cannot
-  // tell the key stores from header memory, and a header read after a store
-  // would wait for the store to complete.
   constexpr uint64_t REC = 16 + 8 * P;
-  const uint64_t off_croot = h->off_croot, off_crec = h->off_crec;
   constexpr uint32_t C = 1u << R;
   const int L = (n + R - 1) / R;
   uint32_t s[2][4] = {{r0[0] & ~3u, r0[1], r0[2], r0[3]}, {r1[0] & ~3u, r1[1], r1[2], r1[3]}};
@@ -1266,8 +1277,8 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
     {
       uint32_t pur[1 + NB];
 #pragma unroll
-      for (int k = 0; k <= NB; ++k) pur[k] = 69u + k;
-      rand_blks<TB, 1 + NB>(tb, rk, e, pur, (uint32_t)i, kr);
+      for (int k = 0; k <= NB; ++k) pur[k] = pur0 + k;
+      rand_blks<TB, 1 + NB>(tb, rk, e, pur, ctr0 + (uint32_t)i, kr);
     }
     const uint32_t tcw_a = kt[0] ^ kt[1] ^ 1u;
     const uint32_t scw_a[4] = {kr[0][0] & ~3u, kr[0][1], kr[0][2], kr[0][3]};
@@ -1293,6 +1304,19 @@ __device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t al
       t[b] = kt[b] ^ (t[b] & tcw_a);
     }
   }
+}
+
+// The operator's lookup DCF: header offsets, corrections R(e, 69 + k, level).
+// Header offsets are read before the first key store: the compiler cannot
+// tell the key stores from header memory, and a header read after a store
+// would wait for the store to complete.
+template <int P, int R, class TB>
+__device__ __forceinline__ void gen_vec(const TB& tb, GHdr h, int n, uint64_t alpha,
+                                        const uint64_t (&beta)[P], const uint32_t (&r0)[4],
+                                        const uint32_t (&r1)[4], const RoundKeys& rk, uint64_t e,
+                                        uint8_t* k0, uint8_t* k1, int lane) {
+  const uint64_t off_croot = h->off_croot, off_crec = h->off_crec;
+  gen_vec_at<P, R>(tb, off_croot, off_crec, 69u, 0u, n, alpha, beta, r0, r1, rk, e, k0, k1, lane);
 }
 
 template <int P, int R, class TB>

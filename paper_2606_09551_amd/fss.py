@@ -116,6 +116,18 @@ def _load():
         "fss_autotune": [C.POINTER(WorkItem), i32, C.c_char_p, C.POINTER(Tune)],
         "fss_aes_variants": [],
         "fss_autotune_radix": [vp, i32, i32, i64, C.c_char_p, C.POINTER(i32)],
+        "fss_lit_key_bytes": [vp, i32, i32, i64, C.POINTER(C.c_size_t)],
+        "fss_lit_keygen": [vp, i32, i32, C.POINTER(C.c_uint8), i64, vp, vp, vp, vp, vp],
+        "fss_lit_eval": [i32, vp, vp, i64, vp, vp, vp],
+        "fss_triples": [C.POINTER(C.c_uint8), i64, i32, vp, vp, vp, vp, vp, vp, vp],
+        "fss_beaver_mask": [vp, vp, vp, vp, i64, vp, vp, vp],
+        "fss_beaver_mul": [i32, vp, vp, vp, vp, vp, vp, i64, vp, vp],
+        "fss_and_triples": [C.POINTER(C.c_uint8), i64, i32, vp, vp, vp, vp, vp, vp, vp],
+        "fss_xor_mask": [vp, vp, vp, vp, i64, vp, vp, vp],
+        "fss_xopen": [vp, vp, i64, vp, vp],
+        "fss_and": [i32, vp, vp, vp, vp, vp, i64, vp, vp],
+        "fss_b2a_rand": [C.POINTER(C.c_uint8), i64, i32, vp, vp, vp, vp, vp],
+        "fss_b2a": [i32, vp, vp, i64, vp, vp],
         "fss_status": [vp, C.POINTER(i32)],
         "fss_last_error": [],
         "fss_version": [],
@@ -255,6 +267,11 @@ class Spec:
         _check(lib.fss_key_bytes(self.handle, n_bits, frac_bits, n_elems, C.byref(out)))
         return out.value
 
+    def lit_key_bytes(self, n_bits: int, frac_bits: int, n_elems: int) -> int:
+        out = C.c_size_t()
+        _check(lib.fss_lit_key_bytes(self.handle, n_bits, frac_bits, n_elems, C.byref(out)))
+        return out.value
+
 
 def seed_bytes(seed: int):
     """A 128-bit dealer seed as the 16 little-endian bytes fss_keygen takes."""
@@ -281,6 +298,53 @@ def fss_rescale_keygen(shift_bits, lookup_bits, seed, n_elems, r_in, key0, key1,
 
 def fss_rescale_eval(party, keys, yhat, n, z, stream=None):
     _check(lib.fss_rescale_eval(party, _p(keys), _p(yhat), n, _p(z), _stream(stream)))
+
+
+def fss_lit_keygen(spec, n_bits, frac_bits, seed, n_elems, key0, key1, r_in, r_out, stream=None):
+    _check(lib.fss_lit_keygen(spec.handle, n_bits, frac_bits, seed_bytes(seed), n_elems, _p(key0), _p(key1),
+                              _p(r_in), _p(r_out), _stream(stream)))
+
+
+def fss_lit_eval(party, keys, xhat, n, coef, x_share, stream=None):
+    _check(lib.fss_lit_eval(party, _p(keys), _p(xhat), n, _p(coef), _p(x_share), _stream(stream)))
+
+
+def fss_triples(seed, n, step, a0, b0, c0, a1, b1, c1, stream=None):
+    _check(lib.fss_triples(seed_bytes(seed), n, step, _p(a0), _p(b0), _p(c0), _p(a1), _p(b1), _p(c1),
+                           _stream(stream)))
+
+
+def fss_beaver_mask(u, v, a, b, n, d, e, stream=None):
+    _check(lib.fss_beaver_mask(_p(u), _p(v), _p(a), _p(b), n, _p(d), _p(e), _stream(stream)))
+
+
+def fss_beaver_mul(party, d, e, a, b, c, add, n, z, stream=None):
+    _check(lib.fss_beaver_mul(party, _p(d), _p(e), _p(a), _p(b), _p(c), _p(add), n, _p(z), _stream(stream)))
+
+
+def fss_and_triples(seed, words, step, a0, b0, c0, a1, b1, c1, stream=None):
+    _check(lib.fss_and_triples(seed_bytes(seed), words, step, _p(a0), _p(b0), _p(c0), _p(a1), _p(b1), _p(c1),
+                               _stream(stream)))
+
+
+def fss_xor_mask(x, a, y, b, words, d, e, stream=None):
+    _check(lib.fss_xor_mask(_p(x), _p(a), _p(y), _p(b), words, _p(d), _p(e), _stream(stream)))
+
+
+def fss_xopen(s0, s1, words, out, stream=None):
+    _check(lib.fss_xopen(_p(s0), _p(s1), words, _p(out), _stream(stream)))
+
+
+def fss_and(party, d, e, a, b, c, words, z, stream=None):
+    _check(lib.fss_and(party, _p(d), _p(e), _p(a), _p(b), _p(c), words, _p(z), _stream(stream)))
+
+
+def fss_b2a_rand(seed, n, step, t0, t1, T0, T1, stream=None):
+    _check(lib.fss_b2a_rand(seed_bytes(seed), n, step, _p(t0), _p(t1), _p(T0), _p(T1), _stream(stream)))
+
+
+def fss_b2a(party, c, T, n, out, stream=None):
+    _check(lib.fss_b2a(party, _p(c), _p(T), n, _p(out), _stream(stream)))
 
 
 def fss_open(y0, y1, n, yhat, stream=None):

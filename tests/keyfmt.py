@@ -19,6 +19,8 @@ HDR = np.dtype([
     ("off_w", "<u8"), ("off_croot", "<u8"), ("off_crec", "<u8"), ("rec_bytes", "<u8"),
     ("off_crho", "<u8"), ("off_crout", "<u8"), ("off_tk0", "<u8"), ("off_tk1", "<u8"),
     ("off_seen", "<u8"), ("off_sentinel", "<u8"),
+    ("lit_M", "<u4"), ("lit_pad", "<u4"), ("off_lrin", "<u8"), ("off_lbase", "<u8"), ("dcf_bytes", "<u8"),
+    ("lcoef", "<u8", (MAXM, MAXP)),
     ("aprime", "<u8", MAXM + 1), ("tab", "<u8", (MAXM, MAXP, MAXP)), ("tabv", "<u8", (MAXP, MAXP)),
 ])
 

@@ -261,3 +261,23 @@ def test_rescale_key_bytes(r):
     with pytest.raises(F.FssError) as e:
         F.fss_rescale_key_bytes(8, 5, 10)
     assert e.value.code == -8
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_literal_key_bytes(r):
+    """Literal lookup: r_in and r_out shares, the last payload's p shares,
+    M - 1 = min(m + 1, 2^n) - 1 vector DCFs (root, ceil(n / r) levels x 2^r
+    children of 16 + 8p bytes) and the one-time record per lane; 64-lane
+    tiles of a multiple of 256 bytes."""
+    for desc, n, f, m, p in ((W.gelu_spec(), 24, 12, 18, 3), (W.clip_relu_spec(), 16, 8, 3, 2)):
+        s = F.Spec(desc, lookup_r=r)
+        per_tile = s.lit_key_bytes(n, f, 64) - s.lit_key_bytes(n, f, 0)
+        dcf = 64 * 16 + (-(-n // r)) * 2**r * 64 * (16 + 8 * p)
+        expect = 64 * 8 * 2 + p * 64 * 8 + m * dcf + 64 * 8 + 8
+        assert per_tile == (expect + 255) // 256 * 256
+        assert s.lit_key_bytes(n, f, 65) == 16384 + 2 * per_tile
+    # m = 2^n intervals: no padding, M - 1 = 2^n - 1 DCFs
+    s = F.Spec.integer(3, list(range(9)), [[k] for k in range(8)], lookup_r=r)
+    per_tile = s.lit_key_bytes(3, 0, 64) - s.lit_key_bytes(3, 0, 0)
+    dcf = 64 * 16 + (-(-3 // r)) * 2**r * 64 * 24
+    assert per_tile == (64 * 8 * 3 + 7 * dcf + 64 * 8 + 8 + 255) // 256 * 256

@@ -99,7 +99,9 @@ def _check_lit(S, n: int, is_int: bool, seed: int, xs):
         x = int(x)
         k = _piece(t, x, n, is_int)
         coef = [(int(a) + int(b)) & M64 for a, b in zip(got["c0"][i], got["c1"][i])]
-        assert coef == [c & M64 for c in t["coef"][k]], (x, k)
+        want = [c & M64 for c in t["coef"][k]]
+        want[0] = (want[0] + int(got["r_out"][i])) & M64  # the output mask rides in the constant term
+        assert coef == want, (x, k)
         y = (int(got["y0"][i]) + int(got["y1"][i]) - int(got["r_out"][i])) & M64
         assert y == _poly(t["coef"][k], x), x
     return got
