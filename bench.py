@@ -172,6 +172,9 @@ def main() -> None:
                     help="also run one copy kernel of this size (HBM counter calibration)")
     ap.add_argument("--ablation", choices=["reuse"], default=None,
                     help="reuse: compiled program cached vs rebuilt per layer (12 GELU layers)")
+    ap.add_argument("--study", choices=["literal"], default=None,
+                    help="literal: the compilation protocol's literal interval lookup (one DCF per boundary) "
+                         "with Horner's rule on shares, against the single-key lookup (GELU 128x3072)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -188,6 +191,9 @@ def main() -> None:
     torch.cuda.set_device(0)
     if args.ablation == "reuse":
         reuse_ablation(args)
+        return
+    if args.study == "literal":
+        literal_study(args)
         return
     if args.workload == "c5":
         serve_bench(args)
@@ -538,6 +544,84 @@ def reuse_ablation(args) -> None:
     out = {"ablation": "program_reuse", "workload": "gelu_bert_base_ffn_128x3072_x12_layers",
            "parties": 2, "cached": run(True), "per_layer": run(False)}
     print(json.dumps(out), flush=True)
+
+
+def literal_study(args) -> None:
+    """Call 2 as the compilation protocol states it against this library's
+    single-key form, GELU over 128x3072 at n = 24, f = 12, both parties.
+    literal: keys of the literal lookup (one vector DCF per inner boundary
+    of the translated partition) plus the Beaver triples of Horner's rule,
+    then both parties' lookups and the d rounds of Horner's rule on shares
+    (openings between the parties' steps).  single_key: fss_keygen (both
+    calls' keys) and fss_eval_coeff for both parties (lookup and local
+    combination at the public x-hat).  Both produce shares of P(x) + r_out
+    from the same seed; the openings are compared element by element.  HIP
+    events on the launch stream; steps alternate between the two paths."""
+    import numpy as np
+    import torch
+
+    from paper_2606_09551_amd import fss as F
+    from paper_2606_09551_amd import runtime as R
+    from paper_2606_09551_amd import workloads as W
+
+    op = W.config2()[0]
+    n_bits, f_bits = W.N_BITS, W.F_BITS
+    spec = F.Spec(op.spec, args.lookup_r)
+    N = len(op.x)
+    single = R.OpInstanceGPU(spec, n_bits, f_bits, N)
+    lit = R.LiteralGPU(spec, n_bits, f_bits, N)
+    single.set_input(op.x)
+    lit.set_input(op.x)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        return e0, e1
+
+    def single_step(seed):
+        k = timed(lambda: (single.keygen(seed), single.mask()))
+        ev = timed(lambda: [F.fss_eval_coeff(b, single.keys[b], single.xhat, N, single.y[b]) for b in (0, 1)])
+        return k, ev
+
+    def lit_step(seed):
+        k = timed(lambda: (lit.keygen(seed), lit.mask()))
+        ev = timed(lit.eval)
+        return k, ev
+
+    rows = {"single_key": [], "literal": []}
+    for s in range(args.warmup + args.steps):
+        seed = op.seed + 104729 * s
+        pair = (single_step(seed), lit_step(seed))
+        torch.cuda.synchronize()
+        if F.fss_status() != 0:
+            raise RuntimeError("device status after a study step")
+        if s >= args.warmup:
+            for name, (k, ev) in zip(("single_key", "literal"), pair):
+                rows[name].append((k[0].elapsed_time(k[1]), ev[0].elapsed_time(ev[1])))
+    sh, lh = single.host(), lit.host()
+    same = bool(np.array_equal(sh["y0"] + sh["y1"], lh["y0"] + lh["y1"]))
+    out = {"study": "literal_lookup", "workload": "gelu_bert_base_ffn_128x3072", "elements": N, "parties": 2,
+           "n_bits": n_bits, "frac_bits": f_bits, "lookup_r": spec.lookup_r, "steps": args.steps,
+           "openings_equal": same}
+    for name, key_bytes in (("single_key", single.key_bytes), ("literal", lit.key_bytes)):
+        kg = statistics.median(r[0] for r in rows[name])
+        ev = statistics.median(r[1] for r in rows[name])
+        out[name] = {"keygen_ms": round(kg, 4), "eval_ms": round(ev, 4),
+                     "element_evals_per_s": round(2 * N / ((kg + ev) * 1e-3), 1),
+                     "key_bytes_per_party": key_bytes}
+    out["single_key"]["keygen_covers"] = "both calls' keys (predicate atoms included)"
+    out["single_key"]["eval_covers"] = "call 2 and the combination at x-hat, both parties"
+    out["literal"]["keygen_covers"] = "literal lookup keys and the Horner triples"
+    out["literal"]["eval_covers"] = f"both parties' lookups and {lit.d} Beaver rounds of Horner's rule"
+    out["literal"]["intervals_after_padding"] = spec.query(n_bits, f_bits)["m"] + 1
+    out["literal_over_single_eval"] = round(out["literal"]["eval_ms"] / out["single_key"]["eval_ms"], 3)
+    out["literal_over_single_keygen"] = round(out["literal"]["keygen_ms"] / out["single_key"]["keygen_ms"], 3)
+    print(json.dumps(out), flush=True)
+    if not same:
+        sys.exit(1)
 
 
 if __name__ == "__main__":
