@@ -105,18 +105,16 @@ def measured_traffic(workload: str, lookup_r: int):
     path = os.path.join(ROOT, "profiles", "k_fused_gelu_128x3072_traffic.md")
     if not os.path.exists(path):
         return None
+    want = f"traffic_bytes_per_launch_r{lookup_r}"
     kv = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0].strip() in ("kernel_sources_sha256_16", "traffic_bytes_per_launch",
-                                                          "lookup_r"):
+        if ":" in line and line.split(":")[0].strip() in ("kernel_sources_sha256_16", want):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in KERNEL_SOURCES)
-    if kv.get("kernel_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+    if kv.get("kernel_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16] or want not in kv:
         return None
-    if kv.get("lookup_r") != str(lookup_r):
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+    return int(kv[want])
 
 
 def build_ops(workload: str):
