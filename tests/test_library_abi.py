@@ -5,6 +5,7 @@ declares, quantise specs to exactly the oracle's integer tables (two
 independent implementations of the same rules), reject invalid specs with
 the documented codes, and size keys independently of masks.
 """
+import ctypes as C
 import math
 import os
 import re
@@ -281,3 +282,37 @@ def test_literal_key_bytes(r):
     per_tile = s.lit_key_bytes(3, 0, 64) - s.lit_key_bytes(3, 0, 0)
     dcf = 64 * 16 + (-(-3 // r)) * 2**r * 64 * 24
     assert per_tile == (64 * 8 * 3 + 7 * dcf + 64 * 8 + 8 + 255) // 256 * 256
+
+
+def test_subprotocol_and_literal_arguments_rejected_on_the_host():
+    """Bad sizes, steps, parties and NULL buffers are rejected before any
+    launch (no device needed)."""
+    seed = O.seed_bytes(1)
+    L = F.lib
+    for call in (lambda: L.fss_triples(seed, -1, 0, *([None] * 6), None),
+                 lambda: L.fss_triples(seed, 4, 70000, *([1] * 6), None),
+                 lambda: L.fss_triples(None, 4, 0, *([1] * 6), None),
+                 lambda: L.fss_triples(seed, 4, 0, 1, None, 1, 1, 1, 1, None),
+                 lambda: L.fss_and_triples(seed, 4, -1, *([1] * 6), None),
+                 lambda: L.fss_b2a_rand(seed, 4, 0, None, 1, 1, 1, None),
+                 lambda: L.fss_beaver_mask(None, 1, 1, 1, 4, 1, 1, None),
+                 lambda: L.fss_beaver_mask(1, 1, 1, 1, -4, 1, 1, None),
+                 lambda: L.fss_beaver_mul(0, 1, 1, 1, 1, None, None, 4, 1, None),
+                 lambda: L.fss_xor_mask(1, 1, 1, None, 4, 1, 1, None),
+                 lambda: L.fss_xopen(1, None, 4, 1, None),
+                 lambda: L.fss_and(0, 1, 1, 1, 1, 1, 4, None, None),
+                 lambda: L.fss_b2a(0, None, 1, 4, 1, None),
+                 lambda: L.fss_lit_eval(0, None, 1, 4, 1, 1, None),
+                 lambda: L.fss_lit_eval(0, 1, None, 4, 1, 1, None),
+                 lambda: L.fss_lit_keygen(None, 24, 12, seed, 4, 1, 1, None, None, None)):
+        assert call() == -8
+    for call in (lambda: L.fss_beaver_mul(2, 1, 1, 1, 1, 1, None, 4, 1, None),
+                 lambda: L.fss_and(-1, 1, 1, 1, 1, 1, 4, 1, None),
+                 lambda: L.fss_b2a(3, 1, 1, 4, 1, None),
+                 lambda: L.fss_lit_eval(2, 1, 1, 4, 1, 1, None)):
+        assert call() == -5
+    s = F.Spec(W.gelu_spec())
+    size = C.c_size_t()
+    assert L.fss_lit_key_bytes(s.handle, 24, 12, -1, C.byref(size)) == -8
+    assert L.fss_lit_key_bytes(None, 24, 12, 4, C.byref(size)) == -8
+    assert L.fss_lit_key_bytes(s.handle, 24, 12, 0, C.byref(size)) == 0 and size.value == 16384
