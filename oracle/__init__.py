@@ -93,7 +93,7 @@ class Spec(C.Structure):
                 ("n_views", C.c_int32), ("view_k", C.c_int32 * MAXPRED),
                 ("view_c", C.c_uint64 * MAXPRED), ("T", C.c_int32),
                 ("negate", C.c_uint8 * MAXL), ("lookup_r", C.c_int32), ("is_int", C.c_int32),
-                ("lookup_c", C.c_uint64)]
+                ("lookup_c", C.c_uint64), ("lookup_view", C.c_int32)]
 
 
 _lib = None
@@ -311,7 +311,7 @@ def spec_tables(S: Spec) -> dict:
         "aprime": [S.aprime[i] for i in range(m + 1)],
         "coef": [[S.coef[i][l] for l in range(p)] for i in range(m)],
         "atoms": ([(S.prim_k[t], S.view_c[S.prim_view[t]], 0) for t in range(S.n_prim)]
-                  + [(S.view_k[v], S.view_c[v], 1) for v in range(S.n_views)]),
+                  + [(S.view_k[v], S.view_c[v], 1) for v in range(S.n_views) if v != S.lookup_view]),
         "negate": [S.negate[j] for j in range(S.ell)],
     }
 

@@ -664,9 +664,27 @@ static int compile_preds(orc_spec* S, const orc_pred* pr, int32_t n_pred, int f)
     S->prim_out[t] = q->out;
     S->prim_bprime[t] = bprime;
   }
-  S->T = S->n_prim + S->n_views;
+  /* The mask query of the lookup's own view, 1[v < r_n] with v = (xhat +
+   * lookup_c) mod 2^n, is the comparison the lookup DCF evaluates at v with
+   * payload rho (rho_0 = 1): additive shares of that bit, reduced mod 2, are
+   * XOR shares of it.  That view gets no mask atom. */
+  S->lookup_view = -1;
+  for (int v = 0; v < S->n_views; v++)
+    if (S->view_k[v] == n && S->view_c[v] == S->lookup_c) S->lookup_view = v;
+  S->T = S->n_prim + S->n_views - (S->lookup_view >= 0 ? 1 : 0);
   if (S->T > ORC_MAXT) return -2;
   return 0;
+}
+
+/* The atom of view v's mask query (-1: answered by the lookup), and the view
+ * of mask atom t >= n_prim. */
+static int mask_atom(const orc_spec* S, int v) {
+  if (v == S->lookup_view) return -1;
+  return S->n_prim + v - (S->lookup_view >= 0 && v > S->lookup_view ? 1 : 0);
+}
+static int mask_view(const orc_spec* S, int t) {
+  const int v = t - S->n_prim;
+  return S->lookup_view >= 0 && v >= S->lookup_view ? v + 1 : v;
 }
 
 int orc_spec_compile(const orc_interval* iv, int32_t m, const orc_piece* pc,
@@ -784,7 +802,7 @@ void orc_keygen_elem(const orc_spec* S, const orc_aes_sched* kseed, uint64_t e,
       alpha = sum & lowmask(k);
       if (sum >> k) wout ^= (uint64_t)1 << S->prim_out[t];
     } else {
-      k = S->view_k[t - S->n_prim];
+      k = S->view_k[mask_view(S, t)];
       alpha = r_in & lowmask(k);
     }
     orc_blk a = orc_rand(kseed, e, 2 + 2 * t, 0);
@@ -831,10 +849,20 @@ static uint64_t binom(int l, int j) {
 
 void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xhat,
                    uint64_t* y_out, uint64_t* z_out) {
-  /* Call 1: packed comparison.  Atom t is evaluated at view_{k,c}(xhat). */
+  /* The lookup DCF at v = view_{n,c}(xhat) (c = 2^(n-1) for the signed
+   * order of real specs, 0 for the canonical order of integer specs): shares
+   * of rho 1[v < r_n]. */
+  const int n = S->n, m = S->m, p = S->p, d = S->d;
+  const uint64_t N = (uint64_t)1 << n;
+  uint64_t v = ((xhat & (N - 1)) + S->lookup_c) & (N - 1);
+  uint64_t Dv[ORC_MAXP];
+  orc_dcfr_eval(b, &K->coeff, v, Dv);
+
+  /* Call 1: packed comparison.  Atom t is evaluated at view_{k,c}(xhat); the
+   * lookup view's mask query is the low bit of this party's share of D(v)_0. */
   int A[ORC_MAXT];
   for (int t = 0; t < S->T; t++) {
-    int vi = (t < S->n_prim) ? S->prim_view[t] : t - S->n_prim;
+    int vi = (t < S->n_prim) ? S->prim_view[t] : mask_view(S, t);
     int k = S->view_k[vi];
     uint64_t u = ((xhat & lowmask(k)) + S->view_c[vi]) & lowmask(k);
     A[t] = orc_dcfz_eval(b, &K->atom[t], u);
@@ -843,20 +871,15 @@ void orc_eval_elem(int b, const orc_spec* S, const orc_elem_key* K, uint64_t xha
   if (b == 0)
     for (int j = 0; j < S->ell; j++) z ^= (uint64_t)S->negate[j] << j;
   for (int t = 0; t < S->n_prim; t++) {
-    int bit = A[t] ^ A[S->n_prim + S->prim_view[t]];
+    const int ma = mask_atom(S, S->prim_view[t]);
+    int bit = A[t] ^ (ma < 0 ? (int)(Dv[0] & 1) : A[ma]);
     z ^= (uint64_t)bit << S->prim_out[t];
   }
 
-  /* Call 2: interval lookup.  With v = view_{n,c}(xhat) (c = 2^(n-1) for the
-   * signed order of real specs, 0 for the canonical order of integer specs)
-   * and x' = (v - r_n) mod N, for each interior boundary a'_i:
+  /* Call 2: interval lookup.  With x' = (v - r_n) mod N, for each interior
+   * boundary a'_i:
    *   1[x' < a'_i] = 1[(v - a'_i) mod N < r_n] - 1[v < r_n] + 1[v < a'_i],
    * so g_i = D(u_i) - D(v) + 1[v < a'_i] rho_b shares 1[x' < a'_i] rho. */
-  const int n = S->n, m = S->m, p = S->p, d = S->d;
-  const uint64_t N = (uint64_t)1 << n;
-  uint64_t v = ((xhat & (N - 1)) + S->lookup_c) & (N - 1);
-  uint64_t Dv[ORC_MAXP];
-  orc_dcfr_eval(b, &K->coeff, v, Dv);
   uint64_t g[ORC_MAXM + 1][ORC_MAXP];
   for (int k = 0; k < p; k++) { g[0][k] = 0; g[m][k] = K->rho[k]; }
   for (int i = 1; i < m; i++) {

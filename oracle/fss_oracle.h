@@ -144,11 +144,16 @@ typedef struct {
   int32_t n_views;
   int32_t view_k[ORC_MAXPRED];
   uint64_t view_c[ORC_MAXPRED];
-  int32_t T;                            /* atoms: n_prim thresholds, then n_views mask atoms */
+  int32_t T;                            /* atoms: n_prim thresholds, then the mask atoms of the
+                                           views other than lookup_view */
   uint8_t negate[ORC_MAXL];             /* public constant flip per output bit */
   int32_t lookup_r;                     /* input bits per level of call 2's DCF (2, 3 or 4) */
   int32_t is_int;                       /* 1: integer spec over canonical representatives */
   uint64_t lookup_c;                    /* public shift of the lookup's view: 2^(n-1) or 0 */
+  /* The view whose mask query 1[view < r_k] is the lookup's own comparison
+   * 1[v < r_n] (k = n, c = lookup_c), or -1: that query has no atom of its
+   * own; its bit is the lookup DCF's first output at v reduced mod 2. */
+  int32_t lookup_view;
 } orc_spec;
 
 /* Returns 0 on success, negative on an invalid or unsupported spec.  Sets

@@ -112,6 +112,7 @@ struct QSpec {
   uint32_t atom_rview[kMaxAtoms] = {};
   uint64_t bprime[kMaxAtoms] = {};
   uint64_t negate = 0;
+  bool mask_from_lookup = false;  // a threshold atom's mask query is the lookup's comparison
   Layout layout{};
   KeyHeader hdr{};
   std::map<int, uint8_t*> dev_hdr;  // device -> header template
@@ -276,14 +277,27 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
     q->bprime[t] = bp;
     prim_view.push_back(v);
   }
-  q->n_views = (int)views.size();
+  // The view the lookup itself reads (n bits, shift lookup_c) needs no mask
+  // atom: its query 1[v < r_n] is the lookup DCF's comparison at v, whose
+  // first output (payload rho_0 = 1) gives XOR shares of the bit mod 2.
+  const uint64_t lookup_c = S->is_int ? 0 : (uint64_t)s;
+  int lookup_view = -1;
+  for (size_t u = 0; u < views.size(); ++u)
+    if (views[u].k == n && views[u].c == lookup_c) lookup_view = (int)u;
+  q->n_views = (int)views.size() - (lookup_view >= 0 ? 1 : 0);  // mask atoms
   q->T = q->n_prim + q->n_views;
   if (q->T > kMaxAtoms) return fail(FSS_E_UNSUPPORTED, "T=%d atoms exceeds %d", q->T, kMaxAtoms);
-  for (int v = 0; v < q->n_views; ++v) {
-    q->atom_k[q->n_prim + v] = (uint32_t)views[v].k;
-    q->atom_c[q->n_prim + v] = views[v].c;
+  std::vector<int> mask_atom(views.size(), -1);
+  for (size_t u = 0, t = (size_t)q->n_prim; u < views.size(); ++u) {
+    if ((int)u == lookup_view) continue;
+    q->atom_k[t] = (uint32_t)views[u].k;
+    q->atom_c[t] = views[u].c;
+    mask_atom[u] = (int)t++;
   }
-  for (int t = 0; t < q->n_prim; ++t) q->atom_rview[t] = (uint32_t)(q->n_prim + prim_view[t]);
+  for (int t = 0; t < q->n_prim; ++t)
+    q->atom_rview[t] = prim_view[t] == lookup_view ? kRviewLookup : (uint32_t)mask_atom[prim_view[t]];
+  q->mask_from_lookup = false;
+  for (int t = 0; t < q->n_prim; ++t) q->mask_from_lookup |= prim_view[t] == lookup_view;
   q->layout = make_layout(q->T, q->atom_k, n, q->p, r);
 
   // Header template (party, n_elems and n_tiles are stamped per buffer).
@@ -307,7 +321,8 @@ int quantize(const fss_spec* S, int n, int f, int r, std::shared_ptr<QSpec>* out
   // chosen to minimise the AES blocks of the walks, B <= kMaxTopBlocks,
   // K < n; no sharing (D = 0) when m < 4 or nothing is saved.
   h.lookup_r = (uint32_t)r;
-  h.lookup_c = S->is_int ? 0u : (uint32_t)s;
+  h.lookup_c = (uint32_t)lookup_c;
+  h.mask_from_lookup = q->mask_from_lookup ? 1u : 0u;
   h.is_int = S->is_int ? 1u : 0u;
   {
     const uint64_t W = (m >= 2) ? (q->aprime[m - 1] - q->aprime[1] + 1) : 1;
@@ -1149,6 +1164,10 @@ int device_cus(int* cus, std::string* name) {
 struct ElemCost {
   double aes_pred = 0, aes_base = 0, aes_tops = 0, aes_point = 0;
   double lk_pred = 0, lk_base = 0, lk_tops = 0, lk_point = 0;
+  // call 1 in a unit of its own also walks the lookup DCF at v (its first
+  // output only) when a mask query is the lookup's; in part 0's unit it
+  // reuses that unit's walk
+  double aes_pred_own = 0, lk_pred_own = 0;
   int points = 0;  // m - 1
   int ell = 0;     // predicate output bits: call 1 runs (and writes them) whenever ell > 0
 };
@@ -1172,6 +1191,10 @@ ElemCost elem_cost(const KeyHeader& h) {
   c.lk_point = (L - D - 1) * shared(lvl) + shared(nb);
   c.points = (int)h.m - 1;
   c.ell = (int)h.ell;
+  // the lookup's comparison alone: seed and one value block per level, the
+  // last level's value block
+  c.aes_pred_own = c.aes_pred + (h.mask_from_lookup ? (L - 1) * 2 + 1 : 0.0);
+  c.lk_pred_own = c.lk_pred + (h.mask_from_lookup ? (L - 1) * shared(2) + shared(1) : 0.0);
   return c;
 }
 
@@ -1250,7 +1273,7 @@ std::vector<Unit> tile_parts(const ElemCost& c, int parts, bool merge_pred, int 
       out[0].lookups += c.lk_pred;
       out[0].span += c.aes_pred;
     } else {
-      out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred, c.lk_pred, c.aes_pred});
+      out.push_back({0, 0, 1u | (1u << 16), kUnitPred, c.aes_pred_own, c.lk_pred_own, c.aes_pred_own});
     }
   }
   return out;

@@ -99,6 +99,10 @@ constexpr AesConst kAes = make_aes_const();
 constexpr uint32_t kMagic = 0x4B535346u;  // "FSSK"
 constexpr uint32_t kVersion = 10;
 constexpr uint32_t kGateOperator = 0, kGateRescale = 1, kGateLiteral = 2;
+// atom_rview of a threshold atom whose view is the lookup's view (k = n,
+// shift lookup_c): its mask query 1[v < r_n] is the lookup DCF's first output
+// at v reduced mod 2, carried in bit 31 of the call-1 atom word.
+constexpr uint32_t kRviewLookup = 31;
 constexpr int kTile = 64;
 constexpr int kMaxAtoms = 16;
 constexpr int kMaxM = 64;
@@ -117,6 +121,9 @@ struct KeyHeader {
   uint32_t is_int;                         // 1: integer spec over canonical representatives
   uint32_t kind;                           // kGateOperator, kGateRescale or kGateLiteral
   uint32_t shift;                          // rescaling gate: bits shifted out (its DCF's domain, = n)
+  uint32_t mask_from_lookup;               // 1: a threshold atom's mask query is the lookup's own
+                                           // comparison (atom_rview = kRviewLookup)
+  uint32_t hdr_pad;
   uint64_t n_elems, n_tiles, tile_bytes, spec_hash;
   uint64_t negate;                         // bit j: public flip of output j (party 0 applies it)
   uint32_t atom_k[kMaxAtoms];

@@ -398,6 +398,77 @@ __device__ __forceinline__ bool claim_once(GHdr h, const uint8_t* tile, int slot
 // (plus the leaf correction when the control bit is set), whose bit
 // (view mod 2^nu) completes the share.
 // ---------------------------------------------------------------------------
+// CNT atoms from atom g on, walked in lockstep (one interleaved AES of CNT
+// blocks per level); returns their bits at positions g ...
+template <int CNT, class TB>
+__device__ __forceinline__ uint32_t atom_group(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
+                                               uint64_t xhat, int g) {
+  uint32_t bits = 0;
+  uint32_t s[CNT][4], t[CNT], V[CNT], xh[CNT], xl[CNT];
+  int lev[CNT];
+  uint64_t vb[CNT];
+  const uint8_t* base[CNT];
+  int lmax = 0;
+#pragma unroll
+  for (int a = 0; a < CNT; ++a) {
+    const int at = g + a;
+    const int k = (int)h->atom_k[at];
+    const int nu = atom_leaf_bits(k);
+    lev[a] = k - nu;
+    lmax = lev[a] > lmax ? lev[a] : lmax;
+    base[a] = tile + h->atom_off[at];
+    const uint4 r = ld16(base[a] + lane * 16);
+    s[a][0] = r.x; s[a][1] = r.y; s[a][2] = r.z; s[a][3] = r.w;
+    t[a] = (uint32_t)b;
+    V[a] = 0;
+    const uint64_t msk = (k >= 64) ? ~0ull : ((1ull << k) - 1);
+    const uint32_t xv = (uint32_t)(((xhat & msk) + h->atom_c[at]) & msk);
+    xh[a] = xv >> nu;
+    xl[a] = xv & ((1u << nu) - 1u);
+    vb[a] = ld8(base[a] + (uint64_t)kTile * 16 * (1 + k - nu) + lane * 8);
+  }
+  for (int i = 0; i < lmax; ++i) {
+    uint32_t j[CNT], o[CNT][4];
+#pragma unroll
+    for (int a = 0; a < CNT; ++a) j[a] = (i < lev[a]) ? ((xh[a] >> (lev[a] - 1 - i)) & 1u) : 0u;
+    prg<TB, CNT>(tb, s, j, o);
+#pragma unroll
+    for (int a = 0; a < CNT; ++a) {
+      if (i < lev[a]) {
+        const uint4 cw = ld16(base[a] + kTile * 16 + ((uint64_t)i * kTile + lane) * 16);
+        const uint32_t msk = 0u - t[a];
+        const uint32_t nt = (o[a][0] & 1u) ^ ((cw.x >> j[a]) & t[a] & 1u);
+        const uint32_t v = ((o[a][0] >> 1) & 1u) ^ ((uint32_t)(vb[a] >> i) & t[a] & 1u);
+        s[a][0] = (o[a][0] & ~3u) ^ (cw.x & ~3u & msk);
+        s[a][1] = o[a][1] ^ (cw.y & msk);
+        s[a][2] = o[a][2] ^ (cw.z & msk);
+        s[a][3] = o[a][3] ^ (cw.w & msk);
+        V[a] ^= v;
+        t[a] = nt;
+      }
+    }
+  }
+  {  // the leaves
+    uint32_t j[CNT], o[CNT][4];
+#pragma unroll
+    for (int a = 0; a < CNT; ++a) j[a] = 2u;
+    prg<TB, CNT>(tb, s, j, o);
+#pragma unroll
+    for (int a = 0; a < CNT; ++a) {
+      const uint4 lc = ld16(base[a] + (uint64_t)kTile * 16 * (1 + lev[a]) + kTile * 8 + lane * 16);
+      const uint32_t msk = 0u - t[a];
+      const uint32_t w = xl[a] >> 5;
+      uint32_t word = (o[a][0] ^ (lc.x & msk));
+      word = w == 1 ? (o[a][1] ^ (lc.y & msk)) : word;
+      word = w == 2 ? (o[a][2] ^ (lc.z & msk)) : word;
+      word = w == 3 ? (o[a][3] ^ (lc.w & msk)) : word;
+      V[a] ^= (word >> (xl[a] & 31u)) & 1u;
+      bits |= (V[a] & 1u) << (g + a);
+    }
+  }
+  return bits;
+}
+
 template <class TB>
 __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8_t* tile,
                                                int lane, int b, uint64_t xhat) {
@@ -405,68 +476,9 @@ __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8
   uint32_t bits = 0;
   for (int g = 0; g < T; g += 3) {
     const int cnt = T - g < 3 ? T - g : 3;
-    uint32_t s[3][4], t[3], V[3], xh[3], xl[3];
-    int lev[3];
-    uint64_t vb[3];
-    const uint8_t* base[3];
-    int lmax = 0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const int at = g + (a < cnt ? a : 0);
-      const int k = (int)h->atom_k[at];
-      const int nu = atom_leaf_bits(k);
-      lev[a] = a < cnt ? k - nu : 0;
-      lmax = lev[a] > lmax ? lev[a] : lmax;
-      base[a] = tile + h->atom_off[at];
-      const uint4 r = ld16(base[a] + lane * 16);
-      s[a][0] = r.x; s[a][1] = r.y; s[a][2] = r.z; s[a][3] = r.w;
-      t[a] = (uint32_t)b;
-      V[a] = 0;
-      const uint64_t msk = (k >= 64) ? ~0ull : ((1ull << k) - 1);
-      const uint32_t xv = (uint32_t)(((xhat & msk) + h->atom_c[at]) & msk);
-      xh[a] = xv >> nu;
-      xl[a] = xv & ((1u << nu) - 1u);
-      vb[a] = ld8(base[a] + (uint64_t)kTile * 16 * (1 + k - nu) + lane * 8);
-    }
-    for (int i = 0; i < lmax; ++i) {
-      uint32_t j[3], o[3][4];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) j[a] = (i < lev[a]) ? ((xh[a] >> (lev[a] - 1 - i)) & 1u) : 0u;
-      prg<TB, 3>(tb, s, j, o);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (i < lev[a]) {
-          const uint4 cw = ld16(base[a] + kTile * 16 + ((uint64_t)i * kTile + lane) * 16);
-          const uint32_t msk = 0u - t[a];
-          const uint32_t nt = (o[a][0] & 1u) ^ ((cw.x >> j[a]) & t[a] & 1u);
-          const uint32_t v = ((o[a][0] >> 1) & 1u) ^ ((uint32_t)(vb[a] >> i) & t[a] & 1u);
-          s[a][0] = (o[a][0] & ~3u) ^ (cw.x & ~3u & msk);
-          s[a][1] = o[a][1] ^ (cw.y & msk);
-          s[a][2] = o[a][2] ^ (cw.z & msk);
-          s[a][3] = o[a][3] ^ (cw.w & msk);
-          V[a] ^= v;
-          t[a] = nt;
-        }
-      }
-    }
-    {  // the leaves
-      uint32_t j[3] = {2u, 2u, 2u}, o[3][4];
-      prg<TB, 3>(tb, s, j, o);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (a < cnt) {
-          const uint4 lc = ld16(base[a] + (uint64_t)kTile * 16 * (1 + lev[a]) + kTile * 8 + lane * 16);
-          const uint32_t msk = 0u - t[a];
-          const uint32_t w = xl[a] >> 5;
-          uint32_t word = (o[a][0] ^ (lc.x & msk));
-          word = w == 1 ? (o[a][1] ^ (lc.y & msk)) : word;
-          word = w == 2 ? (o[a][2] ^ (lc.z & msk)) : word;
-          word = w == 3 ? (o[a][3] ^ (lc.w & msk)) : word;
-          V[a] ^= (word >> (xl[a] & 31u)) & 1u;
-          bits |= (V[a] & 1u) << (g + a);
-        }
-      }
-    }
+    bits |= cnt == 3 ? atom_group<3>(tb, h, tile, lane, b, xhat, g)
+            : cnt == 2 ? atom_group<2>(tb, h, tile, lane, b, xhat, g)
+                       : atom_group<1>(tb, h, tile, lane, b, xhat, g);
   }
   return bits;
 }
@@ -478,8 +490,10 @@ __device__ __forceinline__ uint32_t eval_atoms(const TB& tb, GHdr h, const uint8
 template <class TB, class Claim>
 __device__ __forceinline__ void pred_tile(const TB& tb, GHdr h, const uint8_t* tile,
                                           int lane, int b, uint64_t xhat, bool valid, uint64_t* z,
-                                          uint64_t tile_idx, uint64_t words, Claim&& claim) {
-  const uint32_t A = eval_atoms(tb, h, tile, lane, b, xhat);
+                                          uint64_t tile_idx, uint64_t words, uint32_t lb, Claim&& claim) {
+  // lb: this party's share of the lookup's comparison, the mask query of
+  // threshold atoms with atom_rview = kRviewLookup
+  const uint32_t A = eval_atoms(tb, h, tile, lane, b, xhat) | (lb << kRviewLookup);
   uint64_t bits = ld8(tile + h->off_w + lane * 8);
   if (b == 0) bits ^= h->negate;
   const int np = (int)h->n_prim;
@@ -637,7 +651,8 @@ __device__ __forceinline__ void vec_walk(const TB& tb, GHdr h, const uint8_t* ti
 // the whole of call 2.
 template <int P, int R, class TB>
 __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8_t* tile,
-                                               int lane, int b, uint64_t xhat, int i0, int i1, bool base) {
+                                               int lane, int b, uint64_t xhat, int i0, int i1, bool base,
+                                               uint32_t* lbit) {
   const int n = (int)h->n, m = (int)h->m, D = (int)h->top_depth;
   const int L = (n + R - 1) / R;
   const int iend = i1 < m ? i1 : m;
@@ -660,64 +675,75 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
     for (int w = 0; w < 4; ++w) ts[c][w] = root.s[w];
     ts[c][4] = root.t;
   }
-  if (iend > i0) {
+  // The walks of one tile as a single sequence of jobs, so the walk (and the
+  // AES it unrolls) is emitted once: the NT top blocks through the shared
+  // levels [0, D), the points' walks below them [D, L), then the walk at v
+  // [0, L).  The job kind is the same on every lane.
+  const int ntop = iend > i0 ? NT : 0, npts = iend > i0 ? iend - i0 : 0;
+  const int njobs = ntop + npts + (base ? 1 : 0);
 #pragma unroll 1
-    for (int bk = 0; bk < NT; ++bk) {
-      VState<P> st = root;
-      vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)((blkA + (uint32_t)bk) & blk_mask) << K), 0, D, st);
+  for (int job = 0; job < njobs; ++job) {
+    const int kind = job < ntop ? 0 : job < ntop + npts ? 1 : 2;  // top block, point, base
+    VState<P> st = root;
+    uint32_t x = v;
+    int lo = 0, hi = L, i = 0;
+    if (kind == 0) {
+      x = (uint32_t)((uint64_t)((blkA + (uint32_t)job) & blk_mask) << K);
+      hi = D;
+    } else if (kind == 1) {
+      i = i0 + (job - ntop);
+      x = (v - (uint32_t)h->aprime[i]) & Nmask;
+      const uint32_t off = ((x >> K) - blkA) & blk_mask;  // D = 0: every block holds the root
+#pragma unroll
+      for (int w = 0; w < 5; ++w) {
+        uint32_t y = ts[0][w];
+#pragma unroll
+        for (int c = 1; c < kMaxTopBlocks; ++c) y = off == (uint32_t)c ? ts[c][w] : y;
+        if (w < 4) st.s[w] = y; else st.t = y;
+      }
+      lo = D;
+    }
+    vec_walk<P, R>(tb, h, tile, lane, b, x, lo, hi, st);
+    if (kind == 0) {
+      // the block's state below the shared levels, and its partial sums for
+      // the points it holds
 #pragma unroll
       for (int c = 0; c < kMaxTopBlocks; ++c)
-        if (c == bk) {
+        if (c == job) {
 #pragma unroll
           for (int w = 0; w < 4; ++w) ts[c][w] = st.s[w];
           ts[c][4] = st.t;
         }
-      for (int i = i0; i < iend; ++i) {
-        const uint32_t u = (v - (uint32_t)h->aprime[i]) & Nmask;
-        const uint64_t in = ((((u >> K) - blkA) & blk_mask) == (uint32_t)bk) ? ~0ull : 0ull;
+      for (int pi = i0; pi < iend; ++pi) {
+        const uint32_t u = (v - (uint32_t)h->aprime[pi]) & Nmask;
+        const uint64_t in = ((((u >> K) - blkA) & blk_mask) == (uint32_t)job) ? ~0ull : 0ull;
 #pragma unroll
-        for (int j = 0; j < P; ++j)
+        for (int jj = 0; jj < P; ++jj)
 #pragma unroll
-          for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * (st.V[k] & in);
+          for (int k = 0; jj + k < P; ++k) q[jj] += h->tab[pi][jj][k] * (st.V[k] & in);
       }
+    } else if (kind == 1) {
+      const uint64_t lt = v < (uint32_t)h->aprime[i] ? ~0ull : 0ull;
+      uint64_t g[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) g[k] = st.V[k] + (ld8(rhop + (uint64_t)k * kTile * 8) & lt);
+#pragma unroll
+      for (int jj = 0; jj < P; ++jj)
+#pragma unroll
+        for (int k = 0; jj + k < P; ++k) q[jj] += h->tab[i][jj][k] * g[k];
+    } else {
+      // this party's XOR share of 1[v < r_n]: its share of rho_0 1[v < r_n], mod 2
+      if (lbit) *lbit = (uint32_t)(st.V[0] & 1ull);
+#pragma unroll
+      for (int jj = 0; jj < P; ++jj)
+#pragma unroll
+        for (int k = 0; jj + k < P; ++k) q[jj] -= h->tabv[jj][k] * st.V[k];
+#pragma unroll
+      for (int jj = 0; jj < P; ++jj)
+#pragma unroll
+        for (int k = 0; jj + k < P; ++k) q[jj] += h->tab[0][jj][k] * ld8(rhop + (uint64_t)k * kTile * 8);
+      q[0] += ld8(tile + h->off_crout + lane * 8);
     }
-  }
-  for (int i = i0; i < iend; ++i) {
-    const uint32_t ap = (uint32_t)h->aprime[i];
-    const uint32_t u = (v - ap) & Nmask;
-    const uint32_t off = ((u >> K) - blkA) & blk_mask;  // D = 0: every block holds the root
-    VState<P> st;
-#pragma unroll
-    for (int w = 0; w < 5; ++w) {
-      uint32_t x = ts[0][w];
-#pragma unroll
-      for (int c = 1; c < kMaxTopBlocks; ++c) x = off == (uint32_t)c ? ts[c][w] : x;
-      if (w < 4) st.s[w] = x; else st.t = x;
-    }
-#pragma unroll
-    for (int k = 0; k < P; ++k) st.V[k] = 0;
-    vec_walk<P, R>(tb, h, tile, lane, b, u, D, L, st);
-    const uint64_t lt = v < ap ? ~0ull : 0ull;
-    uint64_t g[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) g[k] = st.V[k] + (ld8(rhop + (uint64_t)k * kTile * 8) & lt);
-#pragma unroll
-    for (int j = 0; j < P; ++j)
-#pragma unroll
-      for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * g[k];
-  }
-  if (base) {
-    VState<P> st = vroot<P>(h, tile, lane, b);
-    vec_walk<P, R>(tb, h, tile, lane, b, v, 0, L, st);
-#pragma unroll
-    for (int j = 0; j < P; ++j)
-#pragma unroll
-      for (int k = 0; j + k < P; ++k) q[j] -= h->tabv[j][k] * st.V[k];
-#pragma unroll
-    for (int j = 0; j < P; ++j)
-#pragma unroll
-      for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * ld8(rhop + (uint64_t)k * kTile * 8);
-    q[0] += ld8(tile + h->off_crout + lane * 8);
   }
   uint64_t y = q[P - 1];
 #pragma unroll
@@ -727,23 +753,88 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
 
 template <int R, class TB>
 __device__ __forceinline__ uint64_t coeff_dispatch_r(const TB& tb, GHdr h, const uint8_t* tile,
-                                                     int lane, int b, uint64_t xhat, int i0, int i1, bool base) {
+                                                     int lane, int b, uint64_t xhat, int i0, int i1, bool base,
+                                                     uint32_t* lbit) {
   switch (h->p) {
-    case 1: return coeff_tile<1, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    case 2: return coeff_tile<2, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    case 3: return coeff_tile<3, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    default: return coeff_tile<4, R>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 1: return coeff_tile<1, R>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
+    case 2: return coeff_tile<2, R>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
+    case 3: return coeff_tile<3, R>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
+    default: return coeff_tile<4, R>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
   }
 }
 
 template <class TB>
 __device__ __forceinline__ uint64_t coeff_dispatch(const TB& tb, GHdr h, const uint8_t* tile,
                                                    int lane, int b, uint64_t xhat, int i0 = 1,
-                                                   int i1 = kMaxM + 1, bool base = true) {
+                                                   int i1 = kMaxM + 1, bool base = true,
+                                                   uint32_t* lbit = nullptr) {
+  // lbit (may be null): with `base`, receives this party's XOR share of the
+  // lookup's comparison 1[v < r_n], the mask query answered by the lookup
   switch (h->lookup_r) {
-    case 2: return coeff_dispatch_r<2>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    case 3: return coeff_dispatch_r<3>(tb, h, tile, lane, b, xhat, i0, i1, base);
-    default: return coeff_dispatch_r<4>(tb, h, tile, lane, b, xhat, i0, i1, base);
+    case 2: return coeff_dispatch_r<2>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
+    case 3: return coeff_dispatch_r<3>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
+    default: return coeff_dispatch_r<4>(tb, h, tile, lane, b, xhat, i0, i1, base, lbit);
+  }
+}
+
+// This party's share of the lookup DCF's first output at x, mod 2: the walk
+// at x with the value stream's first word only.  Child d's word 0 is word d P
+// of its seed's value stream, so each level expands the seed block and one
+// value block (the last level the value block alone); low bits add as XOR.
+template <int P, int R, class TB>
+__device__ __forceinline__ uint32_t bit0_walk(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
+                                              uint32_t x) {
+  constexpr uint32_t C = 1u << R;
+  constexpr uint64_t REC = 16 + 8 * P;
+  const int L = ((int)h->n + R - 1) / R;
+  const uint8_t* recp = tile + h->off_crec + lane * REC;
+  const uint4 root = ld16(tile + h->off_croot + lane * 16);
+  uint32_t s[4] = {root.x, root.y, root.z, root.w}, t = (uint32_t)b, acc = 0;
+  for (int i = 0; i + 1 < L; ++i) {
+    const uint32_t d = (x >> (R * (L - 1 - i))) & (C - 1u), w = d * (uint32_t)P;
+    const uint32_t jj[2] = {d, C + (w >> 1)};
+    uint32_t o[2][4];
+    prg_shared<TB, 2>(tb, s, jj, o);
+    const uint8_t* rp = recp + ((uint64_t)i * C + d) * kTile * REC;
+    const uint64_t c01 = ld8(rp), c23 = ld8(rp + 8), cv = ld8(rp + 16);
+    const uint32_t msk = 0u - t;
+    acc ^= (((w & 1u) ? o[1][2] : o[1][0]) ^ ((uint32_t)cv & msk)) & 1u;
+    t = (o[0][0] & 1u) ^ ((uint32_t)c01 & t & 1u);
+    s[0] = (o[0][0] & ~3u) ^ ((uint32_t)c01 & ~3u & msk);
+    s[1] = o[0][1] ^ ((uint32_t)(c01 >> 32) & msk);
+    s[2] = o[0][2] ^ ((uint32_t)c23 & msk);
+    s[3] = o[0][3] ^ ((uint32_t)(c23 >> 32) & msk);
+  }
+  const uint32_t d = x & (C - 1u), w = d * (uint32_t)P;
+  const uint32_t jj[1] = {C + (w >> 1)};
+  uint32_t o[1][4];
+  prg_shared<TB, 1>(tb, s, jj, o);
+  const uint64_t cv = ld8(recp + ((uint64_t)(L - 1) * C + d) * kTile * REC + 16);
+  acc ^= (((w & 1u) ? o[0][2] : o[0][0]) ^ ((uint32_t)cv & (0u - t))) & 1u;
+  return acc;
+}
+
+// A call-1 unit's share of the lookup's comparison 1[v < r_n] when a mask
+// query is the lookup's, else 0.
+template <class TB>
+__device__ __forceinline__ uint32_t lookup_bit(const TB& tb, GHdr h, const uint8_t* tile, int lane, int b,
+                                               uint64_t xhat) {
+  if (!h->mask_from_lookup) return 0;
+  const int n = (int)h->n;
+  const uint32_t v = (uint32_t)((xhat + h->lookup_c) & (n >= 64 ? ~0ull : ((1ull << n) - 1)));
+  auto by_r = [&](auto pc) -> uint32_t {
+    constexpr int PP = decltype(pc)::value;
+    switch (h->lookup_r) {
+      case 2: return bit0_walk<PP, 2>(tb, h, tile, lane, b, v);
+      case 3: return bit0_walk<PP, 3>(tb, h, tile, lane, b, v);
+      default: return bit0_walk<PP, 4>(tb, h, tile, lane, b, v);
+    }
+  };
+  switch (h->p) {
+    case 1: return by_r(std::integral_constant<int, 1>{});
+    case 2: return by_r(std::integral_constant<int, 2>{});
+    case 3: return by_r(std::integral_constant<int, 3>{});
+    default: return by_r(std::integral_constant<int, 4>{});
   }
 }
 
@@ -772,7 +863,7 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_eval_pred(const uint8_t* k
   const uint64_t xh = valid ? ldg64(xhat + e) : 0;
   TB tb(lds, lane);
   const uint8_t* tp = keys + kHeaderBytes + tile * h->tile_bytes;
-  pred_tile(tb, h, tp, lane, party, xh, valid, z, tile, words,
+  pred_tile(tb, h, tp, lane, party, xh, valid, z, tile, words, lookup_bit(tb, h, tp, lane, party, xh),
             [&] { return claim_once(h, tp, lane, xh, valid, status); });
 }
 
@@ -894,20 +985,26 @@ __global__ __launch_bounds__(TabOf<V>::kBlock) void k_fused(const DevItem* items
     const uint8_t* tp = it.keys + kHeaderBytes + tile * h->tile_bytes;
     // The one-time check runs after the unit's work and before its first
     // store: its atomic's latency then holds up no key load.
-    bool ok = true, claimed = false;
-    if (flags & kUnitPred)  // also with T = 0: the bits are then the public constants and carry shares
-      pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words, [&] {
-        claimed = true;
-        return ok = claim_once(h, tp, lane, xh, valid, status);
-      });
-    if (!(flags & kUnitBase) && (range & 0xffffu) >= (range >> 16)) continue;  // a call-1 unit
+    bool ok = true;
+    auto claim = [&] { return ok = claim_once(h, tp, lane, xh, valid, status); };
+    if (!(flags & kUnitBase) && (range & 0xffffu) >= (range >> 16)) {
+      // call 1 in a unit of its own (also with T = 0: the bits are then the
+      // public constants and carry shares)
+      pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words,
+                lookup_bit(tb, h, tp, lane, it.party, xh), claim);
+      continue;
+    }
     if constexpr (LG > 0) {
       // launches with lane groups run call 2 in kUnitLanes units only
       if (lane == 0) set_status(status, kStatusShape);
     } else {
+      uint32_t lb = 0;
       const uint64_t out = coeff_dispatch(tb, h, tp, lane, it.party, xh, (int)(range & 0xffffu), (int)(range >> 16),
-                                          (flags & kUnitBase) != 0);
-      if (!claimed) ok = claim_once(h, tp, lane, xh, valid, status);
+                                          (flags & kUnitBase) != 0, &lb);
+      if (flags & kUnitPred)  // call 1 in the same pass, after call 2's walk at v gave the lookup's comparison
+        pred_tile(tb, h, tp, lane, it.party, xh, valid, it.z, tile, (uint64_t)it.words, lb, claim);
+      else
+        claim();
       if (valid) {
         if (flags & kUnitAccumulate)  // parts of one tile add their shares of y (mod 2^64)
           __hip_atomic_fetch_add((FSS_GLOBAL unsigned long long*)(it.y + e), (unsigned long long)(ok ? out : 0ull),

@@ -13,7 +13,7 @@ HDR = np.dtype([
     ("ell", "<u4"), ("F_out", "<u4"), ("n_prim", "<u4"), ("n_views", "<u4"), ("kmax", "<u4"),
     ("top_depth", "<u4"), ("lookup_r", "<u4"), ("top_blocks", "<u4"),
     ("lookup_c", "<u4"), ("is_int", "<u4"),
-    ("kind", "<u4"), ("shift", "<u4"), ("n_elems", "<u8"), ("n_tiles", "<u8"), ("tile_bytes", "<u8"),
+    ("kind", "<u4"), ("shift", "<u4"), ("mask_from_lookup", "<u4"), ("hdr_pad", "<u4"), ("n_elems", "<u8"), ("n_tiles", "<u8"), ("tile_bytes", "<u8"),
     ("spec_hash", "<u8"), ("negate", "<u8"), ("atom_k", "<u4", MAXA), ("atom_out", "<u4", MAXA),
     ("atom_rview", "<u4", MAXA), ("atom_c", "<u8", MAXA), ("atom_off", "<u8", MAXA),
     ("off_w", "<u8"), ("off_croot", "<u8"), ("off_crec", "<u8"), ("rec_bytes", "<u8"),

@@ -182,16 +182,17 @@ def test_key_bytes_shape(r):
     assert per_tile % 256 == 0
     for N in (1, 63, 64, 65, 393216):
         assert s.key_bytes(24, 12, N) == 16384 + ((N + 63) // 64) * per_tile
-    # 3 Z_2 atoms (root, 24 - 7 tree levels, value bits, 16-byte leaf correction), w shares,
-    # then the lookup DCF: root, 24 / r levels x 2^r children of seed (16 B) and p = 3
-    # value corrections, rho and r_out shares; the one-time record (x-hat of each element, used mask)
-    expect = (3 * (64 * 16 * 18 + 64 * 8 + 64 * 16) + 64 * 8 + 64 * 16 + (24 // r) * 2**r * 64 * (16 + 3 * 8)
+    # 2 Z_2 threshold atoms (root, 24 - 7 tree levels, value bits, 16-byte leaf correction; the
+    # signed view's mask query is the lookup's own comparison), w shares, then the lookup DCF:
+    # root, 24 / r levels x 2^r children of seed (16 B) and p = 3 value corrections, rho and
+    # r_out shares; the one-time record (x-hat of each element, the sentinel)
+    expect = (2 * (64 * 16 * 18 + 64 * 8 + 64 * 16) + 64 * 8 + 64 * 16 + (24 // r) * 2**r * 64 * (16 + 3 * 8)
               + 3 * 64 * 8 + 64 * 8 + 64 * 8 + 8)
     assert per_tile == (expect + 255) // 256 * 256
     c = F.Spec(W.clip_relu_spec(), lookup_r=r)
-    # n = 16, p = 2: atoms 3 * ((1 + 9) * 16 + 8 + 16), w 8, root 16, ceil(16 / r) levels x 2^r
+    # n = 16, p = 2: atoms 2 * ((1 + 9) * 16 + 8 + 16), w 8, root 16, ceil(16 / r) levels x 2^r
     # x (16 + 16), rho 16, r_out 8 per element; the one-time record; tiles rounded to 256 bytes
-    elem = 3 * (10 * 16 + 8 + 16) + 8 + 16 + (-(-16 // r)) * 2**r * 32 + 16 + 8
+    elem = 2 * (10 * 16 + 8 + 16) + 8 + 16 + (-(-16 // r)) * 2**r * 32 + 16 + 8
     assert c.key_bytes(16, 8, 4096) - 16384 == 64 * ((64 * elem + 64 * 8 + 8 + 255) // 256 * 256)
 
 

@@ -54,14 +54,18 @@ def _direct(alpha, coef, preds, x: int, n: int):
 @pytest.mark.parametrize("n", [4, 7, 10])
 def test_worked_example_relu_integer_spec(n, r):
     """alpha = (0, N/2, N), P_0 = x, P_1 = 0, z = MSB(x): y_0 + y_1 = max(x, 0) + r_out
-    and z_0 ^ z_1 = MSB(x) for every x; the lookup partition has M = 3 intervals
-    and the packed comparison two atoms of width n."""
+    and z_0 ^ z_1 = MSB(x) for every x; the lookup partition has M = 3 intervals.
+    The packed comparison's two queries are 1[v < (r + N/2) mod N] and the mask
+    query 1[v < r] on the canonical view, which is the lookup's own view: the
+    threshold query has an atom of width n, the mask query is answered by the
+    lookup DCF at v (so T = 1)."""
     N = 2**n
     alpha = [0, N // 2, N]
     S = O.compile_spec_int(n, alpha, [[0, 1], [0, 0]], [P(W.MSB_SHIFT, 0, c=0)], lookup_r=r)
     t = O.spec_tables(S)
-    assert (t["m"], t["p"], t["T"]) == (2, 2, 2)
-    assert all(k == n for k, _, _ in t["atoms"])
+    assert (t["m"], t["p"], t["T"]) == (2, 2, 1)
+    assert S.n_prim == 1 and S.n_views == 1 and S.lookup_view == 0
+    assert t["atoms"] == [(n, 0, 0)]
     for rr in (0, 1, N // 2, N - 1, 12345 % N):
         B, ordv = O.protocol3(n, alpha, rr)
         assert len(B) == 4 and len(ordv) == 3

@@ -95,17 +95,22 @@ def test_sentinels_are_folded_not_emitted():
     desc = W.SpecDesc("sent", [(-math.inf, 0.0), (0.0, math.inf)], [[0.0], [1.0]], preds)
     S = O.compile_spec(desc, 8, 2)
     t = O.spec_tables(S)
-    assert t["T"] == 2 and S.n_prim == 1 and S.n_views == 1
+    # one threshold atom; its view (signed, n bits) is the lookup's, so its
+    # mask query is the lookup DCF's and has no atom
+    assert t["T"] == 1 and S.n_prim == 1 and S.n_views == 1 and S.lookup_view == 0
     assert t["negate"][:5] == [0, 1, 0, 1, 0] and t["negate"][5] == 1
 
 
 def test_config_specs_shape():
-    """Every config spec: two signed predicates sharing one view -> T = 3."""
+    """Every config spec: two signed predicates sharing one view, the signed
+    (offset-binary) view the lookup reads too -> two threshold atoms; the
+    view's mask query is answered by the lookup DCF (T = 2)."""
     for desc in W.all_specs()[:7]:
         n, f = (16, 8) if desc.name == "clip_relu" else (24, 12)
-        t = O.spec_tables(O.compile_spec(desc, n, f))
-        assert t["T"] == 3 and t["ell"] == 2
-        assert t["atoms"] == [(n, 2**(n - 1), 0), (n, 2**(n - 1), 0), (n, 2**(n - 1), 1)]
+        S = O.compile_spec(desc, n, f)
+        t = O.spec_tables(S)
+        assert t["T"] == 2 and t["ell"] == 2 and S.n_views == 1 and S.lookup_view == 0
+        assert t["atoms"] == [(n, 2**(n - 1), 0), (n, 2**(n - 1), 0)]
     t = O.spec_tables(O.compile_spec(W.gelu_spec(), 24, 12))
     assert (t["m"], t["p"], t["F_out"]) == (18, 3, 48)
     t = O.spec_tables(O.compile_spec(W.exp_spec(), 24, 12))
