@@ -227,3 +227,57 @@ def test_worked_relu_example():
     _flush("worked ReLU")
     h = _lit_case(spec, S, n, 0, x, 2**127 + 1)
     assert np.array_equal(h["y0"] + h["y1"] - h["r_out"], np.maximum(x, 0).view(np.uint64))
+
+
+def test_relu_phi_composed_from_the_library():
+    """A post-processing circuit built from the library's pieces alone:
+    ReLU(x) = x (1 - MSB(x)) on additively shared x.  The sign bit comes
+    from an operator gate on the masked opening (call 1, predicate MSB(x)),
+    NOT is party 0's local flip, B2A gives additive shares of 1 - MSB(x),
+    and one Beaver product multiplies them with x (n = 16, every input)."""
+    n = 16
+    Nn = 1 << n
+    x = np.arange(-(Nn // 2), Nn // 2, dtype=np.int64)
+    N = len(x)
+    words = (N + 63) // 64
+    # the sign bit: an integer spec with one constant piece and MSB(x) as output 0
+    spec = F.Spec.integer(n, [0, Nn], [[0]], [W.PredDesc(W.MSB_SHIFT, 0, c=0)])
+    gate = R.OpInstanceGPU(spec, n, 0, N)
+    gate.set_input(x)
+    gate.keygen(2**90 + 11)
+    gate.mask()
+    for b in (0, 1):
+        gate.eval_plain(b)
+    # NOT z: party 0 flips its XOR share
+    ones = _dev(np.full(words, 2**64 - 1, dtype=np.uint64))
+    nz0 = _empty(words)
+    F.fss_xor_mask(gate.z[0][:words], ones, None, None, words, nz0, None)
+    nz1 = gate.z[1][:words]
+    # B2A of NOT z
+    seed = 0xB2A
+    t0, t1, T0, T1 = _empty(words), _empty(words), _empty(N), _empty(N)
+    F.fss_b2a_rand(seed, N, 0, t0, t1, T0, T1)
+    c0, c1, C = _empty(words), _empty(words), _empty(words)
+    F.fss_xor_mask(nz0, t0, None, None, words, c0, None)
+    F.fss_xor_mask(nz1, t1, None, None, words, c1, None)
+    F.fss_xopen(c0, c1, words, C)
+    v = {0: _empty(N), 1: _empty(N)}
+    F.fss_b2a(0, C, T0, N, v[0])
+    F.fss_b2a(1, C, T1, N, v[1])
+    # x (1 - MSB(x)) with one Beaver product on additive shares of x
+    g = np.random.Generator(np.random.PCG64(9))
+    x0 = g.integers(0, 2**63, size=N, dtype=np.uint64) * np.uint64(2)
+    X = {0: _dev(x0), 1: _dev(x.view(np.uint64) - x0)}
+    T = {k: _empty(N) for k in ("a0", "b0", "c0", "a1", "b1", "c1")}
+    F.fss_triples(seed, N, 1, T["a0"], T["b0"], T["c0"], T["a1"], T["b1"], T["c1"])
+    d, e, D, E, y = ({b: _empty(N) for b in (0, 1)}, {b: _empty(N) for b in (0, 1)}, _empty(N), _empty(N),
+                     {b: _empty(N) for b in (0, 1)})
+    for b in (0, 1):
+        F.fss_beaver_mask(X[b], v[b], T[f"a{b}"], T[f"b{b}"], N, d[b], e[b])
+    F.fss_open(d[0], d[1], N, D)
+    F.fss_open(e[0], e[1], N, E)
+    for b in (0, 1):
+        F.fss_beaver_mul(b, D, E, T[f"a{b}"], T[f"b{b}"], T[f"c{b}"], None, N, y[b])
+    assert F.fss_status() == 0
+    _flush("relu phi composed")
+    assert np.array_equal(_host(y[0])[:N] + _host(y[1])[:N], np.maximum(x, 0).view(np.uint64))
