@@ -281,3 +281,76 @@ def test_relu_phi_composed_from_the_library():
     assert F.fss_status() == 0
     _flush("relu phi composed")
     assert np.array_equal(_host(y[0])[:N] + _host(y[1])[:N], np.maximum(x, 0).view(np.uint64))
+
+
+def test_literal_lookup_widest_domain_and_degree():
+    """n = 32 (the widest domain) with degree-3 ring coefficients at r = 4
+    and r = 3, ragged size, every share against the oracle."""
+    import random
+    rnd = random.Random(71)
+    n = 32
+    Nn = 1 << n
+    for r in (3, 4):
+        alpha = [0] + sorted(rnd.sample(range(1, Nn), 4)) + [Nn]
+        coef = [[rnd.getrandbits(64) for _ in range(4)] for _ in range(5)]
+        spec = F.Spec.integer(n, alpha, coef, lookup_r=r)
+        S = O.compile_spec_int(n, alpha, coef, lookup_r=r)
+        x = np.array([rnd.randint(-(Nn // 2), Nn // 2 - 1) for _ in range(200 + 3)], dtype=np.int64)
+        x[:4] = [a - Nn if a >= Nn // 2 else a for a in alpha[1:5]]  # on the boundaries
+        _flush(f"literal lookup n=32 d=3 r={r}")
+        _lit_case(spec, S, n, 0, x, rnd.getrandbits(128))
+
+
+def test_literal_keys_are_one_time():
+    """A literal key evaluated again at the same x-hat gives the same shares;
+    at another x-hat the changed elements are refused (zero shares,
+    FSS_E_CONSUMED)."""
+    desc = W.clip_relu_spec()
+    spec = F.Spec(desc)
+    x = W.config1()[0].x[:300]
+    g = R.LiteralGPU(spec, 16, 8, len(x))
+    g.set_input(x)
+    g.keygen(7)
+    g.mask()
+    for b in (0, 1):
+        F.fss_lit_eval(b, g.keys[b], g.xhat, len(x), g.coef[b], g.xs[b])
+    assert F.fss_status() == 0
+    first = [_host(g.coef[b]).copy() for b in (0, 1)]
+    for b in (0, 1):
+        F.fss_lit_eval(b, g.keys[b], g.xhat, len(x), g.coef[b], g.xs[b])
+    assert F.fss_status() == 0
+    assert all(np.array_equal(_host(g.coef[b]), first[b]) for b in (0, 1))
+    g.xhat[5] += 1
+    F.fss_lit_eval(0, g.keys[0], g.xhat, len(x), g.coef[0], g.xs[0])
+    assert F.fss_status() == -9
+    c = _host(g.coef[0])[: g.p * len(x)].reshape(g.p, len(x))
+    assert np.all(c[:, 5] == 0) and int(_host(g.xs[0])[5]) == 0
+    keep = np.r_[0:5, 6:len(x)]
+    assert np.array_equal(c[:, keep], first[0][: g.p * len(x)].reshape(g.p, len(x))[:, keep])
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 129])
+def test_subprotocols_at_edge_sizes(n):
+    """Beaver, AND and B2A over 1, 63, 64, 65 and 129 elements (bit words
+    with a ragged last word), against the operations they implement."""
+    g = np.random.Generator(np.random.PCG64(100 + n))
+    u, v, u0, v0 = (g.integers(0, 2**63, size=n, dtype=np.uint64) * np.uint64(2) + np.uint64(1) for _ in range(4))
+    T = {k: _empty(n) for k in ("a0", "b0", "c0", "a1", "b1", "c1")}
+    F.fss_triples(n, n, 0, T["a0"], T["b0"], T["c0"], T["a1"], T["b1"], T["c1"])
+    U, V = {0: _dev(u0), 1: _dev(u - u0)}, {0: _dev(v0), 1: _dev(v - v0)}
+    d, e, D, E, z = ({b: _empty(n) for b in (0, 1)}, {b: _empty(n) for b in (0, 1)}, _empty(n), _empty(n),
+                     {b: _empty(n) for b in (0, 1)})
+    for b in (0, 1):
+        F.fss_beaver_mask(U[b], V[b], T[f"a{b}"], T[f"b{b}"], n, d[b], e[b])
+    F.fss_open(d[0], d[1], n, D)
+    F.fss_open(e[0], e[1], n, E)
+    for b in (0, 1):
+        F.fss_beaver_mul(b, D, E, T[f"a{b}"], T[f"b{b}"], T[f"c{b}"], None, n, z[b])
+    assert np.array_equal(_host(z[0])[:n] + _host(z[1])[:n], u * v)
+    words = (n + 63) // 64
+    bits = g.integers(0, 2**63, size=words, dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    s0 = g.integers(0, 2**63, size=words, dtype=np.uint64)
+    _flush(f"subprotocols n={n}")
+    o0, o1, *_ = _b2a(_dev(s0), _dev(bits ^ s0), n, 3, 1)
+    assert np.array_equal(o0 + o1, _bits(bits, n))
+    assert F.fss_status() == 0
