@@ -176,8 +176,9 @@ def main() -> None:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build evaluates on one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by element range across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: evaluation runs on one GPU; --gpus {args.gpus} is not supported "
+              "(elements are independent, so the path would shard by element range, one process per GPU)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -675,75 +675,66 @@ __device__ __forceinline__ uint64_t coeff_tile(const TB& tb, GHdr h, const uint8
     for (int w = 0; w < 4; ++w) ts[c][w] = root.s[w];
     ts[c][4] = root.t;
   }
-  // The walks of one tile as a single sequence of jobs, so the walk (and the
-  // AES it unrolls) is emitted once: the NT top blocks through the shared
-  // levels [0, D), the points' walks below them [D, L), then the walk at v
-  // [0, L).  The job kind is the same on every lane.
-  const int ntop = iend > i0 ? NT : 0, npts = iend > i0 ? iend - i0 : 0;
-  const int njobs = ntop + npts + (base ? 1 : 0);
+  if (iend > i0) {
 #pragma unroll 1
-  for (int job = 0; job < njobs; ++job) {
-    const int kind = job < ntop ? 0 : job < ntop + npts ? 1 : 2;  // top block, point, base
-    VState<P> st = root;
-    uint32_t x = v;
-    int lo = 0, hi = L, i = 0;
-    if (kind == 0) {
-      x = (uint32_t)((uint64_t)((blkA + (uint32_t)job) & blk_mask) << K);
-      hi = D;
-    } else if (kind == 1) {
-      i = i0 + (job - ntop);
-      x = (v - (uint32_t)h->aprime[i]) & Nmask;
-      const uint32_t off = ((x >> K) - blkA) & blk_mask;  // D = 0: every block holds the root
-#pragma unroll
-      for (int w = 0; w < 5; ++w) {
-        uint32_t y = ts[0][w];
-#pragma unroll
-        for (int c = 1; c < kMaxTopBlocks; ++c) y = off == (uint32_t)c ? ts[c][w] : y;
-        if (w < 4) st.s[w] = y; else st.t = y;
-      }
-      lo = D;
-    }
-    vec_walk<P, R>(tb, h, tile, lane, b, x, lo, hi, st);
-    if (kind == 0) {
-      // the block's state below the shared levels, and its partial sums for
-      // the points it holds
+    for (int bk = 0; bk < NT; ++bk) {
+      VState<P> st = root;
+      vec_walk<P, R>(tb, h, tile, lane, b, (uint32_t)((uint64_t)((blkA + (uint32_t)bk) & blk_mask) << K), 0, D, st);
 #pragma unroll
       for (int c = 0; c < kMaxTopBlocks; ++c)
-        if (c == job) {
+        if (c == bk) {
 #pragma unroll
           for (int w = 0; w < 4; ++w) ts[c][w] = st.s[w];
           ts[c][4] = st.t;
         }
-      for (int pi = i0; pi < iend; ++pi) {
-        const uint32_t u = (v - (uint32_t)h->aprime[pi]) & Nmask;
-        const uint64_t in = ((((u >> K) - blkA) & blk_mask) == (uint32_t)job) ? ~0ull : 0ull;
+      for (int i = i0; i < iend; ++i) {
+        const uint32_t u = (v - (uint32_t)h->aprime[i]) & Nmask;
+        const uint64_t in = ((((u >> K) - blkA) & blk_mask) == (uint32_t)bk) ? ~0ull : 0ull;
 #pragma unroll
-        for (int jj = 0; jj < P; ++jj)
+        for (int j = 0; j < P; ++j)
 #pragma unroll
-          for (int k = 0; jj + k < P; ++k) q[jj] += h->tab[pi][jj][k] * (st.V[k] & in);
+          for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * (st.V[k] & in);
       }
-    } else if (kind == 1) {
-      const uint64_t lt = v < (uint32_t)h->aprime[i] ? ~0ull : 0ull;
-      uint64_t g[P];
-#pragma unroll
-      for (int k = 0; k < P; ++k) g[k] = st.V[k] + (ld8(rhop + (uint64_t)k * kTile * 8) & lt);
-#pragma unroll
-      for (int jj = 0; jj < P; ++jj)
-#pragma unroll
-        for (int k = 0; jj + k < P; ++k) q[jj] += h->tab[i][jj][k] * g[k];
-    } else {
-      // this party's XOR share of 1[v < r_n]: its share of rho_0 1[v < r_n], mod 2
-      if (lbit) *lbit = (uint32_t)(st.V[0] & 1ull);
-#pragma unroll
-      for (int jj = 0; jj < P; ++jj)
-#pragma unroll
-        for (int k = 0; jj + k < P; ++k) q[jj] -= h->tabv[jj][k] * st.V[k];
-#pragma unroll
-      for (int jj = 0; jj < P; ++jj)
-#pragma unroll
-        for (int k = 0; jj + k < P; ++k) q[jj] += h->tab[0][jj][k] * ld8(rhop + (uint64_t)k * kTile * 8);
-      q[0] += ld8(tile + h->off_crout + lane * 8);
     }
+  }
+  for (int i = i0; i < iend; ++i) {
+    const uint32_t ap = (uint32_t)h->aprime[i];
+    const uint32_t u = (v - ap) & Nmask;
+    const uint32_t off = ((u >> K) - blkA) & blk_mask;  // D = 0: every block holds the root
+    VState<P> st;
+#pragma unroll
+    for (int w = 0; w < 5; ++w) {
+      uint32_t x = ts[0][w];
+#pragma unroll
+      for (int c = 1; c < kMaxTopBlocks; ++c) x = off == (uint32_t)c ? ts[c][w] : x;
+      if (w < 4) st.s[w] = x; else st.t = x;
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) st.V[k] = 0;
+    vec_walk<P, R>(tb, h, tile, lane, b, u, D, L, st);
+    const uint64_t lt = v < ap ? ~0ull : 0ull;
+    uint64_t g[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) g[k] = st.V[k] + (ld8(rhop + (uint64_t)k * kTile * 8) & lt);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int k = 0; j + k < P; ++k) q[j] += h->tab[i][j][k] * g[k];
+  }
+  if (base) {
+    VState<P> st = vroot<P>(h, tile, lane, b);
+    vec_walk<P, R>(tb, h, tile, lane, b, v, 0, L, st);
+    // this party's XOR share of 1[v < r_n]: its share of rho_0 1[v < r_n], mod 2
+    if (lbit) *lbit = (uint32_t)(st.V[0] & 1ull);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int k = 0; j + k < P; ++k) q[j] -= h->tabv[j][k] * st.V[k];
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+      for (int k = 0; j + k < P; ++k) q[j] += h->tab[0][j][k] * ld8(rhop + (uint64_t)k * kTile * 8);
+    q[0] += ld8(tile + h->off_crout + lane * 8);
   }
   uint64_t y = q[P - 1];
 #pragma unroll

@@ -1,6 +1,6 @@
 """Fixed-point approximation error of the config specs against their FP64
-reference functions (reported in the design doc; bounds here are loose sanity
-limits, not accuracy claims)."""
+reference functions (the bounds here are loose sanity limits, not accuracy
+claims)."""
 import numpy as np
 import pytest
 
