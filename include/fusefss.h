@@ -370,8 +370,9 @@ int fss_aes_variants(void);
 /* The key-layout knob: pick the input bits per level of call 2's DCF (2, 3
  * or 4, fss_spec_set_lookup_radix) for `spec` at (n_bits, frac_bits) over
  * n_elems elements by timing one step per candidate -- both parties' keygen
- * and one fused launch of both parties' evaluation -- on scratch buffers this
- * call allocates and frees.  A larger radix (larger keys) must be faster by
+ * and one fused launch of both parties' evaluation, at masked inputs spread
+ * uniformly over the ring -- on scratch buffers this call allocates and
+ * frees; the fastest of four timed steps counts.  A larger radix (larger keys) must be faster by
  * 2 % to be chosen.  Sets the spec's radix to the winner and returns it in
  * *best_bits; results are cached in `cache_path` (may be NULL) keyed by the
  * spec, sizes and device.  Keys generated afterwards use the chosen radix. */

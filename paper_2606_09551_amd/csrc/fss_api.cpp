@@ -1790,7 +1790,7 @@ int fss_autotune_radix(fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_
   int rc = device_cus(&cus, &arch);
   if (rc) return rc;
   std::ostringstream key;
-  key << "radix|" << arch << ":" << cus << "|" << std::hex << spec->hash << std::dec << "," << n_bits << ","
+  key << "radix2|" << arch << ":" << cus << "|" << std::hex << spec->hash << std::dec << "," << n_bits << ","
       << frac_bits << "," << n_elems;
   const std::string k = std::to_string(fnv1a(key.str().data(), key.str().size()));
   if (cache_path) {
@@ -1824,7 +1824,21 @@ int fss_autotune_radix(fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_
   if (hipMalloc(&xh, 8 * (size_t)n_elems) != hipSuccess || hipMalloc(&y, 16 * (size_t)n_elems) != hipSuccess ||
       hipMalloc(&z, 16 * std::max<size_t>(1, (size_t)ell * words)) != hipSuccess)
     rc = fail(FSS_E_HIP, "hipMalloc(radix autotune buffers)");
-  if (rc == FSS_OK) (void)hipMemsetAsync(xh, 0, 8 * (size_t)n_elems, s);
+  if (rc == FSS_OK) {
+    // masked inputs are uniform over the ring: spread x-hat the same way, so
+    // the lookup walks pick children as they do on real inputs (x-hat = 0
+    // would send every lane of a wave down the same records)
+    std::vector<uint64_t> hx((size_t)n_elems);
+    uint64_t st = 0x9e3779b97f4a7c15ull;
+    for (auto& v : hx) {  // splitmix64 (Steele, Lea, Flood 2014)
+      uint64_t z = (st += 0x9e3779b97f4a7c15ull);
+      z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+      z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+      v = z ^ (z >> 31);
+    }
+    if (hipMemcpy(xh, hx.data(), 8 * (size_t)n_elems, hipMemcpyHostToDevice) != hipSuccess)
+      rc = fail(FSS_E_HIP, "hipMemcpy(radix autotune inputs)");
+  }
   for (int r = 2; r <= 4 && rc == FSS_OK; ++r) {
     if ((rc = fss_spec_set_lookup_radix(spec, r))) break;
     size_t kb = 0;
@@ -1836,10 +1850,10 @@ int fss_autotune_radix(fss_spec* spec, int32_t n_bits, int32_t frac_bits, int64_
       break;
     }
     // one step as the benchmark times it: both parties' keys, then one fused
-    // launch of both parties' evaluation; the faster of two after a warm-up
+    // launch of both parties' evaluation; the fastest of four after a warm-up
     double ms = 1e30;
     fss_plan* P = nullptr;
-    for (int rep = 0; rep < 3 && rc == FSS_OK; ++rep) {
+    for (int rep = 0; rep < 5 && rc == FSS_OK; ++rep) {
       (void)hipEventRecord(e0, s);
       rc = fss_keygen(spec, n_bits, frac_bits, seed, n_elems, k0, k1, nullptr, nullptr, s);
       if (rc == FSS_OK && !P) {
