@@ -12,7 +12,7 @@ pass of the whole hot path over the batch:
 of the timed steps.  The plain evaluator (two launches per party) is timed on
 the same inputs for comparison.
 
-Prints ONE JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N with N > 1 exits: evaluation runs on one GPU.
 """
 from __future__ import annotations
 
