@@ -38,12 +38,13 @@ def _flush(msg):
     print(msg, flush=True)
 
 
-def gpu_worklist(ops, tune=None, graph=False, keep=None):
+def gpu_worklist(ops, tune=None, graph=False, keep=None, lookup_r=None):
     """Keygen + masked opening + one fused launch over every op and both
-    parties.  keep: {op index: element indices} to return (default: all)."""
+    parties.  keep: {op index: element indices} to return (default: all);
+    lookup_r: the lookup radix of every op's spec (default: the spec's)."""
     insts = []
     for op in ops:
-        inst = R.OpInstanceGPU(F.Spec(op.spec), W.N_BITS, W.F_BITS, len(op.x))
+        inst = R.OpInstanceGPU(F.Spec(op.spec, lookup_r=lookup_r), W.N_BITS, W.F_BITS, len(op.x))
         inst.set_input(op.x)
         inst.keygen(op.seed)
         inst.mask()
@@ -120,6 +121,25 @@ def test_c2_gelu_every_element_autotuned_plan(tmp_path):
            f"parts={tune.parts} pred_unit={tune.pred_unit}")
     rec = gpu_worklist([op], tune=tune, graph=True)[0]
     check_vs_oracle(op, rec)
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_c2_gelu_every_element_other_radices(r, tmp_path):
+    """The radix autotuner may pick any of r = 2, 3, 4 for the benchmark's
+    GELU: the other two radices, at full size, with the plan autotuned for
+    them and replayed from a HIP graph."""
+    op = W.config2()[0]
+    spec = F.Spec(op.spec, lookup_r=r)
+    inst = R.OpInstanceGPU(spec, W.N_BITS, W.F_BITS, len(op.x))
+    inst.set_input(op.x)
+    inst.keygen(op.seed)
+    torch.cuda.synchronize()
+    tune = F.fss_autotune([inst.item(0), inst.item(1)], str(tmp_path / "tune.txt"))
+    del inst
+    _flush(f"c2 gelu r={r} autotuned: variant={tune.aes_variant} bpc={tune.blocks_per_cu} order={tune.order} "
+           f"parts={tune.parts} pred_unit={tune.pred_unit}")
+    rec = gpu_worklist([op], tune=tune, graph=True, lookup_r=r)[0]
+    check_vs_oracle(op, rec, lookup_r=r)
 
 
 def test_c3_softmax_helpers_every_element():
