@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fss_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
-MAXN, MAXP, MAXM, MAXPRED, MAXT, MAXL = 32, 4, 64, 8, 12, 8
+MAXN, MAXP, MAXM, MAXPRED, MAXT, MAXL = 32, 4, 64, 16, 16, 64
 LT_SIGNED, LT_UNSIGNED, LOWBITS_LT, MSB_SHIFT = 0, 1, 2, 3
 
 

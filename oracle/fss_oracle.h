@@ -31,9 +31,9 @@
 #define ORC_MAXN 32   /* comparison bit width n */
 #define ORC_MAXP 4    /* payload length p = d + 1 */
 #define ORC_MAXM 64   /* intervals m */
-#define ORC_MAXPRED 8 /* primitive predicates */
-#define ORC_MAXT 12   /* comparison atoms */
-#define ORC_MAXL 8    /* predicate output bits */
+#define ORC_MAXPRED 16 /* primitive predicates */
+#define ORC_MAXT 16    /* comparison atoms */
+#define ORC_MAXL 64    /* predicate output bits (one 64-bit word) */
 
 typedef struct { uint64_t lo, hi; } orc_blk;
 

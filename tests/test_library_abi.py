@@ -69,6 +69,10 @@ def test_integer_spec_tables_match_oracle():
                  P(W.LT_UNSIGNED, 1, thr=float(rnd.randint(1, N - 1))),
                  P(W.LOWBITS_LT, 1, f_bits=min(n, 3), gamma=2), P(W.MSB_SHIFT, 2, c=rnd.randint(0, N - 1))]
         cases.append((n, alpha, coef, preds))
+    # the interface's largest spec (64 intervals, degree 3, 16 predicates,
+    # 16 atoms, 64 output bits) at n = 8 and 32
+    from maxspec import max_int_spec
+    cases += [(n, *max_int_spec(rnd, n)) for n in (8, 32)]
     for n, alpha, coef, preds in cases:
         lib_t = F.Spec.integer(n, alpha, coef, preds).query(n, 0)
         orc = O.spec_tables(O.compile_spec_int(n, alpha, coef, preds))

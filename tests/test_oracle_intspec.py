@@ -18,6 +18,7 @@ import pytest
 
 import oracle as O
 from paper_2606_09551_amd import workloads as W
+from maxspec import max_int_spec
 
 M64 = 2**64 - 1
 P = W.PredDesc
@@ -113,6 +114,33 @@ def test_random_integer_specs_reconstruct(r):
         assert np.array_equal(z0 ^ z1, zw), (trial, n)
         yp, zp = O.plain_many(S, xs)
         assert np.array_equal(yp, yw) and np.array_equal(zp, zw)
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_maximum_sizes_reconstruct(r):
+    """At the interface's limits (m = 64, p = 4, 16 predicates, T = 16,
+    ell = 64): exhaustive reconstruction at n = 8 against the definition."""
+    rnd = random.Random(700 + r)
+    n, N = 8, 256
+    alpha, coef, preds = max_int_spec(rnd, n)
+    S = O.compile_spec_int(n, alpha, coef, preds, lookup_r=r)
+    t = O.spec_tables(S)
+    assert (t["m"], t["p"], t["T"], S.ell) == (64, 4, 16, 64)
+    xs = np.arange(-N // 2, N // 2, dtype=np.int64)
+    want = [_direct(alpha, coef, preds, int(x), n) for x in xs]
+    yw = np.array([w[0] for w in want], dtype=np.uint64)
+    zw = np.array([w[1] for w in want], dtype=np.uint64)
+    for seed in (rnd.getrandbits(128), 2**127 + 1):
+        y0, y1, z0, z1, r_in, r_out, _ = O.full(S, seed, np.arange(N, dtype=np.int64), xs, masks=True)
+        assert np.array_equal(y0 + y1 - r_out, yw)
+        assert np.array_equal(z0 ^ z1, zw)
+    yp, zp = O.plain_many(S, xs)
+    assert np.array_equal(yp, yw) and np.array_equal(zp, zw)
+    # one predicate more, or one more atom, is past the limit
+    with pytest.raises(O.SpecError):
+        O.compile_spec_int(n, alpha, coef, preds + [P(W.LT_UNSIGNED, 1, thr=3.0)], lookup_r=r)
+    with pytest.raises(O.SpecError):
+        O.compile_spec_int(n, alpha, coef, preds[:-1] + [P(W.LOWBITS_LT, 2, f_bits=2, gamma=1)], lookup_r=r)
 
 
 def test_integer_spec_rejections():
