@@ -141,6 +141,33 @@ def test_random_integer_specs(r):
 
 
 @pytest.mark.parametrize("r", [2, 3, 4])
+def test_maximum_spec_sizes(r):
+    """The interface's largest spec (64 intervals, degree 3, 16 predicates,
+    16 comparison atoms, 64 output bits): every input at n = 8, and 777
+    inputs over the whole domain at n = 32 (boundaries included), plain and
+    fused with call 1 in the call-2 unit and in its own."""
+    from maxspec import max_int_spec
+    rnd = random.Random(950 + r)
+    for n in (8, 32):
+        N = 1 << n
+        alpha, coef, preds = max_int_spec(rnd, n)
+        spec = F.Spec.integer(n, alpha, coef, preds, lookup_r=r)
+        q = spec.query(n, 0)
+        assert (q["m"], q["p"], q["T"], q["ell"]) == (64, 4, 16, 64)
+        S = O.compile_spec_int(n, alpha, coef, preds, lookup_r=r)
+        if n == 8:
+            x = np.arange(-N // 2, N // 2, dtype=np.int64)
+        else:
+            x = np.array([rnd.randint(-(N // 2), N // 2 - 1) for _ in range(777)], dtype=np.int64)
+            x[:63] = [a - N if a >= N // 2 else a for a in alpha[1:-1]]  # on the boundaries
+        seed = rnd.getrandbits(128)
+        o = _oracle(S, x, seed)
+        for path, tune in (("plain", None), ("plan", F.Tune(0, 0, 1, 0, 1, 1)), ("plan", F.Tune(0, 0, 1, 0, 2, 2))):
+            _flush(f"maximum spec n={n} r={r} path={path} pred_unit={tune and tune.pred_unit}")
+            _check(_run(spec, n, 0, x, seed, path, tune), o, len(x), (n, path, tune and tune.pred_unit))
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
 def test_predicates_all_constant(r):
     """Every predicate folds to a constant (thresholds outside the n-bit range,
     gamma = 0 and gamma = 2^f): no comparison atom remains (T = 0) but the
