@@ -109,13 +109,13 @@ def test_worked_relu_integer_spec(r):
 
 def _random_int_spec(rnd, n):
     N = 1 << n
-    m = rnd.randint(1, 24)
+    m = rnd.randint(1, min(24, N))
     alpha = [0] + sorted(rnd.sample(range(1, N), m - 1)) + [N]
     d = rnd.randint(0, 3)
     coef = [[rnd.getrandbits(64) for _ in range(d + 1)] for _ in range(m)]
     preds = [P(W.LT_SIGNED, 0, thr=float(rnd.randint(-N // 2, N // 2 - 1))),
              P(W.LT_UNSIGNED, 1, thr=float(rnd.randint(1, N - 1)), negate=True),
-             P(W.LOWBITS_LT, 1, f_bits=min(n, 5), gamma=rnd.randint(1, 31)),
+             P(W.LOWBITS_LT, 1, f_bits=min(n, 5), gamma=rnd.randint(1, (1 << min(n, 5)) - 1)),
              P(W.MSB_SHIFT, 2, c=rnd.randint(0, N - 1))]
     return alpha, coef, preds
 
@@ -138,6 +138,25 @@ def test_random_integer_specs(r):
         for path in ("plain", "plan"):
             _flush(f"random integer spec n={n} m={len(alpha) - 1} r={r} path={path}")
             _check(_run(spec, n, 0, x, seed, path), o, N, (n, path))
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_narrowest_domains(r):
+    """n = 2..7: one lookup level when r >= n, leading zero bits, comparison
+    atoms that are a leaf only (k <= 7); random integer specs, every input,
+    three copies of the domain per launch (ragged tiles), plain and fused."""
+    rnd = random.Random(970 + r)
+    for n in range(2, 8):
+        N = 1 << n
+        alpha, coef, preds = _random_int_spec(rnd, n)
+        spec = F.Spec.integer(n, alpha, coef, preds, lookup_r=r)
+        S = O.compile_spec_int(n, alpha, coef, preds, lookup_r=r)
+        x = np.tile(np.arange(-N // 2, N // 2, dtype=np.int64), 3)
+        seed = rnd.getrandbits(128)
+        o = _oracle(S, x, seed)
+        for path in ("plain", "plan"):
+            _flush(f"narrow domain n={n} m={len(alpha) - 1} r={r} path={path}")
+            _check(_run(spec, n, 0, x, seed, path), o, len(x), (n, path))
 
 
 @pytest.mark.parametrize("r", [2, 3, 4])

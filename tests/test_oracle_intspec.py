@@ -117,6 +117,24 @@ def test_random_integer_specs_reconstruct(r):
 
 
 @pytest.mark.parametrize("r", [2, 3, 4])
+def test_narrowest_domains_reconstruct(r):
+    """n = 2, 3, 4 (one lookup level at r >= n, leading zero bits, atoms that
+    are a leaf only): exhaustive reconstruction of random integer specs."""
+    rnd = random.Random(500 + r)
+    for n in (2, 3, 4):
+        N = 1 << n
+        for trial in range(4):
+            alpha, coef, preds = _random_int_spec(rnd, n)
+            S = O.compile_spec_int(n, alpha, coef, preds, lookup_r=r)
+            xs = np.arange(-N // 2, N // 2, dtype=np.int64)
+            want = [_direct(alpha, coef, preds, int(x), n) for x in xs]
+            seed = rnd.getrandbits(128)
+            y0, y1, z0, z1, r_in, r_out, _ = O.full(S, seed, np.arange(N, dtype=np.int64), xs, masks=True)
+            assert np.array_equal(y0 + y1 - r_out, np.array([w[0] for w in want], dtype=np.uint64)), (n, trial)
+            assert np.array_equal(z0 ^ z1, np.array([w[1] for w in want], dtype=np.uint64)), (n, trial)
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
 def test_maximum_sizes_reconstruct(r):
     """At the interface's limits (m = 64, p = 4, 16 predicates, T = 16,
     ell = 64): exhaustive reconstruction at n = 8 against the definition."""
