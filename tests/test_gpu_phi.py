@@ -283,6 +283,22 @@ def test_relu_phi_composed_from_the_library():
     assert np.array_equal(_host(y[0])[:N] + _host(y[1])[:N], np.maximum(x, 0).view(np.uint64))
 
 
+def test_literal_lookup_largest_partition():
+    """64 intervals at n = 8: the partition is padded to M = 65 (64 DCFs per
+    element), degree 3, every input twice (ragged tiles), every radix."""
+    import random
+    rnd = random.Random(81)
+    n, Nn = 8, 256
+    for r in (2, 3, 4):
+        alpha = [0] + sorted(rnd.sample(range(1, Nn), 63)) + [Nn]
+        coef = [[rnd.getrandbits(64) for _ in range(4)] for _ in range(64)]
+        spec = F.Spec.integer(n, alpha, coef, lookup_r=r)
+        S = O.compile_spec_int(n, alpha, coef, lookup_r=r)
+        x = np.tile(np.arange(-128, 128, dtype=np.int64), 2)
+        _flush(f"literal lookup m=64 n=8 r={r}")
+        _lit_case(spec, S, n, 0, x, rnd.getrandbits(128))
+
+
 def test_literal_lookup_widest_domain_and_degree():
     """n = 32 (the widest domain) with degree-3 ring coefficients at r = 4
     and r = 3, ragged size, every share against the oracle."""
