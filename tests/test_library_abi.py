@@ -125,6 +125,38 @@ def test_quantised_tables_match_oracle(desc, n, f):
     assert atoms == [(a[0], a[1], a[2]) for a in orc["atoms"]]
 
 
+def test_quantisers_agree_over_the_size_grid():
+    """Every real spec of the workloads at n = 2..32 and f from 0 to n - 1:
+    the library and the oracle accept the same (n, f) (a partition that
+    collapses, coefficients past 2^62 and the like are refused by both) and,
+    where they accept, build the same tables."""
+    descs = [W.clip_relu_spec(), W.gelu_spec(), W.exp_spec(), W.recip_spec(7), W.rsqrt_spec(),
+             W.relu_worked_example_spec()]
+    accepted = refused = 0
+    for desc in descs:
+        for n in (2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 31, 32):
+            for f in sorted({0, 1, 2, n // 4, n // 2, n - 2, n - 1} & set(range(n))):
+                try:
+                    lib_t = F.Spec(desc).query(n, f)
+                except F.FssError:
+                    lib_t = None
+                try:
+                    orc = O.spec_tables(O.compile_spec(desc, n, f))
+                except O.SpecError:
+                    orc = None
+                assert (lib_t is None) == (orc is None), (desc.name, n, f)
+                if lib_t is None:
+                    refused += 1
+                    continue
+                accepted += 1
+                for k in ("m", "d", "p", "F_out", "T", "ell", "aprime", "coef"):
+                    assert lib_t[k] == orc[k], (desc.name, n, f, k)
+                atoms = [(k, c % 2**64, msk) for k, c, msk in
+                         zip(lib_t["atom_k"], lib_t["atom_c"], lib_t["atom_is_mask"])]
+                assert atoms == [(a[0], a[1], a[2]) for a in orc["atoms"]], (desc.name, n, f)
+    assert accepted > 150 and refused > 150
+
+
 def test_mixed_predicates_match_oracle():
     P = W.PredDesc
     preds = [P(W.LT_SIGNED, 0, thr=-1.0), P(W.LT_SIGNED, 0, thr=2.5), P(W.LT_UNSIGNED, 1, thr=5.0),
