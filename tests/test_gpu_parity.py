@@ -172,6 +172,38 @@ def test_widest_domains(n, name, r):
         compare(g, o, np.arange(N), N, check_keys=8 if path == "plain" else 0)
 
 
+def test_real_specs_size_grid():
+    """The workloads' real specs at every (n, f) of a grid over n = 2..32 that
+    the quantiser accepts, the radix cycling through 2, 3, 4: every input for
+    n <= 8, 300 inputs over the whole domain (its ends included) above;
+    plain path and fused plan, both against the oracle."""
+    descs = [W.clip_relu_spec(), W.gelu_spec(), W.exp_spec(), W.recip_spec(7), W.rsqrt_spec()]
+    g_ = np.random.Generator(np.random.PCG64(2024))
+    done = 0
+    for desc in descs:
+        for n in (2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 31, 32):
+            for f in sorted({0, 1, n // 2, n - 1} & set(range(n))):
+                try:
+                    F.Spec(desc).query(n, f)
+                except F.FssError:
+                    continue  # refused by both quantisers (a host test checks that)
+                r = 2 + done % 3
+                s = 2 ** (n - 1)
+                if n <= 8:
+                    x = np.arange(-s, s, dtype=np.int64)
+                else:
+                    x = g_.integers(-s, s, size=300).astype(np.int64)
+                    x[:4] = [-s, s - 1, 0, -1]
+                seed = 0x6E1D + 97 * done
+                o = oracle_run(desc, n, f, x, seed, np.arange(len(x)), r)
+                for path in ("plain", "fused"):
+                    _flush(f"size grid {desc.name} n={n} f={f} r={r} path={path}")
+                    g = gpu_run(desc, n, f, x, seed, path=path, lookup_r=r)
+                    compare(g, o, np.arange(len(x)), len(x))
+                done += 1
+    assert done > 50
+
+
 @pytest.mark.parametrize("N", [1, 63, 64, 65, 129])
 def test_edge_sizes(N):
     op = W.config1()[0]
