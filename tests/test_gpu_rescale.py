@@ -63,6 +63,30 @@ def test_rescale_vs_oracle(shift, r):
     assert np.array_equal(g["z0"] + g["z1"] - g["r_out"], (y >> shift).view(np.uint64))
 
 
+def test_rescale_every_shift():
+    """Every shift the gate accepts (1..32), the radix cycling through 2, 3, 4,
+    200 elements each (inputs at the 2^62 bound, at multiples of 2^s and
+    beside them), against the oracle and Python's floor shift."""
+    for shift in range(1, 33):
+        r = 2 + shift % 3
+        rng = np.random.Generator(np.random.PCG64(7000 + shift))
+        n = 200
+        y = rng.integers(-2**62 + 1, 2**62, size=n, dtype=np.int64)
+        k = 1 << shift
+        y[:8] = [0, -1, k, -k, k - 1, -k - 1, 2**62 - 1, -2**62 + 1]
+        r_in = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+        r_in[:3] = [0, 2**63, 2**64 - 1]
+        yhat = (y.view(np.uint64) + r_in).astype(np.uint64)
+        y0 = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+        y1 = (yhat - y0).astype(np.uint64)
+        print(f"rescale every shift: shift={shift} r={r}", flush=True)
+        g = _rescale_gpu(shift, r, 0x7A + shift, r_in, y0, y1)
+        z0, z1, r_out = O.trunc(shift, 0x7A + shift, np.arange(n), r_in, yhat, lookup_r=r)
+        for name, v in (("z0", z0), ("z1", z1), ("r_out", r_out)):
+            assert np.array_equal(g[name], v), (shift, name)
+        assert np.array_equal(g["z0"] + g["z1"] - g["r_out"], (y >> shift).view(np.uint64)), shift
+
+
 @pytest.mark.parametrize("case", ["clip_relu_4096", "gelu_65536_fout36"])
 def test_operator_then_rescale(case):
     """An operator gate (fused launch, both parties), the opening of its
