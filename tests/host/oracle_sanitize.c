@@ -1,8 +1,8 @@
 /* Drives the oracle at its size limits for an AddressSanitizer /
  * UndefinedBehaviorSanitizer build (CPU only): the widest comparison domain
  * (n = 32) at the smallest lookup radix (16 levels), the most intervals
- * (m = 64), the most predicates, Protocol 3 at m = 64, integer specs and the
- * rescaling gate at s = 32.  Prints "ok" when every reconstruction holds. */
+ * (m = 64), the most predicates, atoms and output bits (16, 16, 64), Protocol 3
+ * at m = 64, integer specs and the rescaling gate at s = 32.  Prints "ok" when every reconstruction holds. */
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -33,7 +33,7 @@ static int check_spec(orc_spec* S, int r) {
 }
 
 int main(void) {
-  /* m = 64 intervals of degree 3 at n = 32, f = 8, eight predicates */
+  /* m = 64 intervals of degree 3 at n = 32, f = 8, eight predicates of every kind */
   orc_interval iv[64];
   orc_piece pc[64];
   for (int i = 0; i < 64; i++) {
@@ -66,6 +66,29 @@ int main(void) {
   if (orc_spec_compile(iv, 64, pc, pr, 8, 32, 8, -1, &S2) == 0 && S2.T > ORC_MAXT) { puts("T overflow"); return 1; }
   if (orc_spec_compile(iv, 65, pc, pr, 8, 32, 8, -1, &S2) == 0) { puts("m = 65 accepted"); return 1; }
   if (orc_spec_compile(iv, 64, pc, pr, 8, 33, 8, -1, &S2) == 0) { puts("n = 33 accepted"); return 1; }
+  /* sixteen predicates, sixteen atoms and output bit 63 (the interface's
+   * limits); a seventeenth predicate is rejected */
+  {
+    orc_pred pm[17];
+    memset(pm, 0, sizeof pm);
+    for (int i = 0; i < 12; i++) {
+      pm[i].kind = ORC_LT_SIGNED;
+      pm[i].out = 5 * i;
+      pm[i].thr = -20.0 + 3.25 * i;
+      pm[i].negate = i & 1;
+    }
+    pm[12].kind = ORC_LOWBITS_LT; pm[12].out = 63; pm[12].f_bits = 5; pm[12].gamma = 7;
+    pm[13].kind = ORC_MSB_SHIFT;  pm[13].out = 62; pm[13].c = 77;
+    pm[14].kind = ORC_LT_SIGNED;  pm[14].out = 61; pm[14].thr = -1e30;  /* constant 0 */
+    pm[15].kind = ORC_LT_SIGNED;  pm[15].out = 0;  pm[15].thr = 1e30;   /* constant 1 */
+    pm[16] = pm[0];
+    static orc_spec S4;
+    if (orc_spec_compile(iv, 64, pc, pm, 16, 32, 8, -1, &S4) != 0) { puts("16 predicates rejected"); return 1; }
+    if (S4.T != ORC_MAXT || S4.ell != ORC_MAXL) { printf("T=%d ell=%d\n", S4.T, S4.ell); return 1; }
+    for (int r = 2; r <= 4; r++)
+      if (check_spec(&S4, r)) { printf("16-predicate reconstruction failed at r=%d\n", r); return 1; }
+    if (orc_spec_compile(iv, 64, pc, pm, 17, 32, 8, -1, &S4) == 0) { puts("17 predicates accepted"); return 1; }
+  }
   /* Protocol 3 at m = 64, n = 32 and at a tiny domain */
   uint64_t alpha[65], B[67];
   int32_t ord[66];

@@ -1,8 +1,9 @@
 """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer (gcc,
 CPU only) and driven at its size limits (n = 32 at radix 2, m = 64 intervals of
-degree 3, eight predicates, Protocol 3 at m = 64, integer specs, the rescaling
-gate at s = 32): no out-of-bounds access, no undefined behaviour, every
-reconstruction holds."""
+degree 3, 16 predicates with 16 atoms and 64 output bits, Protocol 3 at m = 64,
+integer specs, the rescaling gate at s = 32): no out-of-bounds access, no
+undefined behaviour, every reconstruction holds.  An LD_PRELOAD in the
+environment is left in place; the link-order check that it would trip is off."""
 import os
 import shutil
 import subprocess
@@ -24,7 +25,7 @@ def test_oracle_under_asan_and_ubsan(tmp_path):
     if r.returncode != 0 and "sanitize" in r.stdout and ("cannot find" in r.stdout or "unrecognized" in r.stdout):
         pytest.skip("sanitizer runtime not available: " + r.stdout[-200:])
     assert r.returncode == 0, r.stdout[-2000:]
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
-    env.pop("LD_PRELOAD", None)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
     run = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env, timeout=600)
     assert run.returncode == 0 and run.stdout.strip().endswith("ok"), run.stdout[-3000:]
