@@ -38,6 +38,8 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # (16 table-index extractions + 8 three-input XORs) + 16 for whitening,
 # last-round byte merge and the Matyas-Meyer-Oseas feed-forward.
 OPS_PER_AES = 256
+# MI355X HBM3E bandwidth, GB/s.
+HBM_PEAK_GBPS = 8000.0
 
 
 def pct(xs, q):
@@ -115,6 +117,18 @@ def measured_traffic(workload: str, lookup_r: int):
     if kv.get("kernel_sources_sha256_16") != hashlib.sha256(src).hexdigest()[:16] or want not in kv:
         return None
     return int(kv[want])
+
+
+def hbm_view(alg_bytes: float, traffic, launch_s: float) -> dict:
+    """The fused launch against the HBM roofline: algorithmic bytes and, where
+    the counters are on record, the measured bytes, per launch and as GB/s."""
+    out = {"algorithmic_bytes": int(alg_bytes), "algorithmic_gbps": round(alg_bytes / launch_s / 1e9, 1),
+           "peak_gbps": HBM_PEAK_GBPS, "traffic_bytes": traffic, "traffic_gbps": None, "frac": None}
+    if traffic:
+        gbps = traffic / launch_s / 1e9
+        out["traffic_gbps"] = round(gbps, 1)
+        out["frac"] = round(gbps / HBM_PEAK_GBPS, 4)
+    return out
 
 
 def build_ops(workload: str):
@@ -230,6 +244,9 @@ def main() -> None:
     cfg["parts"] = max(p.parts() for p in plans)
     eval_aes = sum(p.aes_blocks() for p in plans)
     eval_lookups = sum(p.table_lookups() for p in plans)
+    # algorithmic HBM bytes of the evaluation launches: both parties' keys read
+    # once, x-hat read, y and the predicate bit-planes written
+    eval_bytes = sum(2 * (i.key_bytes + 16 * i.n + 8 * i.ell * ((i.n + 63) // 64)) for i in insts)
     kg_work = [i.spec.keygen_work(n_bits, f_bits, i.n) for i in insts]
     kg_aes = sum(w[0] for w in kg_work)
     kg_lookups = sum(w[1] for w in kg_work)
@@ -393,6 +410,8 @@ def main() -> None:
                      "valu": {"achieved": round(valu_achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
                               "unit": "Tops/s", "frac": round(valu_achieved / VALU_PEAK_TOPS, 4),
                               "ops_per_aes_block": OPS_PER_AES},
+                     "hbm": hbm_view(eval_bytes / len(plans), measured_traffic(args.workload, insts[0].lookup_r),
+                                     eval_s / len(plans)),
                      "keygen": {"kernel": "k_keygen", "achieved": round(kg_achieved, 3),
                                 "peak": round(LOOKUP_PEAK_T, 3), "unit": "T table-lookups/s",
                                 "frac": round(kg_achieved / LOOKUP_PEAK_T, 4),
