@@ -687,21 +687,22 @@ int fss_keygen_work(const fss_spec* spec, int32_t n_bits, int32_t frac_bits, int
   // one leaf conversion per atom; per lookup level the 2^r children, two at a
   // time: a pair's seed blocks and the value blocks of the seed's value
   // stream it uses (odd p: the pair shares one of them), the last level
-  // values only.
-  double pair_aes, pair_lk, last_aes, last_lk;
+  // values only.  A lookup level expands every block from the party's one
+  // seed: its tweak-independent AES lookups (27: 15 of round 1, 12 of round
+  // 2) once per party and level, then 133 per block (the tweak byte's, four of
+  // round 2, rounds 3 to 10).
+  double pair_aes, last_aes;
   if (h.p == 3) {
-    pair_aes = 5; pair_lk = shared(3) + shared(2);
-    last_aes = 3; last_lk = shared(2) + shared(1);
+    pair_aes = 5; last_aes = 3;
   } else if (h.p == 1) {
-    pair_aes = 3; pair_lk = shared(2) + shared(1);
-    last_aes = 1; last_lk = shared(1);
+    pair_aes = 3; last_aes = 1;
   } else {
-    pair_aes = 2 * (1 + nb); pair_lk = 2 * shared(1 + nb);
-    last_aes = 2 * nb; last_lk = 2 * shared(nb);
+    pair_aes = 2 * (1 + nb); last_aes = 2 * nb;
   }
   const double pairs = C / 2;
-  const double prg_aes = atoms_lv * 2 * 2 + 2.0 * h.T + 2 * pairs * ((L - 1) * pair_aes + last_aes);
-  const double prg_lk = atoms_lv * 2 * shared(2) + 2.0 * 160 * h.T + 2 * pairs * ((L - 1) * pair_lk + last_lk);
+  const double lookup_blocks = pairs * ((L - 1) * pair_aes + last_aes);
+  const double prg_aes = atoms_lv * 2 * 2 + 2.0 * h.T + 2 * lookup_blocks;
+  const double prg_lk = atoms_lv * 2 * shared(2) + 2.0 * 160 * h.T + 2 * (27.0 * L + 133.0 * lookup_blocks);
   // Counter-mode randomness: masks (drawn by both halves of the work), the
   // r_out share, two roots per atom, carries, two lookup roots, two rho-share
   // blocks and 1 + nb on-path corrections per lookup level above the last.

@@ -352,6 +352,71 @@ __device__ __forceinline__ void prg_shared(const TB& tb, const uint32_t (&s)[4],
   }
 }
 
+// The tweak-independent part of H(s, .) for a seed that expands many blocks:
+// round 1's column-0 lookups other than the tweak byte's (c0), the tweak
+// byte's column word (a3), and round 2's twelve lookups of the columns the
+// tweak does not reach, XORed per output column with round 2's key word (p).
+struct PrgPrefix {
+  uint32_t a3, c0, p[4];
+};
+
+template <class TB>
+__device__ __forceinline__ void prg_prefix(const TB& tb, const uint32_t (&s)[4], PrgPrefix& q) {
+  constexpr PrgKey key{};
+  const uint32_t a0 = s[0] ^ key.template w<0>(), a1 = s[1] ^ key.template w<1>();
+  const uint32_t a2 = s[2] ^ key.template w<2>(), a3 = s[3] ^ key.template w<3>();
+  q.a3 = a3;
+  q.c0 = xor3(tb.template get<0, 0>(a0), tb.template get<1, 1>(a1), tb.template get<2, 2>(a2));
+  const uint32_t c1 = xor3(xor3(tb.template get<0, 0>(a1), tb.template get<1, 1>(a2), tb.template get<2, 2>(a3)),
+                           tb.template get<3, 3>(a0), key.template w<5>());
+  const uint32_t c2 = xor3(xor3(tb.template get<0, 0>(a2), tb.template get<1, 1>(a3), tb.template get<2, 2>(a0)),
+                           tb.template get<3, 3>(a1), key.template w<6>());
+  const uint32_t c3 = xor3(xor3(tb.template get<0, 0>(a3), tb.template get<1, 1>(a0), tb.template get<2, 2>(a1)),
+                           tb.template get<3, 3>(a2), key.template w<7>());
+  // round 2, output column c = T0[c] ^ T1[c+1] ^ T2[c+2] ^ T3[c+3] over the
+  // round-1 columns: every term but the one reading column 0
+  q.p[0] = xor3(tb.template get<1, 1>(c1), tb.template get<2, 2>(c2), tb.template get<3, 3>(c3)) ^ key.template w<8>();
+  q.p[1] = xor3(tb.template get<0, 0>(c1), tb.template get<1, 1>(c2), tb.template get<2, 2>(c3)) ^ key.template w<9>();
+  q.p[2] = xor3(tb.template get<0, 0>(c2), tb.template get<1, 1>(c3), tb.template get<3, 3>(c1)) ^ key.template w<10>();
+  q.p[3] = xor3(tb.template get<0, 0>(c3), tb.template get<2, 2>(c1), tb.template get<3, 3>(c2)) ^ key.template w<11>();
+}
+
+template <class Key, class TB, int K, int... Rs>
+__device__ __forceinline__ void aes_rounds_from3(const Key& key, const TB& tb, uint32_t (&s)[K][4],
+                                                 std::integer_sequence<int, Rs...>) {
+  (aes_round<Rs + 3>(key, tb, s), ...);
+}
+
+// H(s, j_k) for K tweaks of a seed whose prefix q = prg_prefix(s) is
+// computed once: per block, the tweak byte's round-1 lookup, round 2's four
+// lookups of column 0, then rounds 3..10.
+template <class TB, int K>
+__device__ __forceinline__ void prg_from_prefix(const TB& tb, const uint32_t (&s)[4], const PrgPrefix& q,
+                                                const uint32_t (&j)[K], uint32_t (&o)[K][4]) {
+  if constexpr (TB::kBitsliced) {
+    prg_shared<TB, K>(tb, s, j, o);
+    return;
+  }
+  constexpr PrgKey key{};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint32_t x0 = xor3(q.c0, tb.template get<3, 3>(q.a3 ^ (j[k] << 24)), key.template w<4>());
+    o[k][0] = q.p[0] ^ tb.template get<0, 0>(x0);
+    o[k][1] = q.p[1] ^ tb.template get<3, 3>(x0);
+    o[k][2] = q.p[2] ^ tb.template get<2, 2>(x0);
+    o[k][3] = q.p[3] ^ tb.template get<1, 1>(x0);
+  }
+  aes_rounds_from3(key, tb, o, std::make_integer_sequence<int, 7>{});
+  aes_final(key, tb, o);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    o[k][0] ^= s[0];
+    o[k][1] ^= s[1];
+    o[k][2] ^= s[2];
+    o[k][3] ^= s[3] ^ (j[k] << 24);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Header validation (uniform across the launch)
 // ---------------------------------------------------------------------------
@@ -1175,6 +1240,13 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
 #pragma unroll
     for (int q = 0; q < P; ++q) dk[q] = 0;
     const bool last = i + 1 == L;
+    // every child's blocks come from the parties' seeds s[0], s[1]: their
+    // tweak-independent AES work once per level
+    PrgPrefix pre[2];
+    if constexpr (!TB::kBitsliced) {
+      prg_prefix(tb, s[0], pre[0]);
+      prg_prefix(tb, s[1], pre[1]);
+    }
     // The corrections of child c from both parties' expansions: seed blocks
     // sd0 / sd1 (above the last level) and values v0 / v1.  At the last level
     // only values: alpha's child is corrected like the others (without beta),
@@ -1232,8 +1304,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
           if (last) {
             const uint32_t jj[2] = {vb0, vb0 + 1};
             uint32_t p0[2][4], p1[2][4];
-            prg_shared<TB, 2>(tb, s[0], jj, p0);
-            prg_shared<TB, 2>(tb, s[1], jj, p1);
+            prg_from_prefix<TB, 2>(tb, s[0], pre[0], jj, p0);
+            prg_from_prefix<TB, 2>(tb, s[1], pre[1], jj, p1);
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
               o0[0][w] = o1[0][w] = 0u;
@@ -1242,8 +1314,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
             }
           } else {
             const uint32_t jj[3] = {c, vb0, vb0 + 1};
-            prg_shared<TB, 3>(tb, s[0], jj, o0);
-            prg_shared<TB, 3>(tb, s[1], jj, o1);
+            prg_from_prefix<TB, 3>(tb, s[0], pre[0], jj, o0);
+            prg_from_prefix<TB, 3>(tb, s[1], pre[1], jj, o1);
           }
           const uint64_t v0[3] = {mk64(o0[1][0], o0[1][1]), mk64(o0[1][2], o0[1][3]), mk64(o0[2][0], o0[2][1])};
           const uint64_t v1[3] = {mk64(o1[1][0], o1[1][1]), mk64(o1[1][2], o1[1][3]), mk64(o1[2][0], o1[2][1])};
@@ -1258,8 +1330,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
           if (last) {
             const uint32_t jj[1] = {vb0 + 2};
             uint32_t p0[1][4], p1[1][4];
-            prg_shared<TB, 1>(tb, s[0], jj, p0);
-            prg_shared<TB, 1>(tb, s[1], jj, p1);
+            prg_from_prefix<TB, 1>(tb, s[0], pre[0], jj, p0);
+            prg_from_prefix<TB, 1>(tb, s[1], pre[1], jj, p1);
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
               o0[0][w] = o1[0][w] = 0u;
@@ -1268,8 +1340,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
             }
           } else {
             const uint32_t jj[2] = {c + 1, vb0 + 2};
-            prg_shared<TB, 2>(tb, s[0], jj, o0);
-            prg_shared<TB, 2>(tb, s[1], jj, o1);
+            prg_from_prefix<TB, 2>(tb, s[0], pre[0], jj, o0);
+            prg_from_prefix<TB, 2>(tb, s[1], pre[1], jj, o1);
           }
           const uint64_t v0[3] = {carry[0], mk64(o0[1][0], o0[1][1]), mk64(o0[1][2], o0[1][3])};
           const uint64_t v1[3] = {carry[1], mk64(o1[1][0], o1[1][1]), mk64(o1[1][2], o1[1][3])};
@@ -1283,8 +1355,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
         if (last) {
           const uint32_t jj[1] = {vb0};
           uint32_t p0[1][4], p1[1][4];
-          prg_shared<TB, 1>(tb, s[0], jj, p0);
-          prg_shared<TB, 1>(tb, s[1], jj, p1);
+          prg_from_prefix<TB, 1>(tb, s[0], pre[0], jj, p0);
+          prg_from_prefix<TB, 1>(tb, s[1], pre[1], jj, p1);
 #pragma unroll
           for (int w = 0; w < 4; ++w) {
             o0[0][w] = o1[0][w] = 0u;
@@ -1293,8 +1365,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
           }
         } else {
           const uint32_t jj[2] = {c, vb0};
-          prg_shared<TB, 2>(tb, s[0], jj, o0);
-          prg_shared<TB, 2>(tb, s[1], jj, o1);
+          prg_from_prefix<TB, 2>(tb, s[0], pre[0], jj, o0);
+          prg_from_prefix<TB, 2>(tb, s[1], pre[1], jj, o1);
         }
         {
           const uint64_t v0[1] = {mk64(o0[1][0], o0[1][1])}, v1[1] = {mk64(o1[1][0], o1[1][1])};
@@ -1307,8 +1379,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
         if (!last) {
           const uint32_t jj[1] = {c + 1};
           uint32_t p0[1][4], p1[1][4];
-          prg_shared<TB, 1>(tb, s[0], jj, p0);
-          prg_shared<TB, 1>(tb, s[1], jj, p1);
+          prg_from_prefix<TB, 1>(tb, s[0], pre[0], jj, p0);
+          prg_from_prefix<TB, 1>(tb, s[1], pre[1], jj, p1);
 #pragma unroll
           for (int w = 0; w < 4; ++w) {
             sd0[w] = p0[0][w];
@@ -1327,8 +1399,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
             uint32_t jj[NB], p0[NB][4], p1[NB][4];
 #pragma unroll
             for (int k = 0; k < NB; ++k) jj[k] = vb + (uint32_t)k;
-            prg_shared<TB, NB>(tb, s[0], jj, p0);
-            prg_shared<TB, NB>(tb, s[1], jj, p1);
+            prg_from_prefix<TB, NB>(tb, s[0], pre[0], jj, p0);
+            prg_from_prefix<TB, NB>(tb, s[1], pre[1], jj, p1);
 #pragma unroll
             for (int w = 0; w < 4; ++w) {
               o0[0][w] = o1[0][w] = 0u;
@@ -1343,8 +1415,8 @@ __device__ __forceinline__ void gen_vec_at(const TB& tb, uint64_t off_croot, uin
             jj[0] = cc;
 #pragma unroll
             for (int k = 0; k < NB; ++k) jj[1 + k] = vb + (uint32_t)k;
-            prg_shared<TB, 1 + NB>(tb, s[0], jj, o0);
-            prg_shared<TB, 1 + NB>(tb, s[1], jj, o1);
+            prg_from_prefix<TB, 1 + NB>(tb, s[0], pre[0], jj, o0);
+            prg_from_prefix<TB, 1 + NB>(tb, s[1], pre[1], jj, o1);
           }
           uint64_t v0[P], v1[P];
 #pragma unroll
