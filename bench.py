@@ -176,7 +176,7 @@ def main() -> None:
                          "call-1 unit, lanes per element (as fss_tune; replaces the autotuner)")
     ap.add_argument("--latency-reps", type=int, default=None,
                     help="fused/plain step pairs, alternating, for the latency percentiles and ratios "
-                         "(default: as many as fit about 2 s of steps, 60 to 200)")
+                         "(default: as many as fit about 5 s of steps, 60 to 500)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--lookup-r", type=int, default=None, choices=[2, 3, 4],
@@ -329,7 +329,7 @@ def main() -> None:
 
         if args.latency_reps is None:  # a p99 over more samples is less a maximum
             step_ms = wall * 1e3 / max(1, args.steps)
-            reps = min(200, max(60, int(2000.0 / (2.0 * step_ms))))
+            reps = min(500, max(60, int(5000.0 / (2.0 * step_ms))))
         else:
             reps = max(args.latency_reps, 50)
         rec = {True: [], False: []}
