@@ -353,3 +353,53 @@ def test_subprotocol_and_literal_arguments_rejected_on_the_host():
     assert L.fss_lit_key_bytes(s.handle, 24, 12, -1, C.byref(size)) == -8
     assert L.fss_lit_key_bytes(None, 24, 12, 4, C.byref(size)) == -8
     assert L.fss_lit_key_bytes(s.handle, 24, 12, 0, C.byref(size)) == 0 and size.value == 16384
+
+
+@pytest.mark.parametrize("r", [2, 3, 4])
+@pytest.mark.parametrize("name", ["gelu", "exp", "clip", "int_p4", "int_p2"])
+def test_keygen_work_counts(name, r):
+    """fss_keygen_work (the keygen roofline's work figure) equals the dealer's
+    expansions written out call by call, both parties per element: each Z_2
+    atom level above the leaves expands the party's seed under two tweaks
+    (one call, rounds 1-2 shared: 160 K - 24 (K - 1) lookups) and each atom
+    ends in one leaf block; each lookup level expands the 2^r children, two
+    at a time, from the party's one seed (its 27 tweak-independent lookups
+    once per level, then 133 per block); the counter-mode randomness is one
+    full block per draw."""
+    P = W.PredDesc
+    if name.startswith("int"):
+        p = int(name[-1])
+        n, f = 16, 0
+        spec = F.Spec.integer(n, [0, 1 << 14, 1 << 15, 1 << 16], [[1] * p] * 3,
+                              [P(W.LT_UNSIGNED, 0, thr=1000.0), P(W.MSB_SHIFT, 1, c=5)], lookup_r=r)
+    else:
+        desc = {"gelu": W.gelu_spec(), "exp": W.exp_spec(), "clip": W.clip_relu_spec()}[name]
+        n, f = (24, 12) if name != "clip" else (16, 8)
+        spec = F.Spec(desc, lookup_r=r)
+    q = spec.query(n, f)
+    p, T = q["p"], q["T"]
+    L = -(-n // r)
+    nb = (p + 1) // 2
+    lk = lambda k: 160 * k - 24 * (k - 1)
+    aes = lookups = 0
+    for k in q["atom_k"][:T]:
+        levels = k - min(7, k)
+        aes += 2 * (2 * levels + 1)
+        lookups += 2 * (levels * lk(2) + 160)
+    for level in range(L):
+        last = level == L - 1
+        calls = []  # the blocks of each expansion call of one party, over the children pairs
+        for _pair in range((1 << r) // 2):
+            if p == 3:
+                calls += [2, 1] if last else [3, 2]
+            elif p == 1:
+                calls += [1] if last else [2, 1]
+            else:
+                calls += [nb, nb] if last else [1 + nb, 1 + nb]
+        aes += 2 * sum(calls)
+        lookups += 2 * (27 + 133 * sum(calls))
+    draws = 8 + 2 * T + (L - 1) * (1 + nb)
+    aes += draws
+    lookups += 160 * draws
+    got_aes, got_lk = spec.keygen_work(n, f, 1000)
+    assert (got_aes, got_lk) == (1000 * aes, 1000 * lookups), (name, r)
